@@ -1,0 +1,116 @@
+/*
+ * dlb_oracle.h -- CPU FP64 reference ("oracle") for the diffuse-interface
+ * multi-relaxation-time lattice Boltzmann method of Zhan, Chai, Shi, Jiang,
+ * Geng and Sun, "A diffuse-interface lattice Boltzmann method for the
+ * dendritic growth with thermosolutal convection" (arXiv:2209.01444).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is loaded by the test suite, by the
+ * smoke check and by the CPU-baseline leg of the benchmark, never by the
+ * product path.  It shares no code, header, table or helper with the GPU
+ * library; the two meet only in the tests, which feed both the same seeded
+ * inputs.
+ *
+ * Units: lattice units, dx = 1, main step dt = 1, c = 1, cs^2 = 1/3
+ * (Appendix B).  The flow lattice runs N_sub sub-steps of dt' = dt/N_sub per
+ * main step (two-time-scaling, Sec. 4 preamble); inside it velocities are in
+ * lattice units per sub-step.  Everything this header returns is in main-step
+ * units unless stated otherwise.
+ *
+ * Parity status of each part (how it is pinned; see tests/test_oracle_*.py):
+ *   D2Q5/D2Q9 transforms, Lambda, equilibria, forcing moments   pinned
+ *   anisotropy a_s and N                                          pinned
+ *   phi lattice: modified streaming, source, local gradient       pinned
+ *   solute / heat lattices: diffusion, conservation, d_t(Cu)      pinned
+ *   flow lattice: viscosity, diffuse solid forcing                pinned
+ *   anti-trapping current J_at                                    parity unpinned
+ *   non-equilibrium-extrapolation walls                           parity unpinned
+ *   tip position / radius measurement                             pinned (geometry)
+ */
+#ifndef DLB_ORACLE_H
+#define DLB_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct orc_params {
+    int nx, ny;
+    int use_c;        /* solute lattice on (else U = U0 everywhere)          */
+    int use_t;        /* heat lattice on (else theta = theta0 everywhere)     */
+    int use_ns;       /* flow lattice on (else u = 0)                         */
+    int walls;        /* 0: periodic; 1: channel (west inflow, east outflow,
+                         free-slip north/south, zero-gradient phi/C/H)        */
+    int n_sub;        /* flow sub-steps per main step (two-time-scaling N)    */
+    int h_quintic;    /* 0: h(phi)=phi; 1: h = 15(phi-2phi^3/3+phi^5/5)/8    */
+    int c_init_U;     /* 0: initial C uniform = C0; 1: initial U uniform = U0 */
+    int grad_max_iter;/* cap on the implicit local-gradient iteration         */
+    double W0, tau0, eps4, orient, lambda, Mcinf, k, D, alpha, nu, rho0;
+    double u_in_x, u_in_y;   /* inflow / initial velocity, lu per main step  */
+    double theta0, U0, C0;
+    double seed_R, seed_x, seed_y, noise_amp;
+    double grad_tol;  /* relative stopping tolerance of the gradient iteration*/
+    double fixed_as;  /* test hook: >0 fixes a_s to this value and N to 0     */
+} orc_params;
+
+typedef struct orc_state orc_state;
+
+/* Lifecycle.  orc_create returns NULL when a relaxation rate leaves (0,2) or
+ * the grid is smaller than 3x3. */
+orc_state* orc_create(const orc_params* p);
+void       orc_destroy(orc_state* s);
+const char* orc_last_error(void);
+
+/* Initial condition of Sec. 4: diffuse circular seed
+ *   phi = tanh[(R_s - d_s)/(sqrt(2) W0)]
+ * plus noise_amp*noise[x] where |phi| < 0.9 (noise: nx*ny host doubles, or
+ * NULL).  Then orc_set_fields semantics. */
+int orc_init_seed(orc_state* s, const double* noise);
+
+/* Re-initialise every lattice to equilibrium at the given macroscopic fields
+ * (each nx*ny, row-major y*nx+x; NULL -> parameter default: C from C0/U0,
+ * theta0, u_in).  The phi populations also carry the first moment that makes
+ * the local gradient scheme return the central-difference gradient of phi.
+ * History is reset (time derivatives are zero on the next step).  p := 0. */
+int orc_set_fields(orc_state* s, const double* phi, const double* C,
+                   const double* theta, const double* ux, const double* uy);
+
+int  orc_step(orc_state* s, long nsteps);
+long orc_step_count(const orc_state* s);
+
+/* Seven planes of nx*ny: phi, C, U, theta, ux, uy (lu/main step), p
+ * (main-step units). */
+int orc_get_fields(orc_state* s, double* out);
+
+/* Raw populations of one lattice (0 phi, 1 C, 2 H, 3 flow), q*nx*ny,
+ * pre-collision at the current step; flow slot 0 unshifted (includes rho0). */
+int orc_get_pops(orc_state* s, int lattice, double* out);
+
+/* Reductions, out[0..16]:
+ *   0 sum C, 1 sum H, 2 solid fraction sum((1+phi)/2)/N, 3 non-finite count,
+ *   4,5 hydrodynamic force Fx,Fy, 6 torque (flow sub-step units),
+ *   7..10 tip position s_k of arms k=0..3, 11..14 tip radius rho_k,
+ *   15,16 solid centroid */
+int orc_reduce(orc_state* s, double* out);
+
+/* ---- single-node primitives, exposed for the pins ---- */
+void orc_m_d2q5(double* M25);
+void orc_m_d2q9(double* M81);
+void orc_lambda_d2q5(double s0, double s1, double s2, double* L25);
+void orc_lambda_d2q9(const double* s9, double* L81);
+void orc_eq_phi(double phi, double* out5);
+void orc_eq_solute(double C, double phi, double U, double ux, double uy, double* out5);
+void orc_eq_heat(double theta, double phi, int h_quintic, double ux, double uy, double* out5);
+void orc_eq_flow(double rho0, double p, double ux, double uy, double* out9);
+void orc_force_flow(double Fx, double Fy, double* out9);
+void orc_anisotropy(double eps4, double orient, double gx, double gy, double* out3);
+/* out: gx, gy, a_s, Nx, Ny, iterations */
+void orc_local_gradient(const orc_params* p, double m1x, double m1y, double* out6);
+/* One flow collision at a node (sub-step units): pre-collision h (9, slot 0
+ * unshifted), frozen phi -> post-collision populations; aux[0..3] = u*, u. */
+void orc_collide_flow(const orc_params* p, const double* h, double phi,
+                      double* post, double* aux);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,92 @@
+"""Seeded synthetic workloads: parameter sets and random inputs.
+
+This module holds numbers and random draws only, none of the method's
+arithmetic, so both the GPU library and the CPU oracle can be fed from it.
+All parameters are in lattice units (dx = 1, main step dt = 1).
+
+Lattice mapping of the paper's runs: W0 = 1 lu and tau0 = 20 steps, so that
+W0^2/tau0 = 0.05 lu^2/step, the lattice diffusivity of the paper's thermal
+case (dx = 0.4 W0, dt = 0.008 tau0).  Diffusivities follow the paper's
+dimensionless sets: thermal alpha = 4 W0^2/tau0 (Sec. 4.2), thermosolutal
+alpha = D = 2 W0^2/tau0 (Sec. 4.4); viscosity from Pr = nu/alpha = 23.1
+(Sec. 4.2); two-time-scaling N = 15 (Sec. 4 preamble).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+# Sec. 4.2: lambda = a1 W0 / d0 with a1 = 0.8839, d0 = 0.1385 W0
+LAMBDA_THERMAL = 0.8839 / 0.1385
+
+
+def pure_diffusion_128(precision: str = "f64") -> dict:
+    """Plain method without flow: 128x128 periodic, one seed of radius 8 lu
+    at node (64, 64), undercooling 0.55, eps4 = 0.05 at 0 degrees, uniform
+    c (C = 1) and uniform theta; thermal coupling (Mc_inf = 0)."""
+    return dict(
+        name="pure_diffusion_128", nx=128, ny=128, use_c=1, use_t=1, use_ns=0, walls=0, n_sub=1,
+        W0=1.0, tau0=20.0, eps4=0.05, orient=0.0, lambda_=LAMBDA_THERMAL, Mcinf=0.0, k=0.15,
+        D=0.1, alpha=0.2, nu=0.0, rho0=1.0, u_in=(0.0, 0.0), theta0=-0.55, U0=0.0, C0=1.0,
+        c_init_U=0, seed_R=8.0, seed_x=64.0, seed_y=64.0, noise_amp=0.0, precision=precision,
+        steps=2000,
+    )
+
+
+def thermosolutal_flow(nx: int = 1024, ny: int = 1024, seed: int = 2, precision: str = "f32",
+                       orient: float | None = None, u0: float = 0.01, delta: float = 0.55,
+                       eps4: float = 0.05) -> tuple[dict, np.ndarray]:
+    """Full thermosolutal coupling with melt flow (the paper's Sec. 4.4 set
+    in lattice units): central seed of radius 10 lu with an orientation drawn
+    from U[0, pi/4), undercooling 0.55, eps4 = 0.05, uniform inflow u0 from
+    the west, unit Gaussian noise (scaled by noise_amp = 1e-3 where |phi| < 0.9).
+    Returns (parameters, noise field of shape (ny, nx))."""
+    rng = np.random.default_rng(seed)
+    drawn = float(rng.uniform(0.0, math.pi / 4))
+    noise = rng.standard_normal((ny, nx))
+    cfg = dict(
+        name=f"thermosolutal_flow_{nx}x{ny}", nx=nx, ny=ny, use_c=1, use_t=1, use_ns=1, walls=1,
+        n_sub=15, W0=1.0, tau0=20.0, eps4=eps4, orient=drawn if orient is None else orient,
+        lambda_=3.1913, Mcinf=0.5325, k=0.15, D=0.1, alpha=0.1, nu=23.1 * 0.1, rho0=1.0,
+        u_in=(u0, 0.0), theta0=-delta, U0=0.0, C0=1.0, c_init_U=1, seed_R=10.0,
+        seed_x=float(nx // 2), seed_y=float(ny // 2), noise_amp=1e-3, precision=precision,
+        steps=20000,
+    )
+    return cfg, noise
+
+
+def batched_sweep(count: int = 256, seed: int = 4) -> list[tuple[dict, np.ndarray]]:
+    """Independent seeds for a batched sweep: size from {128..1024}^2,
+    undercooling ~ U[0.3, 0.65], eps4 ~ U[0.02, 0.05], orientation ~ U[0, pi/4),
+    u0 ~ U[0, 0.02]; otherwise the thermosolutal set."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(rng.choice([128, 256, 512, 1024]))
+        delta = float(rng.uniform(0.3, 0.65))
+        eps4 = float(rng.uniform(0.02, 0.05))
+        orient = float(rng.uniform(0.0, math.pi / 4))
+        u0 = float(rng.uniform(0.0, 0.02))
+        nseed = int(rng.integers(0, 2**31 - 1))
+        cfg, noise = thermosolutal_flow(n, n, seed=nseed, orient=orient, u0=u0, delta=delta,
+                                        eps4=eps4)
+        cfg["name"] = f"sweep_{i}_{n}"
+        cfg["steps"] = 10000
+        out.append((cfg, noise))
+    return out
+
+
+def random_macro_tuples(count: int, seed: int = 11) -> np.ndarray:
+    """Random macroscopic tuples (phi, C, U, theta, ux, uy, p) for equilibrium
+    checks, in physically plausible ranges."""
+    rng = np.random.default_rng(seed)
+    out = np.empty((count, 7))
+    out[:, 0] = rng.uniform(-1.0, 1.0, count)
+    out[:, 1] = rng.uniform(0.1, 1.5, count)
+    out[:, 2] = rng.uniform(-1.0, 0.5, count)
+    out[:, 3] = rng.uniform(-1.0, 0.2, count)
+    out[:, 4] = rng.uniform(-0.05, 0.05, count)
+    out[:, 5] = rng.uniform(-0.05, 0.05, count)
+    out[:, 6] = rng.uniform(-1e-3, 1e-3, count)
+    return out

@@ -1,0 +1,72 @@
+"""The pins must catch plausible mistakes in the oracle.
+
+Each case plants one mistake (a dropped term, a wrong sign or factor) in a
+private copy of the oracle source, builds it, and runs the pin that should
+catch it against the mutant in a child pytest; the child must fail.  This
+runs on the CPU only."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "dlb_oracle.c")
+
+T = "tests/test_oracle_dynamics.py::"
+TT = "tests/test_oracle_tables.py::"
+
+MUTATIONS = [
+    ("no d_t F^phi term (Remark 2)", "acc += F[i] + 0.5 * a2 * dF[i];", "acc += F[i];",
+     T + "test_phase_field_mode_decay_with_fixed_anisotropy"),
+    ("plain streaming for phi", "(s->pf[o + src] - s->f[o + d]) / s->a2[src]",
+     "(s->pf[o + src] - s->f[o + d])", T + "test_phase_field_mode_decay_with_fixed_anisotropy"),
+    ("sign of G^phi", "G[i] = -W5[i] * (C5X[i] * Nx + C5Y[i] * Ny) / a2;",
+     "G[i] = W5[i] * (C5X[i] * Nx + C5Y[i] * Ny) / a2;",
+     T + "test_front_undulation_relaxes_with_anisotropic_stiffness"),
+    ("no d_t(Cu), d_t(Hu)", "double Vx = 3.0 * dCu[0]", "double Vx = 0.0 * dCu[0]",
+     T + "test_advected_mode_keeps_the_diffusivity"),
+    ("sign of U grad q", "double Vx = 3.0 * dCu[0] + U * (-0.5 * gx)",
+     "double Vx = 3.0 * dCu[0] + U * (0.5 * gx)",
+     T + "test_uniform_U_and_theta_are_steady_across_a_still_front"),
+    ("half the interface force", "Fb[0] = (1.0 - qt) * fx;", "Fb[0] = 0.5 * (1.0 - qt) * fx;",
+     TT + "test_fully_solid_node_stops_the_flow"),
+    ("viscosity not rescaled by N", "double nu_sub = p->nu / (double)p->n_sub;",
+     "double nu_sub = p->nu;", T + "test_taylor_green_decay_with_two_time_scaling"),
+    ("h(phi)/2 dropped from g_0^eq", "out[0] = W5[0] * theta - 0.5 * hp;",
+     "out[0] = W5[0] * theta;", TT + "test_cde_equilibrium_moment_conditions"),
+    ("sign of Mc_inf U", "p->lambda * (theta + p->Mcinf * U)", "p->lambda * (theta - p->Mcinf * U)",
+     T + "test_undercooled_planar_front_speed"),
+    ("U without 1/(1-k)", "s->U[x] = (2.0 * C / (1.0 + p->k - (1.0 - p->k) * ph) - 1.0) / (1.0 - p->k);",
+     "s->U[x] = (2.0 * C / (1.0 + p->k - (1.0 - p->k) * ph) - 1.0);",
+     T + "test_solute_and_heat_modes_decay_at_the_diffusivity"),
+    ("anisotropy strength", "4.0 * eps / (1.0 - 3.0 * eps) * sum_n4", "3.0 * eps / (1.0 - 3.0 * eps) * sum_n4",
+     TT + "test_anisotropy_matches_angle_form"),
+    ("sign of N in the local gradient", "double nx = -3.0 * s1 * (m1x + W2t * Nx);",
+     "double nx = -3.0 * s1 * (m1x - W2t * Nx);",
+     TT + "test_local_gradient_inverts_its_defining_relation"),
+    ("pressure coefficient", "(u[0] * u[0] + u[1] * u[1]) / (2.0 * cs2)", "(u[0] * u[0] + u[1] * u[1]) / cs2",
+     T + "test_uniform_channel_flow_is_steady"),
+    ("velocity term of n^eq", "out[i] = W5[i] * qU + W5[i] * (3.0 * cu);", "out[i] = W5[i] * qU + W5[i] * cu;",
+     TT + "test_cde_equilibrium_moment_conditions"),
+    ("tip interpolation index", "best = (j - 1) + prev / (prev - v);", "best = j + prev / (prev - v);",
+     T + "test_tip_of_a_parabolic_finger"),
+    ("transposed D2Q5 Lambda", "acc += Minv[i * n + k] * s[k] * M[k * n + j];",
+     "acc += Minv[j * n + k] * s[k] * M[k * n + i];", TT + "test_d2q5_lambda_equals_printed_matrix"),
+]
+
+
+@pytest.mark.parametrize("label,old,new,pin", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_pin_catches_planted_mistake(tmp_path, label, old, new, pin):
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation anchor not unique/found: {old!r}"
+    mut_c = tmp_path / "mutant.c"
+    mut_c.write_text(src.replace(old, new))
+    lib = tmp_path / "libmutant.so"
+    subprocess.run(["gcc", "-O2", "-std=gnu11", "-fopenmp", "-ffp-contract=off", "-fPIC",
+                    "-shared", "-I", os.path.dirname(SRC), "-o", str(lib), str(mut_c), "-lm"],
+                   check=True)
+    env = dict(os.environ, DLB_ORACLE_LIB=str(lib))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", pin],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"pin {pin} did not catch: {label}\n{r.stdout[-2000:]}"
