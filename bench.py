@@ -1,0 +1,193 @@
+"""Benchmark: coupled four-lattice main steps of the diffuse-interface MRT
+lattice Boltzmann method on one MI355X.
+
+One step = one main step of the whole hot path: the phi/C/theta kernel plus
+N_sub = 15 flow sub-steps, over the 1024^2 thermosolutal-with-flow workload
+(FP32), inputs resident in HBM.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+  python bench.py --calibrate-copy   # plain copy kernel for counter scaling
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("lattice.h", "kernels.h", "dlb.hip"):
+        with open(os.path.join(ROOT, "paper_2209_01444_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(cfg: dict) -> dict:
+    """Bytes each kernel must move per node (each state word read once and
+    written once; neighbour reuse assumed perfect)."""
+    sb = {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}[cfg["precision"]]
+    cb = 8 if cfg["precision"] == "f64" else 4
+    ns = bool(cfg.get("use_ns"))
+    # k_pct: 15 populations in + out, 8 flow populations in (velocity),
+    # history in + out (phi, Q and, with flow, C u, H u)
+    hist = 6 if ns else 2
+    pct = 30 * sb + (8 * sb if ns else 0) + 2 * hist * cb
+    # k_flow: 9 populations in + out, frozen phi in
+    flow = 18 * sb + cb
+    return {"pct": pct, "flow": flow, "step": pct + (cfg["n_sub"] * flow if ns else 0)}
+
+
+def traffic_from_profiles(kernel: str, workload: str) -> float | None:
+    """Counter-measured HBM bytes per launch from a committed summary, only
+    if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(cfg, noise, budget_s: float = 12.0) -> dict:
+    from oracle import oracle as orc
+
+    o = orc.Oracle(cfg).init_seed(noise)
+    o.step(1)
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        o.step(1)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or steps >= 200:
+            break
+    nodes = cfg["nx"] * cfg["ny"]
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": nodes * steps / el / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": f"{steps} main steps of the same {cfg['nx']}x{cfg['ny']} workload "
+                      f"(FP64 oracle, OpenMP), {el:.1f} s"}
+
+
+def calibrate_copy(nbytes: int = 1 << 30, reps: int = 5):
+    import ctypes
+
+    import torch
+
+    from paper_2209_01444_amd import dlb
+
+    lib = dlb.load_library()
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    st = torch.cuda.current_stream().cuda_stream
+    for _ in range(reps):
+        rc = lib.dlb_copy_kernel(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()),
+                                 nbytes, ctypes.c_void_p(st))
+        assert rc == 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        lib.dlb_copy_kernel(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nbytes,
+                            ctypes.c_void_p(st))
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    print(json.dumps({"copy_bytes": nbytes, "reps": reps,
+                      "copy_GBs": 2 * nbytes * reps / el / 1e9}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--precision", default="f32")
+    ap.add_argument("--size", type=int, default=1024)
+    ap.add_argument("--timed-launch-steps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no multi-GPU "
+              "path: see the sharding design in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+
+    import torch
+
+    from paper_2209_01444_amd import dlb, workloads
+
+    cfg, noise = workloads.thermosolutal_flow(args.size, args.size, seed=2, precision=args.precision)
+    solver = dlb.Solver(cfg).init_seed(noise)
+    nodes = cfg["nx"] * cfg["ny"]
+
+    solver.step(args.warmup)
+    solver.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solver.step(args.steps)
+    solver.sync()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    mlups = nodes * args.steps / el / 1e6
+    ms_per_step = el / args.steps * 1e3
+
+    # per-kernel durations from HIP events on the solver's stream
+    tk = solver.step_timed(args.timed_launch_steps)
+    ab = algorithmic_bytes(cfg)
+    flow_ms = tk["ms_flow"] / max(tk["launches_flow"], 1)
+    pct_ms = tk["ms_pct"] / max(tk["launches_pct"], 1)
+    flow_bytes = ab["flow"] * nodes
+    achieved = flow_bytes / (flow_ms * 1e-3) / 1e9
+    wl = f"thermosolutal_flow_{cfg['nx']}x{cfg['ny']}_{cfg['precision']}"
+    red = solver.reduce(allow_nonfinite=True)
+
+    line = {
+        "metric": "coupled-lattice MLUPS",
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": cfg["precision"],
+        "data": "synthetic",
+        "config": {"workload": wl, "nx": cfg["nx"], "ny": cfg["ny"], "n_sub": cfg["n_sub"],
+                   "lattices": "phi D2Q5 + C D2Q5 + theta D2Q5 + flow D2Q9",
+                   "algorithmic_bytes_per_node_step": ab["step"], "parallelism": "single GPU"},
+        "roofline": {
+            "bound": "hbm", "kernel": "k_flow (flow sub-step)",
+            "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": traffic_from_profiles("k_flow", wl),
+            "avg_launch_ms": round(flow_ms, 5), "bytes_per_launch": flow_bytes,
+        },
+        "kernels": {
+            "k_pct": {"avg_ms": round(pct_ms, 5), "GBs": round(ab["pct"] * nodes / (pct_ms * 1e-3) / 1e9, 1)},
+            "k_flow": {"avg_ms": round(flow_ms, 5), "GBs": round(achieved, 1)},
+            "whole_step_algorithmic_GBs": round(ab["step"] * nodes / (ms_per_step * 1e-3) / 1e9, 1),
+        },
+        "state": {"step": solver.step_count, "solid_fraction": red["solid_fraction"],
+                  "nonfinite": red["nonfinite"]},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(cfg, noise)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

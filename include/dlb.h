@@ -1,0 +1,183 @@
+/*
+ * dlb.h -- C ABI of libdlb.so, the MI355X (gfx950) solver for the
+ * diffuse-interface multi-relaxation-time lattice Boltzmann method of
+ * Zhan, Chai, Shi, Jiang, Geng and Sun, "A diffuse-interface lattice
+ * Boltzmann method for the dendritic growth with thermosolutal convection"
+ * (arXiv:2209.01444).
+ *
+ * The statement of the problem is the paper's: the phase field phi of the
+ * anisotropic phase-field equation (Sec. 2, Sec. 3.1, D2Q5), the solute C and
+ * supersaturation U (Sec. 3.2, D2Q5), the heat variable H and temperature
+ * theta (Sec. 3.3, D2Q5), and the melt flow u, p with the order-parameter
+ * fluid-solid force [1 - q(phi)] f (Sec. 3.4, D2Q9), advanced together by
+ * dt; the flow lattice takes N_sub sub-steps of dt/N_sub (two-time-scaling,
+ * Sec. 4 preamble).
+ *
+ * Units are lattice units: dx = 1, main step dt = 1, c = 1, cs^2 = 1/3.
+ * Velocities are in lu per main step, pressure in main-step units.
+ * Fields are row-major nx*ny planes, index y*nx + x.
+ *
+ * Memory: the caller owns the device state buffer (dev_state, at least
+ * dlb_state_bytes bytes, 256-byte aligned) and the HIP stream; the library
+ * owns only the small host-side handle.  All calls are asynchronous on the
+ * stream unless they say otherwise.  No C++ exception crosses this ABI.
+ *
+ * Errors: every int-returning call returns DLB_OK (0) or a negative code;
+ * dlb_last_error() describes the last failure of the calling thread.
+ */
+#ifndef DLB_H
+#define DLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    DLB_OK = 0,
+    DLB_EINVAL = -1,      /* bad argument: relaxation rate outside (0,2), grid < 16x16,
+                             unknown precision, null handle, n < 0 ...              */
+    DLB_ENOMEM = -2,      /* state buffer smaller than dlb_state_bytes()          */
+    DLB_EHIP = -3,        /* a HIP call failed; dlb_last_error() has its message  */
+    DLB_ENAN = -4,        /* a reduction found non-finite values                  */
+    DLB_EUNSUPPORTED = -5 /* combination not built                                */
+};
+
+/* Population storage / compute precision. */
+enum {
+    DLB_F64 = 0,   /* FP64 storage and arithmetic                                  */
+    DLB_F32 = 1,   /* FP32 storage and arithmetic                                  */
+    DLB_F16S = 2,  /* FP16 storage of shifts from the rest-state populations,
+                      FP32 arithmetic and history, FP64 reductions                 */
+    DLB_BF16S = 3, /* as DLB_F16S with BF16 storage                                */
+    DLB_F32M = 4   /* FP32 storage and history, FP64 arithmetic                     */
+};
+
+/* Boundary configuration. */
+enum {
+    DLB_BC_PERIODIC = 0,
+    /* Channel (Sec. 4.2, non-equilibrium extrapolation of Sec. 4 preamble):
+     * the outermost ring of nodes are wall nodes whose populations are
+     * rebuilt from the inward neighbour x_f (diagonal at corners) whenever
+     * they are read:  f(x_b) = f^eq(Psi_b, u_b) + f(x_f) - f^eq(Psi_f, u_f).
+     * phi, C, H: zero gradient (a copy of x_f).  Flow: west x=0 inflow
+     * u_b = u_in, p_b = p_f; east x=nx-1 du/dx = 0 with p_b = 0 (u_b,y = 0 at
+     * its corners); north/south free slip u_b = (u_f,x, 0), p_b = p_f. */
+    DLB_BC_CHANNEL = 1
+};
+
+typedef struct dlb_params {
+    int32_t nx, ny;       /* grid, >= 16 each                                       */
+    int32_t use_ns;       /* 1: flow lattice on; 0: u = 0 (phi, C, theta always on)  */
+    int32_t bc;           /* DLB_BC_*                                                */
+    int32_t n_sub;        /* flow sub-steps per main step (Sec. 4: N = 15)           */
+    int32_t h_quintic;    /* 0: h(phi) = phi; 1: 15(phi - 2phi^3/3 + phi^5/5)/8      */
+    int32_t c_init_U;     /* initial solute: 0 uniform C = C0; 1 uniform U = U0      */
+    int32_t precision;    /* DLB_F64 .. DLB_F32M                                     */
+    int32_t grad_iters;   /* cap of the local-gradient fixed point (0: default)      */
+    int32_t reserved;
+    double W0, tau0;      /* interface width and kinetic time (Sec. 2)              */
+    double eps4, orient;  /* anisotropy strength and crystal orientation (rad)      */
+    double lambda, Mcinf, k;   /* coupling, M c_inf, partition coefficient          */
+    double D, alpha, nu;  /* solute and heat diffusivities, viscosity (main units)  */
+    double rho0;          /* constant density of the flow model (Sec. 3.4)          */
+    double u_in_x, u_in_y;/* inflow / initial velocity                              */
+    double theta0, U0, C0;/* initial temperature, supersaturation, concentration    */
+    double seed_R, seed_x, seed_y; /* seed radius and centre (lu, node coordinates)  */
+    double noise_amp;     /* amplitude applied to the caller's noise field          */
+    double grad_tol;      /* relative tolerance of the gradient fixed point (0: default) */
+} dlb_params;
+
+typedef struct dlb_solver* dlb_handle;
+
+/* Bytes of device state needed for p; 0 if p is invalid. Pure. */
+size_t dlb_state_bytes(const dlb_params* p);
+
+/* Bind a solver to a caller-owned device buffer and stream (hipStream_t, may
+ * be NULL for the null stream).  Nothing is initialised on the device. */
+int dlb_create(const dlb_params* p, void* dev_state, size_t bytes, void* hip_stream,
+               dlb_handle* out);
+int dlb_destroy(dlb_handle h);
+
+/* Initial condition of Sec. 4: the diffuse seed
+ *   phi = tanh[(R_s - d_s)/(sqrt(2) W0)]
+ * centred at (seed_x, seed_y), plus noise_amp * noise[x] where |phi| < 0.9
+ * (noise: nx*ny doubles on the host, or NULL); then as dlb_set_fields with
+ * the parameter defaults.  Synchronises the stream. */
+int dlb_init_seed(dlb_handle h, const double* noise);
+
+/* Re-initialise every lattice at the given macroscopic fields (nx*ny doubles
+ * each; phi required, others NULL for the parameter default: C from C0/U0,
+ * theta0, u_in).  Populations are set to their equilibria (Sec. 3.1-3.4,
+ * p = 0); the phi populations also carry the first moment that makes the
+ * local gradient of Sec. 3.1 return the isotropic central-difference
+ * gradient of phi.  Time derivatives restart from zero.  on_device: 1 if the
+ * pointers are device memory.  Synchronises the stream when on_device = 0. */
+int dlb_set_fields(dlb_handle h, const double* phi, const double* C, const double* theta,
+                   const double* ux, const double* uy, int on_device);
+
+/* Advance n >= 0 main steps (asynchronous). */
+int dlb_step(dlb_handle h, int64_t n);
+
+/* As dlb_step (without graph replay), recording HIP events on the solver's
+ * stream before and after the phi/C/theta kernel and after the last flow
+ * sub-step of every main step; returns the summed milliseconds of the
+ * phi/C/theta kernels and of the back-to-back flow sub-steps, and the
+ * number of launches of each.  Synchronises the stream after every step. */
+int dlb_step_timed(dlb_handle h, int64_t n, double* ms_pct, double* ms_flow,
+                   int64_t* launches_pct, int64_t* launches_flow);
+
+int64_t dlb_step_count(dlb_handle h);
+
+/* Macroscopic fields (Sec. 3.1-3.4) at the current step.  mask bit f selects
+ * field f of (phi, C, U, theta, ux, uy, p); out receives the selected fields
+ * in that order, nx*ny each, as doubles (out_f32 = 0) or floats.
+ * out_on_device: 1 if out is device memory (asynchronous), else the call
+ * synchronises. */
+int dlb_get_fields(dlb_handle h, uint32_t mask, void* out, int out_on_device, int out_f32);
+
+/* Reductions in FP64 on the device; synchronises.  out[0..16]:
+ *   0 sum C, 1 sum H, 2 solid fraction sum((1+phi)/2)/(nx ny), 3 non-finite
+ *   count, 4-5 hydrodynamic force (Sec. 3.4) -sum [1-q(phi)] f, 6 torque about
+ *   the solid centroid (flow sub-step units), 7-10 tip position s_k of arm k
+ *   (angle orient + k pi/2 from the seed centre), 11-14 tip radius rho_k,
+ *   15-16 solid centroid.
+ * Tip: phi sampled every 1 lu along the arm ray (bilinear); s is the
+ * outermost sample pair phi_j > 0 >= phi_{j+1}, refined linearly; rho fits
+ * s(w) = s0 - w^2/(2 rho) over rays offset sideways by w = -3..3.
+ * Returns DLB_ENAN when the non-finite count is positive (out still filled). */
+int dlb_reduce(dlb_handle h, double* out);
+
+/* Checkpoint: the whole device state plus step counter and history flag.
+ * dlb_checkpoint_bytes() gives the host buffer size.  Synchronise. */
+size_t dlb_checkpoint_bytes(dlb_handle h);
+int dlb_save(dlb_handle h, void* host_buf, size_t bytes);
+int dlb_load(dlb_handle h, const void* host_buf, size_t bytes);
+
+int dlb_sync(dlb_handle h);
+
+/* FP64 equilibria of the four lattices evaluated on the device by the same
+ * functions the initialisation and the walls use (Sec. 3.1-3.4), for n
+ * host tuples macros[8*i..] = (phi, C, U, theta, ux, uy, p, rho0);
+ * out[24*i..] = f^eq(5), n^eq(5), g^eq(5), h^eq(9).  Evaluation order (no
+ * contraction): f_i = w_i*phi; q = 0.5*(1-phi), qU = q*U, n_0 = C +
+ * (w_0-1)*qU, n_i = w_i*qU + w_i*(3*(c_i.(C*u))); hp = h(phi), H = theta -
+ * 0.5*hp, g_0 = w_0*theta - 0.5*hp, g_i = w_i*theta + w_i*(3*(c_i.(H*u)));
+ * uu = ux*ux + uy*uy, cu = c_i.u, sigma_0 = (w_0-1)*(3p) + rho0,
+ * sigma_i = w_i*(3p), h_i = sigma_i + w_i*(3cu + 4.5*cu*cu - 1.5*uu).
+ * Synchronous; uses a temporary device allocation. */
+int dlb_equilibria(int64_t n, const double* macros, double* out, int h_quintic);
+
+/* Device copy of n bytes (a plain streaming kernel), used to calibrate
+ * bandwidth counters against a transfer of known size. */
+int dlb_copy_kernel(void* dst, const void* src, size_t bytes, void* hip_stream);
+
+const char* dlb_strerror(int code);
+const char* dlb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DLB_H */

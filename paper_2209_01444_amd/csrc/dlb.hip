@@ -1,0 +1,597 @@
+// dlb.hip -- host runtime and C ABI of libdlb.so (see include/dlb.h).
+//
+// The solver binds to a caller-owned device buffer and stream.  A main step
+// is one k_pct launch followed by N_sub k_flow launches, all on that stream;
+// long runs replay a captured HIP graph of two main steps (two steps bring
+// both ping-pong buffers back to the same parity, so one graph serves every
+// replay).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "dlb.h"
+#include "kernels.h"
+
+using namespace dlb;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(DLB_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));        \
+    } while (0)
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+size_t storage_bytes(int precision) {
+    switch (precision) {
+        case DLB_F64: return 8;
+        case DLB_F32:
+        case DLB_F32M: return 4;
+        case DLB_F16S:
+        case DLB_BF16S: return 2;
+    }
+    return 0;
+}
+// history planes are FP64 only in the all-FP64 configuration
+size_t history_bytes(int precision) { return precision == DLB_F64 ? 8 : 4; }
+
+struct Layout {
+    size_t plane;  // elements per plane
+    size_t pop[2], flow[2], hist, red, redout, total;
+    int nblocks;
+};
+
+int check_params(const dlb_params* p) {
+    if (!p) return fail(DLB_EINVAL, "null params");
+    if (p->nx < 16 || p->ny < 16) return fail(DLB_EINVAL, "grid must be at least 16x16");
+    if ((long long)p->nx * p->ny > (1ll << 31)) return fail(DLB_EINVAL, "grid too large");
+    if (storage_bytes(p->precision) == 0) return fail(DLB_EINVAL, "unknown precision");
+    if (p->bc != DLB_BC_PERIODIC && p->bc != DLB_BC_CHANNEL) return fail(DLB_EINVAL, "unknown bc");
+    if (p->use_ns && p->n_sub < 1) return fail(DLB_EINVAL, "n_sub must be >= 1");
+    if (!(p->W0 > 0 && p->tau0 > 0 && p->D > 0 && p->alpha > 0)) return fail(DLB_EINVAL, "W0, tau0, D, alpha must be > 0");
+    if (!(p->k > 0 && p->k < 1)) return fail(DLB_EINVAL, "partition coefficient k must be in (0,1)");
+    double W2t = p->W0 * p->W0 / p->tau0;
+    double lo = 1.0 - p->eps4, hi = 1.0 + p->eps4;  // range of a_s
+    double rates[4] = {1.0 / (3.0 * lo * lo * W2t + 0.5), 1.0 / (3.0 * p->D * (1.0 - p->k) + 0.5),
+                       1.0 / (3.0 * p->alpha + 0.5), 1.0};
+    double r2 = 1.0 / (3.0 * hi * hi * W2t + 0.5);
+    if (p->use_ns) {
+        if (!(p->nu > 0)) return fail(DLB_EINVAL, "nu must be > 0");
+        rates[3] = 1.0 / (3.0 * p->nu / p->n_sub + 0.5);
+        double mach = std::sqrt(p->u_in_x * p->u_in_x + p->u_in_y * p->u_in_y) / p->n_sub * std::sqrt(3.0);
+        if (mach > 0.1) return fail(DLB_EINVAL, "inflow Mach number |u| sqrt(3)/N_sub exceeds 0.1");
+    }
+    for (double r : rates)
+        if (!(r > 0.0 && r < 2.0)) return fail(DLB_EINVAL, "relaxation rate outside (0,2)");
+    if (!(r2 > 0.0 && r2 < 2.0)) return fail(DLB_EINVAL, "relaxation rate outside (0,2)");
+    if (!(p->eps4 >= 0.0 && p->eps4 < 1.0 / 15.0)) return fail(DLB_EINVAL, "eps4 must be in [0, 1/15)");
+    return DLB_OK;
+}
+
+Layout layout_of(const dlb_params* p) {
+    Layout L{};
+    size_t N = (size_t)p->nx * p->ny;
+    L.plane = (N + 63) & ~size_t(63);
+    size_t sb = storage_bytes(p->precision), cb = history_bytes(p->precision);
+    size_t off = 0;
+    for (int b = 0; b < 2; ++b) {
+        L.pop[b] = off;
+        off = align256(off + 15 * L.plane * sb);
+    }
+    for (int b = 0; b < 2; ++b) {
+        L.flow[b] = off;
+        if (p->use_ns) off = align256(off + 9 * L.plane * sb);
+    }
+    L.hist = off;
+    off = align256(off + (p->use_ns ? 6 : 2) * L.plane * cb);
+    int nbx = (p->nx + TILE_X - 1) / TILE_X, nby = (p->ny + TILE_Y - 1) / TILE_Y;
+    L.nblocks = nbx * nby;
+    L.red = off;
+    off = align256(off + (size_t)L.nblocks * NRED * sizeof(double));
+    L.redout = off;
+    off = align256(off + 32 * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+// Rest-state populations used as storage shifts for the 16-bit formats:
+// liquid phi = -1, the initial far-field C and theta, inflow velocity.
+static void rest_shifts(const dlb_params* p, float* sh) {
+    const double w5[5] = {1.0 / 3.0, 1.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0};
+    double phi = -1.0, k = p->k;
+    double C = p->c_init_U ? 0.5 * (1.0 + k - (1.0 - k) * phi) * (1.0 + (1.0 - k) * p->U0) : p->C0;
+    double U = (2.0 * C / (1.0 + k - (1.0 - k) * phi) - 1.0) / (1.0 - k);
+    double ux = p->use_ns ? p->u_in_x : 0.0, uy = p->use_ns ? p->u_in_y : 0.0;
+    double q = 0.5 * (1.0 - phi), qU = q * U;
+    double H = p->theta0 - 0.5 * phi;  // h(-1) = -1 for both forms of h
+    int cx[5] = {0, 1, 0, -1, 0}, cy[5] = {0, 0, 1, 0, -1};
+    for (int i = 0; i < 5; ++i) {
+        sh[i] = (float)(w5[i] * phi);
+        double cu = cx[i] * C * ux + cy[i] * C * uy;
+        sh[5 + i] = (float)(i == 0 ? C + (w5[0] - 1.0) * qU : w5[i] * qU + w5[i] * 3.0 * cu);
+        double hu = cx[i] * H * ux + cy[i] * H * uy;
+        sh[10 + i] = (float)(i == 0 ? w5[0] * p->theta0 - 0.5 * phi : w5[i] * p->theta0 + w5[i] * 3.0 * hu);
+    }
+    const double w9[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    int c9x[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1}, c9y[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    double n = p->use_ns ? p->n_sub : 1;
+    double vx = ux / n, vy = uy / n, uu = vx * vx + vy * vy;
+    for (int i = 0; i < 9; ++i) {
+        double cu = c9x[i] * vx + c9y[i] * vy;
+        sh[15 + i] = (float)(w9[i] * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
+    }
+}
+
+static KParams make_kparams(const dlb_params* p, const Layout& L) {
+    KParams k{};
+    k.nx = p->nx;
+    k.ny = p->ny;
+    k.plane = (long long)L.plane;
+    k.n_sub = p->use_ns ? p->n_sub : 1;
+    k.h_quintic = p->h_quintic;
+    // fixed-point defaults per arithmetic type: FP64 to 1e-14, the mixed
+    // FP32-storage/FP64-arithmetic mode to 1e-10, FP32 to 1e-6
+    bool f64 = p->precision == DLB_F64, mixed = p->precision == DLB_F32M;
+    k.grad_iters = p->grad_iters > 0 ? p->grad_iters : (f64 ? 100 : (mixed ? 40 : 20));
+    double tol = p->grad_tol > 0 ? p->grad_tol : (f64 ? 1e-14 : (mixed ? 1e-10 : 1e-6));
+    k.grad_tol2 = tol * tol;
+    k.walls = p->bc == DLB_BC_CHANNEL;
+    k.nbx = (p->nx + TILE_X - 1) / TILE_X;
+    k.nby = (p->ny + TILE_Y - 1) / TILE_Y;
+    k.nblocks = L.nblocks;
+    k.W0 = p->W0;
+    k.W2t = p->W0 * p->W0 / p->tau0;
+    k.inv_tau0 = 1.0 / p->tau0;
+    k.eps4 = p->eps4;
+    k.orient = p->orient;
+    k.co = std::cos(p->orient);
+    k.so = std::sin(p->orient);
+    k.lambda = p->lambda;
+    k.Mcinf = p->Mcinf;
+    k.k = p->k;
+    k.invD = 1.0 / p->D;
+    k.s1c = 1.0 / (3.0 * p->D * (1.0 - p->k) + 0.5);
+    k.s1t = 1.0 / (3.0 * p->alpha + 0.5);
+    k.s2u = p->use_ns ? 1.0 / (3.0 * p->nu / p->n_sub + 0.5) : 1.0;
+    k.jat = p->W0 / (2.0 * std::sqrt(2.0));
+    k.nsub_d = k.n_sub;
+    k.uin_x_sub = p->u_in_x / k.n_sub;
+    k.uin_y_sub = p->u_in_y / k.n_sub;
+    k.seed_R = p->seed_R;
+    k.seed_x = p->seed_x;
+    k.seed_y = p->seed_y;
+    k.noise_amp = p->noise_amp;
+    if (p->precision == DLB_F16S || p->precision == DLB_BF16S) rest_shifts(p, k.shift);
+    return k;
+}
+
+// ---------------------------------------------------------------------------
+// Kernel dispatch per (storage type, flow on, walls)
+// ---------------------------------------------------------------------------
+struct Ops {
+    void (*pct)(const KParams&, const void*, void*, const void*, void*, int, hipStream_t, dim3);
+    void (*flow)(const KParams&, const void*, void*, const void*, hipStream_t, dim3);
+    void (*set_fields)(const KParams&, const InitFields&, void*, void*, hipStream_t, dim3);
+    void (*fields)(const KParams&, const void*, const void*, uint32_t, void*, int, hipStream_t, dim3);
+    void (*reduce)(const KParams&, const void*, const void*, double*, hipStream_t, dim3);
+    void (*tips)(const KParams&, const void*, double*, hipStream_t);
+};
+
+template <class CF, bool NS, bool W> struct OpsImpl {
+    using S = typename CF::S;
+    using H = typename CF::H;
+    static void pct(const KParams& kp, const void* pin, void* pout, const void* hin, void* hist,
+                    int hv, hipStream_t st, dim3 grid) {
+        hipLaunchKernelGGL((k_pct<CF, NS, W>), grid, dim3(BLOCK), 0, st, kp, (const S*)pin, (S*)pout,
+                           (const S*)hin, (H*)hist, hv);
+    }
+    static void flow(const KParams& kp, const void* hin, void* hout, const void* phi, hipStream_t st,
+                     dim3 grid) {
+        hipLaunchKernelGGL((k_flow<CF, W>), grid, dim3(BLOCK), 0, st, kp, (const S*)hin, (S*)hout,
+                           (const H*)phi);
+    }
+    static void set_fields(const KParams& kp, const InitFields& in, void* pop, void* flow,
+                           hipStream_t st, dim3 grid) {
+        hipLaunchKernelGGL((k_set_fields<CF, NS, W>), grid, dim3(BLOCK), 0, st, kp, in, (S*)pop,
+                           (S*)flow);
+    }
+    static void fields(const KParams& kp, const void* pop, const void* flow, uint32_t mask, void* out,
+                       int f32, hipStream_t st, dim3 grid) {
+        hipLaunchKernelGGL((k_fields<CF, NS, W>), grid, dim3(BLOCK), 0, st, kp, (const S*)pop,
+                           (const S*)flow, mask, out, f32);
+    }
+    static void reduce(const KParams& kp, const void* pop, const void* flow, double* partial,
+                       hipStream_t st, dim3 grid) {
+        hipLaunchKernelGGL((k_reduce_partial<CF, NS, W>), grid, dim3(BLOCK), 0, st, kp,
+                           (const S*)pop, (const S*)flow, partial);
+    }
+    static void tips(const KParams& kp, const void* pop, double* out, hipStream_t st) {
+        hipLaunchKernelGGL((k_tips<CF, W>), dim3(4), dim3(448), 0, st, kp, (const S*)pop, out);
+    }
+    static Ops ops() { return Ops{pct, flow, set_fields, fields, reduce, tips}; }
+};
+
+template <class CF> static Ops ops_for(bool ns, bool walls) {
+    if (ns) return walls ? OpsImpl<CF, true, true>::ops() : OpsImpl<CF, true, false>::ops();
+    return walls ? OpsImpl<CF, false, true>::ops() : OpsImpl<CF, false, false>::ops();
+}
+
+static Ops select_ops(const dlb_params* p) {
+    bool ns = p->use_ns != 0, walls = p->bc == DLB_BC_CHANNEL;
+    switch (p->precision) {
+        case DLB_F64: return ops_for<CfgF64>(ns, walls);
+        case DLB_F32: return ops_for<CfgF32>(ns, walls);
+        case DLB_F32M: return ops_for<CfgF32M>(ns, walls);
+        case DLB_F16S: return ops_for<CfgF16>(ns, walls);
+        default: return ops_for<CfgBF16>(ns, walls);
+    }
+}
+
+struct dlb_solver {
+    dlb_params p;
+    Layout L;
+    KParams kp;
+    Ops ops;
+    char* base;
+    size_t bytes;
+    hipStream_t stream;
+    int pop_cur = 0, flow_cur = 0;
+    int hist_valid = 0;
+    int64_t step = 0;
+    dim3 grid;
+    hipGraphExec_t graph = nullptr;  // two main steps, valid once history is valid
+    int graph_pop = -1, graph_flow = -1;
+
+    void* pop(int b) const { return base + L.pop[b]; }
+    void* flow(int b) const { return base + L.flow[b]; }
+    void* hist() const { return base + L.hist; }
+    double* red() const { return (double*)(base + L.red); }
+    double* redout() const { return (double*)(base + L.redout); }
+};
+
+// Enqueue one main step.  Events, when given (3 of them), are recorded
+// before the phi/C/theta kernel, between it and the flow sub-steps, and after
+// the last sub-step, so the N_sub flow kernels run back to back as in a plain
+// step.
+static void enqueue_step(dlb_solver* s, hipEvent_t* ev) {
+    if (ev) (void)hipEventRecord(ev[0], s->stream);
+    s->ops.pct(s->kp, s->pop(s->pop_cur), s->pop(1 - s->pop_cur), s->flow(s->flow_cur), s->hist(),
+               s->hist_valid, s->stream, s->grid);
+    if (ev) (void)hipEventRecord(ev[1], s->stream);
+    s->pop_cur ^= 1;
+    s->hist_valid = 1;
+    if (s->p.use_ns) {
+        for (int i = 0; i < s->p.n_sub; ++i) {
+            s->ops.flow(s->kp, s->flow(s->flow_cur), s->flow(1 - s->flow_cur), s->hist(), s->stream,
+                        s->grid);
+            s->flow_cur ^= 1;
+        }
+    }
+    if (ev) (void)hipEventRecord(ev[2], s->stream);
+    s->step += 1;
+}
+
+static int build_graph(dlb_solver* s) {
+    if (s->graph) {
+        (void)hipGraphExecDestroy(s->graph);
+        s->graph = nullptr;
+    }
+    hipGraph_t g;
+    int pc = s->pop_cur, fc = s->flow_cur;
+    int64_t st = s->step;
+    HIP_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+    enqueue_step(s, nullptr);
+    enqueue_step(s, nullptr);
+    hipError_t e = hipStreamEndCapture(s->stream, &g);
+    s->pop_cur = pc;
+    s->flow_cur = fc;
+    s->step = st;
+    if (e != hipSuccess) return fail(DLB_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&s->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        s->graph = nullptr;
+        return fail(DLB_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    s->graph_pop = pc;
+    s->graph_flow = fc;
+    return DLB_OK;
+}
+
+extern "C" {
+
+const char* dlb_last_error(void) { return g_last_error.c_str(); }
+
+const char* dlb_strerror(int code) {
+    switch (code) {
+        case DLB_OK: return "ok";
+        case DLB_EINVAL: return "invalid argument";
+        case DLB_ENOMEM: return "state buffer too small";
+        case DLB_EHIP: return "HIP error";
+        case DLB_ENAN: return "non-finite values detected";
+        case DLB_EUNSUPPORTED: return "unsupported combination";
+    }
+    return "unknown error";
+}
+
+size_t dlb_state_bytes(const dlb_params* p) {
+    if (check_params(p) != DLB_OK) return 0;
+    return layout_of(p).total;
+}
+
+int dlb_create(const dlb_params* p, void* dev_state, size_t bytes, void* hip_stream, dlb_handle* out) {
+    if (!out) return fail(DLB_EINVAL, "null output handle");
+    *out = nullptr;
+    int rc = check_params(p);
+    if (rc) return rc;
+    Layout L = layout_of(p);
+    if (!dev_state || bytes < L.total)
+        return fail(DLB_ENOMEM, "state buffer smaller than dlb_state_bytes()");
+    if (((uintptr_t)dev_state & 255) != 0) return fail(DLB_EINVAL, "state buffer must be 256-byte aligned");
+    dlb_solver* s = new (std::nothrow) dlb_solver();
+    if (!s) return fail(DLB_ENOMEM, "host allocation failed");
+    s->p = *p;
+    s->L = L;
+    s->kp = make_kparams(p, L);
+    s->ops = select_ops(p);
+    s->base = (char*)dev_state;
+    s->bytes = bytes;
+    s->stream = (hipStream_t)hip_stream;
+    s->grid = dim3(L.nblocks);
+    *out = s;
+    return DLB_OK;
+}
+
+int dlb_destroy(dlb_handle h) {
+    if (!h) return fail(DLB_EINVAL, "null handle");
+    if (h->graph) (void)hipGraphExecDestroy(h->graph);
+    delete h;
+    return DLB_OK;
+}
+
+static int set_fields_device(dlb_handle h, const double* phi, const double* C, const double* th,
+                             const double* ux, const double* uy) {
+    InitFields in{phi, C, th, ux, uy, h->p.C0, h->p.U0, h->p.theta0, h->p.u_in_x, h->p.u_in_y,
+                  h->p.c_init_U, h->p.use_ns};
+    h->ops.set_fields(h->kp, in, h->pop(h->pop_cur), h->flow(h->flow_cur), h->stream, h->grid);
+    HIP_TRY(hipGetLastError());
+    h->hist_valid = 0;
+    return DLB_OK;
+}
+
+int dlb_set_fields(dlb_handle h, const double* phi, const double* C, const double* theta,
+                   const double* ux, const double* uy, int on_device) {
+    if (!h || !phi) return fail(DLB_EINVAL, "null handle or phi");
+    if (on_device) return set_fields_device(h, phi, C, theta, ux, uy);
+    size_t N = (size_t)h->p.nx * h->p.ny;
+    const double* src[5] = {phi, C, theta, ux, uy};
+    double* tmp = nullptr;
+    HIP_TRY(hipMalloc(&tmp, 5 * N * sizeof(double)));
+    const double* dev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    int rc = DLB_OK;
+    for (int i = 0; i < 5 && rc == DLB_OK; ++i) {
+        if (!src[i]) continue;
+        hipError_t e = hipMemcpyAsync(tmp + i * N, src[i], N * sizeof(double), hipMemcpyHostToDevice,
+                                      h->stream);
+        if (e != hipSuccess) rc = fail(DLB_EHIP, hipGetErrorString(e));
+        dev[i] = tmp + i * N;
+    }
+    if (rc == DLB_OK) rc = set_fields_device(h, dev[0], dev[1], dev[2], dev[3], dev[4]);
+    hipError_t e = hipStreamSynchronize(h->stream);
+    (void)hipFree(tmp);
+    if (rc == DLB_OK && e != hipSuccess) rc = fail(DLB_EHIP, hipGetErrorString(e));
+    return rc;
+}
+
+int dlb_init_seed(dlb_handle h, const double* noise) {
+    if (!h) return fail(DLB_EINVAL, "null handle");
+    size_t N = (size_t)h->p.nx * h->p.ny;
+    double* tmp = nullptr;
+    HIP_TRY(hipMalloc(&tmp, 2 * N * sizeof(double)));
+    int rc = DLB_OK;
+    double* dnoise = nullptr;
+    if (noise) {
+        hipError_t e = hipMemcpyAsync(tmp + N, noise, N * sizeof(double), hipMemcpyHostToDevice, h->stream);
+        if (e != hipSuccess) rc = fail(DLB_EHIP, hipGetErrorString(e));
+        dnoise = tmp + N;
+    }
+    if (rc == DLB_OK) {
+        hipLaunchKernelGGL(k_seed_phi, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, h->stream, h->kp,
+                           (const double*)dnoise, tmp);
+        rc = set_fields_device(h, tmp, nullptr, nullptr, nullptr, nullptr);
+    }
+    hipError_t e = hipStreamSynchronize(h->stream);
+    (void)hipFree(tmp);
+    if (rc == DLB_OK && e != hipSuccess) rc = fail(DLB_EHIP, hipGetErrorString(e));
+    return rc;
+}
+
+int dlb_step(dlb_handle h, int64_t n) {
+    if (!h || n < 0) return fail(DLB_EINVAL, "null handle or negative step count");
+    int64_t done = 0;
+    // the first step after (re-)initialisation runs with zero time derivatives
+    while (done < n && !h->hist_valid) {
+        enqueue_step(h, nullptr);
+        ++done;
+    }
+    // graphs need a capturable (non-null) stream
+    if (n - done >= 4 && h->stream != nullptr) {
+        if (!h->graph || h->graph_pop != h->pop_cur || h->graph_flow != h->flow_cur) {
+            int rc = build_graph(h);
+            if (rc) return rc;
+        }
+        while (n - done >= 2) {
+            HIP_TRY(hipGraphLaunch(h->graph, h->stream));
+            done += 2;
+            h->step += 2;
+        }
+    }
+    while (done < n) {
+        enqueue_step(h, nullptr);
+        ++done;
+    }
+    HIP_TRY(hipGetLastError());
+    return DLB_OK;
+}
+
+int dlb_step_timed(dlb_handle h, int64_t n, double* ms_pct, double* ms_flow, int64_t* l_pct,
+                   int64_t* l_flow) {
+    if (!h || n < 0) return fail(DLB_EINVAL, "null handle or negative step count");
+    hipEvent_t ev[3];
+    for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+    double a = 0.0, b = 0.0;
+    int64_t la = 0, lb = 0;
+    int rc = DLB_OK;
+    for (int64_t s = 0; s < n && rc == DLB_OK; ++s) {
+        enqueue_step(h, ev);
+        hipError_t e = hipEventSynchronize(ev[2]);
+        if (e != hipSuccess) {
+            rc = fail(DLB_EHIP, hipGetErrorString(e));
+            break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
+        a += ms;
+        ++la;
+        if (h->p.use_ns) {
+            (void)hipEventElapsedTime(&ms, ev[1], ev[2]);
+            b += ms;
+            lb += h->p.n_sub;
+        }
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    if (ms_pct) *ms_pct = a;
+    if (ms_flow) *ms_flow = b;
+    if (l_pct) *l_pct = la;
+    if (l_flow) *l_flow = lb;
+    return rc;
+}
+
+int64_t dlb_step_count(dlb_handle h) { return h ? h->step : -1; }
+
+int dlb_get_fields(dlb_handle h, uint32_t mask, void* out, int out_on_device, int out_f32) {
+    if (!h || !out) return fail(DLB_EINVAL, "null handle or output");
+    if (mask == 0 || mask >= (1u << 7)) return fail(DLB_EINVAL, "field mask must select bits 0..6");
+    size_t N = (size_t)h->p.nx * h->p.ny;
+    int nf = __builtin_popcount(mask);
+    size_t bytes = (size_t)nf * N * (out_f32 ? 4 : 8);
+    void* dst = out;
+    if (!out_on_device) HIP_TRY(hipMalloc(&dst, bytes));
+    h->ops.fields(h->kp, h->pop(h->pop_cur), h->flow(h->flow_cur), mask, dst, out_f32, h->stream,
+                  h->grid);
+    hipError_t e = hipGetLastError();
+    if (!out_on_device) {
+        if (e == hipSuccess) e = hipMemcpyAsync(out, dst, bytes, hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        (void)hipFree(dst);
+    }
+    if (e != hipSuccess) return fail(DLB_EHIP, hipGetErrorString(e));
+    return DLB_OK;
+}
+
+int dlb_reduce(dlb_handle h, double* out) {
+    if (!h || !out) return fail(DLB_EINVAL, "null handle or output");
+    h->ops.reduce(h->kp, h->pop(h->pop_cur), h->flow(h->flow_cur), h->red(), h->stream, h->grid);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(BLOCK), 0, h->stream, (const double*)h->red(),
+                       h->L.nblocks, (long long)h->p.nx * h->p.ny, h->redout());
+    h->ops.tips(h->kp, h->pop(h->pop_cur), h->redout(), h->stream);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(out, h->redout(), 17 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (out[3] > 0) return fail(DLB_ENAN, "non-finite values in the state");
+    return DLB_OK;
+}
+
+static const uint64_t CKPT_MAGIC = 0x444c42434b505431ull;  // "DLBCKPT1"
+struct CkptHeader {
+    uint64_t magic;
+    dlb_params p;
+    int64_t step;
+    int32_t pop_cur, flow_cur, hist_valid, pad;
+    uint64_t state_bytes;
+};
+
+size_t dlb_checkpoint_bytes(dlb_handle h) { return h ? sizeof(CkptHeader) + h->L.total : 0; }
+
+int dlb_save(dlb_handle h, void* host, size_t bytes) {
+    if (!h || !host) return fail(DLB_EINVAL, "null handle or buffer");
+    if (bytes < dlb_checkpoint_bytes(h)) return fail(DLB_ENOMEM, "checkpoint buffer too small");
+    CkptHeader hd{CKPT_MAGIC, h->p, h->step, h->pop_cur, h->flow_cur, h->hist_valid, 0, h->L.total};
+    std::memcpy(host, &hd, sizeof hd);
+    HIP_TRY(hipMemcpyAsync((char*)host + sizeof hd, h->base, h->L.total, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return DLB_OK;
+}
+
+int dlb_load(dlb_handle h, const void* host, size_t bytes) {
+    if (!h || !host) return fail(DLB_EINVAL, "null handle or buffer");
+    if (bytes < sizeof(CkptHeader)) return fail(DLB_EINVAL, "checkpoint truncated");
+    CkptHeader hd;
+    std::memcpy(&hd, host, sizeof hd);
+    if (hd.magic != CKPT_MAGIC) return fail(DLB_EINVAL, "not a checkpoint");
+    if (std::memcmp(&hd.p, &h->p, sizeof(dlb_params)) != 0)
+        return fail(DLB_EINVAL, "checkpoint parameters differ from the solver's");
+    if (hd.state_bytes != h->L.total || bytes < sizeof hd + hd.state_bytes)
+        return fail(DLB_EINVAL, "checkpoint size mismatch");
+    HIP_TRY(hipMemcpyAsync(h->base, (const char*)host + sizeof hd, h->L.total, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    h->step = hd.step;
+    h->pop_cur = hd.pop_cur;
+    h->flow_cur = hd.flow_cur;
+    h->hist_valid = hd.hist_valid;
+    return DLB_OK;
+}
+
+int dlb_sync(dlb_handle h) {
+    if (!h) return fail(DLB_EINVAL, "null handle");
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return DLB_OK;
+}
+
+int dlb_equilibria(int64_t n, const double* macros, double* out, int h_quintic) {
+    if (n <= 0 || !macros || !out) return fail(DLB_EINVAL, "bad arguments");
+    double *din = nullptr, *dout = nullptr;
+    HIP_TRY(hipMalloc(&din, (size_t)n * 8 * sizeof(double)));
+    hipError_t e = hipMalloc(&dout, (size_t)n * 24 * sizeof(double));
+    if (e == hipSuccess) e = hipMemcpy(din, macros, (size_t)n * 8 * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_equilibria, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, 0, (long long)n,
+                           (const double*)din, dout, h_quintic);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpy(out, dout, (size_t)n * 24 * sizeof(double), hipMemcpyDeviceToHost);
+    (void)hipFree(din);
+    if (dout) (void)hipFree(dout);
+    if (e != hipSuccess) return fail(DLB_EHIP, hipGetErrorString(e));
+    return DLB_OK;
+}
+
+int dlb_copy_kernel(void* dst, const void* src, size_t bytes, void* stream) {
+    if (!dst || !src || (bytes & 15) || ((uintptr_t)dst & 15) || ((uintptr_t)src & 15))
+        return fail(DLB_EINVAL, "copy needs 16-byte aligned pointers and size");
+    size_t n = bytes / 16;
+    unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 256 * 16);
+    if (blocks == 0) return DLB_OK;
+    hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, (hipStream_t)stream, (const float4*)src,
+                       (float4*)dst, n);
+    HIP_TRY(hipGetLastError());
+    return DLB_OK;
+}
+
+}  // extern "C"

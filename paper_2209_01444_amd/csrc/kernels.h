@@ -1,0 +1,587 @@
+// kernels.h -- HIP kernels for gfx950 of the diffuse-interface MRT lattice
+// Boltzmann method (Zhan et al., arXiv:2209.01444).
+//
+// State layout in the caller's buffer (SoA, one plane per population,
+// x fastest, planes padded to 64 elements):
+//   pop[2][15]  phi (0-4), solute (5-9), heat (10-14) populations, ping-pong
+//   flow[2][9]  flow populations (h_0 stored as h_0 - rho0), ping-pong
+//   hist[6]     phi, Q, (C u)x, (C u)y, (H u)x, (H u)y of the previous step
+//
+// One main step (Jacobi order: every lattice reads the fields of time t):
+//   k_pct      phi, C, theta collide at every node and push-stream; the
+//              phi lattice uses the modified streaming of Remark 2 / Sec. 3.1;
+//              the history planes are overwritten with the time-t values, so
+//              hist[0] holds phi^t for the flow sub-steps that follow.
+//   k_flow     x N_sub: D2Q9 MRT collision with the diffuse force of
+//              Sec. 3.4 at frozen phi^t, push-streamed.
+// Wall nodes of the channel configuration are never stored: whoever reads
+// one rebuilds it from its inward neighbour (zero gradient for phi, C, H;
+// non-equilibrium extrapolation for the flow).
+#pragma once
+
+#include "lattice.h"
+
+namespace dlb {
+
+static constexpr int C5X[5] = {0, 1, 0, -1, 0};
+static constexpr int C5Y[5] = {0, 0, 1, 0, -1};
+static constexpr int C9X[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+static constexpr int C9Y[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+
+// Destination of a push along (cx, cy): periodic wrap, or -1 when the
+// destination is a wall node / outside the channel.
+template <bool WALLS>
+__device__ __forceinline__ long long push_dest(const KParams& kp, int x, int y, int cx, int cy) {
+    int dx = x + cx, dy = y + cy;
+    if constexpr (WALLS) {
+        if (dx < 1 || dy < 1 || dx > kp.nx - 2 || dy > kp.ny - 2) return -1;
+    } else {
+        dx = dx < 0 ? dx + kp.nx : (dx >= kp.nx ? dx - kp.nx : dx);
+        dy = dy < 0 ? dy + kp.ny : (dy >= kp.ny ? dy - kp.ny : dy);
+    }
+    return (long long)dy * kp.nx + dx;
+}
+
+// Flow populations of node (x, y) at the current sub-step.  Interior nodes
+// load them; wall nodes rebuild them from the inward neighbour x_f with the
+// frozen phi there (non-equilibrium extrapolation, Sec. 4 preamble).
+template <class T, class S, bool WALLS>
+__device__ __forceinline__ void flow_node(const KParams& kp, const S* __restrict__ h_in, int x,
+                                          int y, size_t idx, T phi_f, T* h) {
+    const size_t P = (size_t)kp.plane;
+    if (!WALLS || !is_wall(kp, x, y)) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) h[i] = ld_pop<T>(h_in, i * P + idx, kp.shift[15 + i]);
+        return;
+    }
+    size_t f = inward_idx(kp, x, y);
+    T hf[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) hf[i] = ld_pop<T>(h_in, i * P + f, kp.shift[15 + i]);
+    FlowMacro<T> m = flow_macro(hf, phi_f);
+    T ubx, uby, pb;
+    if (x == 0) {  // velocity inlet
+        ubx = T(kp.uin_x_sub);
+        uby = T(kp.uin_y_sub);
+        pb = m.p;
+    } else if (x == kp.nx - 1) {  // outflow: du/dx = 0, p = 0
+        ubx = m.ux;
+        uby = (y == 0 || y == kp.ny - 1) ? T(0) : m.uy;
+        pb = T(0);
+    } else {  // free slip
+        ubx = m.ux;
+        uby = T(0);
+        pb = m.p;
+    }
+    T eb[9], ef[9];
+    eq_flow(T(0), pb, ubx, uby, eb);
+    eq_flow(T(0), m.p, m.ux, m.uy, ef);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) h[i] = eb[i] + (hf[i] - ef[i]);
+}
+
+// ---------------------------------------------------------------------------
+// K1: phi, C, theta main step.
+// ---------------------------------------------------------------------------
+template <class CF, bool NS, bool WALLS>
+__global__ __launch_bounds__(BLOCK) void k_pct(const KParams kp, const typename CF::S* __restrict__ pin,
+                                               typename CF::S* __restrict__ pout,
+                                               const typename CF::S* __restrict__ hin,
+                                               typename CF::H* __restrict__ hist, int hist_valid) {
+    using T = typename CF::T;
+    using S = typename CF::S;
+    using HT = typename CF::H;
+    int x, y;
+    if (!node_of_thread(kp, x, y)) return;
+    const size_t P = (size_t)kp.plane;
+    const size_t idx = (size_t)y * kp.nx + x;
+    const bool wall = WALLS && is_wall(kp, x, y);
+    const size_t src = wall ? inward_idx(kp, x, y) : idx;
+
+    T f[5], n[5], g[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        f[i] = ld_pop<T>(pin, i * P + src, kp.shift[i]);
+        n[i] = ld_pop<T>(pin, (5 + i) * P + src, kp.shift[5 + i]);
+        g[i] = ld_pop<T>(pin, (10 + i) * P + src, kp.shift[10 + i]);
+    }
+    // macroscopic fields of time t (Sec. 3.1-3.3)
+    const T phi = (((f[0] + f[1]) + f[2]) + f[3]) + f[4];
+    const T C = (((n[0] + n[1]) + n[2]) + n[3]) + n[4];
+    const T H = (((g[0] + g[1]) + g[2]) + g[3]) + g[4];
+    const T k = T(kp.k);
+    const T hphi = h_of(phi, kp.h_quintic);
+    const T theta = H + T(0.5) * hphi;
+    const T U = (T(2) * C / (T(1) + k - (T(1) - k) * phi) - T(1)) / (T(1) - k);
+
+    // melt velocity of time t in main-step units: N_sub (3 - phi)/4 u*
+    T ux = T(0), uy = T(0);
+    if constexpr (NS) {
+        T h[9];
+        flow_node<T, S, WALLS>(kp, hin, x, y, idx, phi, h);
+        T d57 = h[5] - h[7], d68 = h[6] - h[8];
+        T mx = (h[1] - h[3]) + (d57 - d68);
+        T my = (h[2] - h[4]) + (d57 + d68);
+        T fac = T(kp.nsub_d) * (T(3) - phi) * T(0.25);
+        ux = mx * fac;
+        uy = my * fac;
+    }
+
+    // local gradient, anisotropy (Sec. 2, Sec. 3.1)
+    T gx, gy, a, Nx, Ny;
+    local_gradient<T>(kp, f[1] - f[3], f[2] - f[4], gx, gy, a, Nx, Ny);
+    const T a2 = a * a;
+    const T inv_a2 = T(1) / a2;
+    const T W2t = T(kp.W2t);
+    const T s1 = T(1) / (T(3) * a2 * W2t + T(0.5));
+
+    // coupling source and time derivatives (backward differences)
+    const T om = T(1) - phi * phi;
+    const T Q = phi * om - T(kp.lambda) * (theta + T(kp.Mcinf) * U) * om * om;
+    T dQ = T(0), dphi = T(0), dCx = T(0), dCy = T(0), dHx = T(0), dHy = T(0);
+    const T Cux = C * ux, Cuy = C * uy, Hux = H * ux, Huy = H * uy;
+    if (hist_valid) {
+        dphi = phi - T(hist[idx]);
+        dQ = Q - T(hist[P + idx]);
+        if constexpr (NS) {
+            dCx = Cux - T(hist[2 * P + idx]);
+            dCy = Cuy - T(hist[3 * P + idx]);
+            dHx = Hux - T(hist[4 * P + idx]);
+            dHy = Huy - T(hist[5 * P + idx]);
+        }
+    }
+    hist[idx] = HT(phi);
+    hist[P + idx] = HT(Q);
+    if constexpr (NS) {
+        hist[2 * P + idx] = HT(Cux);
+        hist[3 * P + idx] = HT(Cuy);
+        hist[4 * P + idx] = HT(Hux);
+        hist[5 * P + idx] = HT(Huy);
+    }
+
+    // ---- phi lattice (Sec. 3.1): S = diag(1, s1, s1, 1, 1) ----
+    T pf[5];
+    {
+        const T A = (Q + T(0.5) * a2 * dQ) * T(kp.inv_tau0);  // F + (a^2/2) d_t F, summed
+        const T gfac = (T(1) - T(0.5) * s1) * T(-1.0 / 3.0) * inv_a2;  // (1 - s1/2) sum c G
+        const T m1x = (T(1) - s1) * (f[1] - f[3]) + gfac * Nx;
+        const T m1y = (T(1) - s1) * (f[2] - f[4]) + gfac * Ny;
+        const T m3 = (phi + A) * T(1.0 / 3.0);
+        pf[0] = m3;  // m0 - m3 - m4 with m0 = phi + A
+        pf[1] = T(0.5) * (m3 + m1x);
+        pf[3] = T(0.5) * (m3 - m1x);
+        pf[2] = T(0.5) * (m3 + m1y);
+        pf[4] = T(0.5) * (m3 - m1y);
+    }
+
+    // anti-trapping current (Sec. 2)
+    T Jx = T(0), Jy = T(0);
+    {
+        T gn2 = gx * gx + gy * gy;
+        if (gn2 > T(0)) {
+            T c = -T(kp.jat) * (T(1) + (T(1) - k) * U) * dphi / sqrt(gn2);
+            Jx = c * gx;
+            Jy = c * gy;
+        }
+    }
+
+    // ---- solute lattice (Sec. 3.2): S = diag(1, s1C, s1C, 1, 1) ----
+    T pn[5];
+    {
+        const T s1c = T(kp.s1c);
+        const T qU = T(0.5) * (T(1) - phi) * U;
+        const T invD = T(kp.invD);
+        const T Vx = T(3) * dCx - T(0.5) * U * gx + Jx * invD;
+        const T Vy = T(3) * dCy - T(0.5) * U * gy + Jy * invD;
+        const T gf = (T(1) - T(0.5) * s1c) * T(1.0 / 3.0);
+        const T m1x = (n[1] - n[3]) - s1c * ((n[1] - n[3]) - Cux) + gf * Vx;
+        const T m1y = (n[2] - n[4]) - s1c * ((n[2] - n[4]) - Cuy) + gf * Vy;
+        const T m3 = qU * T(1.0 / 3.0);
+        pn[0] = C - T(2) * m3;
+        pn[1] = T(0.5) * (m3 + m1x);
+        pn[3] = T(0.5) * (m3 - m1x);
+        pn[2] = T(0.5) * (m3 + m1y);
+        pn[4] = T(0.5) * (m3 - m1y);
+    }
+
+    // ---- heat lattice (Sec. 3.3): S = diag(1, s1T, s1T, 1, 1) ----
+    T pg[5];
+    {
+        const T s1t = T(kp.s1t);
+        const T gf = T(1) - T(0.5) * s1t;  // (1 - s1/2) (1/3)(3 d_t(Hu))
+        const T m1x = (g[1] - g[3]) - s1t * ((g[1] - g[3]) - Hux) + gf * dHx;
+        const T m1y = (g[2] - g[4]) - s1t * ((g[2] - g[4]) - Huy) + gf * dHy;
+        const T m3 = theta * T(1.0 / 3.0);
+        pg[0] = H - T(2) * m3;
+        pg[1] = T(0.5) * (m3 + m1x);
+        pg[3] = T(0.5) * (m3 - m1x);
+        pg[2] = T(0.5) * (m3 + m1y);
+        pg[4] = T(0.5) * (m3 - m1y);
+    }
+
+    // ---- streaming (push).  phi: f(y,t+1) = f(y,t) + (post - f(y,t)) / a_s^2 ----
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        long long d = push_dest<WALLS>(kp, x, y, C5X[i], C5Y[i]);
+        if (d < 0) continue;
+        T fold = i == 0 ? f[0] : ld_pop<T>(pin, i * P + (size_t)d, kp.shift[i]);
+        st_pop(pout, i * P + (size_t)d, fold + (pf[i] - fold) * inv_a2, kp.shift[i]);
+        st_pop(pout, (5 + i) * P + (size_t)d, pn[i], kp.shift[5 + i]);
+        st_pop(pout, (10 + i) * P + (size_t)d, pg[i], kp.shift[10 + i]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K2: one flow sub-step (Sec. 3.4) at frozen phi^t (= hist[0]).
+// ---------------------------------------------------------------------------
+template <class CF, bool WALLS>
+__global__ __launch_bounds__(BLOCK) void k_flow(const KParams kp, const typename CF::S* __restrict__ hin,
+                                                typename CF::S* __restrict__ hout,
+                                                const typename CF::H* __restrict__ phi_t) {
+    using T = typename CF::T;
+    using S = typename CF::S;
+    int x, y;
+    if (!node_of_thread(kp, x, y)) return;
+    const size_t P = (size_t)kp.plane;
+    const size_t idx = (size_t)y * kp.nx + x;
+    const T phi = T(phi_t[idx]);
+    T h[9];
+    T phi_f = phi;
+    if (WALLS && is_wall(kp, x, y)) phi_f = T(phi_t[inward_idx(kp, x, y)]);
+    flow_node<T, S, WALLS>(kp, hin, x, y, idx, phi_f, h);
+    T o[9];
+    flow_collide<T>(h, phi, T(kp.s2u), o);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        long long d = push_dest<WALLS>(kp, x, y, C9X[i], C9Y[i]);
+        if (d < 0) continue;
+        st_pop(hout, i * P + (size_t)d, o[i], kp.shift[15 + i]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Initialisation (Sec. 4 preamble) and re-initialisation at given fields.
+// ---------------------------------------------------------------------------
+__global__ void k_seed_phi(const KParams kp, const double* __restrict__ noise,
+                           double* __restrict__ phi) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t N = (size_t)kp.nx * kp.ny;
+    if (i >= N) return;
+    int x = (int)(i % kp.nx), y = (int)(i / kp.nx);
+    double dx = x - kp.seed_x, dy = y - kp.seed_y;
+    double d = sqrt(dx * dx + dy * dy);
+    double v = tanh((kp.seed_R - d) / (sqrt(2.0) * kp.W0));
+    if (noise && fabs(v) < 0.9) v += kp.noise_amp * noise[i];
+    phi[i] = v;
+}
+
+struct InitFields {
+    const double *phi, *C, *theta, *ux, *uy;  // device, nullable except phi
+    double C0, U0, theta0, uin_x, uin_y;
+    int c_init_U, use_ns;
+};
+
+template <class CF, bool NS, bool WALLS>
+__global__ __launch_bounds__(BLOCK) void k_set_fields(const KParams kp, const InitFields in,
+                                                      typename CF::S* __restrict__ pop,
+                                                      typename CF::S* __restrict__ flow) {
+    int x, y;
+    if (!node_of_thread(kp, x, y)) return;
+    const size_t P = (size_t)kp.plane;
+    const size_t idx = (size_t)y * kp.nx + x;
+    const double phi = in.phi[idx];
+    // isotropic D2Q9 central difference: grad phi = 3 sum_i w_i c_i phi(x + c_i)
+    double gx = 0.0, gy = 0.0;
+    for (int i = 1; i < 9; ++i) {
+        int xx = x + C9X[i], yy = y + C9Y[i];
+        if (WALLS) {
+            xx = xx < 0 ? 0 : (xx > kp.nx - 1 ? kp.nx - 1 : xx);
+            yy = yy < 0 ? 0 : (yy > kp.ny - 1 ? kp.ny - 1 : yy);
+        } else {
+            xx = xx < 0 ? xx + kp.nx : (xx >= kp.nx ? xx - kp.nx : xx);
+            yy = yy < 0 ? yy + kp.ny : (yy >= kp.ny ? yy - kp.ny : yy);
+        }
+        double w = i < 5 ? 1.0 / 9.0 : 1.0 / 36.0;
+        double v = in.phi[(size_t)yy * kp.nx + xx];
+        gx += 3.0 * w * C9X[i] * v;
+        gy += 3.0 * w * C9Y[i] * v;
+    }
+    // first moment that the local scheme maps back to (gx, gy)
+    double Vx = 0.0, Vy = 0.0;
+    if (gx * gx + gy * gy >= GRAD_GUARD) {
+        double a, Nx, Ny;
+        anisotropy<double>(kp, gx, gy, a, Nx, Ny);
+        double s1 = 1.0 / (3.0 * a * a * kp.W2t + 0.5);
+        Vx = -gx / (3.0 * s1) - kp.W2t * Nx;
+        Vy = -gy / (3.0 * s1) - kp.W2t * Ny;
+    }
+    double k = kp.k;
+    double C = in.C ? in.C[idx]
+                    : (in.c_init_U ? 0.5 * (1.0 + k - (1.0 - k) * phi) * (1.0 + (1.0 - k) * in.U0)
+                                   : in.C0);
+    double th = in.theta ? in.theta[idx] : in.theta0;
+    double ux = in.ux ? in.ux[idx] : in.uin_x;
+    double uy = in.uy ? in.uy[idx] : in.uin_y;
+    if (!NS) ux = uy = 0.0;
+    double U = (2.0 * C / (1.0 + k - (1.0 - k) * phi) - 1.0) / (1.0 - k);
+    double e[9];
+    eq_phi<double>(phi, e);
+    const double w5[5] = {1.0 / 3.0, 1.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0};
+    for (int i = 0; i < 5; ++i)
+        st_pop(pop, i * P + idx, e[i] + 3.0 * w5[i] * (C5X[i] * Vx + C5Y[i] * Vy), kp.shift[i]);
+    eq_solute<double>(C, phi, U, ux, uy, e);
+    for (int i = 0; i < 5; ++i) st_pop(pop, (5 + i) * P + idx, e[i], kp.shift[5 + i]);
+    eq_heat<double>(th, phi, kp.h_quintic, ux, uy, e);
+    for (int i = 0; i < 5; ++i) st_pop(pop, (10 + i) * P + idx, e[i], kp.shift[10 + i]);
+    if constexpr (NS) {
+        eq_flow<double>(0.0, 0.0, ux / kp.nsub_d, uy / kp.nsub_d, e);
+        for (int i = 0; i < 9; ++i) st_pop(flow, i * P + idx, e[i], kp.shift[15 + i]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Observation: macroscopic fields, reductions, tips.
+// ---------------------------------------------------------------------------
+template <class CF, bool NS, bool WALLS>
+__device__ __forceinline__ void node_macros(const KParams& kp, const typename CF::S* __restrict__ pop,
+                                            const typename CF::S* __restrict__ flow, int x, int y,
+                                            double* m) {
+    using T = typename CF::T;
+    using S = typename CF::S;
+    const size_t P = (size_t)kp.plane;
+    const size_t idx = (size_t)y * kp.nx + x;
+    const size_t src = (WALLS && is_wall(kp, x, y)) ? inward_idx(kp, x, y) : idx;
+    T phi = T(0), C = T(0), H = T(0);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        phi += ld_pop<T>(pop, i * P + src, kp.shift[i]);
+        C += ld_pop<T>(pop, (5 + i) * P + src, kp.shift[5 + i]);
+        H += ld_pop<T>(pop, (10 + i) * P + src, kp.shift[10 + i]);
+    }
+    T k = T(kp.k);
+    m[0] = phi;
+    m[1] = C;
+    m[2] = (T(2) * C / (T(1) + k - (T(1) - k) * phi) - T(1)) / (T(1) - k);
+    m[3] = H + T(0.5) * h_of(phi, kp.h_quintic);
+    m[4] = m[5] = m[6] = 0.0;
+    m[7] = H;
+    m[8] = m[9] = 0.0;  // interface force (sub-step units)
+    if constexpr (NS) {
+        T h[9];
+        flow_node<T, S, WALLS>(kp, flow, x, y, idx, phi, h);
+        FlowMacro<T> fm = flow_macro(h, phi);
+        m[4] = kp.nsub_d * fm.ux;
+        m[5] = kp.nsub_d * fm.uy;
+        m[6] = kp.nsub_d * kp.nsub_d * fm.p;
+        m[8] = fm.Fx;
+        m[9] = fm.Fy;
+    }
+}
+
+template <class CF, bool NS, bool WALLS>
+__global__ __launch_bounds__(BLOCK) void k_fields(const KParams kp,
+                                                  const typename CF::S* __restrict__ pop,
+                                                  const typename CF::S* __restrict__ flow,
+                                                  uint32_t mask, void* __restrict__ out, int f32) {
+    int x, y;
+    if (!node_of_thread(kp, x, y)) return;
+    double m[10];
+    node_macros<CF, NS, WALLS>(kp, pop, flow, x, y, m);
+    size_t N = (size_t)kp.nx * kp.ny, idx = (size_t)y * kp.nx + x;
+    int slot = 0;
+    for (int f = 0; f < 7; ++f) {
+        if (!(mask & (1u << f))) continue;
+        if (f32) ((float*)out)[slot * N + idx] = (float)m[f];
+        else ((double*)out)[slot * N + idx] = m[f];
+        ++slot;
+    }
+}
+
+// Block-wide FP64 sum of NR values: wave shuffles, then LDS across the
+// four waves.  Result valid in thread 0.
+template <int NR> __device__ __forceinline__ void block_sum(double* v) {
+    __shared__ double sh[NR][BLOCK / 64];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+        for (int off = 32; off > 0; off >>= 1) v[r] += __shfl_xor(v[r], off, 64);
+    int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0)
+        for (int r = 0; r < NR; ++r) sh[r][wave] = v[r];
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int r = 0; r < NR; ++r) {
+            double s = 0.0;
+            for (int w = 0; w < BLOCK / 64; ++w) s += sh[r][w];
+            v[r] = s;
+        }
+}
+
+static constexpr int NRED = 10;
+// partial sums per workgroup: C, H, (1+phi)/2, non-finite, x w, y w, Fx, Fy,
+// x Fy - y Fx, (unused)
+template <class CF, bool NS, bool WALLS>
+__global__ __launch_bounds__(BLOCK) void k_reduce_partial(const KParams kp,
+                                                          const typename CF::S* __restrict__ pop,
+                                                          const typename CF::S* __restrict__ flow,
+                                                          double* __restrict__ partial) {
+    double v[NRED] = {0};
+    int x, y;
+    if (node_of_thread(kp, x, y)) {
+        double m[10];
+        node_macros<CF, NS, WALLS>(kp, pop, flow, x, y, m);
+        double w = 0.5 * (1.0 + m[0]);
+        v[0] = m[1];
+        v[1] = m[7];
+        v[2] = w;
+        bool ok = isfinite(m[0]) && isfinite(m[1]) && isfinite(m[7]);
+        if (NS) ok = ok && isfinite(m[4]) && isfinite(m[5]);
+        v[3] = ok ? 0.0 : 1.0;
+        v[4] = w * x;
+        v[5] = w * y;
+        v[6] = m[8];
+        v[7] = m[9];
+        v[8] = x * m[9] - y * m[8];
+    }
+    block_sum<NRED>(v);
+    if (threadIdx.x == 0)
+        for (int r = 0; r < NRED; ++r) partial[(size_t)blockIdx.x * NRED + r] = v[r];
+}
+
+// out[0..6] and out[15..16] of the reduction record (see dlb.h)
+__global__ __launch_bounds__(BLOCK) void k_reduce_final(const double* __restrict__ partial, int nb,
+                                                        long long nodes, double* __restrict__ out) {
+    double v[NRED] = {0};
+    for (int b = threadIdx.x; b < nb; b += BLOCK)
+        for (int r = 0; r < NRED; ++r) v[r] += partial[(size_t)b * NRED + r];
+    block_sum<NRED>(v);
+    if (threadIdx.x == 0) {
+        double cx = v[4] / v[2], cy = v[5] / v[2];
+        out[0] = v[0];
+        out[1] = v[1];
+        out[2] = v[2] / (double)nodes;
+        out[3] = v[3];
+        out[4] = -v[6];
+        out[5] = -v[7];
+        // -sum (x - cx) x F = -(sum (x Fy - y Fx) - cx sum Fy + cy sum Fx)
+        out[6] = -(v[8] - cx * v[7] + cy * v[6]);
+        out[15] = cx;
+        out[16] = cy;
+    }
+}
+
+template <class CF, bool WALLS>
+__device__ __forceinline__ double node_phi(const KParams& kp, const typename CF::S* __restrict__ pop,
+                                           int x, int y) {
+    using T = typename CF::T;
+    const size_t P = (size_t)kp.plane;
+    size_t idx = (WALLS && is_wall(kp, x, y)) ? inward_idx(kp, x, y) : (size_t)y * kp.nx + x;
+    T s = 0;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) s += ld_pop<T>(pop, i * P + idx, kp.shift[i]);
+    return (double)s;
+}
+
+// Bilinear sample of phi; NaN outside [0, nx-1] x [0, ny-1].
+template <class CF, bool WALLS>
+__device__ double sample_phi(const KParams& kp, const typename CF::S* __restrict__ pop, double x,
+                             double y) {
+    if (!(x >= 0.0 && y >= 0.0 && x <= kp.nx - 1 && y <= kp.ny - 1)) return __builtin_nan("");
+    int i0 = (int)floor(x), j0 = (int)floor(y);
+    if (i0 > kp.nx - 2) i0 = kp.nx - 2;
+    if (j0 > kp.ny - 2) j0 = kp.ny - 2;
+    double fx = x - i0, fy = y - j0;
+    double p00 = node_phi<CF, WALLS>(kp, pop, i0, j0), p10 = node_phi<CF, WALLS>(kp, pop, i0 + 1, j0);
+    double p01 = node_phi<CF, WALLS>(kp, pop, i0, j0 + 1);
+    double p11 = node_phi<CF, WALLS>(kp, pop, i0 + 1, j0 + 1);
+    return (1.0 - fx) * (1.0 - fy) * p00 + fx * (1.0 - fy) * p10 + (1.0 - fx) * fy * p01 +
+           fx * fy * p11;
+}
+
+// Tips: one workgroup per arm, one wave per sideways offset w = -3..3.
+template <class CF, bool WALLS>
+__global__ __launch_bounds__(448) void k_tips(const KParams kp, const typename CF::S* __restrict__ pop,
+                                              double* __restrict__ out) {
+    __shared__ double cross[7];
+    const int arm = blockIdx.x, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const double w = (double)(wave - 3);
+    const double th = kp.orient + arm * (M_PI / 2.0);
+    const double dx = cos(th), dy = sin(th), ex = -sin(th), ey = cos(th);
+    long long best = -1;
+    // samples j = 0, 1, ... until the first one outside the domain (index J);
+    // a crossing needs both samples of the pair inside
+    for (long long base = 0;; base += 64) {
+        long long j = base + lane;
+        double x0 = kp.seed_x + j * dx + w * ex, y0 = kp.seed_y + j * dy + w * ey;
+        double x1 = kp.seed_x + (j + 1) * dx + w * ex, y1 = kp.seed_y + (j + 1) * dy + w * ey;
+        double v0 = sample_phi<CF, WALLS>(kp, pop, x0, y0);
+        double v1 = sample_phi<CF, WALLS>(kp, pop, x1, y1);
+        unsigned long long out_mask = __ballot(isnan(v0));
+        long long J = out_mask ? base + __ffsll((long long)out_mask) - 1 : base + 64 + 1;
+        if (j + 1 < J && v0 > 0.0 && v1 <= 0.0) best = j;
+        if (out_mask) break;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        long long o = __shfl_xor(best, off, 64);
+        best = o > best ? o : best;
+    }
+    if (lane == 0) {
+        double s = __builtin_nan("");
+        if (best >= 0) {
+            double x0 = kp.seed_x + best * dx + w * ex, y0 = kp.seed_y + best * dy + w * ey;
+            double x1 = kp.seed_x + (best + 1) * dx + w * ex;
+            double y1 = kp.seed_y + (best + 1) * dy + w * ey;
+            double v0 = sample_phi<CF, WALLS>(kp, pop, x0, y0);
+            double v1 = sample_phi<CF, WALLS>(kp, pop, x1, y1);
+            s = best + v0 / (v0 - v1);
+        }
+        cross[wave] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double Sx = 0, Sy = 0, Sxx = 0, Sxy = 0;
+        int n = 0;
+        for (int k = 0; k < 7; ++k) {
+            double c = cross[k];
+            if (isnan(c)) continue;
+            double X = (double)((k - 3) * (k - 3));
+            Sx += X;
+            Sy += c;
+            Sxx += X * X;
+            Sxy += X * c;
+            ++n;
+        }
+        double rho = __builtin_nan("");
+        if (n >= 3) {
+            double den = n * Sxx - Sx * Sx;
+            if (den != 0.0) {
+                double B = (n * Sxy - Sx * Sy) / den;
+                if (B < 0.0) rho = -1.0 / (2.0 * B);
+            }
+        }
+        out[7 + arm] = cross[3];
+        out[11 + arm] = rho;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Equilibrium check entry point and bandwidth calibration copy.
+// ---------------------------------------------------------------------------
+__global__ void k_equilibria(long long n, const double* __restrict__ in, double* __restrict__ out,
+                             int quintic) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double* m = in + 8 * i;
+    double* o = out + 24 * i;
+    eq_phi<double>(m[0], o);
+    eq_solute<double>(m[1], m[0], m[2], m[4], m[5], o + 5);
+    eq_heat<double>(m[3], m[0], quintic, m[4], m[5], o + 10);
+    eq_flow<double>(m[7], m[6], m[4], m[5], o + 15);
+}
+
+__global__ __launch_bounds__(256) void k_copy(const float4* __restrict__ src, float4* __restrict__ dst,
+                                              size_t n) {
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+}  // namespace dlb

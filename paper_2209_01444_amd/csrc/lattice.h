@@ -1,0 +1,290 @@
+// lattice.h -- device-side lattice arithmetic of the diffuse-interface MRT
+// lattice Boltzmann method (Zhan et al., arXiv:2209.01444) for gfx950.
+//
+// Everything here works in moment space with the closed forms of the
+// Appendix B transforms: the D2Q5 lattices keep (m0, m1x, m1y) live and relax
+// the second moments fully (s0 = s2 = 1, Sec. 4 preamble); the D2Q9 flow
+// lattice relaxes the raw moments (1, cx, cy, cx^2, cy^2, cxcy, cx^2cy,
+// cxcy^2, cx^2cy^2) with S = diag(1, 1, 1, s2, s2, s2, 1, 1, 1).
+//
+// Velocity order (columns of M, Appendix B):
+//   D2Q5: (0,0) (1,0) (0,1) (-1,0) (0,-1)
+//   D2Q9: the same, then (1,1) (-1,1) (-1,-1) (1,-1)
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace dlb {
+
+// Kernel-side parameters, passed by value.  Derived quantities are filled in
+// on the host from dlb_params (see make_kparams in dlb.hip).
+struct KParams {
+    int nx, ny;
+    long long plane;        // elements per SoA plane (>= nx*ny, 64-element multiple)
+    int n_sub, h_quintic, grad_iters, walls;
+    int nbx, nby, nblocks;  // tile grid of the node kernels
+    double W0, W2t;         // W0, W0^2/tau0
+    double inv_tau0, eps4, co, so;
+    double lambda, Mcinf, k, invD, s1c, s1t, s2u, jat;  // jat = W0/(2 sqrt 2)
+    double nsub_d, uin_x_sub, uin_y_sub, grad_tol2;
+    double seed_R, seed_x, seed_y, noise_amp, orient;
+    float shift[24];        // storage shifts (rest-state populations) for 16-bit storage
+};
+
+static constexpr int TILE_X = 64;
+static constexpr int TILE_Y = 4;
+static constexpr int BLOCK = TILE_X * TILE_Y;
+static constexpr double GRAD_GUARD = 1e-12;
+
+// ---------------------------------------------------------------------------
+// Storage codecs.  16-bit formats hold shifts from rest-state populations.
+// ---------------------------------------------------------------------------
+template <class S> struct Prec;
+template <> struct Prec<double> { using T = double; static constexpr bool half = false; };
+template <> struct Prec<float> { using T = float; static constexpr bool half = false; };
+template <> struct Prec<__half> { using T = float; static constexpr bool half = true; };
+template <> struct Prec<__hip_bfloat16> { using T = float; static constexpr bool half = true; };
+
+__device__ __forceinline__ double ld_raw(const double* p, size_t i) { return p[i]; }
+__device__ __forceinline__ float ld_raw(const float* p, size_t i) { return p[i]; }
+__device__ __forceinline__ float ld_raw(const __half* p, size_t i) { return __half2float(p[i]); }
+__device__ __forceinline__ float ld_raw(const __hip_bfloat16* p, size_t i) {
+    return __bfloat162float(p[i]);
+}
+__device__ __forceinline__ void st_raw(double* p, size_t i, double v) { p[i] = v; }
+__device__ __forceinline__ void st_raw(float* p, size_t i, float v) { p[i] = v; }
+__device__ __forceinline__ void st_raw(__half* p, size_t i, float v) { p[i] = __float2half_rn(v); }
+__device__ __forceinline__ void st_raw(__hip_bfloat16* p, size_t i, float v) {
+    p[i] = __float2bfloat16(v);
+}
+
+// Load a population as compute type T / store one from T.
+template <class T, class S>
+__device__ __forceinline__ T ld_pop(const S* p, size_t i, float shift) {
+    if constexpr (Prec<S>::half) return T(ld_raw(p, i) + shift);
+    else return T(ld_raw(p, i));
+}
+template <class S, class T>
+__device__ __forceinline__ void st_pop(S* p, size_t i, T v, float shift) {
+    using N = typename Prec<S>::T;
+    if constexpr (Prec<S>::half) st_raw(p, i, N(v) - shift);
+    else st_raw(p, i, N(v));
+}
+
+// Precision configurations: storage type S, arithmetic type T, history
+// storage type H.
+template <class S_, class T_, class H_> struct Cfg {
+    using S = S_;
+    using T = T_;
+    using H = H_;
+};
+using CfgF64 = Cfg<double, double, double>;
+using CfgF32 = Cfg<float, float, float>;
+using CfgF32M = Cfg<float, double, float>;  // FP32 storage, FP64 arithmetic
+using CfgF16 = Cfg<__half, float, float>;
+using CfgBF16 = Cfg<__hip_bfloat16, float, float>;
+
+// ---------------------------------------------------------------------------
+// Node geometry.  Workgroups are 64 x 4 tiles; the linear workgroup id is
+// remapped so each of the 8 XCDs (which receive ids round-robin) walks a
+// contiguous band of rows and keeps the y-neighbour rows in its own L2.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int xcd_remap(int bid, int nb) {
+    int q = nb >> 3, r = nb & 7;
+    int xcd = bid & 7, slot = bid >> 3;
+    int base = xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q;
+    return base + slot;
+}
+
+__device__ __forceinline__ bool node_of_thread(const KParams& kp, int& x, int& y) {
+    int t = xcd_remap(blockIdx.x, kp.nblocks);
+    int bx = t % kp.nbx, by = t / kp.nbx;
+    x = bx * TILE_X + (threadIdx.x & (TILE_X - 1));
+    y = by * TILE_Y + (threadIdx.x >> 6);
+    return x < kp.nx && y < kp.ny;
+}
+
+__device__ __forceinline__ bool is_wall(const KParams& kp, int x, int y) {
+    return x == 0 || y == 0 || x == kp.nx - 1 || y == kp.ny - 1;
+}
+__device__ __forceinline__ size_t inward_idx(const KParams& kp, int x, int y) {
+    int xf = x < 1 ? 1 : (x > kp.nx - 2 ? kp.nx - 2 : x);
+    int yf = y < 1 ? 1 : (y > kp.ny - 2 ? kp.ny - 2 : y);
+    return (size_t)yf * kp.nx + xf;
+}
+
+// ---------------------------------------------------------------------------
+// Equilibria in the documented evaluation order (no contraction), shared by
+// initialisation, wall rebuilding and the equilibrium check entry point.
+// ---------------------------------------------------------------------------
+template <class T> __device__ __forceinline__ T h_of(T phi, int quintic) {
+#pragma clang fp contract(off)
+    if (!quintic) return phi;
+    T p2 = phi * phi;
+    return T(15.0) * (phi - T(2.0) * phi * p2 / T(3.0) + phi * p2 * p2 / T(5.0)) / T(8.0);
+}
+
+// f_i^eq = w_i phi (Sec. 3.1)
+template <class T> __device__ void eq_phi(T phi, T* o) {
+#pragma clang fp contract(off)
+    const T w0 = T(1.0) / T(3.0), w1 = T(1.0) / T(6.0);
+    o[0] = w0 * phi;
+    o[1] = w1 * phi; o[2] = w1 * phi; o[3] = w1 * phi; o[4] = w1 * phi;
+}
+
+// n^eq (Sec. 3.2)
+template <class T> __device__ void eq_solute(T C, T phi, T U, T ux, T uy, T* o) {
+#pragma clang fp contract(off)
+    const T w0 = T(1.0) / T(3.0), w1 = T(1.0) / T(6.0);
+    T q = T(0.5) * (T(1.0) - phi);
+    T qU = q * U;
+    T Cux = C * ux, Cuy = C * uy;
+    o[0] = C + (w0 - T(1.0)) * qU;
+    o[1] = w1 * qU + w1 * (T(3.0) * Cux);
+    o[2] = w1 * qU + w1 * (T(3.0) * Cuy);
+    o[3] = w1 * qU + w1 * (T(3.0) * (-Cux));
+    o[4] = w1 * qU + w1 * (T(3.0) * (-Cuy));
+}
+
+// g^eq (Sec. 3.3)
+template <class T> __device__ void eq_heat(T theta, T phi, int quintic, T ux, T uy, T* o) {
+#pragma clang fp contract(off)
+    const T w0 = T(1.0) / T(3.0), w1 = T(1.0) / T(6.0);
+    T hp = h_of(phi, quintic);
+    T H = theta - T(0.5) * hp;
+    T Hux = H * ux, Huy = H * uy;
+    o[0] = w0 * theta - T(0.5) * hp;
+    o[1] = w1 * theta + w1 * (T(3.0) * Hux);
+    o[2] = w1 * theta + w1 * (T(3.0) * Huy);
+    o[3] = w1 * theta + w1 * (T(3.0) * (-Hux));
+    o[4] = w1 * theta + w1 * (T(3.0) * (-Huy));
+}
+
+// h^eq (Sec. 3.4).  rho0 = 0 gives the shifted form the solver stores.
+template <class T> __device__ void eq_flow(T rho0, T p, T ux, T uy, T* o) {
+#pragma clang fp contract(off)
+    const T w0 = T(4.0) / T(9.0), w1 = T(1.0) / T(9.0), w2 = T(1.0) / T(36.0);
+    T uu = ux * ux + uy * uy;
+    T cu[9] = {T(0.0), ux, uy, -ux, -uy, ux + uy, -ux + uy, -ux + -uy, ux + -uy};
+    o[0] = ((w0 - T(1.0)) * (T(3.0) * p) + rho0) +
+           w0 * (T(3.0) * cu[0] + T(4.5) * cu[0] * cu[0] - T(1.5) * uu);
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+        T w = i < 5 ? w1 : w2;
+        o[i] = w * (T(3.0) * p) + w * (T(3.0) * cu[i] + T(4.5) * cu[i] * cu[i] - T(1.5) * uu);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Anisotropy (Sec. 2), 2-D closed form in the crystal frame:
+//   a_s = 1 - 3e + 4e (g'x^4 + g'y^4)/|g|^4
+//   N'  = 16 e a_s / |g|^4 (g'x g'y^2 (g'x^2 - g'y^2), g'y g'x^2 (g'y^2 - g'x^2))
+// with g' = R(-orient) g and N = R(orient) N'.
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ void anisotropy(const KParams& kp, T gx, T gy, T& a, T& Nx, T& Ny) {
+    const T co = T(kp.co), so = T(kp.so), e = T(kp.eps4);
+    T px = co * gx + so * gy, py = -so * gx + co * gy;
+    T px2 = px * px, py2 = py * py, g2 = px2 + py2;
+    T inv = T(1) / (g2 * g2);
+    a = T(1) - T(3) * e + T(4) * e * (px2 * px2 + py2 * py2) * inv;
+    T c = T(16) * e * a * inv;
+    T nxp = c * px * py2 * (px2 - py2);
+    T nyp = c * py * px2 * (py2 - px2);
+    Nx = co * nxp - so * nyp;
+    Ny = so * nxp + co * nyp;
+}
+
+// Local gradient of Sec. 3.1,
+//   grad phi = -3 s1(a_s) (m1 + W0^2 N / tau0),  s1 = 1/(3 a_s^2 W0^2/tau0 + 1/2),
+// solved by fixed-point iteration from the isotropic guess, with the bulk
+// guard |g|^2 < 1e-12 -> g = 0, a_s = 1, N = 0.
+template <class T>
+__device__ __forceinline__ void local_gradient(const KParams& kp, T m1x, T m1y, T& gx, T& gy, T& a,
+                                               T& Nx, T& Ny) {
+    const T W2t = T(kp.W2t);
+    T s1 = T(1) / (T(3) * W2t + T(0.5));
+    gx = T(-3) * s1 * m1x;
+    gy = T(-3) * s1 * m1y;
+    a = T(1);
+    Nx = Ny = T(0);
+    const T tol2 = T(kp.grad_tol2);
+    for (int it = 0; it < kp.grad_iters; ++it) {
+        if (gx * gx + gy * gy < T(GRAD_GUARD)) break;
+        anisotropy(kp, gx, gy, a, Nx, Ny);
+        s1 = T(1) / (T(3) * a * a * W2t + T(0.5));
+        T nx = T(-3) * s1 * (m1x + W2t * Nx);
+        T ny = T(-3) * s1 * (m1y + W2t * Ny);
+        T d2 = (nx - gx) * (nx - gx) + (ny - gy) * (ny - gy);
+        gx = nx;
+        gy = ny;
+        if (d2 <= tol2 * (gx * gx + gy * gy)) break;
+    }
+    if (gx * gx + gy * gy < T(GRAD_GUARD)) {
+        gx = gy = T(0);
+        a = T(1);
+        Nx = Ny = T(0);
+    } else {
+        anisotropy(kp, gx, gy, a, Nx, Ny);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Flow lattice (Sec. 3.4), sub-step units, h_0 stored shifted by -rho0.
+// ---------------------------------------------------------------------------
+template <class T> struct FlowMacro {
+    T mx, my;   // u* = sum c_i h_i
+    T ux, uy;   // u = u* + [1 - q(phi)] f / 2,  f = -u* (u_s = 0, dt' = 1)
+    T Fx, Fy;   // [1 - q(phi)] f
+    T p;        // cs^2/(1-w0) (sum_{i>0} h_i - w0 |u|^2 / (2 cs^2))
+};
+
+template <class T> __device__ __forceinline__ FlowMacro<T> flow_macro(const T* h, T phi) {
+    FlowMacro<T> m;
+    T d57 = h[5] - h[7], d68 = h[6] - h[8];
+    m.mx = (h[1] - h[3]) + (d57 - d68);
+    m.my = (h[2] - h[4]) + (d57 + d68);
+    T rest = (h[1] + h[2]) + (h[3] + h[4]) + ((h[5] + h[6]) + (h[7] + h[8]));
+    T solid = T(0.5) * (T(1) + phi);  // 1 - q(phi)
+    m.Fx = -solid * m.mx;
+    m.Fy = -solid * m.my;
+    m.ux = m.mx + T(0.5) * m.Fx;
+    m.uy = m.my + T(0.5) * m.Fy;
+    m.p = T(0.6) * (rest - T(2.0 / 3.0) * (m.ux * m.ux + m.uy * m.uy));
+    return m;
+}
+
+// One MRT collision; returns post-collision populations (shifted h_0).
+template <class T> __device__ __forceinline__ void flow_collide(const T* h, T phi, T s2, T* o) {
+    FlowMacro<T> M = flow_macro(h, phi);
+    T h57 = h[5] + h[7], h68 = h[6] + h[8];
+    T m3 = h[1] + h[3] + (h57 + h68);
+    T m4 = h[2] + h[4] + (h57 + h68);
+    T m5 = h57 - h68;
+    T ux = M.ux, uy = M.uy;
+    T m1 = ux + T(0.5) * M.Fx;  // s1 = 1: relaxed to u, plus (1 - 1/2) F
+    T m2 = uy + T(0.5) * M.Fy;
+    T n3 = m3 - s2 * (m3 - (M.p + ux * ux));
+    T n4 = m4 - s2 * (m4 - (M.p + uy * uy));
+    T n5 = m5 - s2 * (m5 - ux * uy);
+    T n6 = m2 * T(1.0 / 3.0);  // (uy + Fy/2)/3
+    T n7 = m1 * T(1.0 / 3.0);
+    T n8 = (M.p + ux * ux + uy * uy) * T(1.0 / 3.0);
+    // h = M^-1 m (inverse of the Appendix B transform)
+    o[0] = n8 - n3 - n4;
+    T a1 = n3 - n8, a2 = n4 - n8, d1 = m1 - n7, d2 = m2 - n6;
+    o[1] = T(0.5) * (a1 + d1);
+    o[3] = T(0.5) * (a1 - d1);
+    o[2] = T(0.5) * (a2 + d2);
+    o[4] = T(0.5) * (a2 - d2);
+    T b = n6 + n8, c = n8 - n6;
+    o[5] = T(0.25) * (n5 + n7 + b);
+    o[6] = T(0.25) * (-n5 - n7 + b);
+    o[7] = T(0.25) * (n5 - n7 + c);
+    o[8] = T(0.25) * (-n5 + n7 + c);
+}
+
+}  // namespace dlb

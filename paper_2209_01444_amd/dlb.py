@@ -1,0 +1,273 @@
+"""Python binding of libdlb.so (include/dlb.h): argument marshalling only.
+
+Every step of the method runs in the library's HIP kernels; this module
+allocates the caller-owned device state with torch, hands the library a
+torch stream, and converts arguments.  It fails loudly when the library is
+missing: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libdlb.so")
+
+DLB_OK, DLB_EINVAL, DLB_ENOMEM, DLB_EHIP, DLB_ENAN, DLB_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+PRECISION = {"f64": 0, "f32": 1, "f16s": 2, "bf16s": 3, "f32m": 4}
+FIELDS = ("phi", "C", "U", "theta", "ux", "uy", "p")
+
+
+class DlbError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"dlb error {code}: {msg}")
+        self.code = code
+
+
+class DlbParams(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in (
+        "nx", "ny", "use_ns", "bc", "n_sub", "h_quintic", "c_init_U", "precision", "grad_iters",
+        "reserved")] + [(n, ctypes.c_double) for n in (
+            "W0", "tau0", "eps4", "orient", "lambda_", "Mcinf", "k", "D", "alpha", "nu", "rho0",
+            "u_in_x", "u_in_y", "theta0", "U0", "C0", "seed_R", "seed_x", "seed_y", "noise_amp",
+            "grad_tol")]
+
+
+EXPORTS = (
+    "dlb_state_bytes", "dlb_create", "dlb_destroy", "dlb_init_seed", "dlb_set_fields", "dlb_step",
+    "dlb_step_timed", "dlb_step_count", "dlb_get_fields", "dlb_reduce", "dlb_checkpoint_bytes",
+    "dlb_save", "dlb_load", "dlb_sync", "dlb_equilibria", "dlb_copy_kernel", "dlb_strerror",
+    "dlb_last_error",
+)
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libdlb.so (built in-tree by paper_2209_01444_amd/build.py)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python paper_2209_01444_amd/build.py`"
+                          " (there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    P, vp, d, i64 = ctypes.POINTER, ctypes.c_void_p, ctypes.c_double, ctypes.c_int64
+    dp = P(d)
+    sig = {
+        "dlb_state_bytes": (ctypes.c_size_t, [P(DlbParams)]),
+        "dlb_create": (ctypes.c_int, [P(DlbParams), vp, ctypes.c_size_t, vp, P(vp)]),
+        "dlb_destroy": (ctypes.c_int, [vp]),
+        "dlb_init_seed": (ctypes.c_int, [vp, dp]),
+        "dlb_set_fields": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, ctypes.c_int]),
+        "dlb_step": (ctypes.c_int, [vp, i64]),
+        "dlb_step_timed": (ctypes.c_int, [vp, i64, dp, dp, P(i64), P(i64)]),
+        "dlb_step_count": (i64, [vp]),
+        "dlb_get_fields": (ctypes.c_int, [vp, ctypes.c_uint32, vp, ctypes.c_int, ctypes.c_int]),
+        "dlb_reduce": (ctypes.c_int, [vp, dp]),
+        "dlb_checkpoint_bytes": (ctypes.c_size_t, [vp]),
+        "dlb_save": (ctypes.c_int, [vp, vp, ctypes.c_size_t]),
+        "dlb_load": (ctypes.c_int, [vp, vp, ctypes.c_size_t]),
+        "dlb_sync": (ctypes.c_int, [vp]),
+        "dlb_equilibria": (ctypes.c_int, [i64, dp, dp, ctypes.c_int]),
+        "dlb_copy_kernel": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp]),
+        "dlb_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "dlb_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(lib, rc: int):
+    if rc != DLB_OK:
+        raise DlbError(rc, lib.dlb_last_error().decode())
+
+
+DEFAULTS = dict(
+    nx=64, ny=64, use_ns=0, walls=0, n_sub=1, h_quintic=0, c_init_U=0, precision="f64",
+    grad_iters=0, W0=1.0, tau0=20.0, eps4=0.05, orient=0.0, lambda_=0.0, Mcinf=0.0, k=0.15, D=0.1,
+    alpha=0.1, nu=0.1, rho0=1.0, u_in=(0.0, 0.0), theta0=0.0, U0=0.0, C0=1.0, seed_R=8.0,
+    seed_x=None, seed_y=None, noise_amp=0.0, grad_tol=0.0, use_c=1, use_t=1,
+)
+_IGNORED = {"name", "steps"}
+
+
+def make_params(cfg: dict) -> DlbParams:
+    c = dict(DEFAULTS)
+    for key, val in cfg.items():
+        if key in _IGNORED:
+            continue
+        key = "lambda_" if key == "lambda" else key
+        if key not in c:
+            raise KeyError(f"unknown parameter {key!r}")
+        c[key] = val
+    if not (c["use_c"] and c["use_t"]):
+        raise ValueError("the GPU solver always runs the solute and heat lattices")
+    p = DlbParams()
+    p.nx, p.ny = int(c["nx"]), int(c["ny"])
+    p.use_ns = int(c["use_ns"])
+    p.bc = int(c["walls"])
+    p.n_sub = int(c["n_sub"])
+    p.h_quintic = int(c["h_quintic"])
+    p.c_init_U = int(c["c_init_U"])
+    p.precision = PRECISION[c["precision"]] if isinstance(c["precision"], str) else int(c["precision"])
+    p.grad_iters = int(c["grad_iters"])
+    for name in ("W0", "tau0", "eps4", "orient", "lambda_", "Mcinf", "k", "D", "alpha", "nu", "rho0",
+                 "theta0", "U0", "C0", "seed_R", "noise_amp", "grad_tol"):
+        setattr(p, name, float(c[name]))
+    p.u_in_x, p.u_in_y = float(c["u_in"][0]), float(c["u_in"][1])
+    p.seed_x = float(c["nx"] // 2 if c["seed_x"] is None else c["seed_x"])
+    p.seed_y = float(c["ny"] // 2 if c["seed_y"] is None else c["seed_y"])
+    return p
+
+
+def _host_ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Solver:
+    """One lattice Boltzmann simulation in caller-owned (torch) device memory."""
+
+    def __init__(self, cfg: dict, device: str = "cuda:0", stream=None):
+        import torch
+
+        self.torch = torch
+        self.lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("libdlb needs a GPU (no CPU fallback)")
+        self.cfg = dict(cfg)
+        self.p = make_params(cfg)
+        self.nx, self.ny = self.p.nx, self.p.ny
+        self.device = torch.device(device)
+        nbytes = self.lib.dlb_state_bytes(ctypes.byref(self.p))
+        if nbytes == 0:
+            raise DlbError(DLB_EINVAL, self.lib.dlb_last_error().decode())
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+            self.state = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.handle = ctypes.c_void_p()
+        _check(self.lib, self.lib.dlb_create(ctypes.byref(self.p), ctypes.c_void_p(self.state.data_ptr()),
+                                             nbytes, ctypes.c_void_p(self.stream.cuda_stream),
+                                             ctypes.byref(self.handle)))
+
+    # -- lifecycle --------------------------------------------------------
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            self.lib.dlb_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _plane(self, a):
+        if a is None:
+            return None
+        return np.ascontiguousarray(a, dtype=np.float64).reshape(self.ny * self.nx)
+
+    def init_seed(self, noise=None):
+        n = self._plane(noise)
+        _check(self.lib, self.lib.dlb_init_seed(self.handle, None if n is None else
+                                                n.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return self
+
+    def set_fields(self, phi, C=None, theta=None, ux=None, uy=None):
+        """Host numpy arrays or device torch tensors (float64, ny x nx)."""
+        arrs = (phi, C, theta, ux, uy)
+        if any(self.torch.is_tensor(a) for a in arrs if a is not None):
+            keep = [None if a is None else a.to(self.device, self.torch.float64).contiguous()
+                    for a in arrs]
+            ptrs = [None if a is None else ctypes.c_void_p(a.data_ptr()) for a in keep]
+            self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+            _check(self.lib, self.lib.dlb_set_fields(self.handle, *ptrs, 1))
+            self.stream.synchronize()
+            return self
+        keep = [self._plane(a) for a in arrs]
+        _check(self.lib, self.lib.dlb_set_fields(self.handle, *[_host_ptr(a) for a in keep], 0))
+        return self
+
+    def step(self, n: int):
+        _check(self.lib, self.lib.dlb_step(self.handle, int(n)))
+        return self
+
+    def step_timed(self, n: int) -> dict:
+        a, b = ctypes.c_double(), ctypes.c_double()
+        la, lb = ctypes.c_int64(), ctypes.c_int64()
+        _check(self.lib, self.lib.dlb_step_timed(self.handle, int(n), ctypes.byref(a), ctypes.byref(b),
+                                                 ctypes.byref(la), ctypes.byref(lb)))
+        return dict(ms_pct=a.value, ms_flow=b.value, launches_pct=la.value, launches_flow=lb.value)
+
+    def sync(self):
+        _check(self.lib, self.lib.dlb_sync(self.handle))
+
+    @property
+    def step_count(self) -> int:
+        return int(self.lib.dlb_step_count(self.handle))
+
+    # -- observation ------------------------------------------------------
+    def fields(self, names=FIELDS) -> dict:
+        mask = 0
+        for nm in names:
+            mask |= 1 << FIELDS.index(nm)
+        sel = [f for f in FIELDS if mask & (1 << FIELDS.index(f))]
+        out = np.empty((len(sel), self.ny, self.nx), dtype=np.float64)
+        _check(self.lib, self.lib.dlb_get_fields(self.handle, mask, out.ctypes.data_as(ctypes.c_void_p),
+                                                 0, 0))
+        return {f: out[i] for i, f in enumerate(sel)}
+
+    def fields_device(self, names=FIELDS, f32: bool = True):
+        """Selected fields as a (n_fields, ny, nx) torch tensor on the device."""
+        mask = 0
+        for nm in names:
+            mask |= 1 << FIELDS.index(nm)
+        n = bin(mask).count("1")
+        dt = self.torch.float32 if f32 else self.torch.float64
+        with self.torch.cuda.device(self.device):
+            out = self.torch.empty((n, self.ny, self.nx), dtype=dt, device=self.device)
+        _check(self.lib, self.lib.dlb_get_fields(self.handle, mask, ctypes.c_void_p(out.data_ptr()), 1,
+                                                 int(f32)))
+        self.torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        return out
+
+    def reduce(self, allow_nonfinite: bool = False) -> dict:
+        out = np.empty(17)
+        rc = self.lib.dlb_reduce(self.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        if rc != DLB_OK and not (rc == DLB_ENAN and allow_nonfinite):
+            _check(self.lib, rc)
+        keys = ("sum_C", "sum_H", "solid_fraction", "nonfinite", "Fx", "Fy", "torque")
+        r = {k: float(out[i]) for i, k in enumerate(keys)}
+        r["tip_s"] = out[7:11].copy()
+        r["tip_rho"] = out[11:15].copy()
+        r["centroid"] = out[15:17].copy()
+        r["code"] = rc
+        return r
+
+    # -- checkpoint -------------------------------------------------------
+    def save(self) -> bytes:
+        n = self.lib.dlb_checkpoint_bytes(self.handle)
+        buf = ctypes.create_string_buffer(n)
+        _check(self.lib, self.lib.dlb_save(self.handle, ctypes.cast(buf, ctypes.c_void_p), n))
+        return buf.raw
+
+    def load(self, blob: bytes):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        _check(self.lib, self.lib.dlb_load(self.handle, ctypes.cast(buf, ctypes.c_void_p), len(blob)))
+        return self
+
+
+def equilibria(macros: np.ndarray, h_quintic: int = 0) -> np.ndarray:
+    """FP64 device equilibria for rows (phi, C, U, theta, ux, uy, p, rho0)."""
+    lib = load_library()
+    m = np.ascontiguousarray(macros, dtype=np.float64)
+    out = np.empty((m.shape[0], 24))
+    _check(lib, lib.dlb_equilibria(m.shape[0], m.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(h_quintic)))
+    return out

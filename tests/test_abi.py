@@ -1,0 +1,61 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol
+include/dlb.h declares, and validates parameters (no GPU work)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2209_01444_amd import dlb, workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "dlb.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dlb_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = dlb.load_library()
+    names = declared_symbols()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(dlb.EXPORTS)
+
+
+def test_state_bytes_and_validation():
+    lib = dlb.load_library()
+    p = dlb.make_params(W.pure_diffusion_128())
+    n64 = lib.dlb_state_bytes(ctypes.byref(p))
+    p32 = dlb.make_params(W.pure_diffusion_128("f32"))
+    n32 = lib.dlb_state_bytes(ctypes.byref(p32))
+    assert n64 > 0 and n32 > 0 and n64 > 1.9 * (n32 - 64 * 1024) - 64 * 1024
+    cfg, _ = W.thermosolutal_flow()
+    pf = dlb.make_params(cfg)
+    nb = lib.dlb_state_bytes(ctypes.byref(pf))
+    # 2 x (15 + 9) FP32 population planes + 6 FP32 history planes per node
+    assert nb >= 1024 * 1024 * 4 * (48 + 6)
+    for bad in (dict(nx=8), dict(precision=7), dict(tau0=-1.0), dict(k=1.5), dict(eps4=0.2),
+                dict(use_ns=1, n_sub=1, nu=0.0),
+                dict(use_ns=1, n_sub=1, nu=0.1, u_in=(0.2, 0.0))):  # Mach limit
+        q = dlb.make_params(dict(W.pure_diffusion_128(), **bad))
+        assert lib.dlb_state_bytes(ctypes.byref(q)) == 0, bad
+        assert lib.dlb_last_error()
+
+
+def test_strerror_codes():
+    lib = dlb.load_library()
+    for code in (0, -1, -2, -3, -4, -5):
+        assert lib.dlb_strerror(code)
+    assert lib.dlb_strerror(-99) == b"unknown error"
+
+
+def test_gpu_solver_refuses_to_run_without_gpu():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(RuntimeError):
+        dlb.Solver(W.pure_diffusion_128())

