@@ -34,8 +34,8 @@ def kernel_source_hash() -> str:
 def algorithmic_bytes(cfg: dict) -> dict:
     """Bytes each kernel must move per node (each state word read once and
     written once; neighbour reuse assumed perfect)."""
-    sb = {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}[cfg["precision"]]
-    cb = 8 if cfg["precision"] == "f64" else 4
+    sb = {"f64": 8, "f32": 4, "f32m": 4, "f16s": 2, "bf16s": 2}[cfg["precision"]]
+    cb = 8 if cfg["precision"] == "f64" else 4  # history planes
     ns = bool(cfg.get("use_ns"))
     # k_pct: 15 populations in + out, 8 flow populations in (velocity),
     # history in + out (phi, Q and, with flow, C u, H u)
