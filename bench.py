@@ -111,6 +111,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--precision", default="f32")
     ap.add_argument("--size", type=int, default=1024)
+    ap.add_argument("--flow-fuse", type=int, default=0, help="flow sub-steps per launch (0: library default)")
     ap.add_argument("--timed-launch-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
@@ -129,6 +130,7 @@ def main():
     from paper_2209_01444_amd import dlb, workloads
 
     cfg, noise = workloads.thermosolutal_flow(args.size, args.size, seed=2, precision=args.precision)
+    cfg["flow_fuse"] = args.flow_fuse
     solver = dlb.Solver(cfg).init_seed(noise)
     nodes = cfg["nx"] * cfg["ny"]
 

@@ -77,7 +77,9 @@ typedef struct dlb_params {
     int32_t c_init_U;     /* initial solute: 0 uniform C = C0; 1 uniform U = U0      */
     int32_t precision;    /* DLB_F64 .. DLB_F32M                                     */
     int32_t grad_iters;   /* cap of the local-gradient fixed point (0: default)      */
-    int32_t reserved;
+    int32_t flow_fuse;    /* flow sub-steps fused per launch: 1, 3 or 5 (0: 5); the
+                             fused kernel keeps a tile in registers and LDS for
+                             that many sub-steps; results equal the unfused ones */
     double W0, tau0;      /* interface width and kinetic time (Sec. 2)              */
     double eps4, orient;  /* anisotropy strength and crystal orientation (rad)      */
     double lambda, Mcinf, k;   /* coupling, M c_inf, partition coefficient          */
@@ -123,9 +125,10 @@ int dlb_step(dlb_handle h, int64_t n);
 
 /* As dlb_step (without graph replay), recording HIP events on the solver's
  * stream before and after the phi/C/theta kernel and after the last flow
- * sub-step of every main step; returns the summed milliseconds of the
- * phi/C/theta kernels and of the back-to-back flow sub-steps, and the
- * number of launches of each.  Synchronises the stream after every step. */
+ * launch of every main step; returns the summed milliseconds of the
+ * phi/C/theta kernels and of the back-to-back flow launches, and the
+ * number of launches of each (a fused launch counts once).  Synchronises the
+ * stream after every step. */
 int dlb_step_timed(dlb_handle h, int64_t n, double* ms_pct, double* ms_flow,
                    int64_t* launches_pct, int64_t* launches_flow);
 

@@ -95,7 +95,7 @@ DEFAULTS = dict(
 )
 
 # keys of a workload dictionary that only concern the GPU library
-_GPU_ONLY = {"precision", "grad_iters", "name", "steps"}
+_GPU_ONLY = {"precision", "grad_iters", "flow_fuse", "name", "steps"}
 
 
 def make_params(cfg: dict) -> OrcParams:

@@ -187,6 +187,8 @@ static KParams make_kparams(const dlb_params* p, const Layout& L) {
 struct Ops {
     void (*pct)(const KParams&, const void*, void*, const void*, void*, int, hipStream_t, dim3);
     void (*flow)(const KParams&, const void*, void*, const void*, hipStream_t, dim3);
+    // K fused sub-steps (K in {3, 5}); returns false if K is not built
+    bool (*flow_tb)(int, const KParams&, const void*, void*, const void*, hipStream_t);
     void (*set_fields)(const KParams&, const InitFields&, void*, void*, hipStream_t, dim3);
     void (*fields)(const KParams&, const void*, const void*, uint32_t, void*, int, hipStream_t, dim3);
     void (*reduce)(const KParams&, const void*, const void*, double*, hipStream_t, dim3);
@@ -206,6 +208,24 @@ template <class CF, bool NS, bool W> struct OpsImpl {
         hipLaunchKernelGGL((k_flow<CF, W>), grid, dim3(BLOCK), 0, st, kp, (const S*)hin, (S*)hout,
                            (const H*)phi);
     }
+    template <int K>
+    static void tb_launch(const KParams& kp, const void* hin, void* hout, const void* phi,
+                          hipStream_t st) {
+        using T = typename CF::T;
+        constexpr int EX = TbTile<T>::EX, EY = TbTile<T>::EY;
+        constexpr int OX = TbShape<EX, EY, K>::OX, OY = TbShape<EX, EY, K>::OY;
+        int nbx = (kp.nx + OX - 1) / OX, nby = (kp.ny + OY - 1) / OY;
+        hipLaunchKernelGGL((k_flow_tb<CF, W, EX, EY, K>), dim3(nbx * nby), dim3(EX * EY), 0, st, kp,
+                           (const S*)hin, (S*)hout, (const H*)phi, nbx, nbx * nby);
+    }
+    static bool flow_tb(int K, const KParams& kp, const void* hin, void* hout, const void* phi,
+                        hipStream_t st) {
+        switch (K) {
+            case 3: tb_launch<3>(kp, hin, hout, phi, st); return true;
+            case 5: tb_launch<5>(kp, hin, hout, phi, st); return true;
+        }
+        return false;
+    }
     static void set_fields(const KParams& kp, const InitFields& in, void* pop, void* flow,
                            hipStream_t st, dim3 grid) {
         hipLaunchKernelGGL((k_set_fields<CF, NS, W>), grid, dim3(BLOCK), 0, st, kp, in, (S*)pop,
@@ -224,7 +244,7 @@ template <class CF, bool NS, bool W> struct OpsImpl {
     static void tips(const KParams& kp, const void* pop, double* out, hipStream_t st) {
         hipLaunchKernelGGL((k_tips<CF, W>), dim3(4), dim3(448), 0, st, kp, (const S*)pop, out);
     }
-    static Ops ops() { return Ops{pct, flow, set_fields, fields, reduce, tips}; }
+    static Ops ops() { return Ops{pct, flow, flow_tb, set_fields, fields, reduce, tips}; }
 };
 
 template <class CF> static Ops ops_for(bool ns, bool walls) {
@@ -255,6 +275,7 @@ struct dlb_solver {
     int hist_valid = 0;
     int64_t step = 0;
     dim3 grid;
+    int fuse = 1;                    // flow sub-steps fused per launch
     hipGraphExec_t graph = nullptr;  // two main steps, valid once history is valid
     int graph_pop = -1, graph_flow = -1;
 
@@ -277,7 +298,16 @@ static void enqueue_step(dlb_solver* s, hipEvent_t* ev) {
     s->pop_cur ^= 1;
     s->hist_valid = 1;
     if (s->p.use_ns) {
-        for (int i = 0; i < s->p.n_sub; ++i) {
+        // K fused sub-steps per launch while K fit, single sub-steps after
+        int left = s->p.n_sub;
+        const int K = s->fuse;
+        while (K > 1 && left >= K) {
+            s->ops.flow_tb(K, s->kp, s->flow(s->flow_cur), s->flow(1 - s->flow_cur), s->hist(),
+                           s->stream);
+            s->flow_cur ^= 1;
+            left -= K;
+        }
+        for (; left > 0; --left) {
             s->ops.flow(s->kp, s->flow(s->flow_cur), s->flow(1 - s->flow_cur), s->hist(), s->stream,
                         s->grid);
             s->flow_cur ^= 1;
@@ -354,6 +384,11 @@ int dlb_create(const dlb_params* p, void* dev_state, size_t bytes, void* hip_str
     s->bytes = bytes;
     s->stream = (hipStream_t)hip_stream;
     s->grid = dim3(L.nblocks);
+    s->fuse = p->flow_fuse == 0 ? 5 : p->flow_fuse;
+    if (s->fuse != 1 && s->fuse != 3 && s->fuse != 5) {
+        delete s;
+        return fail(DLB_EINVAL, "flow_fuse must be 0 (default), 1, 3 or 5");
+    }
     *out = s;
     return DLB_OK;
 }
@@ -472,7 +507,7 @@ int dlb_step_timed(dlb_handle h, int64_t n, double* ms_pct, double* ms_flow, int
         if (h->p.use_ns) {
             (void)hipEventElapsedTime(&ms, ev[1], ev[2]);
             b += ms;
-            lb += h->p.n_sub;
+            lb += h->p.n_sub / h->fuse + h->p.n_sub % h->fuse;
         }
     }
     for (auto& e : ev) (void)hipEventDestroy(e);

@@ -84,15 +84,14 @@ __device__ __forceinline__ void flow_node(const KParams& kp, const S* __restrict
 // K1: phi, C, theta main step.
 // ---------------------------------------------------------------------------
 template <class CF, bool NS, bool WALLS>
-__global__ __launch_bounds__(BLOCK) void k_pct(const KParams kp, const typename CF::S* __restrict__ pin,
-                                               typename CF::S* __restrict__ pout,
-                                               const typename CF::S* __restrict__ hin,
-                                               typename CF::H* __restrict__ hist, int hist_valid) {
+__device__ __forceinline__ void pct_node(const KParams& kp, const typename CF::S* __restrict__ pin,
+                                         typename CF::S* __restrict__ pout,
+                                         const typename CF::S* __restrict__ hin,
+                                         typename CF::H* __restrict__ hist, int hist_valid, int x,
+                                         int y) {
     using T = typename CF::T;
-    using S = typename CF::S;
     using HT = typename CF::H;
-    int x, y;
-    if (!node_of_thread(kp, x, y)) return;
+    using S = typename CF::S;
     const size_t P = (size_t)kp.plane;
     const size_t idx = (size_t)y * kp.nx + x;
     const bool wall = WALLS && is_wall(kp, x, y);
@@ -231,17 +230,25 @@ __global__ __launch_bounds__(BLOCK) void k_pct(const KParams kp, const typename 
     }
 }
 
+template <class CF, bool NS, bool WALLS>
+__global__ __launch_bounds__(BLOCK) void k_pct(const KParams kp, const typename CF::S* __restrict__ pin,
+                                               typename CF::S* __restrict__ pout,
+                                               const typename CF::S* __restrict__ hin,
+                                               typename CF::H* __restrict__ hist, int hist_valid) {
+    int x, y;
+    if (!node_of_thread(kp, x, y)) return;
+    pct_node<CF, NS, WALLS>(kp, pin, pout, hin, hist, hist_valid, x, y);
+}
+
 // ---------------------------------------------------------------------------
 // K2: one flow sub-step (Sec. 3.4) at frozen phi^t (= hist[0]).
 // ---------------------------------------------------------------------------
 template <class CF, bool WALLS>
-__global__ __launch_bounds__(BLOCK) void k_flow(const KParams kp, const typename CF::S* __restrict__ hin,
-                                                typename CF::S* __restrict__ hout,
-                                                const typename CF::H* __restrict__ phi_t) {
+__device__ __forceinline__ void flow_step_node(const KParams& kp, const typename CF::S* __restrict__ hin,
+                                               typename CF::S* __restrict__ hout,
+                                               const typename CF::H* __restrict__ phi_t, int x, int y) {
     using T = typename CF::T;
     using S = typename CF::S;
-    int x, y;
-    if (!node_of_thread(kp, x, y)) return;
     const size_t P = (size_t)kp.plane;
     const size_t idx = (size_t)y * kp.nx + x;
     const T phi = T(phi_t[idx]);
@@ -257,6 +264,133 @@ __global__ __launch_bounds__(BLOCK) void k_flow(const KParams kp, const typename
         if (d < 0) continue;
         st_pop(hout, i * P + (size_t)d, o[i], kp.shift[15 + i]);
     }
+}
+
+template <class CF, bool WALLS>
+__global__ __launch_bounds__(BLOCK) void k_flow(const KParams kp, const typename CF::S* __restrict__ hin,
+                                                typename CF::S* __restrict__ hout,
+                                                const typename CF::H* __restrict__ phi_t) {
+    int x, y;
+    if (!node_of_thread(kp, x, y)) return;
+    flow_step_node<CF, WALLS>(kp, hin, hout, phi_t, x, y);
+}
+
+// ---------------------------------------------------------------------------
+// K2': K fused flow sub-steps per launch (temporal blocking).  A workgroup
+// holds an extended tile of EX x EY nodes, one per thread, with the
+// populations in registers.  Each sub-step: collide, write the post-collision
+// populations to LDS, pull the streamed ones back from the neighbours' LDS
+// slots (wall nodes instead rebuild theirs from the inward neighbour's pulled
+// populations, read from the same LDS slots).  Values near the tile edge go
+// stale by one ring per sub-step, so after K sub-steps the central
+// (EX-2K) x (EY-2K) nodes are exact and are stored, aligned, to the output
+// buffer.  Arithmetic per node and sub-step is that of k_flow.
+// ---------------------------------------------------------------------------
+template <int EX, int EY, int K> struct TbShape {
+    static constexpr int OX = EX - 2 * K, OY = EY - 2 * K;
+};
+// extended tile per arithmetic type: 9 LDS planes of EX*EY values stay at
+// 36 KiB (32x32 in FP32, 32x16 in FP64)
+template <class T> struct TbTile;
+template <> struct TbTile<float> { static constexpr int EX = 32, EY = 32; };
+template <> struct TbTile<double> { static constexpr int EX = 32, EY = 16; };
+
+template <class CF, bool WALLS, int EX, int EY, int K>
+__device__ __forceinline__ void flow_tb_tile(const KParams& kp, const typename CF::S* __restrict__ hin,
+                                             typename CF::S* __restrict__ hout,
+                                             const typename CF::H* __restrict__ phi_t, int bx, int by) {
+    using T = typename CF::T;
+    using S = typename CF::S;
+    constexpr int OX = TbShape<EX, EY, K>::OX, OY = TbShape<EX, EY, K>::OY;
+    __shared__ T lds[9][EY][EX];
+    const size_t P = (size_t)kp.plane;
+    const int tx = threadIdx.x % EX, ty = threadIdx.x / EX;
+    int gx = bx * OX - K + tx, gy = by * OY - K + ty;
+    bool exists = true;
+    if constexpr (WALLS) {
+        exists = gx >= 0 && gy >= 0 && gx < kp.nx && gy < kp.ny;
+    } else {
+        gx = gx < 0 ? gx + kp.nx : (gx >= kp.nx ? gx - kp.nx : gx);
+        gy = gy < 0 ? gy + kp.ny : (gy >= kp.ny ? gy - kp.ny : gy);
+    }
+    const bool wall = WALLS && exists && is_wall(kp, gx, gy);
+    const size_t idx = exists ? (size_t)gy * kp.nx + gx : 0;
+    // local coordinates of the inward neighbour (wall nodes only)
+    int fx = tx, fy = ty;
+    T phi = T(0), phi_f = T(0);
+    T h[9];
+    if (exists) {
+        phi = T(phi_t[idx]);
+        phi_f = phi;
+        if (wall) {
+            int xf = gx < 1 ? 1 : (gx > kp.nx - 2 ? kp.nx - 2 : gx);
+            int yf = gy < 1 ? 1 : (gy > kp.ny - 2 ? kp.ny - 2 : gy);
+            fx = tx + (xf - gx);
+            fy = ty + (yf - gy);
+            phi_f = T(phi_t[(size_t)yf * kp.nx + xf]);
+        }
+        flow_node<T, S, WALLS>(kp, hin, gx, gy, idx, phi_f, h);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) h[i] = T(0);
+    }
+    const T s2 = T(kp.s2u);
+    for (int sub = 0; sub < K; ++sub) {
+        T o[9];
+        flow_collide<T>(h, phi, s2, o);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) lds[i][ty][tx] = o[i];
+        __syncthreads();
+        // pull: source (x - c_i) of this node, or of the inward neighbour
+        const int px = wall ? fx : tx, py = wall ? fy : ty;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            int sx = px - C9X[i], sy = py - C9Y[i];
+            sx = sx < 0 ? 0 : (sx > EX - 1 ? EX - 1 : sx);  // stale ring: any in-tile slot
+            sy = sy < 0 ? 0 : (sy > EY - 1 ? EY - 1 : sy);
+            h[i] = lds[i][sy][sx];
+        }
+        if (WALLS && wall) {
+            // rebuild from the inward neighbour's pulled populations
+            FlowMacro<T> m = flow_macro(h, phi_f);
+            T ubx, uby, pb;
+            if (gx == 0) {
+                ubx = T(kp.uin_x_sub);
+                uby = T(kp.uin_y_sub);
+                pb = m.p;
+            } else if (gx == kp.nx - 1) {
+                ubx = m.ux;
+                uby = (gy == 0 || gy == kp.ny - 1) ? T(0) : m.uy;
+                pb = T(0);
+            } else {
+                ubx = m.ux;
+                uby = T(0);
+                pb = m.p;
+            }
+            T eb[9], ef[9];
+            eq_flow(T(0), pb, ubx, uby, eb);
+            eq_flow(T(0), m.p, m.ux, m.uy, ef);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) h[i] = eb[i] + (h[i] - ef[i]);
+        }
+        __syncthreads();
+    }
+    const bool out = tx >= K && tx < EX - K && ty >= K && ty < EY - K;
+    const int ox = bx * OX + (tx - K), oy = by * OY + (ty - K);
+    if (out && exists && !wall && ox < kp.nx && oy < kp.ny) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) st_pop(hout, i * P + idx, h[i], kp.shift[15 + i]);
+    }
+}
+
+template <class CF, bool WALLS, int EX, int EY, int K>
+__global__ __launch_bounds__(EX* EY) void k_flow_tb(const KParams kp,
+                                                    const typename CF::S* __restrict__ hin,
+                                                    typename CF::S* __restrict__ hout,
+                                                    const typename CF::H* __restrict__ phi_t, int nbx,
+                                                    int nblocks) {
+    const int t = xcd_remap(blockIdx.x, nblocks);
+    flow_tb_tile<CF, WALLS, EX, EY, K>(kp, hin, hout, phi_t, t % nbx, t / nbx);
 }
 
 // ---------------------------------------------------------------------------

@@ -164,6 +164,25 @@ def test_thermosolutal_flow_parity_ragged(dlb, precision, tol, steps):
         assert rg[key] == pytest.approx(ro[key], rel=max(tol, 1e-12) * 10, abs=1e-12), key
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32", "f16s"])
+@pytest.mark.parametrize("walls", [1, 0])
+def test_fused_flow_substeps_match_single_substeps(dlb, precision, walls):
+    """Fusing 3 or 5 flow sub-steps per launch (registers + LDS tile) does
+    the same arithmetic per node as one launch per sub-step: FP64 and FP32
+    results agree to rounding; 16-bit storage is re-rounded only once per
+    launch when fused, so there the check is the storage tolerance."""
+    _say(f"case: fused flow sub-steps {precision} walls={walls}")
+    cfg, noise = _flow_case(96, 78, precision)
+    cfg["walls"] = walls
+    runs = {}
+    for fuse in (1, 3, 5):
+        s = dlb.Solver(dict(cfg, flow_fuse=fuse)).init_seed(noise).step(30)
+        runs[fuse] = s.fields()
+    tol = {"f64": 1e-12, "f32": 2e-5, "f16s": 6e-2}[precision]
+    for fuse in (3, 5):
+        compare(runs[fuse], runs[1], tol, label=f"fuse {fuse} vs 1")
+
+
 def test_thermosolutal_full_size_first_steps(dlb):
     """At the benchmark's size and launch shape (1024^2, FP32) the first
     main steps agree with the oracle field by field."""
@@ -192,11 +211,13 @@ def test_channel_mirror_symmetry_full_size(dlb):
 # Edge cases and runtime behaviour
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("nx,ny,walls", [(16, 16, 0), (17, 19, 0), (16, 16, 1), (65, 21, 1)])
-def test_small_and_ragged_grids(dlb, nx, ny, walls):
-    _say(f"case: small grid {nx}x{ny} walls={walls} FP64")
+@pytest.mark.parametrize("nx,ny,walls,fuse", [(16, 16, 0, 1), (17, 19, 0, 3), (16, 16, 1, 1),
+                                              (16, 16, 1, 3), (65, 21, 1, 3), (40, 37, 0, 3)])
+def test_small_and_ragged_grids(dlb, nx, ny, walls, fuse):
+    _say(f"case: small grid {nx}x{ny} walls={walls} flow_fuse={fuse} FP64")
     cfg = dict(W.pure_diffusion_128("f64"), nx=nx, ny=ny, seed_x=nx / 2 - 0.3, seed_y=ny / 2 + 0.2,
-               seed_R=3.0, walls=walls, use_ns=walls, n_sub=3, nu=0.3, u_in=(0.01, 0.0))
+               seed_R=3.0, walls=walls, use_ns=1, n_sub=3, nu=0.3, u_in=(0.01 * walls, 0.0),
+               flow_fuse=fuse)
     o = O.Oracle(cfg).init_seed().step(40)
     s = dlb.Solver(cfg).init_seed().step(40)
     compare(s.fields(), o.fields(), 1e-10, label=f"{nx}x{ny}")
