@@ -177,6 +177,40 @@ int dlb_equilibria(int64_t n, const double* macros, double* out, int h_quintic);
  * bandwidth counters against a transfer of known size. */
 int dlb_copy_kernel(void* dst, const void* src, size_t bytes, void* hip_stream);
 
+/* ---------------------------------------------------------------------------
+ * Batches: many independent solvers (any grid sizes, their own physical
+ * parameters; shared precision, use_ns, bc and n_sub) stepped in lockstep,
+ * each kernel class as one persistent launch over a (seed, tile) work list.
+ * Every member evolves bit for bit as it would alone with the same
+ * flow_fuse.  The caller owns one device buffer for the whole batch.
+ * ------------------------------------------------------------------------- */
+typedef struct dlb_batch* dlb_batch_handle;
+
+/* Bytes for `count` members described by ps[0..count-1]; 0 if invalid. */
+size_t dlb_batch_state_bytes(const dlb_params* ps, int count);
+int dlb_batch_create(const dlb_params* ps, int count, void* dev_state, size_t bytes, void* hip_stream,
+                     dlb_batch_handle* out);
+int dlb_batch_destroy(dlb_batch_handle b);
+/* Borrowed handle of member i (owned by the batch; never destroy it).  It
+ * accepts every solver call except stepping and dlb_load: initialise with
+ * dlb_init_seed / dlb_set_fields, observe with dlb_get_fields / dlb_reduce /
+ * dlb_save.  NULL if i is out of range. */
+dlb_handle dlb_batch_member(dlb_batch_handle b, int i);
+/* Advance every member n >= 0 main steps (asynchronous; replays a captured
+ * two-step HIP graph for long runs). */
+int dlb_batch_step(dlb_batch_handle b, int64_t n);
+int64_t dlb_batch_step_count(dlb_batch_handle b);
+/* Launch configuration: flow sub-steps fused per launch (1, 3, 5) and the
+ * persistent grid as workgroups per compute unit for the node kernels
+ * (1..64) and the fused flow kernel (1..16). */
+int dlb_batch_set_config(dlb_batch_handle b, int fuse, int bpc_node, int bpc_tb);
+int dlb_batch_get_config(dlb_batch_handle b, int* out3);
+/* Autotuner: times trial_steps batch steps (HIP events) for each candidate
+ * launch configuration, keeps the fastest, returns its ms per step.  The
+ * trial steps consume the state: call it before initialising the members
+ * (member step counters restart at 0).  Synchronises. */
+int dlb_batch_autotune(dlb_batch_handle b, int trial_steps, double* ms_best);
+
 const char* dlb_strerror(int code);
 const char* dlb_last_error(void);
 

@@ -1,0 +1,98 @@
+// batch.h -- one launch per kernel class for many independent solvers.
+//
+// A batch holds independent seeds (grids of any size, their own physical
+// parameters) that step in lockstep.  Each kernel class runs as one
+// persistent launch: workgroup b walks the contiguous slice
+// [b*chunk, (b+1)*chunk) of a global list of (seed, tile) work items, so a
+// workgroup sweeps neighbouring tiles of one seed in turn.  Per node the
+// arithmetic is the single-solver kernels' (same device functions), so every
+// member evolves bit for bit as it would alone.
+#pragma once
+
+#include "kernels.h"
+
+namespace dlb {
+
+struct SeedDesc {
+    KParams kp;
+    void* pop[2];
+    void* flow[2];
+    void* hist;
+    int hist_valid;
+    int tile0;      // first 64x4 tile of this seed in the node-kernel work list
+    int tb0[2];     // first extended tile in the fused-flow work list, K = 3 / K = 5
+    int tb_nbx[2];  // extended tiles per row, K = 3 / K = 5
+};
+
+// seed owning work item `item`; list -1 = node tiles, 0/1 = fused tiles K = 3/5
+__device__ __forceinline__ int seed_of(const SeedDesc* __restrict__ d, int count, int item, int list) {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        int start = list < 0 ? d[mid].tile0 : d[mid].tb0[list];
+        if (start <= item) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <class CF, bool NS, bool WALLS>
+__global__ __launch_bounds__(BLOCK) void k_pct_batch(const SeedDesc* __restrict__ d, int count,
+                                                     int total, int cur, int fcur) {
+    using S = typename CF::S;
+    using H = typename CF::H;
+    const int chunk = (total + gridDim.x - 1) / gridDim.x;
+    const int beg = blockIdx.x * chunk, end = min(beg + chunk, total);
+    int s = beg < end ? seed_of(d, count, beg, -1) : 0;
+    for (int item = beg; item < end; ++item) {
+        while (s + 1 < count && d[s + 1].tile0 <= item) ++s;
+        const SeedDesc& sd = d[s];
+        const int t = item - sd.tile0;
+        const int x = (t % sd.kp.nbx) * TILE_X + (threadIdx.x & (TILE_X - 1));
+        const int y = (t / sd.kp.nbx) * TILE_Y + (threadIdx.x >> 6);
+        if (x < sd.kp.nx && y < sd.kp.ny)
+            pct_node<CF, NS, WALLS>(sd.kp, (const S*)sd.pop[cur], (S*)sd.pop[1 - cur],
+                                    (const S*)sd.flow[fcur], (H*)sd.hist, sd.hist_valid, x, y);
+    }
+}
+
+template <class CF, bool WALLS>
+__global__ __launch_bounds__(BLOCK) void k_flow_batch(const SeedDesc* __restrict__ d, int count,
+                                                      int total, int fcur) {
+    using S = typename CF::S;
+    using H = typename CF::H;
+    const int chunk = (total + gridDim.x - 1) / gridDim.x;
+    const int beg = blockIdx.x * chunk, end = min(beg + chunk, total);
+    int s = beg < end ? seed_of(d, count, beg, -1) : 0;
+    for (int item = beg; item < end; ++item) {
+        while (s + 1 < count && d[s + 1].tile0 <= item) ++s;
+        const SeedDesc& sd = d[s];
+        const int t = item - sd.tile0;
+        const int x = (t % sd.kp.nbx) * TILE_X + (threadIdx.x & (TILE_X - 1));
+        const int y = (t / sd.kp.nbx) * TILE_Y + (threadIdx.x >> 6);
+        if (x < sd.kp.nx && y < sd.kp.ny)
+            flow_step_node<CF, WALLS>(sd.kp, (const S*)sd.flow[fcur], (S*)sd.flow[1 - fcur],
+                                      (const H*)sd.hist, x, y);
+    }
+}
+
+template <class CF, bool WALLS, int EX, int EY, int K>
+__global__ __launch_bounds__(EX* EY) void k_flow_tb_batch(const SeedDesc* __restrict__ d, int count,
+                                                          int total, int fcur) {
+    using S = typename CF::S;
+    using H = typename CF::H;
+    const int chunk = (total + gridDim.x - 1) / gridDim.x;
+    const int beg = blockIdx.x * chunk, end = min(beg + chunk, total);
+    constexpr int L = K == 5 ? 1 : 0;
+    int s = beg < end ? seed_of(d, count, beg, L) : 0;
+    for (int item = beg; item < end; ++item) {
+        while (s + 1 < count && d[s + 1].tb0[L] <= item) ++s;
+        const SeedDesc& sd = d[s];
+        const int t = item - sd.tb0[L];
+        flow_tb_tile<CF, WALLS, EX, EY, K>(sd.kp, (const S*)sd.flow[fcur], (S*)sd.flow[1 - fcur],
+                                           (const H*)sd.hist, t % sd.tb_nbx[L], t / sd.tb_nbx[L]);
+        __syncthreads();  // LDS of this tile is reused by the next
+    }
+}
+
+}  // namespace dlb

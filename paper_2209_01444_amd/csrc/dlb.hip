@@ -14,7 +14,11 @@
 #include <string>
 
 #include "dlb.h"
+#include "batch.h"
 #include "kernels.h"
+
+#include <algorithm>
+#include <vector>
 
 using namespace dlb;
 
@@ -195,6 +199,12 @@ struct Ops {
     void (*tips)(const KParams&, const void*, double*, hipStream_t);
 };
 
+struct BatchOps {
+    void (*pct)(const SeedDesc*, int, int, int, int, int, hipStream_t);
+    void (*flow)(const SeedDesc*, int, int, int, int, hipStream_t);
+    void (*flow_tb)(int, const SeedDesc*, int, int, int, int, hipStream_t);
+};
+
 template <class CF, bool NS, bool W> struct OpsImpl {
     using S = typename CF::S;
     using H = typename CF::H;
@@ -245,11 +255,49 @@ template <class CF, bool NS, bool W> struct OpsImpl {
         hipLaunchKernelGGL((k_tips<CF, W>), dim3(4), dim3(448), 0, st, kp, (const S*)pop, out);
     }
     static Ops ops() { return Ops{pct, flow, flow_tb, set_fields, fields, reduce, tips}; }
+
+    // batched persistent launches
+    static void b_pct(const SeedDesc* d, int count, int total, int cur, int fcur, int blocks,
+                      hipStream_t st) {
+        hipLaunchKernelGGL((k_pct_batch<CF, NS, W>), dim3(blocks), dim3(BLOCK), 0, st, d, count, total,
+                           cur, fcur);
+    }
+    static void b_flow(const SeedDesc* d, int count, int total, int fcur, int blocks, hipStream_t st) {
+        hipLaunchKernelGGL((k_flow_batch<CF, W>), dim3(blocks), dim3(BLOCK), 0, st, d, count, total, fcur);
+    }
+    static void b_flow_tb(int K, const SeedDesc* d, int count, int total, int fcur, int blocks,
+                          hipStream_t st) {
+        using T = typename CF::T;
+        constexpr int EX = TbTile<T>::EX, EY = TbTile<T>::EY;
+        if (K == 3)
+            hipLaunchKernelGGL((k_flow_tb_batch<CF, W, EX, EY, 3>), dim3(blocks), dim3(EX * EY), 0, st, d,
+                               count, total, fcur);
+        else
+            hipLaunchKernelGGL((k_flow_tb_batch<CF, W, EX, EY, 5>), dim3(blocks), dim3(EX * EY), 0, st, d,
+                               count, total, fcur);
+    }
+    static BatchOps bops() { return BatchOps{b_pct, b_flow, b_flow_tb}; }
 };
 
 template <class CF> static Ops ops_for(bool ns, bool walls) {
     if (ns) return walls ? OpsImpl<CF, true, true>::ops() : OpsImpl<CF, true, false>::ops();
     return walls ? OpsImpl<CF, false, true>::ops() : OpsImpl<CF, false, false>::ops();
+}
+
+template <class CF> static BatchOps bops_for(bool ns, bool walls) {
+    if (ns) return walls ? OpsImpl<CF, true, true>::bops() : OpsImpl<CF, true, false>::bops();
+    return walls ? OpsImpl<CF, false, true>::bops() : OpsImpl<CF, false, false>::bops();
+}
+
+static BatchOps select_bops(const dlb_params* p) {
+    bool ns = p->use_ns != 0, walls = p->bc == DLB_BC_CHANNEL;
+    switch (p->precision) {
+        case DLB_F64: return bops_for<CfgF64>(ns, walls);
+        case DLB_F32: return bops_for<CfgF32>(ns, walls);
+        case DLB_F32M: return bops_for<CfgF32M>(ns, walls);
+        case DLB_F16S: return bops_for<CfgF16>(ns, walls);
+        default: return bops_for<CfgBF16>(ns, walls);
+    }
 }
 
 static Ops select_ops(const dlb_params* p) {
@@ -276,6 +324,7 @@ struct dlb_solver {
     int64_t step = 0;
     dim3 grid;
     int fuse = 1;                    // flow sub-steps fused per launch
+    int batched = 0;                 // member of a batch: stepped by the batch only
     hipGraphExec_t graph = nullptr;  // two main steps, valid once history is valid
     int graph_pop = -1, graph_flow = -1;
 
@@ -459,6 +508,7 @@ int dlb_init_seed(dlb_handle h, const double* noise) {
 
 int dlb_step(dlb_handle h, int64_t n) {
     if (!h || n < 0) return fail(DLB_EINVAL, "null handle or negative step count");
+    if (h->batched) return fail(DLB_EINVAL, "a batch member is stepped by dlb_batch_step only");
     int64_t done = 0;
     // the first step after (re-)initialisation runs with zero time derivatives
     while (done < n && !h->hist_valid) {
@@ -488,6 +538,7 @@ int dlb_step(dlb_handle h, int64_t n) {
 int dlb_step_timed(dlb_handle h, int64_t n, double* ms_pct, double* ms_flow, int64_t* l_pct,
                    int64_t* l_flow) {
     if (!h || n < 0) return fail(DLB_EINVAL, "null handle or negative step count");
+    if (h->batched) return fail(DLB_EINVAL, "a batch member is stepped by dlb_batch_step only");
     hipEvent_t ev[3];
     for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
     double a = 0.0, b = 0.0;
@@ -576,6 +627,7 @@ int dlb_save(dlb_handle h, void* host, size_t bytes) {
 
 int dlb_load(dlb_handle h, const void* host, size_t bytes) {
     if (!h || !host) return fail(DLB_EINVAL, "null handle or buffer");
+    if (h->batched) return fail(DLB_EINVAL, "a batch member cannot load a checkpoint");
     if (bytes < sizeof(CkptHeader)) return fail(DLB_EINVAL, "checkpoint truncated");
     CkptHeader hd;
     std::memcpy(&hd, host, sizeof hd);
@@ -628,5 +680,315 @@ int dlb_copy_kernel(void* dst, const void* src, size_t bytes, void* stream) {
     HIP_TRY(hipGetLastError());
     return DLB_OK;
 }
+
+
+// ---------------------------------------------------------------------------
+// Batches
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+struct dlb_batch {
+    int count = 0;
+    dlb_params p0;  // shared precision / flow / walls / n_sub
+    std::vector<dlb_solver*> members;
+    std::vector<SeedDesc> desc;
+    SeedDesc* d_desc = nullptr;
+    int total_tiles = 0, total_tb[2] = {0, 0};
+    hipStream_t stream = nullptr;
+    int pop_cur = 0, flow_cur = 0;
+    int64_t step = 0;
+    int fuse = 5, bpc_node = 8, bpc_tb = 2, num_cu = 256;
+    BatchOps ops;
+    hipGraphExec_t graph = nullptr;
+    int graph_pop = -1, graph_flow = -1;
+};
+
+extern "C" int dlb_batch_destroy(dlb_batch_handle b);
+
+static bool batch_compatible(const dlb_params* a, const dlb_params* b) {
+    return a->precision == b->precision && a->use_ns == b->use_ns && a->bc == b->bc &&
+           (!a->use_ns || a->n_sub == b->n_sub);
+}
+
+static int batch_layout(const dlb_params* ps, int count, std::vector<size_t>* offs, size_t* total) {
+    if (!ps || count < 1) return fail(DLB_EINVAL, "empty batch");
+    size_t off = 0;
+    for (int i = 0; i < count; ++i) {
+        int rc = check_params(&ps[i]);
+        if (rc) return rc;
+        if (!batch_compatible(&ps[0], &ps[i]))
+            return fail(DLB_EINVAL, "batch members must share precision, use_ns, bc and n_sub");
+        if (offs) offs->push_back(off);
+        off = align256(off + layout_of(&ps[i]).total);
+    }
+    off = align256(off + (size_t)count * sizeof(SeedDesc));
+    *total = off;
+    return DLB_OK;
+}
+
+static int upload_desc(dlb_batch* b) {
+    for (int i = 0; i < b->count; ++i) {
+        dlb_solver* m = b->members[i];
+        b->desc[i].hist_valid = m->hist_valid;
+    }
+    HIP_TRY(hipMemcpyAsync(b->d_desc, b->desc.data(), b->desc.size() * sizeof(SeedDesc),
+                           hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    return DLB_OK;
+}
+
+static void batch_enqueue_step(dlb_batch* b, int fuse, int bpc_node, int bpc_tb) {
+    const int bn = std::min(b->total_tiles, b->num_cu * bpc_node);
+    b->ops.pct(b->d_desc, b->count, b->total_tiles, b->pop_cur, b->flow_cur, bn, b->stream);
+    b->pop_cur ^= 1;
+    if (b->p0.use_ns) {
+        int left = b->p0.n_sub;
+        while (fuse > 1 && left >= fuse) {
+            int L = fuse == 5 ? 1 : 0;
+            int bt = std::min(b->total_tb[L], b->num_cu * bpc_tb);
+            b->ops.flow_tb(fuse, b->d_desc, b->count, b->total_tb[L], b->flow_cur, bt, b->stream);
+            b->flow_cur ^= 1;
+            left -= fuse;
+        }
+        for (; left > 0; --left) {
+            b->ops.flow(b->d_desc, b->count, b->total_tiles, b->flow_cur, bn, b->stream);
+            b->flow_cur ^= 1;
+        }
+    }
+    b->step += 1;
+}
+
+static void batch_sync_members(dlb_batch* b) {
+    for (dlb_solver* m : b->members) {
+        m->pop_cur = b->pop_cur;
+        m->flow_cur = b->flow_cur;
+        m->step = b->step;
+        m->hist_valid = 1;
+    }
+}
+
+extern "C" {
+
+size_t dlb_batch_state_bytes(const dlb_params* ps, int count) {
+    size_t total = 0;
+    if (batch_layout(ps, count, nullptr, &total) != DLB_OK) return 0;
+    return total;
+}
+
+int dlb_batch_create(const dlb_params* ps, int count, void* dev_state, size_t bytes, void* hip_stream,
+                     dlb_batch_handle* out) {
+    if (!out) return fail(DLB_EINVAL, "null output handle");
+    *out = nullptr;
+    std::vector<size_t> offs;
+    size_t total = 0;
+    int rc = batch_layout(ps, count, &offs, &total);
+    if (rc) return rc;
+    if (!dev_state || bytes < total) return fail(DLB_ENOMEM, "state buffer smaller than dlb_batch_state_bytes()");
+    if (((uintptr_t)dev_state & 255) != 0) return fail(DLB_EINVAL, "state buffer must be 256-byte aligned");
+    dlb_batch* b = new (std::nothrow) dlb_batch();
+    if (!b) return fail(DLB_ENOMEM, "host allocation failed");
+    b->count = count;
+    b->p0 = ps[0];
+    b->stream = (hipStream_t)hip_stream;
+    b->ops = select_bops(&ps[0]);
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+        b->num_cu = ncu;
+    const bool f64 = ps[0].precision == DLB_F64 || ps[0].precision == DLB_F32M;
+    const int EX = f64 ? TbTile<double>::EX : TbTile<float>::EX;
+    const int EY = f64 ? TbTile<double>::EY : TbTile<float>::EY;
+    for (int i = 0; i < count; ++i) {
+        dlb_handle m = nullptr;
+        rc = dlb_create(&ps[i], (char*)dev_state + offs[i], layout_of(&ps[i]).total, hip_stream, &m);
+        if (rc) {
+            for (dlb_solver* x : b->members) dlb_destroy(x);
+            delete b;
+            return rc;
+        }
+        m->batched = 1;
+        b->members.push_back(m);
+        SeedDesc d{};
+        d.kp = m->kp;
+        d.pop[0] = m->pop(0);
+        d.pop[1] = m->pop(1);
+        d.flow[0] = m->flow(0);
+        d.flow[1] = m->flow(1);
+        d.hist = m->hist();
+        d.tile0 = b->total_tiles;
+        b->total_tiles += m->L.nblocks;
+        const int Ks[2] = {3, 5};
+        for (int L = 0; L < 2; ++L) {
+            int OX = EX - 2 * Ks[L], OY = EY - 2 * Ks[L];
+            int nbx = (ps[i].nx + OX - 1) / OX, nby = (ps[i].ny + OY - 1) / OY;
+            d.tb0[L] = b->total_tb[L];
+            d.tb_nbx[L] = nbx;
+            b->total_tb[L] += nbx * nby;
+        }
+        b->desc.push_back(d);
+    }
+    b->d_desc = (SeedDesc*)((char*)dev_state + total - align256((size_t)count * sizeof(SeedDesc)));
+    rc = upload_desc(b);
+    if (rc) {
+        dlb_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return DLB_OK;
+}
+
+int dlb_batch_destroy(dlb_batch_handle b) {
+    if (!b) return fail(DLB_EINVAL, "null batch");
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    for (dlb_solver* m : b->members) dlb_destroy(m);
+    delete b;
+    return DLB_OK;
+}
+
+dlb_handle dlb_batch_member(dlb_batch_handle b, int i) {
+    if (!b || i < 0 || i >= b->count) {
+        fail(DLB_EINVAL, "member index out of range");
+        return nullptr;
+    }
+    return b->members[i];
+}
+
+int dlb_batch_set_config(dlb_batch_handle b, int fuse, int bpc_node, int bpc_tb) {
+    if (!b) return fail(DLB_EINVAL, "null batch");
+    if ((fuse != 1 && fuse != 3 && fuse != 5) || bpc_node < 1 || bpc_node > 64 || bpc_tb < 1 || bpc_tb > 16)
+        return fail(DLB_EINVAL, "fuse in {1,3,5}, blocks per CU in [1,64] (node) and [1,16] (fused)");
+    b->fuse = fuse;
+    b->bpc_node = bpc_node;
+    b->bpc_tb = bpc_tb;
+    if (b->graph) {
+        (void)hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    return DLB_OK;
+}
+
+int dlb_batch_get_config(dlb_batch_handle b, int* out3) {
+    if (!b || !out3) return fail(DLB_EINVAL, "null argument");
+    out3[0] = b->fuse;
+    out3[1] = b->bpc_node;
+    out3[2] = b->bpc_tb;
+    return DLB_OK;
+}
+
+int dlb_batch_step(dlb_batch_handle b, int64_t n) {
+    if (!b || n < 0) return fail(DLB_EINVAL, "null batch or negative step count");
+    if (n == 0) return DLB_OK;
+    bool any_invalid = false, changed = false;
+    for (int i = 0; i < b->count; ++i) {
+        any_invalid |= !b->members[i]->hist_valid;
+        changed |= b->desc[i].hist_valid != b->members[i]->hist_valid;
+    }
+    if (changed) {
+        int rc = upload_desc(b);
+        if (rc) return rc;
+    }
+    int64_t done = 0;
+    if (any_invalid) {  // one step with zero time derivatives where re-initialised
+        batch_enqueue_step(b, b->fuse, b->bpc_node, b->bpc_tb);
+        batch_sync_members(b);
+        ++done;
+        int rc = upload_desc(b);
+        if (rc) return rc;
+    }
+    if (n - done >= 4 && b->stream != nullptr) {
+        if (!b->graph || b->graph_pop != b->pop_cur || b->graph_flow != b->flow_cur) {
+            if (b->graph) (void)hipGraphExecDestroy(b->graph);
+            b->graph = nullptr;
+            int pc = b->pop_cur, fc = b->flow_cur;
+            int64_t st = b->step;
+            hipGraph_t g;
+            HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+            batch_enqueue_step(b, b->fuse, b->bpc_node, b->bpc_tb);
+            batch_enqueue_step(b, b->fuse, b->bpc_node, b->bpc_tb);
+            hipError_t e = hipStreamEndCapture(b->stream, &g);
+            b->pop_cur = pc;
+            b->flow_cur = fc;
+            b->step = st;
+            if (e != hipSuccess) return fail(DLB_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+            e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                b->graph = nullptr;
+                return fail(DLB_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+            }
+            b->graph_pop = pc;
+            b->graph_flow = fc;
+        }
+        while (n - done >= 2) {
+            HIP_TRY(hipGraphLaunch(b->graph, b->stream));
+            done += 2;
+            b->step += 2;
+        }
+    }
+    while (done < n) {
+        batch_enqueue_step(b, b->fuse, b->bpc_node, b->bpc_tb);
+        ++done;
+    }
+    HIP_TRY(hipGetLastError());
+    batch_sync_members(b);
+    return DLB_OK;
+}
+
+// Time `steps` batch steps of one launch configuration with HIP events.
+static int batch_time(dlb_batch* b, int fuse, int bn, int bt, int steps, float* ms) {
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    batch_enqueue_step(b, fuse, bn, bt);  // warm-up
+    (void)hipEventRecord(e0, b->stream);
+    for (int i = 0; i < steps; ++i) batch_enqueue_step(b, fuse, bn, bt);
+    (void)hipEventRecord(e1, b->stream);
+    hipError_t e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(DLB_EHIP, hipGetErrorString(e));
+    return DLB_OK;
+}
+
+int dlb_batch_autotune(dlb_batch_handle b, int trial_steps, double* ms_best) {
+    if (!b || trial_steps < 1) return fail(DLB_EINVAL, "null batch or trial_steps < 1");
+    int rc = upload_desc(b);
+    if (rc) return rc;
+    const int fuses[3] = {5, 3, 1}, bns[4] = {4, 8, 16, 32}, bts[3] = {1, 2, 4};
+    float best = 1e30f;
+    int bf = b->fuse, bn = b->bpc_node, bt = b->bpc_tb;
+    // coordinate search: fused-launch shape first, then the node-kernel grid
+    for (int f : fuses) {
+        if (b->p0.use_ns && f > b->p0.n_sub) continue;
+        for (int t : bts) {
+            if (f == 1 && t != bts[0]) continue;
+            float ms = 0.f;
+            rc = batch_time(b, f, bn, t, trial_steps, &ms);
+            if (rc) return rc;
+            if (ms < best) best = ms, bf = f, bt = t;
+        }
+    }
+    for (int n : bns) {
+        float ms = 0.f;
+        rc = batch_time(b, bf, n, bt, trial_steps, &ms);
+        if (rc) return rc;
+        if (ms < best) best = ms, bn = n;
+    }
+    rc = dlb_batch_set_config(b, bf, bn, bt);
+    if (rc) return rc;
+    // the trial steps consumed the state: members must be (re-)initialised
+    b->step = 0;
+    for (dlb_solver* m : b->members) {
+        m->hist_valid = 0;
+        m->step = 0;
+        m->pop_cur = b->pop_cur;
+        m->flow_cur = b->flow_cur;
+    }
+    if (ms_best) *ms_best = best / trial_steps;
+    return DLB_OK;
+}
+
+int64_t dlb_batch_step_count(dlb_batch_handle b) { return b ? b->step : -1; }
 
 }  // extern "C"

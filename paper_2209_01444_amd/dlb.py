@@ -39,7 +39,9 @@ EXPORTS = (
     "dlb_state_bytes", "dlb_create", "dlb_destroy", "dlb_init_seed", "dlb_set_fields", "dlb_step",
     "dlb_step_timed", "dlb_step_count", "dlb_get_fields", "dlb_reduce", "dlb_checkpoint_bytes",
     "dlb_save", "dlb_load", "dlb_sync", "dlb_equilibria", "dlb_copy_kernel", "dlb_strerror",
-    "dlb_last_error",
+    "dlb_last_error", "dlb_batch_state_bytes", "dlb_batch_create", "dlb_batch_destroy",
+    "dlb_batch_member", "dlb_batch_step", "dlb_batch_step_count", "dlb_batch_set_config",
+    "dlb_batch_get_config", "dlb_batch_autotune",
 )
 
 _lib = None
@@ -75,6 +77,15 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "dlb_copy_kernel": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp]),
         "dlb_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "dlb_last_error": (ctypes.c_char_p, []),
+        "dlb_batch_state_bytes": (ctypes.c_size_t, [P(DlbParams), ctypes.c_int]),
+        "dlb_batch_create": (ctypes.c_int, [P(DlbParams), ctypes.c_int, vp, ctypes.c_size_t, vp, P(vp)]),
+        "dlb_batch_destroy": (ctypes.c_int, [vp]),
+        "dlb_batch_member": (vp, [vp, ctypes.c_int]),
+        "dlb_batch_step": (ctypes.c_int, [vp, i64]),
+        "dlb_batch_step_count": (i64, [vp]),
+        "dlb_batch_set_config": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+        "dlb_batch_get_config": (ctypes.c_int, [vp, P(ctypes.c_int)]),
+        "dlb_batch_autotune": (ctypes.c_int, [vp, ctypes.c_int, dp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -135,7 +146,7 @@ def _host_ptr(a):
 class Solver:
     """One lattice Boltzmann simulation in caller-owned (torch) device memory."""
 
-    def __init__(self, cfg: dict, device: str = "cuda:0", stream=None):
+    def __init__(self, cfg: dict, device: str = "cuda:0", stream=None, _member_of=None, _handle=None):
         import torch
 
         self.torch = torch
@@ -146,6 +157,13 @@ class Solver:
         self.p = make_params(cfg)
         self.nx, self.ny = self.p.nx, self.p.ny
         self.device = torch.device(device)
+        if _member_of is not None:  # borrowed view of a batch member
+            self._owner = _member_of
+            self.stream = _member_of.stream
+            self.handle = ctypes.c_void_p(_handle)
+            self._borrowed = True
+            return
+        self._borrowed = False
         nbytes = self.lib.dlb_state_bytes(ctypes.byref(self.p))
         if nbytes == 0:
             raise DlbError(DLB_EINVAL, self.lib.dlb_last_error().decode())
@@ -159,6 +177,8 @@ class Solver:
 
     # -- lifecycle --------------------------------------------------------
     def close(self):
+        if getattr(self, "_borrowed", False):
+            return
         if getattr(self, "handle", None) and self.handle.value:
             self.lib.dlb_destroy(self.handle)
             self.handle = ctypes.c_void_p()
@@ -262,6 +282,75 @@ class Solver:
         buf = ctypes.create_string_buffer(blob, len(blob))
         _check(self.lib, self.lib.dlb_load(self.handle, ctypes.cast(buf, ctypes.c_void_p), len(blob)))
         return self
+
+
+class Batch:
+    """Independent solvers stepped in lockstep by one persistent launch per
+    kernel class (see dlb_batch_* in include/dlb.h)."""
+
+    def __init__(self, cfgs: list[dict], device: str = "cuda:0"):
+        import torch
+
+        self.torch = torch
+        self.lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("libdlb needs a GPU (no CPU fallback)")
+        self.cfgs = [dict(c) for c in cfgs]
+        n = len(cfgs)
+        self.params = (DlbParams * n)(*[make_params(c) for c in cfgs])
+        nbytes = self.lib.dlb_batch_state_bytes(self.params, n)
+        if nbytes == 0:
+            raise DlbError(DLB_EINVAL, self.lib.dlb_last_error().decode())
+        self.device = torch.device(device)
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.Stream(self.device)
+            self.state = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.handle = ctypes.c_void_p()
+        _check(self.lib, self.lib.dlb_batch_create(self.params, n, ctypes.c_void_p(self.state.data_ptr()),
+                                                   nbytes, ctypes.c_void_p(self.stream.cuda_stream),
+                                                   ctypes.byref(self.handle)))
+        self.members = [Solver(c, device, _member_of=self, _handle=self.lib.dlb_batch_member(self.handle, i))
+                        for i, c in enumerate(cfgs)]
+
+    @property
+    def nodes(self) -> int:
+        return sum(c["nx"] * c["ny"] for c in self.cfgs)
+
+    def step(self, n: int):
+        _check(self.lib, self.lib.dlb_batch_step(self.handle, int(n)))
+        return self
+
+    def sync(self):
+        self.stream.synchronize()
+
+    @property
+    def step_count(self) -> int:
+        return int(self.lib.dlb_batch_step_count(self.handle))
+
+    def set_config(self, fuse: int, bpc_node: int, bpc_tb: int):
+        _check(self.lib, self.lib.dlb_batch_set_config(self.handle, fuse, bpc_node, bpc_tb))
+
+    def config(self) -> tuple:
+        out = (ctypes.c_int * 3)()
+        _check(self.lib, self.lib.dlb_batch_get_config(self.handle, out))
+        return tuple(out)
+
+    def autotune(self, trial_steps: int = 20) -> float:
+        """Pick the fastest launch configuration (consumes the state)."""
+        ms = ctypes.c_double()
+        _check(self.lib, self.lib.dlb_batch_autotune(self.handle, int(trial_steps), ctypes.byref(ms)))
+        return ms.value
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            self.lib.dlb_batch_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def equilibria(macros: np.ndarray, h_quintic: int = 0) -> np.ndarray:

@@ -286,3 +286,63 @@ def test_create_rejects_small_buffer(dlb):
     h = ctypes.c_void_p()
     rc = lib.dlb_create(ctypes.byref(p), ctypes.c_void_p(buf.data_ptr()), need // 2, None, ctypes.byref(h))
     assert rc == dlb.DLB_ENOMEM
+
+
+# ---------------------------------------------------------------------------
+# Batched persistent launches
+# ---------------------------------------------------------------------------
+
+def _sweep_cfgs(precision="f32", fuse=5):
+    import math as _m
+    sizes = [(64, 64), (96, 80), (128, 128), (40, 48), (70, 33), (128, 96)]
+    rng = np.random.default_rng(9)
+    out = []
+    for i, (nx, ny) in enumerate(sizes):
+        cfg, noise = W.thermosolutal_flow(nx, ny, seed=100 + i, precision=precision,
+                                          orient=float(rng.uniform(0, _m.pi / 4)),
+                                          u0=float(rng.uniform(0, 0.02)),
+                                          delta=float(rng.uniform(0.3, 0.65)),
+                                          eps4=float(rng.uniform(0.02, 0.05)))
+        cfg.update(seed_R=6.0, flow_fuse=fuse)
+        out.append((cfg, noise))
+    return out
+
+
+@pytest.mark.parametrize("precision,fuse", [("f32", 5), ("f64", 3), ("f32", 1)])
+def test_batch_members_match_single_runs(dlb, precision, fuse):
+    """A batch of seeds of different sizes and parameters, stepped by one
+    persistent launch per kernel class, evolves every member bit for bit
+    like a single solver with the same settings."""
+    _say(f"case: batch of 6 seeds {precision} fuse={fuse} vs single runs")
+    cases = _sweep_cfgs(precision, fuse)
+    b = dlb.Batch([c for c, _ in cases])
+    for m, (_, noise) in zip(b.members, cases):
+        m.init_seed(noise)
+    b.set_config(fuse, 8, 2)
+    b.step(23)
+    assert b.step_count == 23
+    for i, (m, (cfg, noise)) in enumerate(zip(b.members, cases)):
+        s = dlb.Solver(cfg).init_seed(noise).step(23)
+        fb, fs = m.fields(), s.fields()
+        for k in FIELDS:
+            assert np.array_equal(fb[k], fs[k]), f"member {i} field {k} differs"
+        assert m.step_count == 23
+
+
+def test_batch_autotune_and_member_rules(dlb):
+    _say("case: batch autotune, member stepping refused")
+    cases = _sweep_cfgs("f32", 5)
+    b = dlb.Batch([c for c, _ in cases])
+    for m, (_, noise) in zip(b.members, cases):
+        m.init_seed(noise)
+    ms = b.autotune(3)
+    fuse, bn, bt = b.config()
+    _say(f"  tuned: fuse={fuse} node blocks/CU={bn} fused blocks/CU={bt}, {ms:.4f} ms/step")
+    assert ms > 0 and fuse in (1, 3, 5)
+    with pytest.raises(dlb.DlbError):
+        b.members[0].step(1)
+    for m, (_, noise) in zip(b.members, cases):
+        m.init_seed(noise)
+    b.step(5)
+    r = b.members[2].reduce()
+    assert r["nonfinite"] == 0
