@@ -159,6 +159,11 @@ size_t dlb_checkpoint_bytes(dlb_handle h);
 int dlb_save(dlb_handle h, void* host_buf, size_t bytes);
 int dlb_load(dlb_handle h, const void* host_buf, size_t bytes);
 
+/* Copy the whole state (device buffer and step counter) of src into dst,
+ * device to device; both solvers must have identical parameters.  Ordered
+ * on src's stream (and waits for it when the streams differ). */
+int dlb_copy_state(dlb_handle dst, dlb_handle src);
+
 int dlb_sync(dlb_handle h);
 
 /* FP64 equilibria of the four lattices evaluated on the device by the same

@@ -148,31 +148,34 @@ def forward(P, x, base=32, rnd=None):
     return y, cache
 
 
-def backward(P, cache, dy, base=32):
-    """Gradients of sum(dy * forward(P, x)) w.r.t. every parameter."""
+def backward(P, cache, dy, base=32, rnd=None):
+    """Gradients of sum(dy * forward(P, x)) w.r.t. every parameter.  `rnd`
+    (e.g. round_bf16) is applied to every stored activation gradient."""
+    r = rnd or (lambda a: a)
     G = {}
     a = cache["head.in"]
     G["head.W"] = np.einsum("nhwo,nhwc->oc", dy, a)
     G["head.b"] = dy.sum(axis=(0, 1, 2))
-    da = np.einsum("nhwo,oc->nhwc", dy, P["head.W"])
+    da = r(np.einsum("nhwo,oc->nhwc", dy, P["head.W"]))
     dskip = {}
     for i in (0, 1, 2):
         for s in "ba":
             name = f"dec{i}{s}"
-            dpre = leaky_backward(cache[name + ".out"], da)
+            dpre = r(leaky_backward(cache[name + ".out"], da))
             da, G[name + ".W"], G[name + ".b"] = conv3x3_backward(cache[name + ".in"], P[name + ".W"], dpre)
+            da = r(da)
         cu, cs = cache[f"cat{i}"]
         dskip[i] = da[..., cu:]
-        da = up2_backward(da[..., :cu])
+        da = r(up2_backward(da[..., :cu]))
     for i in (3, 2, 1, 0):
-        if i < 3:
-            da = da + dskip[i]
         for s in "ba":
             name = f"enc{i}{s}"
-            dpre = leaky_backward(cache[name + ".out"], da)
+            dpre = r(leaky_backward(cache[name + ".out"], da))
             da, G[name + ".W"], G[name + ".b"] = conv3x3_backward(cache[name + ".in"], P[name + ".W"], dpre)
+            da = r(da)
         if i > 0:
-            da = pool2_backward(da)
+            # the pooled path adds into the gradient of the level above's skip
+            da = r(dskip[i - 1] + pool2_backward(da))
     G["x"] = da
     return G
 

@@ -11,8 +11,10 @@ CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libdlb.so")
 SOURCES = [os.path.join(CSRC, "dlb.hip")]
-DEPS = SOURCES + [os.path.join(CSRC, f) for f in ("lattice.h", "kernels.h")] + [
+DEPS = SOURCES + [os.path.join(CSRC, f) for f in ("lattice.h", "kernels.h", "batch.h")] + [
     os.path.join(ROOT, "include", "dlb.h")]
+SUR_LIB = os.path.join(LIBDIR, "libsur.so")
+SUR_SOURCES = [os.path.join(CSRC, "sur.hip")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -26,16 +28,21 @@ def hipcc() -> str:
     return os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(LIBDIR, exist_ok=True)
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", tmp,
-           *SOURCES]
+def _compile(sources, lib, verbose):
+    tmp = lib + ".tmp"
+    cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", tmp, *sources]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
+
+
+def build(verbose: bool = False) -> str:
+    """Compile libdlb.so (lattice Boltzmann solver) and libsur.so (surrogate)."""
+    os.makedirs(LIBDIR, exist_ok=True)
+    _compile(SUR_SOURCES, SUR_LIB, verbose)
+    return _compile(SOURCES, LIB, verbose)
 
 
 def stale() -> bool:

@@ -645,6 +645,20 @@ int dlb_load(dlb_handle h, const void* host, size_t bytes) {
     return DLB_OK;
 }
 
+int dlb_copy_state(dlb_handle dst, dlb_handle src) {
+    if (!dst || !src) return fail(DLB_EINVAL, "null handle");
+    if (std::memcmp(&dst->p, &src->p, sizeof(dlb_params)) != 0)
+        return fail(DLB_EINVAL, "solvers have different parameters");
+    if (dst->batched) return fail(DLB_EINVAL, "cannot overwrite a batch member");
+    HIP_TRY(hipMemcpyAsync(dst->base, src->base, src->L.total, hipMemcpyDeviceToDevice, src->stream));
+    if (dst->stream != src->stream) HIP_TRY(hipStreamSynchronize(src->stream));
+    dst->step = src->step;
+    dst->pop_cur = src->pop_cur;
+    dst->flow_cur = src->flow_cur;
+    dst->hist_valid = src->hist_valid;
+    return DLB_OK;
+}
+
 int dlb_sync(dlb_handle h) {
     if (!h) return fail(DLB_EINVAL, "null handle");
     HIP_TRY(hipStreamSynchronize(h->stream));

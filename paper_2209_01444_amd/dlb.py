@@ -38,7 +38,7 @@ class DlbParams(ctypes.Structure):
 EXPORTS = (
     "dlb_state_bytes", "dlb_create", "dlb_destroy", "dlb_init_seed", "dlb_set_fields", "dlb_step",
     "dlb_step_timed", "dlb_step_count", "dlb_get_fields", "dlb_reduce", "dlb_checkpoint_bytes",
-    "dlb_save", "dlb_load", "dlb_sync", "dlb_equilibria", "dlb_copy_kernel", "dlb_strerror",
+    "dlb_save", "dlb_load", "dlb_copy_state", "dlb_sync", "dlb_equilibria", "dlb_copy_kernel", "dlb_strerror",
     "dlb_last_error", "dlb_batch_state_bytes", "dlb_batch_create", "dlb_batch_destroy",
     "dlb_batch_member", "dlb_batch_step", "dlb_batch_step_count", "dlb_batch_set_config",
     "dlb_batch_get_config", "dlb_batch_autotune",
@@ -73,6 +73,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "dlb_save": (ctypes.c_int, [vp, vp, ctypes.c_size_t]),
         "dlb_load": (ctypes.c_int, [vp, vp, ctypes.c_size_t]),
         "dlb_sync": (ctypes.c_int, [vp]),
+        "dlb_copy_state": (ctypes.c_int, [vp, vp]),
         "dlb_equilibria": (ctypes.c_int, [i64, dp, dp, ctypes.c_int]),
         "dlb_copy_kernel": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp]),
         "dlb_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -277,6 +278,11 @@ class Solver:
         buf = ctypes.create_string_buffer(n)
         _check(self.lib, self.lib.dlb_save(self.handle, ctypes.cast(buf, ctypes.c_void_p), n))
         return buf.raw
+
+    def copy_from(self, other: "Solver"):
+        """Device-to-device copy of another solver's state (same parameters)."""
+        _check(self.lib, self.lib.dlb_copy_state(self.handle, other.handle))
+        return self
 
     def load(self, blob: bytes):
         buf = ctypes.create_string_buffer(blob, len(blob))

@@ -1,0 +1,214 @@
+"""Python binding of libsur.so (include/sur.h): argument marshalling only.
+
+The surrogate's forward, backward and Adam run in the library's HIP kernels
+(bf16 matrix-core convolutions); this module allocates the caller-owned
+parameter block and workspace with torch and converts arguments.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libsur.so")
+
+LEVEL_CH = (32, 64, 128, 256)
+EXPORTS = ("sur_param_count", "sur_param_bytes", "sur_workspace_bytes", "sur_create", "sur_destroy",
+           "sur_set_params", "sur_get_params", "sur_get_grads", "sur_set_normalization", "sur_forward",
+           "sur_gradients", "sur_train_step", "sur_conv_check", "sur_mfma_check", "sur_last_error")
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python paper_2209_01444_amd/build.py`")
+    lib = ctypes.CDLL(path)
+    vp, fp, i, sz = ctypes.c_void_p, ctypes.POINTER(ctypes.c_float), ctypes.c_int, ctypes.c_size_t
+    sig = {
+        "sur_param_count": (sz, []),
+        "sur_param_bytes": (sz, []),
+        "sur_workspace_bytes": (sz, [i, i, i]),
+        "sur_create": (i, [i, i, i, vp, sz, vp, sz, vp, ctypes.POINTER(vp)]),
+        "sur_destroy": (i, [vp]),
+        "sur_set_params": (i, [vp, fp]),
+        "sur_get_params": (i, [vp, fp]),
+        "sur_get_grads": (i, [vp, fp]),
+        "sur_set_normalization": (i, [vp, fp, fp, fp]),
+        "sur_forward": (i, [vp, i, vp, vp]),
+        "sur_gradients": (i, [vp, i, vp, vp, fp]),
+        "sur_train_step": (i, [vp, i, vp, vp, ctypes.c_float, fp]),
+        "sur_conv_check": (i, [i, i, i, i, i, i, fp, fp, fp, fp]),
+        "sur_mfma_check": (i, [fp, fp, fp]),
+        "sur_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(lib, rc):
+    if rc != 0:
+        raise RuntimeError(f"sur error {rc}: {lib.sur_last_error().decode()}")
+
+
+def _fptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def layers():
+    """(name, Cin, Cin_padded, Cout) of the 3x3 layers in parameter order."""
+    out, c = [], 5
+    for lv, co in enumerate(LEVEL_CH):
+        out += [(f"enc{lv}a", c, (c + 31) // 32 * 32, co), (f"enc{lv}b", co, co, co)]
+        c = co
+    for lv in (2, 1, 0):
+        ci = c + LEVEL_CH[lv]
+        out += [(f"dec{lv}a", ci, ci, LEVEL_CH[lv]), (f"dec{lv}b", LEVEL_CH[lv], LEVEL_CH[lv], LEVEL_CH[lv])]
+        c = LEVEL_CH[lv]
+    return out
+
+
+def flatten(P: dict) -> np.ndarray:
+    """Parameter dictionary {name.W: [3,3,co,ci], name.b: [co], head.W: [5,32],
+    head.b: [5]} -> the library's flat FP32 vector (enc0a padded to 32 inputs)."""
+    parts = []
+    for name, ci, cip, co in layers():
+        W = np.zeros((3, 3, co, cip), dtype=np.float32)
+        W[..., :ci] = P[name + ".W"]
+        parts += [W.ravel(), np.asarray(P[name + ".b"], dtype=np.float32).ravel()]
+    parts += [np.asarray(P["head.W"], dtype=np.float32).ravel(), np.asarray(P["head.b"], dtype=np.float32)]
+    return np.concatenate(parts)
+
+
+def unflatten(v: np.ndarray) -> dict:
+    P, off = {}, 0
+    for name, ci, cip, co in layers():
+        n = 9 * co * cip
+        P[name + ".W"] = v[off:off + n].reshape(3, 3, co, cip)[..., :ci].astype(np.float64)
+        off += n
+        P[name + ".b"] = v[off:off + co].astype(np.float64)
+        off += co
+    P["head.W"] = v[off:off + 160].reshape(5, 32).astype(np.float64)
+    P["head.b"] = v[off + 160:off + 165].astype(np.float64)
+    return P
+
+
+class Surrogate:
+    """U-Net surrogate for batch B of H x W fields (H, W multiples of 8)."""
+
+    def __init__(self, B: int, H: int, W: int, device: str = "cuda:0", stream=None):
+        import torch
+
+        self.torch = torch
+        self.lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("libsur needs a GPU (no CPU fallback)")
+        self.B, self.H, self.W = B, H, W
+        self.device = torch.device(device)
+        pb = self.lib.sur_param_bytes()
+        wb = self.lib.sur_workspace_bytes(B, H, W)
+        if wb == 0:
+            raise ValueError("B >= 1 and H, W multiples of 8 are required")
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+            self.params = torch.zeros(pb, dtype=torch.uint8, device=self.device)
+            self.work = torch.empty(wb, dtype=torch.uint8, device=self.device)
+        self.P = self.lib.sur_param_count()
+        self.handle = ctypes.c_void_p()
+        _check(self.lib, self.lib.sur_create(B, H, W, ctypes.c_void_p(self.params.data_ptr()), pb,
+                                             ctypes.c_void_p(self.work.data_ptr()), wb,
+                                             ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self.handle)))
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            self.lib.sur_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, flat: np.ndarray):
+        flat = np.ascontiguousarray(flat, dtype=np.float32)
+        assert flat.size == self.P
+        _check(self.lib, self.lib.sur_set_params(self.handle, _fptr(flat)))
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.P, dtype=np.float32)
+        _check(self.lib, self.lib.sur_get_params(self.handle, _fptr(out)))
+        return out
+
+    def get_grads(self) -> np.ndarray:
+        out = np.empty(self.P, dtype=np.float32)
+        _check(self.lib, self.lib.sur_get_grads(self.handle, _fptr(out)))
+        return out
+
+    def set_normalization(self, mean, std, rstd):
+        m, s, r = (np.ascontiguousarray(a, dtype=np.float32) for a in (mean, std, rstd))
+        _check(self.lib, self.lib.sur_set_normalization(self.handle, _fptr(m), _fptr(s), _fptr(r)))
+
+    def _dev(self, t, dtype):
+        assert t.is_cuda and t.dtype == dtype and t.is_contiguous()
+        return ctypes.c_void_p(t.data_ptr())
+
+    def forward(self, x, out=None):
+        """x: device float32 [b,5,H,W]; out: device float64 [b,5,H,W] or None."""
+        torch = self.torch
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        _check(self.lib, self.lib.sur_forward(self.handle, x.shape[0], self._dev(x, torch.float32),
+                                              None if out is None else self._dev(out, torch.float64)))
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        return out
+
+    def gradients(self, x, y) -> float:
+        torch = self.torch
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        loss = ctypes.c_float()
+        _check(self.lib, self.lib.sur_gradients(self.handle, x.shape[0], self._dev(x, torch.float32),
+                                                self._dev(y, torch.float32), ctypes.byref(loss)))
+        return loss.value
+
+    def train_step(self, x, y, lr: float) -> float:
+        torch = self.torch
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        loss = ctypes.c_float()
+        _check(self.lib, self.lib.sur_train_step(self.handle, x.shape[0], self._dev(x, torch.float32),
+                                                 self._dev(y, torch.float32), ctypes.c_float(lr),
+                                                 ctypes.byref(loss)))
+        return loss.value
+
+
+def conv_check(op: int, X: np.ndarray, Wt: np.ndarray, dY: np.ndarray | None = None) -> np.ndarray:
+    """Run one convolution kernel (0 forward, 1 input gradient, 2 weight
+    gradient) on host arrays X [B,H,W,Cin], Wt [3,3,Cout,Cin], dY [B,H,W,Cout]."""
+    lib = load_library()
+    B, H, W, Cin = X.shape
+    Cout = Wt.shape[2]
+    x = np.ascontiguousarray(X, dtype=np.float32)
+    w = np.ascontiguousarray(Wt, dtype=np.float32)
+    dy = None if dY is None else np.ascontiguousarray(dY, dtype=np.float32)
+    shape = {0: (B, H, W, Cout), 1: (B, H, W, Cin), 2: (3, 3, Cout, Cin)}[op]
+    out = np.empty(shape, dtype=np.float32)
+    _check(lib, lib.sur_conv_check(op, B, H, W, Cin, Cout, _fptr(x), _fptr(w),
+                                   None if dy is None else _fptr(dy), _fptr(out)))
+    return out
+
+
+def mfma_check(A: np.ndarray, B: np.ndarray) -> np.ndarray:
+    lib = load_library()
+    a = np.ascontiguousarray(A, dtype=np.float32)
+    b = np.ascontiguousarray(B, dtype=np.float32)
+    d = np.empty((16, 16), dtype=np.float32)
+    _check(lib, lib.sur_mfma_check(_fptr(a), _fptr(b), _fptr(d)))
+    return d

@@ -1,0 +1,239 @@
+"""Surrogate workflow: training data from batched lattice Boltzmann runs,
+training of the U-Net with the library's own kernels, and the hybrid loop
+that alternates network jumps of K main steps with lattice Boltzmann
+segments, using the lattice Boltzmann solver as judge and fallback.
+
+    python -m paper_2209_01444_amd.surrogate --size 512 --train-seeds 16 --iters 1500
+
+Hybrid loop (per cycle): checkpoint the solver on the device; read the
+fields (phi, C, theta, ux, uy); jump: fields + network residual (or, for the
+baseline without a network, the fields unchanged); re-initialise every
+lattice at equilibrium at the jumped fields (p = 0, phi first moment from
+the central-difference gradient); run L lattice Boltzmann steps.  Judge:
+the tip velocity implied by the jump, (s_after_jump - s_before)/K, must
+agree with the one the lattice Boltzmann segment measures, (s_after_L -
+s_after_jump)/L, within `tol` (2%) on every arm; otherwise the checkpoint is
+restored and K + L plain steps run instead (fallback).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import time
+
+import numpy as np
+
+from paper_2209_01444_amd import dlb, workloads
+from paper_2209_01444_amd import sur as sur_mod
+
+FIELDS5 = ("phi", "C", "theta", "ux", "uy")
+
+
+def sweep_cases(count: int, size: int, seed: int):
+    """Seeds drawn like the batched sweep, all at size x size."""
+    rng = np.random.default_rng(seed)
+    cases = []
+    for i in range(count):
+        cfg, noise = workloads.thermosolutal_flow(
+            size, size, seed=int(rng.integers(0, 2**31 - 1)), precision="f32",
+            orient=float(rng.uniform(0.0, math.pi / 4)), u0=float(rng.uniform(0.0, 0.02)),
+            delta=float(rng.uniform(0.3, 0.65)), eps4=float(rng.uniform(0.02, 0.05)))
+        cfg["name"] = f"train_{i}"
+        cases.append((cfg, noise))
+    return cases
+
+
+def make_dataset(cases, t0: int, K: int, pairs_per_seed: int):
+    """Snapshots x(t0 + jK), j = 0..pairs_per_seed, of every member of one
+    batch; returns device tensors X (inputs) and Y (K steps later)."""
+    import torch
+
+    b = dlb.Batch([c for c, _ in cases])
+    for m, (_, noise) in zip(b.members, cases):
+        m.init_seed(noise)
+    b.step(t0)
+    snaps = [[m.fields_device(FIELDS5) for m in b.members]]
+    for _ in range(pairs_per_seed):
+        b.step(K)
+        snaps.append([m.fields_device(FIELDS5) for m in b.members])
+    torch.cuda.synchronize()
+    X = torch.stack([s for row in snaps[:-1] for s in row])
+    Y = torch.stack([s for row in snaps[1:] for s in row])
+    b.close()
+    return X, Y
+
+
+def normalization(X, Y):
+    d = Y - X
+    mean = X.mean(dim=(0, 2, 3)).cpu().numpy()
+    std = X.std(dim=(0, 2, 3)).clamp_min(1e-6).cpu().numpy()
+    rstd = d.std(dim=(0, 2, 3)).clamp_min(1e-9).cpu().numpy()
+    return mean, std, rstd
+
+
+def train(net, X, Y, iters: int, batch: int, lr: float, seed: int = 0, log_every: int = 100):
+    import torch
+
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    n = X.shape[0]
+    losses = []
+    t0 = time.perf_counter()
+    for it in range(iters):
+        idx = torch.randint(0, n, (batch,), generator=g)
+        xb = X[idx].contiguous()
+        yb = Y[idx].contiguous()
+        lr_t = lr * 0.5 * (1 + math.cos(math.pi * it / iters))  # cosine decay
+        loss = net.train_step(xb, yb, lr_t)
+        losses.append(loss)
+        if log_every and (it % log_every == 0 or it == iters - 1):
+            print(json.dumps({"iter": it, "loss": loss, "lr": lr_t}), flush=True)
+    torch.cuda.synchronize()
+    return losses, time.perf_counter() - t0
+
+
+def tips(solver) -> np.ndarray:
+    return solver.reduce(allow_nonfinite=True)["tip_s"]
+
+
+def run_plain(cfg, noise, T: int):
+    import torch
+
+    s = dlb.Solver(cfg).init_seed(noise)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(T - 100)
+    a = tips(s)
+    s.step(100)
+    b = tips(s)
+    el = time.perf_counter() - t0
+    return {"seconds": el, "tip_s": b, "tip_v": (b - a) / 100.0, "solver": s}
+
+
+def run_hybrid(cfg, noise, T: int, t_start: int, K: int, L: int, net=None, tol: float = 0.02):
+    """Hybrid time stepping to main step T (see module docstring).  net=None
+    is the baseline without a network (identity jump)."""
+    import torch
+
+    s = dlb.Solver(cfg).init_seed(noise)
+    backup = dlb.Solver(cfg)
+    H, W = cfg["ny"], cfg["nx"]
+    out = torch.empty((1, 5, H, W), dtype=torch.float64, device=s.device)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(t_start)
+    t = t_start
+    accepted, fallbacks, errs = 0, 0, []
+    while t + K + L + 100 <= T:
+        backup.copy_from(s)
+        s0 = tips(s)
+        x = s.fields_device(FIELDS5)
+        if net is not None:
+            net.forward(x[None].contiguous(), out)
+        else:
+            out.copy_(x[None].double())
+        s.set_fields(out[0, 0], out[0, 1], out[0, 2], out[0, 3], out[0, 4])
+        s1 = tips(s)
+        s.step(L)
+        s2 = tips(s)
+        v_jump, v_lb = (s1 - s0) / K, (s2 - s1) / L
+        with np.errstate(invalid="ignore", divide="ignore"):
+            err = float(np.nanmax(np.abs(v_jump / v_lb - 1))) if np.all(np.isfinite(v_lb)) else math.inf
+        if not np.isfinite(err) or not np.all(np.isfinite(v_jump)):
+            err = math.inf
+        errs.append(err)
+        if err > tol:
+            s.copy_from(backup)
+            s.step(K + L)
+            fallbacks += 1
+        else:
+            accepted += 1
+        t += K + L
+    s.step(T - 100 - t)
+    a = tips(s)
+    s.step(100)
+    b = tips(s)
+    el = time.perf_counter() - t0
+    return {"seconds": el, "tip_s": b, "tip_v": (b - a) / 100.0, "accepted": accepted,
+            "fallbacks": fallbacks, "jump_errors": errs, "solver": s}
+
+
+def compare(h, p):
+    with np.errstate(invalid="ignore", divide="ignore"):
+        return {"speedup": p["seconds"] / h["seconds"],
+                "tip_v_rel_err": float(np.nanmax(np.abs(h["tip_v"] / p["tip_v"] - 1))),
+                "tip_s_abs_err": float(np.nanmax(np.abs(h["tip_s"] - p["tip_s"]))),
+                "accepted": h["accepted"], "fallbacks": h["fallbacks"]}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--size", type=int, default=512)
+    ap.add_argument("--train-seeds", type=int, default=16)
+    ap.add_argument("--t0", type=int, default=500)
+    ap.add_argument("--pairs", type=int, default=25)
+    ap.add_argument("--K", type=int, default=100)
+    ap.add_argument("--L", type=int, default=100)
+    ap.add_argument("--iters", type=int, default=1500)
+    ap.add_argument("--batch", type=int, default=4)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--T", type=int, default=3000)
+    ap.add_argument("--tol", type=float, default=0.02)
+    ap.add_argument("--seed", type=int, default=5)
+    args = ap.parse_args()
+    import torch
+
+    n = args.size
+    cases = sweep_cases(args.train_seeds + 1, n, args.seed)
+    train_cases, test_case = cases[:-1], cases[-1]
+    t_gen = time.perf_counter()
+    X, Y = make_dataset(train_cases, args.t0, args.K, args.pairs)
+    t_gen = time.perf_counter() - t_gen
+    mean, std, rstd = normalization(X, Y)
+    print(json.dumps({"pairs": int(X.shape[0]), "gen_seconds": t_gen, "mean": mean.tolist(),
+                      "std": std.tolist(), "rstd": rstd.tolist()}), flush=True)
+
+    net = sur_mod.Surrogate(args.batch, n, n)
+    net.set_params(sur_mod.flatten(init_params(args.seed)))
+    net.set_normalization(mean, std, rstd)
+    losses, t_train = train(net, X, Y, args.iters, args.batch, args.lr, seed=args.seed)
+    # forward timing at batch 1
+    x1 = X[:1].contiguous()
+    o1 = torch.empty((1, 5, n, n), dtype=torch.float64, device="cuda")
+    net.forward(x1, o1)
+    torch.cuda.synchronize()
+    tf = time.perf_counter()
+    for _ in range(20):
+        net.forward(x1, o1)
+    torch.cuda.synchronize()
+    fwd_ms = (time.perf_counter() - tf) / 20 * 1e3
+
+    cfg, noise = test_case
+    plain = run_plain(cfg, noise, args.T)
+    hyb = run_hybrid(cfg, noise, args.T, args.t0, args.K, args.L, net, args.tol)
+    base = run_hybrid(cfg, noise, args.T, args.t0, args.K, args.L, None, args.tol)
+    res = {
+        "size": n, "train_pairs": int(X.shape[0]), "iters": args.iters, "train_seconds": t_train,
+        "loss_first": losses[0], "loss_last": float(np.mean(losses[-50:])), "forward_ms": fwd_ms,
+        "forward_TFLOPs": 85.0e9 * (n / 512) ** 2 / (fwd_ms * 1e-3) / 1e12,
+        "plain_seconds": plain["seconds"], "T": args.T, "K": args.K, "L": args.L, "tol": args.tol,
+        "with_network": compare(hyb, plain), "without_network": compare(base, plain),
+        "jump_errors_with_network": [round(e, 4) if np.isfinite(e) else None for e in hyb["jump_errors"]],
+    }
+    print(json.dumps(res), flush=True)
+
+
+def init_params(seed: int) -> dict:
+    """He-normal 3x3 weights, zero biases, small head (the residual starts near 0)."""
+    rng = np.random.default_rng(seed)
+    P = {}
+    for name, ci, cip, co in sur_mod.layers():
+        P[name + ".W"] = rng.normal(size=(3, 3, co, ci)) * np.sqrt(2.0 / (9 * ci))
+        P[name + ".b"] = np.zeros(co)
+    P["head.W"] = rng.normal(size=(5, 32)) * 0.01
+    P["head.b"] = np.zeros(5)
+    return P
+
+
+if __name__ == "__main__":
+    main()
