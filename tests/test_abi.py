@@ -11,10 +11,10 @@ from paper_2209_01444_amd import dlb, workloads as W
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def declared_symbols():
-    text = open(os.path.join(ROOT, "include", "dlb.h")).read()
+def declared_symbols(header="dlb.h", prefix="dlb"):
+    text = open(os.path.join(ROOT, "include", header)).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(dlb_[a-z0-9_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(" + prefix + r"_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -24,6 +24,32 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(dlb.EXPORTS)
+
+
+def test_surrogate_library_exports_every_declared_symbol():
+    from paper_2209_01444_amd import sur
+    lib = sur.load_library()
+    names = declared_symbols("sur.h", "sur")
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(sur.EXPORTS)
+    # host-only sizing queries
+    assert lib.sur_param_count() == len(sur.flatten(
+        {k: v for k, v in _zero_params(sur).items()}))
+    assert lib.sur_workspace_bytes(2, 30, 32) == 0  # H not a multiple of 8
+    assert lib.sur_workspace_bytes(2, 32, 32) > 0
+
+
+def _zero_params(sur):
+    import numpy as np
+    P = {}
+    for name, ci, cip, co in sur.layers():
+        P[name + ".W"] = np.zeros((3, 3, co, ci))
+        P[name + ".b"] = np.zeros(co)
+    P["head.W"] = np.zeros((5, 32))
+    P["head.b"] = np.zeros(5)
+    return P
 
 
 def test_state_bytes_and_validation():
