@@ -120,6 +120,26 @@ int dlb_init_seed(dlb_handle h, const double* noise);
 int dlb_set_fields(dlb_handle h, const double* phi, const double* C, const double* theta,
                    const double* ux, const double* uy, int on_device);
 
+/* dlb_set_fields with continuation flags, for restarting from fields that
+ * were advanced outside the lattice Boltzmann method (a learned jump):
+ *   DLB_KEEP_FLOW:  the flow lattice keeps its populations; the C and theta
+ *                   equilibria use its velocity at the new phi (ux, uy are
+ *                   ignored).
+ *   DLB_KEEP_NONEQ: the phi, C and H populations keep their non-equilibrium
+ *                   parts: each moves by the change of its equilibrium
+ *                   (Sec. 3.1-3.3) between the current and the new fields,
+ *                   and the phi first moment also by the change of its
+ *                   central-difference gradient term; at interior nodes the
+ *                   time derivatives of phi, Q, Cu and Hu carry over
+ *                   (history := new value - (current value - history)).
+ * With both flags, restarting at the state's own fields changes nothing
+ * beyond rounding.  KEEP_NONEQ uses the idle ping-pong population buffer as
+ * scratch.  Unknown flag bits: DLB_EINVAL. */
+#define DLB_KEEP_FLOW 1u
+#define DLB_KEEP_NONEQ 2u
+int dlb_set_fields_ex(dlb_handle h, const double* phi, const double* C, const double* theta,
+                      const double* ux, const double* uy, int on_device, uint32_t flags);
+
 /* Advance n >= 0 main steps (asynchronous). */
 int dlb_step(dlb_handle h, int64_t n);
 
@@ -147,9 +167,11 @@ int dlb_get_fields(dlb_handle h, uint32_t mask, void* out, int out_on_device, in
  *   the solid centroid (flow sub-step units), 7-10 tip position s_k of arm k
  *   (angle orient + k pi/2 from the seed centre), 11-14 tip radius rho_k,
  *   15-16 solid centroid.
- * Tip: phi sampled every 1 lu along the arm ray (bilinear); s is the
- * outermost sample pair phi_j > 0 >= phi_{j+1}, refined linearly; rho fits
- * s(w) = s0 - w^2/(2 rho) over rays offset sideways by w = -3..3.
+ * Tip: psi = atanh(phi) (phi clamped to |phi| <= 1 - 2^-30) sampled every
+ * 1 lu along the arm ray by bilinear interpolation of the node values of
+ * psi; s is the outermost sample pair psi_j > 0 >= psi_{j+1}, refined
+ * linearly in psi (exact for a planar tanh interface at any orientation);
+ * rho fits s(w) = s0 - w^2/(2 rho) over rays offset sideways by w = -3..3.
  * Returns DLB_ENAN when the non-finite count is positive (out still filled). */
 int dlb_reduce(dlb_handle h, double* out);
 

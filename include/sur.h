@@ -53,13 +53,19 @@ int sur_get_grads(sur_handle h, float* host);
  * the head predicts (x(t+K) - x(t))_c / rstd[c]. */
 int sur_set_normalization(sur_handle h, const float* mean5, const float* std5, const float* rstd5);
 
+/* Per-channel weights w of the training loss (default 1 each): loss = sum
+ * over samples, pixels and channels c of w_c (prediction - target)^2, divided
+ * by b H W 5.  Weights finite and >= 0, at least one positive. */
+int sur_set_loss_weights(sur_handle h, const float* w5);
+
 /* Forward pass for b <= B samples.  x: device FP32 [b][5][H][W].  out (may
  * be NULL): device FP64 [b][5][H][W] receiving x + rstd * prediction. */
 int sur_forward(sur_handle h, int b, const float* x, double* out);
 
 /* Forward + backward on (x, y = fields K steps later), both device FP32
  * [b][5][H][W]; gradients accumulate from zero; *loss (host) receives the
- * mean squared error of the normalised residual.  Synchronises. */
+ * (weighted, see sur_set_loss_weights) mean squared error of the normalised
+ * residual.  Synchronises. */
 int sur_gradients(sur_handle h, int b, const float* x, const float* y, float* loss);
 
 /* sur_gradients followed by one Adam step (beta1 0.9, beta2 0.999,

@@ -733,68 +733,149 @@ int orc_step(orc_state* s, long n) {
  * ------------------------------------------------------------------------- */
 int orc_set_fields(orc_state* s, const double* phi, const double* Cin, const double* thin,
                    const double* uxin, const double* uyin) {
+    return orc_set_fields_ex(s, phi, Cin, thin, uxin, uyin, 0u);
+}
+
+/* The first moment of the phi populations that the local gradient scheme
+ * (Sec. 3.1) maps back to a given gradient g:
+ *   sum_i c_i f_i = -g/(3 s1) - W0^2 N(g)/tau0,
+ * for g the isotropic D2Q9 central difference of the node field F,
+ *   g = (1/cs^2) sum_i w_i c_i F(x + c_i)
+ * (periodic wrap, or clamped at the channel walls). */
+static void cd_first_moment(const orc_state* s, const double* F, int x, int y, double* V) {
+    const orc_params* p = &s->p;
+    int nx = s->nx, ny = s->ny;
+    double gx = 0.0, gy = 0.0;
+    for (int i = 1; i < 9; ++i) {
+        int xx = x + C9X[i], yy = y + C9Y[i];
+        if (p->walls) {
+            xx = xx < 0 ? 0 : (xx > nx - 1 ? nx - 1 : xx);
+            yy = yy < 0 ? 0 : (yy > ny - 1 ? ny - 1 : yy);
+        } else {
+            xx = wrap(xx, nx);
+            yy = wrap(yy, ny);
+        }
+        gx += 3.0 * W9[i] * C9X[i] * F[yy * nx + xx];
+        gy += 3.0 * W9[i] * C9Y[i] * F[yy * nx + xx];
+    }
+    V[0] = V[1] = 0.0;
+    if (gx * gx + gy * gy >= GRAD_GUARD) {
+        double a, Nx, Ny;
+        aniso_or_hook(p, gx, gy, &a, &Nx, &Ny);
+        double s1 = s1_phi(p, a);
+        double W2t = p->W0 * p->W0 / p->tau0;
+        V[0] = -gx / (3.0 * s1) - W2t * Nx;
+        V[1] = -gy / (3.0 * s1) - W2t * Ny;
+    }
+}
+
+/* Melt velocity (main-step units) of the flow populations h9 at phi, as the
+ * phi/C/theta update of a main step evaluates it (Sec. 3.4). */
+static void main_step_velocity(const orc_state* s, const double* h9, double ph, double* u) {
+    double us[2], Fb[2], uu[2], pr;
+    flow_macros(h9, ph, us, Fb, uu, &pr);
+    u[0] = s->p.n_sub * uu[0];
+    u[1] = s->p.n_sub * uu[1];
+}
+
+int orc_set_fields_ex(orc_state* s, const double* phi, const double* Cin, const double* thin,
+                      const double* uxin, const double* uyin, unsigned flags) {
     const orc_params* p = &s->p;
     if (!phi) {
         set_err("phi is required");
         return -1;
     }
+    if (flags & ~(ORC_KEEP_FLOW | ORC_KEEP_NONEQ)) {
+        set_err("unknown flag");
+        return -1;
+    }
     int N = s->N, nx = s->nx, ny = s->ny;
-    double W2t = p->W0 * p->W0 / p->tau0;
+    int keep_flow = (flags & ORC_KEEP_FLOW) && p->use_ns;
+    int keep_neq = (flags & ORC_KEEP_NONEQ) != 0;
+    int carry = keep_neq && s->hist_valid;
+    /* the current fields (s->phi, C, U, H, theta, ux, uy; walls filled from
+     * the inward node), read by the continuation flags; the loop below
+     * writes populations and history only */
+    if (flags) compute_macros(s);
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             int id = y * nx + x;
             double ph = phi[id];
             /* Reading: the phi populations carry the first moment that makes
-             * the local gradient scheme reproduce grad(phi) at t = 0, taken
-             * here by the isotropic D2Q9 central difference
-             *   grad phi = (1/cs^2) sum_i w_i c_i phi(x + c_i)
-             * (periodic wrap, or clamped at the channel walls). */
-            double gx = 0.0, gy = 0.0;
-            for (int i = 1; i < 9; ++i) {
-                int xx = x + C9X[i], yy = y + C9Y[i];
-                if (p->walls) {
-                    xx = xx < 0 ? 0 : (xx > nx - 1 ? nx - 1 : xx);
-                    yy = yy < 0 ? 0 : (yy > ny - 1 ? ny - 1 : yy);
-                } else {
-                    xx = wrap(xx, nx);
-                    yy = wrap(yy, ny);
-                }
-                gx += 3.0 * W9[i] * C9X[i] * phi[yy * nx + xx];
-                gy += 3.0 * W9[i] * C9Y[i] * phi[yy * nx + xx];
-            }
-            double Vx = 0.0, Vy = 0.0;
-            if (gx * gx + gy * gy >= GRAD_GUARD) {
-                double a, Nx, Ny;
-                aniso_or_hook(p, gx, gy, &a, &Nx, &Ny);
-                double s1 = s1_phi(p, a);
-                /* invert the local scheme: sum c_i f_i = -grad/(3 s1) - W0^2 N/tau0 */
-                Vx = -gx / (3.0 * s1) - W2t * Nx;
-                Vy = -gy / (3.0 * s1) - W2t * Ny;
-            }
-            double feq[5];
+             * the local gradient scheme reproduce the central-difference
+             * gradient of phi. */
+            double V[2], feq[5];
+            cd_first_moment(s, phi, x, y, V);
             orc_eq_phi(ph, feq);
-            for (int i = 0; i < 5; ++i)
-                s->f[(size_t)i * N + id] = feq[i] + 3.0 * W5[i] * (C5X[i] * Vx + C5Y[i] * Vy);
+            if (keep_neq) {
+                /* keep f - f^eq and the part of the first moment that the
+                 * central difference does not explain */
+                double Vo[2], fo_eq[5];
+                cd_first_moment(s, s->phi, x, y, Vo);
+                orc_eq_phi(s->phi[id], fo_eq);
+                for (int i = 0; i < 5; ++i)
+                    s->f[(size_t)i * N + id] += (feq[i] - fo_eq[i]) +
+                                                3.0 * W5[i] * (C5X[i] * (V[0] - Vo[0]) + C5Y[i] * (V[1] - Vo[1]));
+            } else {
+                for (int i = 0; i < 5; ++i)
+                    s->f[(size_t)i * N + id] = feq[i] + 3.0 * W5[i] * (C5X[i] * V[0] + C5Y[i] * V[1]);
+            }
 
             double C;
             if (Cin) C = Cin[id];
             else if (p->c_init_U) C = 0.5 * (1.0 + p->k - (1.0 - p->k) * ph) * (1.0 + (1.0 - p->k) * p->U0);
             else C = p->C0;
             double th = thin ? thin[id] : p->theta0;
-            double ux = uxin ? uxin[id] : p->u_in_x;
-            double uy = uyin ? uyin[id] : p->u_in_y;
-            if (!p->use_ns) ux = uy = 0.0;
+            double u[2] = {uxin ? uxin[id] : p->u_in_x, uyin ? uyin[id] : p->u_in_y};
+            double h9[9];
+            for (int i = 0; i < 9; ++i) h9[i] = s->h[(size_t)i * N + id];
+            if (!p->use_ns) u[0] = u[1] = 0.0;
+            if (keep_flow) main_step_velocity(s, h9, ph, u);
             double U = (2.0 * C / (1.0 + p->k - (1.0 - p->k) * ph) - 1.0) / (1.0 - p->k);
-            double e5[5];
-            orc_eq_solute(C, ph, U, ux, uy, e5);
-            for (int i = 0; i < 5; ++i) s->n[(size_t)i * N + id] = e5[i];
-            orc_eq_heat(th, ph, p->h_quintic, ux, uy, e5);
-            for (int i = 0; i < 5; ++i) s->g[(size_t)i * N + id] = e5[i];
-            double e9[9];
-            orc_eq_flow(p->rho0, 0.0, ux / p->n_sub, uy / p->n_sub, e9);
-            for (int i = 0; i < 9; ++i) s->h[(size_t)i * N + id] = e9[i];
+            double e5[5], o5[5];
+            orc_eq_solute(C, ph, U, u[0], u[1], e5);
+            if (keep_neq) {
+                /* keep n - n^eq (Sec. 3.2) */
+                orc_eq_solute(s->C[id], s->phi[id], s->U[id], s->ux[id], s->uy[id], o5);
+                for (int i = 0; i < 5; ++i) s->n[(size_t)i * N + id] += e5[i] - o5[i];
+            } else {
+                for (int i = 0; i < 5; ++i) s->n[(size_t)i * N + id] = e5[i];
+            }
+            orc_eq_heat(th, ph, p->h_quintic, u[0], u[1], e5);
+            if (keep_neq) {
+                /* keep g - g^eq (Sec. 3.3) */
+                orc_eq_heat(s->theta[id], s->phi[id], p->h_quintic, s->ux[id], s->uy[id], o5);
+                for (int i = 0; i < 5; ++i) s->g[(size_t)i * N + id] += e5[i] - o5[i];
+            } else {
+                for (int i = 0; i < 5; ++i) s->g[(size_t)i * N + id] = e5[i];
+            }
+            double su[2] = {u[0], u[1]}; /* the velocity the next step evaluates */
+            if (p->use_ns && !keep_flow) {
+                double e9[9];
+                orc_eq_flow(p->rho0, 0.0, u[0] / p->n_sub, u[1] / p->n_sub, e9);
+                for (int i = 0; i < 9; ++i) s->h[(size_t)i * N + id] = e9[i];
+                main_step_velocity(s, e9, ph, su);
+            }
+            /* time derivatives carry over at interior nodes:
+             * history := new value - (current value - history) */
+            int wall = p->walls && (x == 0 || y == 0 || x == nx - 1 || y == ny - 1);
+            if (carry && !wall) {
+                double pho = s->phi[id], omo = 1.0 - pho * pho;
+                double Qo = pho * omo - p->lambda * (s->theta[id] + p->Mcinf * s->U[id]) * omo * omo;
+                double om = 1.0 - ph * ph;
+                double Q = ph * om - p->lambda * (th + p->Mcinf * U) * om * om;
+                double H = th - 0.5 * h_of(ph, p->h_quintic);
+                s->phi_prev[id] = ph - (pho - s->phi_prev[id]);
+                s->Q_prev[id] = Q - (Qo - s->Q_prev[id]);
+                if (p->use_ns) {
+                    s->Cu_prev[id] = C * su[0] - (s->C[id] * s->ux[id] - s->Cu_prev[id]);
+                    s->Cu_prev[N + id] = C * su[1] - (s->C[id] * s->uy[id] - s->Cu_prev[N + id]);
+                    s->Hu_prev[id] = H * su[0] - (s->H[id] * s->ux[id] - s->Hu_prev[id]);
+                    s->Hu_prev[N + id] = H * su[1] - (s->H[id] * s->uy[id] - s->Hu_prev[N + id]);
+                }
+            }
         }
-    s->hist_valid = 0;
+    if (!keep_neq) s->hist_valid = 0;
     return 0;
 }
 
@@ -855,8 +936,19 @@ int orc_get_pops(orc_state* s, int lattice, double* out) {
     return -1;
 }
 
-/* Bilinear sample of a node field; NaN outside [0,nx-1] x [0,ny-1]. */
-static double bilinear(const orc_state* s, const double* F, double x, double y) {
+/* psi = atanh(phi), phi clamped to |phi| <= 1 - 2^-30.  Across a diffuse
+ * interface of the model's tanh profile phi = tanh(d / (sqrt(2) W)), psi is
+ * linear in the distance d, whatever the width and the direction. */
+static double psi_of(double phi) {
+    const double c = 1.0 - 1.0 / 1073741824.0;
+    if (phi > c) phi = c;
+    if (phi < -c) phi = -c;
+    return atanh(phi);
+}
+
+/* Bilinear sample of psi from the four surrounding nodes; NaN outside
+ * [0,nx-1] x [0,ny-1]. */
+static double bilinear_psi(const orc_state* s, const double* F, double x, double y) {
     if (!(x >= 0.0 && y >= 0.0 && x <= s->nx - 1 && y <= s->ny - 1)) return NAN;
     int i0 = (int)floor(x), j0 = (int)floor(y);
     if (i0 > s->nx - 2) i0 = s->nx - 2;
@@ -864,17 +956,20 @@ static double bilinear(const orc_state* s, const double* F, double x, double y) 
     double fx = x - i0, fy = y - j0;
     const double* r0 = F + (size_t)j0 * s->nx;
     const double* r1 = r0 + s->nx;
-    return (1.0 - fx) * (1.0 - fy) * r0[i0] + fx * (1.0 - fy) * r0[i0 + 1] + (1.0 - fx) * fy * r1[i0] +
-           fx * fy * r1[i0 + 1];
+    return (1.0 - fx) * (1.0 - fy) * psi_of(r0[i0]) + fx * (1.0 - fy) * psi_of(r0[i0 + 1]) +
+           (1.0 - fx) * fy * psi_of(r1[i0]) + fx * fy * psi_of(r1[i0 + 1]);
 }
 
 /* Reading of the tip measurement (the paper's tip plots are not recoverable):
- * arm k points along angle orient + k pi/2 from the seed centre.  phi is
- * sampled every 1 lu along the ray (bilinear); the tip is the outermost
- * sample pair with phi_j > 0 >= phi_{j+1}, refined linearly:
- *   s = j + phi_j / (phi_j - phi_{j+1}).
- * The tip radius fits s(w) = s0 - w^2/(2 rho) by least squares over rays
- * shifted sideways by w = -3..3. */
+ * arm k points along angle orient + k pi/2 from the seed centre.  psi =
+ * atanh(phi) is sampled every 1 lu along the ray (bilinear in psi); the tip
+ * is the outermost sample pair with psi_j > 0 >= psi_{j+1}, refined
+ * linearly in psi:
+ *   s = j + psi_j / (psi_j - psi_{j+1}),
+ * which is exact for a planar tanh interface of any width and orientation
+ * (interpolating phi itself would add a sub-lattice error that oscillates as
+ * the tip crosses nodes).  The tip radius fits s(w) = s0 - w^2/(2 rho) by
+ * least squares over rays shifted sideways by w = -3..3. */
 static double ray_crossing(const orc_state* s, int k, double w) {
     const orc_params* p = &s->p;
     double th = p->orient + k * (M_PI / 2.0);
@@ -883,7 +978,7 @@ static double ray_crossing(const orc_state* s, int k, double w) {
     double prev = NAN;
     for (int j = 0;; ++j) {
         double x = p->seed_x + j * dx + w * ex, y = p->seed_y + j * dy + w * ey;
-        double v = bilinear(s, s->phi, x, y);
+        double v = bilinear_psi(s, s->phi, x, y);
         if (isnan(v)) break;
         if (j > 0 && prev > 0.0 && v <= 0.0) best = (j - 1) + prev / (prev - v);
         prev = v;

@@ -74,6 +74,21 @@ int orc_init_seed(orc_state* s, const double* noise);
 int orc_set_fields(orc_state* s, const double* phi, const double* C,
                    const double* theta, const double* ux, const double* uy);
 
+/* orc_set_fields with continuation flags, for restarting from fields that
+ * were advanced outside the lattice Boltzmann method:
+ *   ORC_KEEP_FLOW:  the flow lattice keeps its populations; the C and theta
+ *                   equilibria use the velocity of the current flow state
+ *                   (ux, uy ignored).
+ *   ORC_KEEP_NONEQ: the solute and heat lattices keep their non-equilibrium
+ *                   parts: each population moves by the change of its
+ *                   equilibrium between the current and the new fields.
+ * The phi lattice and the history are set as by orc_set_fields. */
+#define ORC_KEEP_FLOW 1u
+#define ORC_KEEP_NONEQ 2u
+int orc_set_fields_ex(orc_state* s, const double* phi, const double* C,
+                      const double* theta, const double* ux, const double* uy,
+                      unsigned flags);
+
 int  orc_step(orc_state* s, long nsteps);
 long orc_step_count(const orc_state* s);
 

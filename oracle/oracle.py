@@ -65,6 +65,7 @@ def load():
     lib.orc_last_error.restype = ctypes.c_char_p
     lib.orc_init_seed.argtypes = [vp, dp]
     lib.orc_set_fields.argtypes = [vp, dp, dp, dp, dp, dp]
+    lib.orc_set_fields_ex.argtypes = [vp, dp, dp, dp, dp, dp, ctypes.c_uint]
     lib.orc_step.argtypes = [vp, ctypes.c_long]
     lib.orc_step_count.restype = ctypes.c_long
     lib.orc_step_count.argtypes = [vp]
@@ -165,9 +166,12 @@ class Oracle:
             raise RuntimeError(self.lib.orc_last_error().decode())
         return self
 
-    def set_fields(self, phi, C=None, theta=None, ux=None, uy=None):
+    def set_fields(self, phi, C=None, theta=None, ux=None, uy=None, keep_flow=False,
+                   keep_noneq=False):
+        """orc_set_fields / orc_set_fields_ex (continuation flags)."""
         arrs = [self._plane(a) for a in (phi, C, theta, ux, uy)]
-        rc = self.lib.orc_set_fields(self.h, *[_dptr(a) for a in arrs])
+        flags = (1 if keep_flow else 0) | (2 if keep_noneq else 0)
+        rc = self.lib.orc_set_fields_ex(self.h, *[_dptr(a) for a in arrs], flags)
         if rc:
             raise RuntimeError(self.lib.orc_last_error().decode())
         return self

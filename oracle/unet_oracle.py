@@ -180,10 +180,12 @@ def backward(P, cache, dy, base=32, rnd=None):
     return G
 
 
-def mse(pred, target):
-    """Mean squared error and its gradient w.r.t. pred."""
+def mse(pred, target, weights=None):
+    """Mean squared error and its gradient w.r.t. pred; optional per-channel
+    (last axis) weights w: mean of w_c d^2 over all elements."""
     d = pred - target
-    return float(np.mean(d * d)), 2.0 * d / d.size
+    w = np.ones(d.shape[-1]) if weights is None else np.asarray(weights, dtype=np.float64)
+    return float(np.mean(w * d * d)), 2.0 * w * d / d.size
 
 
 def adam(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):

@@ -193,7 +193,9 @@ struct Ops {
     void (*flow)(const KParams&, const void*, void*, const void*, hipStream_t, dim3);
     // K fused sub-steps (K in {3, 5}); returns false if K is not built
     bool (*flow_tb)(int, const KParams&, const void*, void*, const void*, hipStream_t);
-    void (*set_fields)(const KParams&, const InitFields&, void*, void*, hipStream_t, dim3);
+    void (*set_fields)(const KParams&, const InitFields&, void*, void*, void*, hipStream_t, dim3);
+    void (*restart_prep)(const KParams&, const void*, const void*, void*, double*, int, hipStream_t,
+                         dim3);
     void (*fields)(const KParams&, const void*, const void*, uint32_t, void*, int, hipStream_t, dim3);
     void (*reduce)(const KParams&, const void*, const void*, double*, hipStream_t, dim3);
     void (*tips)(const KParams&, const void*, double*, hipStream_t);
@@ -236,10 +238,15 @@ template <class CF, bool NS, bool W> struct OpsImpl {
         }
         return false;
     }
-    static void set_fields(const KParams& kp, const InitFields& in, void* pop, void* flow,
+    static void set_fields(const KParams& kp, const InitFields& in, void* pop, void* flow, void* hist,
                            hipStream_t st, dim3 grid) {
         hipLaunchKernelGGL((k_set_fields<CF, NS, W>), grid, dim3(BLOCK), 0, st, kp, in, (S*)pop,
-                           (S*)flow);
+                           (S*)flow, (H*)hist);
+    }
+    static void restart_prep(const KParams& kp, const void* pop, const void* flow, void* hist,
+                             double* phi_old, int hv, hipStream_t st, dim3 grid) {
+        hipLaunchKernelGGL((k_restart_prep<CF, NS, W>), grid, dim3(BLOCK), 0, st, kp, (const S*)pop,
+                           (const S*)flow, (H*)hist, phi_old, hv);
     }
     static void fields(const KParams& kp, const void* pop, const void* flow, uint32_t mask, void* out,
                        int f32, hipStream_t st, dim3 grid) {
@@ -254,7 +261,7 @@ template <class CF, bool NS, bool W> struct OpsImpl {
     static void tips(const KParams& kp, const void* pop, double* out, hipStream_t st) {
         hipLaunchKernelGGL((k_tips<CF, W>), dim3(4), dim3(448), 0, st, kp, (const S*)pop, out);
     }
-    static Ops ops() { return Ops{pct, flow, flow_tb, set_fields, fields, reduce, tips}; }
+    static Ops ops() { return Ops{pct, flow, flow_tb, set_fields, restart_prep, fields, reduce, tips}; }
 
     // batched persistent launches
     static void b_pct(const SeedDesc* d, int count, int total, int cur, int fcur, int blocks,
@@ -450,19 +457,35 @@ int dlb_destroy(dlb_handle h) {
 }
 
 static int set_fields_device(dlb_handle h, const double* phi, const double* C, const double* th,
-                             const double* ux, const double* uy) {
+                             const double* ux, const double* uy, unsigned flags = 0u) {
+    const bool keep_neq = (flags & DLB_KEEP_NONEQ) != 0;
+    // phi of the current state goes to the idle ping-pong population buffer
+    // (at least 15 planes of 2-byte values per node, room for one double),
+    // which the next step overwrites
+    double* phi_old = keep_neq ? (double*)h->pop(1 - h->pop_cur) : nullptr;
+    int hv = keep_neq ? h->hist_valid : 0;
+    if (keep_neq)
+        h->ops.restart_prep(h->kp, h->pop(h->pop_cur), h->flow(h->flow_cur), h->hist(), phi_old, hv,
+                            h->stream, h->grid);
     InitFields in{phi, C, th, ux, uy, h->p.C0, h->p.U0, h->p.theta0, h->p.u_in_x, h->p.u_in_y,
-                  h->p.c_init_U, h->p.use_ns};
-    h->ops.set_fields(h->kp, in, h->pop(h->pop_cur), h->flow(h->flow_cur), h->stream, h->grid);
+                  h->p.c_init_U, h->p.use_ns, flags, hv, phi_old};
+    h->ops.set_fields(h->kp, in, h->pop(h->pop_cur), h->flow(h->flow_cur), h->hist(), h->stream,
+                      h->grid);
     HIP_TRY(hipGetLastError());
-    h->hist_valid = 0;
+    h->hist_valid = hv;
     return DLB_OK;
 }
 
 int dlb_set_fields(dlb_handle h, const double* phi, const double* C, const double* theta,
                    const double* ux, const double* uy, int on_device) {
+    return dlb_set_fields_ex(h, phi, C, theta, ux, uy, on_device, 0u);
+}
+
+int dlb_set_fields_ex(dlb_handle h, const double* phi, const double* C, const double* theta,
+                      const double* ux, const double* uy, int on_device, uint32_t flags) {
     if (!h || !phi) return fail(DLB_EINVAL, "null handle or phi");
-    if (on_device) return set_fields_device(h, phi, C, theta, ux, uy);
+    if (flags & ~(uint32_t)(DLB_KEEP_FLOW | DLB_KEEP_NONEQ)) return fail(DLB_EINVAL, "unknown flag");
+    if (on_device) return set_fields_device(h, phi, C, theta, ux, uy, flags);
     size_t N = (size_t)h->p.nx * h->p.ny;
     const double* src[5] = {phi, C, theta, ux, uy};
     double* tmp = nullptr;
@@ -476,7 +499,7 @@ int dlb_set_fields(dlb_handle h, const double* phi, const double* C, const doubl
         if (e != hipSuccess) rc = fail(DLB_EHIP, hipGetErrorString(e));
         dev[i] = tmp + i * N;
     }
-    if (rc == DLB_OK) rc = set_fields_device(h, dev[0], dev[1], dev[2], dev[3], dev[4]);
+    if (rc == DLB_OK) rc = set_fields_device(h, dev[0], dev[1], dev[2], dev[3], dev[4], flags);
     hipError_t e = hipStreamSynchronize(h->stream);
     (void)hipFree(tmp);
     if (rc == DLB_OK && e != hipSuccess) rc = fail(DLB_EHIP, hipGetErrorString(e));

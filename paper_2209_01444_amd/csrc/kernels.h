@@ -413,19 +413,20 @@ struct InitFields {
     const double *phi, *C, *theta, *ux, *uy;  // device, nullable except phi
     double C0, U0, theta0, uin_x, uin_y;
     int c_init_U, use_ns;
+    unsigned flags;          // DLB_KEEP_FLOW (1) | DLB_KEEP_NONEQ (2)
+    int hist_valid;          // KEEP_NONEQ: hist holds rates (see k_restart_prep)
+    const double* phi_old;   // KEEP_NONEQ: phi of the current state (k_restart_prep)
 };
 
-template <class CF, bool NS, bool WALLS>
-__global__ __launch_bounds__(BLOCK) void k_set_fields(const KParams kp, const InitFields in,
-                                                      typename CF::S* __restrict__ pop,
-                                                      typename CF::S* __restrict__ flow) {
-    int x, y;
-    if (!node_of_thread(kp, x, y)) return;
-    const size_t P = (size_t)kp.plane;
-    const size_t idx = (size_t)y * kp.nx + x;
-    const double phi = in.phi[idx];
-    // isotropic D2Q9 central difference: grad phi = 3 sum_i w_i c_i phi(x + c_i)
-    double gx = 0.0, gy = 0.0;
+constexpr unsigned KEEP_FLOW = 1u, KEEP_NONEQ = 2u;
+
+// Isotropic D2Q9 central difference of a node field F: grad = 3 sum_i w_i c_i
+// F(x + c_i), wrapped (periodic) or clamped at the channel walls.
+template <bool WALLS>
+__device__ __forceinline__ void cd_gradient(const KParams& kp, const double* __restrict__ F, int x,
+                                            int y, double& gx, double& gy) {
+    gx = 0.0;
+    gy = 0.0;
     for (int i = 1; i < 9; ++i) {
         int xx = x + C9X[i], yy = y + C9Y[i];
         if (WALLS) {
@@ -436,12 +437,18 @@ __global__ __launch_bounds__(BLOCK) void k_set_fields(const KParams kp, const In
             yy = yy < 0 ? yy + kp.ny : (yy >= kp.ny ? yy - kp.ny : yy);
         }
         double w = i < 5 ? 1.0 / 9.0 : 1.0 / 36.0;
-        double v = in.phi[(size_t)yy * kp.nx + xx];
+        double v = F[(size_t)yy * kp.nx + xx];
         gx += 3.0 * w * C9X[i] * v;
         gy += 3.0 * w * C9Y[i] * v;
     }
-    // first moment that the local scheme maps back to (gx, gy)
-    double Vx = 0.0, Vy = 0.0;
+}
+
+// First moment of the phi populations that the local gradient scheme
+// (Sec. 3.1) maps back to the gradient (gx, gy).
+__device__ __forceinline__ void phi_first_moment(const KParams& kp, double gx, double gy, double& Vx,
+                                                 double& Vy) {
+    Vx = 0.0;
+    Vy = 0.0;
     if (gx * gx + gy * gy >= GRAD_GUARD) {
         double a, Nx, Ny;
         anisotropy<double>(kp, gx, gy, a, Nx, Ny);
@@ -449,7 +456,88 @@ __global__ __launch_bounds__(BLOCK) void k_set_fields(const KParams kp, const In
         Vx = -gx / (3.0 * s1) - kp.W2t * Nx;
         Vy = -gy / (3.0 * s1) - kp.W2t * Ny;
     }
-    double k = kp.k;
+}
+
+// Melt velocity in main-step units from the flow populations h at phi, as a
+// main step evaluates it: N_sub (3 - phi)/4 u*.
+__device__ __forceinline__ void step_velocity(const KParams& kp, const double* h, double phi,
+                                              double& ux, double& uy) {
+    double d57 = h[5] - h[7], d68 = h[6] - h[8];
+    double mx = (h[1] - h[3]) + (d57 - d68);
+    double my = (h[2] - h[4]) + (d57 + d68);
+    double fac = kp.nsub_d * (3.0 - phi) * 0.25;
+    ux = mx * fac;
+    uy = my * fac;
+}
+
+// Restart with KEEP_NONEQ, pass 1 (reads the state, writes no population):
+// phi of every node (walls rebuilt from the inward node) into phi_old, and,
+// with a valid history, the time-derivative numerators value - history of
+// phi, Q, Cu, Hu into the history planes at interior nodes.
+template <class CF, bool NS, bool WALLS>
+__global__ __launch_bounds__(BLOCK) void k_restart_prep(const KParams kp,
+                                                        const typename CF::S* __restrict__ pop,
+                                                        const typename CF::S* __restrict__ flow,
+                                                        typename CF::H* __restrict__ hist,
+                                                        double* __restrict__ phi_old, int hist_valid) {
+    using HT = typename CF::H;
+    int x, y;
+    if (!node_of_thread(kp, x, y)) return;
+    const size_t P = (size_t)kp.plane;
+    const size_t idx = (size_t)y * kp.nx + x;
+    const bool wall = WALLS && is_wall(kp, x, y);
+    const size_t src = wall ? inward_idx(kp, x, y) : idx;
+    double phi = 0.0, C = 0.0, H = 0.0;
+    for (int i = 0; i < 5; ++i) {
+        phi += ld_pop<double>(pop, i * P + src, kp.shift[i]);
+        C += ld_pop<double>(pop, (5 + i) * P + src, kp.shift[5 + i]);
+        H += ld_pop<double>(pop, (10 + i) * P + src, kp.shift[10 + i]);
+    }
+    phi_old[idx] = phi;
+    if (!hist_valid || wall) return;
+    const double k = kp.k;
+    const double U = (2.0 * C / (1.0 + k - (1.0 - k) * phi) - 1.0) / (1.0 - k);
+    const double theta = H + 0.5 * h_of(phi, kp.h_quintic);
+    const double om = 1.0 - phi * phi;
+    const double Q = phi * om - kp.lambda * (theta + kp.Mcinf * U) * om * om;
+    hist[idx] = HT(phi - (double)hist[idx]);
+    hist[P + idx] = HT(Q - (double)hist[P + idx]);
+    if constexpr (NS) {
+        double h[9], ux, uy;
+        for (int i = 0; i < 9; ++i) h[i] = ld_pop<double>(flow, i * P + idx, kp.shift[15 + i]);
+        step_velocity(kp, h, phi, ux, uy);
+        hist[2 * P + idx] = HT(C * ux - (double)hist[2 * P + idx]);
+        hist[3 * P + idx] = HT(C * uy - (double)hist[3 * P + idx]);
+        hist[4 * P + idx] = HT(H * ux - (double)hist[4 * P + idx]);
+        hist[5 * P + idx] = HT(H * uy - (double)hist[5 * P + idx]);
+    }
+}
+
+// (Re-)initialisation at given fields.  Default: every lattice at its
+// equilibrium (Sec. 3.1-3.4, p = 0), the phi populations carrying the first
+// moment of the central-difference gradient.  KEEP_FLOW: the flow lattice is
+// left as it is and its velocity (at the new phi) enters the C and theta
+// equilibria.  KEEP_NONEQ: the phi, C and H populations keep their
+// non-equilibrium parts (each moves by the change of its equilibrium, and the
+// phi first moment by the change of the central-difference term), and the
+// time derivatives carry over at interior nodes.
+template <class CF, bool NS, bool WALLS>
+__global__ __launch_bounds__(BLOCK) void k_set_fields(const KParams kp, const InitFields in,
+                                                      typename CF::S* __restrict__ pop,
+                                                      typename CF::S* __restrict__ flow,
+                                                      typename CF::H* __restrict__ hist) {
+    using HT = typename CF::H;
+    int x, y;
+    if (!node_of_thread(kp, x, y)) return;
+    const size_t P = (size_t)kp.plane;
+    const size_t idx = (size_t)y * kp.nx + x;
+    const bool keep_flow = NS && (in.flags & KEEP_FLOW);
+    const bool keep_neq = (in.flags & KEEP_NONEQ) != 0;
+    const double phi = in.phi[idx];
+    double gx, gy, Vx, Vy;
+    cd_gradient<WALLS>(kp, in.phi, x, y, gx, gy);
+    phi_first_moment(kp, gx, gy, Vx, Vy);
+    const double k = kp.k;
     double C = in.C ? in.C[idx]
                     : (in.c_init_U ? 0.5 * (1.0 + k - (1.0 - k) * phi) * (1.0 + (1.0 - k) * in.U0)
                                    : in.C0);
@@ -457,19 +545,83 @@ __global__ __launch_bounds__(BLOCK) void k_set_fields(const KParams kp, const In
     double ux = in.ux ? in.ux[idx] : in.uin_x;
     double uy = in.uy ? in.uy[idx] : in.uin_y;
     if (!NS) ux = uy = 0.0;
-    double U = (2.0 * C / (1.0 + k - (1.0 - k) * phi) - 1.0) / (1.0 - k);
-    double e[9];
-    eq_phi<double>(phi, e);
-    const double w5[5] = {1.0 / 3.0, 1.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0};
-    for (int i = 0; i < 5; ++i)
-        st_pop(pop, i * P + idx, e[i] + 3.0 * w5[i] * (C5X[i] * Vx + C5Y[i] * Vy), kp.shift[i]);
-    eq_solute<double>(C, phi, U, ux, uy, e);
-    for (int i = 0; i < 5; ++i) st_pop(pop, (5 + i) * P + idx, e[i], kp.shift[5 + i]);
-    eq_heat<double>(th, phi, kp.h_quintic, ux, uy, e);
-    for (int i = 0; i < 5; ++i) st_pop(pop, (10 + i) * P + idx, e[i], kp.shift[10 + i]);
+    double hflow[9];
     if constexpr (NS) {
-        eq_flow<double>(0.0, 0.0, ux / kp.nsub_d, uy / kp.nsub_d, e);
-        for (int i = 0; i < 9; ++i) st_pop(flow, i * P + idx, e[i], kp.shift[15 + i]);
+        if (keep_flow || keep_neq)
+            for (int i = 0; i < 9; ++i) hflow[i] = ld_pop<double>(flow, i * P + idx, kp.shift[15 + i]);
+        if (keep_flow) step_velocity(kp, hflow, phi, ux, uy);
+    }
+    const double U = (2.0 * C / (1.0 + k - (1.0 - k) * phi) - 1.0) / (1.0 - k);
+
+    // the current state at this node (KEEP_NONEQ)
+    double fo[5], no[5], go[5], phio = 0.0, Co = 0.0, Ho = 0.0, uox = 0.0, uoy = 0.0;
+    double dVx = 0.0, dVy = 0.0;
+    if (keep_neq) {
+        for (int i = 0; i < 5; ++i) {
+            fo[i] = ld_pop<double>(pop, i * P + idx, kp.shift[i]);
+            no[i] = ld_pop<double>(pop, (5 + i) * P + idx, kp.shift[5 + i]);
+            go[i] = ld_pop<double>(pop, (10 + i) * P + idx, kp.shift[10 + i]);
+            phio += fo[i];
+            Co += no[i];
+            Ho += go[i];
+        }
+        if constexpr (NS) step_velocity(kp, hflow, phio, uox, uoy);
+        double gox, goy, Vox, Voy;
+        cd_gradient<WALLS>(kp, in.phi_old, x, y, gox, goy);
+        phi_first_moment(kp, gox, goy, Vox, Voy);
+        dVx = Vx - Vox;
+        dVy = Vy - Voy;
+    }
+
+    const double w5[5] = {1.0 / 3.0, 1.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0};
+    double e[9], eo[5];
+    eq_phi<double>(phi, e);
+    if (keep_neq) {
+        eq_phi<double>(phio, eo);
+        for (int i = 0; i < 5; ++i)
+            st_pop(pop, i * P + idx, fo[i] + (e[i] - eo[i]) + 3.0 * w5[i] * (C5X[i] * dVx + C5Y[i] * dVy),
+                   kp.shift[i]);
+    } else {
+        for (int i = 0; i < 5; ++i)
+            st_pop(pop, i * P + idx, e[i] + 3.0 * w5[i] * (C5X[i] * Vx + C5Y[i] * Vy), kp.shift[i]);
+    }
+    eq_solute<double>(C, phi, U, ux, uy, e);
+    if (keep_neq) {
+        double Uo = (2.0 * Co / (1.0 + k - (1.0 - k) * phio) - 1.0) / (1.0 - k);
+        eq_solute<double>(Co, phio, Uo, uox, uoy, eo);
+        for (int i = 0; i < 5; ++i) st_pop(pop, (5 + i) * P + idx, no[i] + (e[i] - eo[i]), kp.shift[5 + i]);
+    } else {
+        for (int i = 0; i < 5; ++i) st_pop(pop, (5 + i) * P + idx, e[i], kp.shift[5 + i]);
+    }
+    eq_heat<double>(th, phi, kp.h_quintic, ux, uy, e);
+    if (keep_neq) {
+        double tho = Ho + 0.5 * h_of(phio, kp.h_quintic);
+        eq_heat<double>(tho, phio, kp.h_quintic, uox, uoy, eo);
+        for (int i = 0; i < 5; ++i) st_pop(pop, (10 + i) * P + idx, go[i] + (e[i] - eo[i]), kp.shift[10 + i]);
+    } else {
+        for (int i = 0; i < 5; ++i) st_pop(pop, (10 + i) * P + idx, e[i], kp.shift[10 + i]);
+    }
+    double sux = ux, suy = uy;  // the velocity the next step will evaluate
+    if constexpr (NS) {
+        if (!keep_flow) {
+            eq_flow<double>(0.0, 0.0, ux / kp.nsub_d, uy / kp.nsub_d, e);
+            for (int i = 0; i < 9; ++i) st_pop(flow, i * P + idx, e[i], kp.shift[15 + i]);
+            step_velocity(kp, e, phi, sux, suy);
+        }
+    }
+    // time derivatives: history := new value - (old value - old history)
+    if (keep_neq && in.hist_valid && !(WALLS && is_wall(kp, x, y))) {
+        const double om = 1.0 - phi * phi;
+        const double Q = phi * om - kp.lambda * (th + kp.Mcinf * U) * om * om;
+        const double H = th - 0.5 * h_of(phi, kp.h_quintic);
+        hist[idx] = HT(phi - (double)hist[idx]);
+        hist[P + idx] = HT(Q - (double)hist[P + idx]);
+        if constexpr (NS) {
+            hist[2 * P + idx] = HT(C * sux - (double)hist[2 * P + idx]);
+            hist[3 * P + idx] = HT(C * suy - (double)hist[3 * P + idx]);
+            hist[4 * P + idx] = HT(H * sux - (double)hist[4 * P + idx]);
+            hist[5 * P + idx] = HT(H * suy - (double)hist[5 * P + idx]);
+        }
     }
 }
 
@@ -615,23 +767,30 @@ __device__ __forceinline__ double node_phi(const KParams& kp, const typename CF:
     return (double)s;
 }
 
-// Bilinear sample of phi; NaN outside [0, nx-1] x [0, ny-1].
+// Bilinear sample of psi = atanh(phi); NaN outside [0, nx-1] x [0, ny-1].
 template <class CF, bool WALLS>
-__device__ double sample_phi(const KParams& kp, const typename CF::S* __restrict__ pop, double x,
+__device__ double sample_psi(const KParams& kp, const typename CF::S* __restrict__ pop, double x,
                              double y) {
+    // psi = atanh(phi) (phi clamped to |phi| <= 1 - 2^-30) is linear across
+    // a tanh interface, so bilinear interpolation of psi is exact for a
+    // planar front at any orientation.
     if (!(x >= 0.0 && y >= 0.0 && x <= kp.nx - 1 && y <= kp.ny - 1)) return __builtin_nan("");
     int i0 = (int)floor(x), j0 = (int)floor(y);
     if (i0 > kp.nx - 2) i0 = kp.nx - 2;
     if (j0 > kp.ny - 2) j0 = kp.ny - 2;
     double fx = x - i0, fy = y - j0;
-    double p00 = node_phi<CF, WALLS>(kp, pop, i0, j0), p10 = node_phi<CF, WALLS>(kp, pop, i0 + 1, j0);
-    double p01 = node_phi<CF, WALLS>(kp, pop, i0, j0 + 1);
-    double p11 = node_phi<CF, WALLS>(kp, pop, i0 + 1, j0 + 1);
+    const double c = 1.0 - 1.0 / 1073741824.0;
+    auto psi = [c](double v) { return atanh(v > c ? c : (v < -c ? -c : v)); };
+    double p00 = psi(node_phi<CF, WALLS>(kp, pop, i0, j0));
+    double p10 = psi(node_phi<CF, WALLS>(kp, pop, i0 + 1, j0));
+    double p01 = psi(node_phi<CF, WALLS>(kp, pop, i0, j0 + 1));
+    double p11 = psi(node_phi<CF, WALLS>(kp, pop, i0 + 1, j0 + 1));
     return (1.0 - fx) * (1.0 - fy) * p00 + fx * (1.0 - fy) * p10 + (1.0 - fx) * fy * p01 +
            fx * fy * p11;
 }
 
-// Tips: one workgroup per arm, one wave per sideways offset w = -3..3.
+// Tips: one workgroup per arm, one wave per sideways offset w = -3..3; the
+// crossing psi_j > 0 >= psi_{j+1} is refined linearly in psi = atanh(phi).
 template <class CF, bool WALLS>
 __global__ __launch_bounds__(448) void k_tips(const KParams kp, const typename CF::S* __restrict__ pop,
                                               double* __restrict__ out) {
@@ -647,8 +806,8 @@ __global__ __launch_bounds__(448) void k_tips(const KParams kp, const typename C
         long long j = base + lane;
         double x0 = kp.seed_x + j * dx + w * ex, y0 = kp.seed_y + j * dy + w * ey;
         double x1 = kp.seed_x + (j + 1) * dx + w * ex, y1 = kp.seed_y + (j + 1) * dy + w * ey;
-        double v0 = sample_phi<CF, WALLS>(kp, pop, x0, y0);
-        double v1 = sample_phi<CF, WALLS>(kp, pop, x1, y1);
+        double v0 = sample_psi<CF, WALLS>(kp, pop, x0, y0);
+        double v1 = sample_psi<CF, WALLS>(kp, pop, x1, y1);
         unsigned long long out_mask = __ballot(isnan(v0));
         long long J = out_mask ? base + __ffsll((long long)out_mask) - 1 : base + 64 + 1;
         if (j + 1 < J && v0 > 0.0 && v1 <= 0.0) best = j;
@@ -664,8 +823,8 @@ __global__ __launch_bounds__(448) void k_tips(const KParams kp, const typename C
             double x0 = kp.seed_x + best * dx + w * ex, y0 = kp.seed_y + best * dy + w * ey;
             double x1 = kp.seed_x + (best + 1) * dx + w * ex;
             double y1 = kp.seed_y + (best + 1) * dy + w * ey;
-            double v0 = sample_phi<CF, WALLS>(kp, pop, x0, y0);
-            double v1 = sample_phi<CF, WALLS>(kp, pop, x1, y1);
+            double v0 = sample_psi<CF, WALLS>(kp, pop, x0, y0);
+            double v1 = sample_psi<CF, WALLS>(kp, pop, x1, y1);
             s = best + v0 / (v0 - v1);
         }
         cross[wave] = s;

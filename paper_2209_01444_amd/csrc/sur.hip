@@ -263,11 +263,12 @@ __global__ void k_pack(const float* __restrict__ F, bf16* __restrict__ X, int N,
 
 // 1x1 head, loss and their gradients.  pred[m][o] = bh[o] + sum_c A[m][c] Wh[o][c];
 // with a target T (planar FP32 fields K steps later) and the inputs F:
-// r = (T - F)/rstd, loss += sum (pred - r)^2 / count, dpred = 2 (pred - r)/count,
+// r = (T - F)/rstd, loss += sum w_o (pred - r)^2 / count, dpred = 2 w_o (pred - r)/count,
 // dA[m][c] = sum_o dpred[o] Wh[o][c].  Without a target, writes F + rstd pred
 // as FP64 fields (if out != NULL).
 struct HeadArgs {
     float rstd[5];
+    float lw[5];  // per-channel loss weights
     float inv_count;
 };
 __global__ __launch_bounds__(256) void k_head(const bf16* __restrict__ A, const float* __restrict__ Wh,
@@ -306,8 +307,8 @@ __global__ __launch_bounds__(256) void k_head(const bf16* __restrict__ A, const 
                 const size_t fi = ((size_t)n * 5 + o) * hw + q;
                 float r = (T[fi] - F[fi]) / ha.rstd[o];
                 float d = pred[o] - r;
-                lsum += d * d * ha.inv_count;
-                dpo[o] = 2.f * d * ha.inv_count;
+                lsum += ha.lw[o] * d * d * ha.inv_count;
+                dpo[o] = 2.f * ha.lw[o] * d * ha.inv_count;
                 dpred[m * 5 + o] = dpo[o];
             }
 #pragma unroll
@@ -479,7 +480,7 @@ struct sur_net {
     float* dpred;   // [M][5]
     float* scal;    // loss accumulator etc.
     hipStream_t st;
-    float mean[5], std[5], rstd[5];
+    float mean[5], std[5], rstd[5], lw[5];
     int t = 0;
 };
 
@@ -661,7 +662,7 @@ int sur_create(int B, int H, int W, void* params, size_t pbytes, void* work, siz
     h->dpred = (float*)(h->work + 2 * h->fwd.total);
     h->scal = (float*)(h->work + 2 * h->fwd.total + a256((size_t)B * H * W * 5 * 4));
     h->st = (hipStream_t)stream;
-    for (int c = 0; c < 5; ++c) h->mean[c] = 0.f, h->std[c] = 1.f, h->rstd[c] = 1.f;
+    for (int c = 0; c < 5; ++c) h->mean[c] = 0.f, h->std[c] = 1.f, h->rstd[c] = 1.f, h->lw[c] = 1.f;
     *out = h;
     return 0;
 }
@@ -708,6 +709,18 @@ int sur_set_normalization(sur_handle h, const float* mean5, const float* std5, c
     return 0;
 }
 
+int sur_set_loss_weights(sur_handle h, const float* w5) {
+    if (!h || !w5) return fail(-1, "null argument");
+    float sum = 0.f;
+    for (int c = 0; c < 5; ++c) {
+        if (!(w5[c] >= 0.f) || !(w5[c] < 1e30f)) return fail(-1, "weights must be finite and >= 0");
+        sum += w5[c];
+    }
+    if (!(sum > 0.f)) return fail(-1, "at least one weight must be positive");
+    for (int c = 0; c < 5; ++c) h->lw[c] = w5[c];
+    return 0;
+}
+
 static void pack(sur_net* h, int b, const float* x) {
     hipLaunchKernelGGL(k_pack, dim3(nb((long long)b * h->H * h->W * 32)), dim3(256), 0, h->st, x,
                        ACT(h, false, h->fwd.x0), b, h->H, h->W, h->mean[0], h->mean[1], h->mean[2], h->mean[3],
@@ -716,7 +729,7 @@ static void pack(sur_net* h, int b, const float* x) {
 
 static HeadArgs head_args(sur_net* h, int b) {
     HeadArgs ha;
-    for (int c = 0; c < 5; ++c) ha.rstd[c] = h->rstd[c];
+    for (int c = 0; c < 5; ++c) ha.rstd[c] = h->rstd[c], ha.lw[c] = h->lw[c];
     ha.inv_count = 1.f / (float)((double)b * h->H * h->W * 5);
     return ha;
 }

@@ -35,8 +35,10 @@ class DlbParams(ctypes.Structure):
             "grad_tol")]
 
 
+KEEP_FLOW, KEEP_NONEQ = 1, 2  # continuation flags of dlb_set_fields_ex
+
 EXPORTS = (
-    "dlb_state_bytes", "dlb_create", "dlb_destroy", "dlb_init_seed", "dlb_set_fields", "dlb_step",
+    "dlb_state_bytes", "dlb_create", "dlb_destroy", "dlb_init_seed", "dlb_set_fields", "dlb_set_fields_ex", "dlb_step",
     "dlb_step_timed", "dlb_step_count", "dlb_get_fields", "dlb_reduce", "dlb_checkpoint_bytes",
     "dlb_save", "dlb_load", "dlb_copy_state", "dlb_sync", "dlb_equilibria", "dlb_copy_kernel", "dlb_strerror",
     "dlb_last_error", "dlb_batch_state_bytes", "dlb_batch_create", "dlb_batch_destroy",
@@ -64,6 +66,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "dlb_destroy": (ctypes.c_int, [vp]),
         "dlb_init_seed": (ctypes.c_int, [vp, dp]),
         "dlb_set_fields": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, ctypes.c_int]),
+        "dlb_set_fields_ex": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, ctypes.c_int, ctypes.c_uint32]),
         "dlb_step": (ctypes.c_int, [vp, i64]),
         "dlb_step_timed": (ctypes.c_int, [vp, i64, dp, dp, P(i64), P(i64)]),
         "dlb_step_count": (i64, [vp]),
@@ -201,19 +204,23 @@ class Solver:
                                                 n.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return self
 
-    def set_fields(self, phi, C=None, theta=None, ux=None, uy=None):
-        """Host numpy arrays or device torch tensors (float64, ny x nx)."""
+    def set_fields(self, phi, C=None, theta=None, ux=None, uy=None, keep_flow=False,
+                   keep_noneq=False):
+        """Host numpy arrays or device torch tensors (float64, ny x nx);
+        keep_flow / keep_noneq select the continuation flags of
+        dlb_set_fields_ex."""
         arrs = (phi, C, theta, ux, uy)
+        flags = (KEEP_FLOW if keep_flow else 0) | (KEEP_NONEQ if keep_noneq else 0)
         if any(self.torch.is_tensor(a) for a in arrs if a is not None):
             keep = [None if a is None else a.to(self.device, self.torch.float64).contiguous()
                     for a in arrs]
             ptrs = [None if a is None else ctypes.c_void_p(a.data_ptr()) for a in keep]
             self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
-            _check(self.lib, self.lib.dlb_set_fields(self.handle, *ptrs, 1))
+            _check(self.lib, self.lib.dlb_set_fields_ex(self.handle, *ptrs, 1, flags))
             self.stream.synchronize()
             return self
         keep = [self._plane(a) for a in arrs]
-        _check(self.lib, self.lib.dlb_set_fields(self.handle, *[_host_ptr(a) for a in keep], 0))
+        _check(self.lib, self.lib.dlb_set_fields_ex(self.handle, *[_host_ptr(a) for a in keep], 0, flags))
         return self
 
     def step(self, n: int):

@@ -16,7 +16,8 @@ LIB_PATH = os.path.join(HERE, "_lib", "libsur.so")
 
 LEVEL_CH = (32, 64, 128, 256)
 EXPORTS = ("sur_param_count", "sur_param_bytes", "sur_workspace_bytes", "sur_create", "sur_destroy",
-           "sur_set_params", "sur_get_params", "sur_get_grads", "sur_set_normalization", "sur_forward",
+           "sur_set_params", "sur_get_params", "sur_get_grads", "sur_set_normalization",
+           "sur_set_loss_weights", "sur_forward",
            "sur_gradients", "sur_train_step", "sur_conv_check", "sur_mfma_check", "sur_last_error")
 
 _lib = None
@@ -40,6 +41,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "sur_get_params": (i, [vp, fp]),
         "sur_get_grads": (i, [vp, fp]),
         "sur_set_normalization": (i, [vp, fp, fp, fp]),
+        "sur_set_loss_weights": (i, [vp, fp]),
         "sur_forward": (i, [vp, i, vp, vp]),
         "sur_gradients": (i, [vp, i, vp, vp, fp]),
         "sur_train_step": (i, [vp, i, vp, vp, ctypes.c_float, fp]),
@@ -156,7 +158,13 @@ class Surrogate:
 
     def set_normalization(self, mean, std, rstd):
         m, s, r = (np.ascontiguousarray(a, dtype=np.float32) for a in (mean, std, rstd))
+        self.mean, self.std, self.rstd = m.copy(), s.copy(), r.copy()
         _check(self.lib, self.lib.sur_set_normalization(self.handle, _fptr(m), _fptr(s), _fptr(r)))
+
+    def set_loss_weights(self, w5):
+        w = np.ascontiguousarray(w5, dtype=np.float32)
+        assert w.shape == (5,)
+        _check(self.lib, self.lib.sur_set_loss_weights(self.handle, _fptr(w)))
 
     def _dev(self, t, dtype):
         assert t.is_cuda and t.dtype == dtype and t.is_contiguous()

@@ -264,6 +264,70 @@ def test_checkpoint_resume_is_bitwise(dlb):
         np.testing.assert_array_equal(fa[k], fb[k])
 
 
+FIELDS5 = ("phi", "C", "theta", "ux", "uy")
+
+
+def _smooth_noise(shape, seed, amp):
+    """A smooth seeded perturbation (a few low Fourier modes)."""
+    rng = np.random.default_rng(seed)
+    ny, nx = shape
+    Y, X = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    out = np.zeros(shape)
+    for _ in range(4):
+        kx, ky = rng.integers(1, 4, 2)
+        ph = rng.uniform(0, 2 * np.pi)
+        out += np.sin(2 * np.pi * (kx * X / nx + ky * Y / ny) + ph)
+    return amp * out / 4
+
+
+@pytest.mark.parametrize("flags", [{}, {"keep_flow": True}, {"keep_noneq": True},
+                                   {"keep_flow": True, "keep_noneq": True}],
+                         ids=["equilibrium", "keep_flow", "keep_noneq", "keep_both"])
+def test_restart_at_new_fields_matches_oracle(dlb, flags):
+    """Restart at perturbed fields with each continuation flag (FP64): the
+    GPU and the oracle agree right after and 30 steps later."""
+    _say(f"case: restart at perturbed fields, flags {flags}, 96x78 f64")
+    cfg, noise = _flow_case(96, 78, "f64")
+    o = O.Oracle(cfg).init_seed(noise).step(60)
+    s = dlb.Solver(cfg).init_seed(noise).step(60)
+    f = o.fields()
+    new = {k: f[k] + _smooth_noise(f[k].shape, 5 + i, 1e-3 * (np.abs(f[k]).max() + 1e-3))
+           for i, k in enumerate(FIELDS5)}
+    o.set_fields(*[new[k] for k in FIELDS5], **flags)
+    s.set_fields(*[new[k] for k in FIELDS5], **flags)
+    gf, of = s.fields(), o.fields()
+    if flags.get("keep_flow"):
+        compare(gf, of, 1e-10, label="after restart")
+    else:
+        # the flow restarts at p = 0: p is then a small O(u^2) remainder whose
+        # differences are rounding of O(1) populations; compare it absolutely
+        compare(gf, of, 1e-10, fields=FIELDS[:-1], label="after restart")
+        assert np.abs(gf["p"] - of["p"]).max() < 1e-13
+    o.step(30)
+    s.step(30)
+    compare(s.fields(), o.fields(), 1e-10, label="30 steps later")
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-13), ("f32", 2e-5)])
+def test_restart_at_own_fields_continues_the_run(dlb, precision, tol):
+    """With both continuation flags, restarting at the solver's own fields
+    (device FP64 fields) leaves the run unchanged up to rounding; a restart at
+    equilibrium does not."""
+    _say(f"case: restart at own fields, {precision}")
+    cfg, noise = _flow_case(96, 78, precision)
+    a = dlb.Solver(cfg).init_seed(noise).step(60)
+    b = dlb.Solver(cfg).init_seed(noise).step(60)
+    c = dlb.Solver(cfg).init_seed(noise).step(60)
+    x = b.fields_device(FIELDS5, f32=False)
+    b.set_fields(*[x[i] for i in range(5)], keep_flow=True, keep_noneq=True)
+    c.set_fields(*[x[i] for i in range(5)])
+    for sv in (a, b, c):
+        sv.step(40)
+    fa, fb, fc = a.fields(), b.fields(), c.fields()
+    compare(fb, fa, tol, fields=("phi", "C", "theta", "ux", "uy"), label="continued")
+    assert rel_linf(fc["phi"], fa["phi"]) > 1e-5
+
+
 def test_nonfinite_is_reported(dlb):
     _say("case: NaN injection -> DLB_ENAN")
     cfg = dict(W.pure_diffusion_128("f32"), nx=32, ny=32)

@@ -96,14 +96,17 @@ def test_surrogate_forward_matches_reference(sur):
     assert rel < 1e-2
 
 
-def test_surrogate_gradients_match_reference(sur):
-    _say("case: surrogate gradients vs reference, B=2 32x32")
+@pytest.mark.parametrize("weights", [None, (1.0, 2.0, 0.5, 0.0, 0.0)], ids=["unweighted", "weighted"])
+def test_surrogate_gradients_match_reference(sur, weights):
+    _say(f"case: surrogate gradients vs reference, B=2 32x32, loss weights {weights}")
     s, Pr, x, y, xn, xt, yt, rstd = _setup(sur)
+    if weights is not None:
+        s.set_loss_weights(np.array(weights))
     loss = s.gradients(xt, yt)
     g = sur.unflatten(s.get_grads())
     pred, cache = U.forward(Pr, xn, rnd=U.round_bf16)
     target = ((y - x) / rstd[None, :, None, None]).transpose(0, 2, 3, 1).astype(np.float64)
-    L, dy = U.mse(pred, target)
+    L, dy = U.mse(pred, target, weights)
     G = U.backward(Pr, cache, dy, rnd=U.round_bf16)
     _say(f"  loss gpu {loss:.6f} reference {L:.6f}")
     assert loss == pytest.approx(L, rel=1e-4)

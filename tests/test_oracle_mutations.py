@@ -15,6 +15,7 @@ SRC = os.path.join(ROOT, "oracle", "dlb_oracle.c")
 
 T = "tests/test_oracle_dynamics.py::"
 TT = "tests/test_oracle_tables.py::"
+TR = "tests/test_oracle_restart.py::"
 
 MUTATIONS = [
     ("no d_t F^phi term (Remark 2)", "acc += F[i] + 0.5 * a2 * dF[i];", "acc += F[i];",
@@ -53,6 +54,12 @@ MUTATIONS = [
      T + "test_tip_of_a_parabolic_finger"),
     ("transposed D2Q5 Lambda", "acc += Minv[i * n + k] * s[k] * M[k * n + j];",
      "acc += Minv[j * n + k] * s[k] * M[k * n + i];", TT + "test_d2q5_lambda_equals_printed_matrix"),
+    ("restart drops the first-moment remainder",
+     "3.0 * W5[i] * (C5X[i] * (V[0] - Vo[0]) + C5Y[i] * (V[1] - Vo[1]))",
+     "3.0 * W5[i] * (C5X[i] * V[0] + C5Y[i] * V[1])",
+     TR + "test_restart_at_own_fields_with_both_flags_changes_nothing"),
+    ("restart drops the rates", "s->Q_prev[id] = Q - (Qo - s->Q_prev[id]);", "s->Q_prev[id] = Q;",
+     TR + "test_restart_at_own_fields_with_both_flags_changes_nothing"),
 ]
 
 

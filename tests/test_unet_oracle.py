@@ -108,3 +108,21 @@ def test_bf16_rounding_closed_forms():
 def test_adam_first_step_is_signed_lr():
     p, m, v = U.adam(np.array([1.0, -2.0]), np.array([0.3, -7.0]), np.zeros(2), np.zeros(2), 1, 0.01)
     np.testing.assert_allclose(p, [1.0 - 0.01, -2.0 + 0.01], rtol=1e-6)
+
+
+def test_weighted_mse_gradient_by_finite_differences():
+    """Per-channel weights: the gradient matches central differences, and
+    zero-weight channels get no gradient."""
+    rng = np.random.default_rng(8)
+    p = rng.normal(size=(2, 3, 4, 5))
+    t = rng.normal(size=p.shape)
+    w = np.array([1.0, 2.0, 0.5, 0.0, 0.0])
+    L, g = U.mse(p, t, w)
+    assert L == pytest.approx(np.sum(w * (p - t) ** 2) / p.size, rel=1e-14)
+    h = 1e-6
+    for idx in [(0, 0, 0, 0), (1, 2, 3, 1), (0, 1, 2, 2), (1, 0, 1, 3)]:
+        e = np.zeros_like(p)
+        e[idx] = h
+        fd = (U.mse(p + e, t, w)[0] - U.mse(p - e, t, w)[0]) / (2 * h)
+        assert g[idx] == pytest.approx(fd, rel=1e-7, abs=1e-12)
+    assert np.all(g[..., 3:] == 0)
