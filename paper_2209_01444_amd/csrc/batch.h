@@ -76,9 +76,9 @@ __global__ __launch_bounds__(BLOCK) void k_flow_batch(const SeedDesc* __restrict
     }
 }
 
-template <class CF, bool WALLS, int EX, int EY, int K>
-__global__ __launch_bounds__(EX* EY) void k_flow_tb_batch(const SeedDesc* __restrict__ d, int count,
-                                                          int total, int fcur) {
+template <class CF, bool WALLS, int K>
+__global__ __launch_bounds__(TbGeom<typename CF::T>::THREADS) void k_flow_tb_batch(const SeedDesc* __restrict__ d,
+                                                                                  int count, int total, int fcur) {
     using S = typename CF::S;
     using H = typename CF::H;
     const int chunk = (total + gridDim.x - 1) / gridDim.x;
@@ -89,8 +89,8 @@ __global__ __launch_bounds__(EX* EY) void k_flow_tb_batch(const SeedDesc* __rest
         while (s + 1 < count && d[s + 1].tb0[L] <= item) ++s;
         const SeedDesc& sd = d[s];
         const int t = item - sd.tb0[L];
-        flow_tb_tile<CF, WALLS, EX, EY, K>(sd.kp, (const S*)sd.flow[fcur], (S*)sd.flow[1 - fcur],
-                                           (const H*)sd.hist, t % sd.tb_nbx[L], t / sd.tb_nbx[L]);
+        flow_fused_tile<CF, WALLS, K>(sd.kp, (const S*)sd.flow[fcur], (S*)sd.flow[1 - fcur],
+                                      (const H*)sd.hist, t % sd.tb_nbx[L], t / sd.tb_nbx[L]);
         __syncthreads();  // LDS of this tile is reused by the next
     }
 }

@@ -224,11 +224,15 @@ template <class CF, bool NS, bool W> struct OpsImpl {
     static void tb_launch(const KParams& kp, const void* hin, void* hout, const void* phi,
                           hipStream_t st) {
         using T = typename CF::T;
-        constexpr int EX = TbTile<T>::EX, EY = TbTile<T>::EY;
-        constexpr int OX = TbShape<EX, EY, K>::OX, OY = TbShape<EX, EY, K>::OY;
+        using G = TbGeom<T>;
+        constexpr int OX = G::EX - 2 * K, OY = G::EY - 2 * K;
         int nbx = (kp.nx + OX - 1) / OX, nby = (kp.ny + OY - 1) / OY;
-        hipLaunchKernelGGL((k_flow_tb<CF, W, EX, EY, K>), dim3(nbx * nby), dim3(EX * EY), 0, st, kp,
-                           (const S*)hin, (S*)hout, (const H*)phi, nbx, nbx * nby);
+        if constexpr (sizeof(T) == 4)
+            hipLaunchKernelGGL((k_flow_tbw<CF, W, K>), dim3(nbx * nby), dim3(G::THREADS), 0, st, kp,
+                               (const S*)hin, (S*)hout, (const H*)phi, nbx, nbx * nby);
+        else
+            hipLaunchKernelGGL((k_flow_tb<CF, W, G::EX, G::EY, K>), dim3(nbx * nby), dim3(G::THREADS), 0, st,
+                               kp, (const S*)hin, (S*)hout, (const H*)phi, nbx, nbx * nby);
     }
     static bool flow_tb(int K, const KParams& kp, const void* hin, void* hout, const void* phi,
                         hipStream_t st) {
@@ -274,14 +278,13 @@ template <class CF, bool NS, bool W> struct OpsImpl {
     }
     static void b_flow_tb(int K, const SeedDesc* d, int count, int total, int fcur, int blocks,
                           hipStream_t st) {
-        using T = typename CF::T;
-        constexpr int EX = TbTile<T>::EX, EY = TbTile<T>::EY;
+        constexpr int TH = TbGeom<typename CF::T>::THREADS;
         if (K == 3)
-            hipLaunchKernelGGL((k_flow_tb_batch<CF, W, EX, EY, 3>), dim3(blocks), dim3(EX * EY), 0, st, d,
-                               count, total, fcur);
+            hipLaunchKernelGGL((k_flow_tb_batch<CF, W, 3>), dim3(blocks), dim3(TH), 0, st, d, count, total,
+                               fcur);
         else
-            hipLaunchKernelGGL((k_flow_tb_batch<CF, W, EX, EY, 5>), dim3(blocks), dim3(EX * EY), 0, st, d,
-                               count, total, fcur);
+            hipLaunchKernelGGL((k_flow_tb_batch<CF, W, 5>), dim3(blocks), dim3(TH), 0, st, d, count, total,
+                               fcur);
     }
     static BatchOps bops() { return BatchOps{b_pct, b_flow, b_flow_tb}; }
 };
@@ -833,8 +836,8 @@ int dlb_batch_create(const dlb_params* ps, int count, void* dev_state, size_t by
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
         b->num_cu = ncu;
     const bool f64 = ps[0].precision == DLB_F64 || ps[0].precision == DLB_F32M;
-    const int EX = f64 ? TbTile<double>::EX : TbTile<float>::EX;
-    const int EY = f64 ? TbTile<double>::EY : TbTile<float>::EY;
+    const int EX = f64 ? TbGeom<double>::EX : TbGeom<float>::EX;
+    const int EY = f64 ? TbGeom<double>::EY : TbGeom<float>::EY;
     for (int i = 0; i < count; ++i) {
         dlb_handle m = nullptr;
         rc = dlb_create(&ps[i], (char*)dev_state + offs[i], layout_of(&ps[i]).total, hip_stream, &m);

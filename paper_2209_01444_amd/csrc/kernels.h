@@ -42,22 +42,15 @@ __device__ __forceinline__ long long push_dest(const KParams& kp, int x, int y, 
     return (long long)dy * kp.nx + dx;
 }
 
-// Flow populations of node (x, y) at the current sub-step.  Interior nodes
-// load them; wall nodes rebuild them from the inward neighbour x_f with the
-// frozen phi there (non-equilibrium extrapolation, Sec. 4 preamble).
-template <class T, class S, bool WALLS>
-__device__ __forceinline__ void flow_node(const KParams& kp, const S* __restrict__ h_in, int x,
-                                          int y, size_t idx, T phi_f, T* h) {
-    const size_t P = (size_t)kp.plane;
-    if (!WALLS || !is_wall(kp, x, y)) {
-#pragma unroll
-        for (int i = 0; i < 9; ++i) h[i] = ld_pop<T>(h_in, i * P + idx, kp.shift[15 + i]);
-        return;
-    }
-    size_t f = inward_idx(kp, x, y);
-    T hf[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) hf[i] = ld_pop<T>(h_in, i * P + f, kp.shift[15 + i]);
+// Non-equilibrium extrapolation (Sec. 4 preamble) of the wall node (x, y)
+// from the populations hf of its inward neighbour x_f, with the frozen phi
+// there: h = hf + h^eq(p_b, u_b) - h^eq(p_f, u_f), boundary values by wall;
+// the equilibrium (eq_flow) difference is expanded in closed form.
+template <class T>
+__device__ __forceinline__ void wall_rebuild(const KParams& kp, int x, int y, const T* hf, T phi_f,
+                                             T* h) {
+    // no contraction: the same rounding in every kernel that inlines this
+#pragma clang fp contract(off)
     FlowMacro<T> m = flow_macro(hf, phi_f);
     T ubx, uby, pb;
     if (x == 0) {  // velocity inlet
@@ -73,11 +66,42 @@ __device__ __forceinline__ void flow_node(const KParams& kp, const S* __restrict
         uby = T(0);
         pb = m.p;
     }
-    T eb[9], ef[9];
-    eq_flow(T(0), pb, ubx, uby, eb);
-    eq_flow(T(0), m.p, m.ux, m.uy, ef);
+    // h^eq(p_b, u_b) - h^eq(p_f, u_f) written out with du = u_b - u_f and
+    // su = u_b + u_f: w_i [A + 3 c.du + 9/2 (c.du)(c.su)] for i > 0 and
+    // w_0 A - 3 dp for i = 0, where A = 3 dp - 3/2 du.su
+    const T dp = pb - m.p, dx = ubx - m.ux, dy = uby - m.uy, sx = ubx + m.ux, sy = uby + m.uy;
+    const T A = T(3) * dp - T(1.5) * (dx * sx + dy * sy);
+    const T w1 = T(1.0 / 9.0), w2 = T(1.0 / 36.0);
+    const T qx = T(4.5) * dx * sx, qy = T(4.5) * dy * sy;
+    const T d5 = dx + dy, s5 = sx + sy, d6 = dy - dx, s6 = sy - sx;
+    const T q5 = T(4.5) * d5 * s5, q6 = T(4.5) * d6 * s6;
+    h[0] = hf[0] + (T(4.0 / 9.0) * A - T(3) * dp);
+    h[1] = hf[1] + w1 * ((A + qx) + T(3) * dx);
+    h[3] = hf[3] + w1 * ((A + qx) - T(3) * dx);
+    h[2] = hf[2] + w1 * ((A + qy) + T(3) * dy);
+    h[4] = hf[4] + w1 * ((A + qy) - T(3) * dy);
+    h[5] = hf[5] + w2 * ((A + q5) + T(3) * d5);
+    h[7] = hf[7] + w2 * ((A + q5) - T(3) * d5);
+    h[6] = hf[6] + w2 * ((A + q6) + T(3) * d6);
+    h[8] = hf[8] + w2 * ((A + q6) - T(3) * d6);
+}
+
+// Flow populations of node (x, y) at the current sub-step.  Interior nodes
+// load them; wall nodes rebuild them from the inward neighbour x_f.
+template <class T, class S, bool WALLS>
+__device__ __forceinline__ void flow_node(const KParams& kp, const S* __restrict__ h_in, int x,
+                                          int y, size_t idx, T phi_f, T* h) {
+    const size_t P = (size_t)kp.plane;
+    if (!WALLS || !is_wall(kp, x, y)) {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) h[i] = eb[i] + (hf[i] - ef[i]);
+        for (int i = 0; i < 9; ++i) h[i] = ld_pop<T>(h_in, i * P + idx, kp.shift[15 + i]);
+        return;
+    }
+    size_t f = inward_idx(kp, x, y);
+    T hf[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) hf[i] = ld_pop<T>(h_in, i * P + f, kp.shift[15 + i]);
+    wall_rebuild(kp, x, y, hf, phi_f, h);
 }
 
 // ---------------------------------------------------------------------------
@@ -352,26 +376,10 @@ __device__ __forceinline__ void flow_tb_tile(const KParams& kp, const typename C
         }
         if (WALLS && wall) {
             // rebuild from the inward neighbour's pulled populations
-            FlowMacro<T> m = flow_macro(h, phi_f);
-            T ubx, uby, pb;
-            if (gx == 0) {
-                ubx = T(kp.uin_x_sub);
-                uby = T(kp.uin_y_sub);
-                pb = m.p;
-            } else if (gx == kp.nx - 1) {
-                ubx = m.ux;
-                uby = (gy == 0 || gy == kp.ny - 1) ? T(0) : m.uy;
-                pb = T(0);
-            } else {
-                ubx = m.ux;
-                uby = T(0);
-                pb = m.p;
-            }
-            T eb[9], ef[9];
-            eq_flow(T(0), pb, ubx, uby, eb);
-            eq_flow(T(0), m.p, m.ux, m.uy, ef);
+            T hf[9];
 #pragma unroll
-            for (int i = 0; i < 9; ++i) h[i] = eb[i] + (h[i] - ef[i]);
+            for (int i = 0; i < 9; ++i) hf[i] = h[i];
+            wall_rebuild(kp, gx, gy, hf, phi_f, h);
         }
         __syncthreads();
     }
@@ -381,6 +389,271 @@ __device__ __forceinline__ void flow_tb_tile(const KParams& kp, const typename C
 #pragma unroll
         for (int i = 0; i < 9; ++i) st_pop(hout, i * P + idx, h[i], kp.shift[15 + i]);
     }
+}
+
+// ---------------------------------------------------------------------------
+// K2'' (FP32 arithmetic): the same K fused sub-steps with a wave-row tile.
+// The extended tile is 64 x (NW R) nodes: wave w owns rows [w R, w R + R),
+// lane l column l, each thread R nodes of one column in registers.  After a
+// collision, streaming along x is a one-lane shift of the wave (DPP), along y
+// a move between the thread's own rows; only the first and last row of each
+// wave cross to the neighbouring waves, through a small double-buffered LDS
+// exchange (one barrier per sub-step).  Wall nodes take the inward
+// neighbour's pulled populations: first along x (lane shift), then along y
+// (own rows or an LDS slot), so a corner takes the diagonal one, and rebuild
+// (wall_rebuild).  Arithmetic per node and sub-step is that of k_flow.
+// ---------------------------------------------------------------------------
+struct TbWave {
+    static constexpr int NW = 8, R = 4, EX = 64, EY = NW * R;
+};
+
+// DPP wave shifts: lane l receives the value of lane l - 1 (from_left) or
+// l + 1 (from_right); the edge lane receives 0 (a stale column).
+__device__ __forceinline__ float lane_from_left(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float lane_from_right(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
+}
+
+template <class CF, bool WALLS, int K>
+__device__ __forceinline__ void flow_tbw_tile(const KParams& kp, const typename CF::S* __restrict__ hin,
+                                              typename CF::S* __restrict__ hout,
+                                              const typename CF::H* __restrict__ phi_t, int bx, int by) {
+    using T = typename CF::T;
+    using S = typename CF::S;
+    static_assert(sizeof(T) == 4, "wave-row tile is for FP32 arithmetic");
+    constexpr int NW = TbWave::NW, R = TbWave::R, EX = TbWave::EX, EY = TbWave::EY;
+    constexpr int OX = EX - 2 * K, OY = EY - 2 * K;
+    // exchange slots: [buffer][wave][k][lane]; k 0-2 = up-movers (2, 5, 6) of
+    // the wave's last row, k 3-5 = down-movers (4, 7, 8) of its first row
+    __shared__ float xch[2][NW][6][64];
+    __shared__ float ywall[2][9][64];  // inward rows of the y walls (top, bottom)
+    const size_t P = (size_t)kp.plane;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int X0 = bx * OX - K, Y0 = by * OY - K;
+    int gx = X0 + lane;
+    bool xin = true;
+    if constexpr (WALLS) {
+        xin = gx >= 0 && gx < kp.nx;
+    } else {
+        gx = gx < 0 ? gx + kp.nx : (gx >= kp.nx ? gx - kp.nx : gx);
+    }
+    T h[R][9], phi[R], phi_f[R];
+    int gy[R];
+    bool ex[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        int y = Y0 + w * R + r;
+        bool e = xin;
+        if constexpr (WALLS) {
+            e = e && y >= 0 && y < kp.ny;
+        } else {
+            y = y < 0 ? y + kp.ny : (y >= kp.ny ? y - kp.ny : y);
+        }
+        gy[r] = y;
+        ex[r] = e;
+        phi[r] = phi_f[r] = T(0);
+        if (e) {
+            const size_t idx = (size_t)y * kp.nx + gx;
+            phi[r] = T(phi_t[idx]);
+            phi_f[r] = phi[r];
+            if (WALLS && is_wall(kp, gx, y)) phi_f[r] = T(phi_t[inward_idx(kp, gx, y)]);
+            flow_node<T, S, WALLS>(kp, hin, gx, y, idx, phi_f[r], h[r]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) h[r][i] = T(0);
+        }
+    }
+    // tile-uniform wall flags (channel only)
+    const bool xwall_tile = WALLS && (X0 <= 0 || X0 + EX - 1 >= kp.nx - 1);
+    const int top_row = -Y0, bot_row = kp.ny - 1 - Y0;  // local rows of y = 0 and y = ny - 1
+    const bool top_tile = WALLS && top_row >= 0 && top_row + 1 < EY;
+    const bool bot_tile = WALLS && bot_row - 1 >= 0 && bot_row < EY;
+    const T s2 = T(kp.s2u);
+#pragma unroll
+    for (int sub = 0; sub < K; ++sub) {
+        const int buf = sub & 1;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            T o[9];
+            flow_collide<T>(h[r], phi[r], s2, o);
+            // x streaming: c_x = +1 from the left lane, c_x = -1 from the right lane
+            h[r][0] = o[0];
+            h[r][2] = o[2];
+            h[r][4] = o[4];
+            h[r][1] = lane_from_left(o[1]);
+            h[r][5] = lane_from_left(o[5]);
+            h[r][8] = lane_from_left(o[8]);
+            h[r][3] = lane_from_right(o[3]);
+            h[r][6] = lane_from_right(o[6]);
+            h[r][7] = lane_from_right(o[7]);
+        }
+        xch[buf][w][0][lane] = h[R - 1][2];
+        xch[buf][w][1][lane] = h[R - 1][5];
+        xch[buf][w][2][lane] = h[R - 1][6];
+        xch[buf][w][3][lane] = h[0][4];
+        xch[buf][w][4][lane] = h[0][7];
+        xch[buf][w][5][lane] = h[0][8];
+        __syncthreads();
+        // y streaming: c_y = +1 from the row below (index r - 1), c_y = -1
+        // from the row above (r + 1); the tile's outer rows keep stale values
+        {
+            const int wd = w > 0 ? w - 1 : 0, wu = w < NW - 1 ? w + 1 : NW - 1;
+            T up2 = xch[buf][wd][0][lane], up5 = xch[buf][wd][1][lane], up6 = xch[buf][wd][2][lane];
+            T dn4 = xch[buf][wu][3][lane], dn7 = xch[buf][wu][4][lane], dn8 = xch[buf][wu][5][lane];
+#pragma unroll
+            for (int r = R - 1; r > 0; --r) {
+                h[r][2] = h[r - 1][2];
+                h[r][5] = h[r - 1][5];
+                h[r][6] = h[r - 1][6];
+            }
+            h[0][2] = up2;
+            h[0][5] = up5;
+            h[0][6] = up6;
+#pragma unroll
+            for (int r = 0; r < R - 1; ++r) {
+                h[r][4] = h[r + 1][4];
+                h[r][7] = h[r + 1][7];
+                h[r][8] = h[r + 1][8];
+            }
+            h[R - 1][4] = dn4;
+            h[R - 1][7] = dn7;
+            h[R - 1][8] = dn8;
+        }
+        if constexpr (WALLS) {
+            // wall nodes (edge tiles only): the inward neighbour's pulled
+            // populations, taken along x first (lane shift), then along y
+            if (xwall_tile || top_tile || bot_tile) {
+                const bool west = xin && gx == 0, east = xin && gx == kp.nx - 1;
+                const bool west_tile = X0 <= 0, east_tile = X0 + EX - 1 >= kp.nx - 1;
+                if (top_tile || bot_tile) {
+                    // the thread rows holding y = 1 and y = ny - 2 publish their x-staged values
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const int lr = w * R + r;
+                        const bool pub_top = top_tile && lr == top_row + 1;
+                        const bool pub_bot = bot_tile && lr == bot_row - 1;
+                        if (pub_top || pub_bot) {  // wave-uniform
+#pragma unroll
+                            for (int i = 0; i < 9; ++i) {
+                                T v = h[r][i];
+                                if (west_tile) {
+                                    T a = lane_from_right(v);
+                                    v = west ? a : v;
+                                }
+                                if (east_tile) {
+                                    T b = lane_from_left(v);
+                                    v = east ? b : v;
+                                }
+                                ywall[pub_top ? 0 : 1][i][lane] = v;
+                            }
+                        }
+                    }
+                    __syncthreads();
+                }
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int lr = w * R + r;
+                    const bool yrow_top = top_tile && lr == top_row, yrow_bot = bot_tile && lr == bot_row;
+                    if (!(xwall_tile || yrow_top || yrow_bot)) continue;  // wave-uniform
+                    T hf[9];
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) {
+                        T v = h[r][i];
+                        if (west_tile) {
+                            T a = lane_from_right(v);
+                            v = west ? a : v;
+                        }
+                        if (east_tile) {
+                            T b = lane_from_left(v);
+                            v = east ? b : v;
+                        }
+                        if (yrow_top) v = ywall[0][i][lane];
+                        if (yrow_bot) v = ywall[1][i][lane];
+                        hf[i] = v;
+                    }
+                    if (ex[r] && is_wall(kp, gx, gy[r])) wall_rebuild(kp, gx, gy[r], hf, phi_f[r], h[r]);
+                }
+                if (top_tile || bot_tile) __syncthreads();  // ywall is rewritten next sub-step
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int lr = w * R + r;
+        const bool out = lane >= K && lane < EX - K && lr >= K && lr < EY - K;
+        const int ox = bx * OX + (lane - K), oy = by * OY + (lr - K);
+        if (out && ex[r] && !(WALLS && is_wall(kp, gx, gy[r])) && ox < kp.nx && oy < kp.ny) {
+            const size_t idx = (size_t)gy[r] * kp.nx + gx;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) st_pop(hout, i * P + idx, h[r][i], kp.shift[15 + i]);
+        }
+    }
+}
+
+// Tile geometry of the fused flow launch per arithmetic type: the wave-row
+// tile for FP32, the LDS tile for FP64.
+template <class T> struct TbGeom;
+template <> struct TbGeom<float> {
+    static constexpr int EX = TbWave::EX, EY = TbWave::EY, THREADS = 64 * TbWave::NW;
+};
+template <> struct TbGeom<double> {
+    static constexpr int EX = TbTile<double>::EX, EY = TbTile<double>::EY, THREADS = EX * EY;
+};
+
+// one fused tile of either kind
+template <class CF, bool WALLS, int K>
+__device__ __forceinline__ void flow_fused_tile(const KParams& kp, const typename CF::S* __restrict__ hin,
+                                                typename CF::S* __restrict__ hout,
+                                                const typename CF::H* __restrict__ phi_t, int bx, int by) {
+    using T = typename CF::T;
+    if constexpr (sizeof(T) == 4)
+        flow_tbw_tile<CF, WALLS, K>(kp, hin, hout, phi_t, bx, by);
+    else
+        flow_tb_tile<CF, WALLS, TbTile<T>::EX, TbTile<T>::EY, K>(kp, hin, hout, phi_t, bx, by);
+}
+
+// Tile of workgroup b.  Periodic grids: XCD-contiguous order.  Channel
+// grids: the tiles on the domain edge (whose wall handling costs more) come
+// first, so they start early and do not trail the launch, then the interior
+// tiles in XCD-contiguous order (the first group is padded to a multiple of
+// the 8 XCDs so that block b keeps running on XCD b mod 8).
+template <bool WALLS>
+__device__ __forceinline__ void tbw_tile_of(int b, int nbx, int nby, int& bx, int& by) {
+    const int nb = nbx * nby;
+    if (!WALLS || nbx <= 2 || nby <= 2) {
+        const int t = xcd_remap(b, nb);
+        bx = t % nbx;
+        by = t / nbx;
+        return;
+    }
+    const int E = 2 * nbx + 2 * (nby - 2), E8 = (E + 7) & ~7;
+    const int o = b < E8 ? b : E8 + xcd_remap(b - E8, nb - E8);
+    if (o < nbx) {
+        bx = o, by = 0;
+    } else if (o < 2 * nbx) {
+        bx = o - nbx, by = nby - 1;
+    } else if (o < E - (nby - 2)) {
+        bx = 0, by = 1 + o - 2 * nbx;
+    } else if (o < E) {
+        bx = nbx - 1, by = 1 + o - (E - (nby - 2));
+    } else {
+        const int u = o - E;
+        bx = 1 + u % (nbx - 2);
+        by = 1 + u / (nbx - 2);
+    }
+}
+
+template <class CF, bool WALLS, int K>
+__global__ __launch_bounds__(64 * TbWave::NW) void k_flow_tbw(const KParams kp,
+                                                               const typename CF::S* __restrict__ hin,
+                                                               typename CF::S* __restrict__ hout,
+                                                               const typename CF::H* __restrict__ phi_t,
+                                                               int nbx, int nblocks) {
+    int bx, by;
+    tbw_tile_of<WALLS>(blockIdx.x, nbx, nblocks / nbx, bx, by);
+    flow_tbw_tile<CF, WALLS, K>(kp, hin, hout, phi_t, bx, by);
 }
 
 template <class CF, bool WALLS, int EX, int EY, int K>
