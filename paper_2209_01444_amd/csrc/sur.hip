@@ -10,6 +10,7 @@
 #include <hip/hip_bf16.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -41,195 +42,397 @@ __device__ __forceinline__ bf16 f2bf(float v) { return (bf16)v; }
 
 // ---------------------------------------------------------------------------
 // 3x3 convolution, forward (also used for the input gradient with flipped,
-// transposed weights).  Workgroup: 4 waves x 16 pixels = 64 consecutive
-// pixels of the flattened (n, y, x) index, CO_T output channels.
+// transposed weights).  Workgroup: a tile of 4 rows x 64 pixels of one image
+// and 16 NJ output channels; wave w computes row w as 4 blocks of 16 pixels
+// x NJ blocks of 16 channels (4 NJ accumulators).  Per chunk of 32 input
+// channels the tile with its one-pixel halo and the chunk's weights for the
+// workgroup's channels (all 9 shifts) are staged in LDS (rows padded to 40
+// bf16 = 80 B, so the 16 rows a matrix-core operand reads fall in distinct
+// banks); the 9 shifts then read both operands from LDS.
 // ---------------------------------------------------------------------------
-template <int CO_T, bool ACT, bool BIAS>
+constexpr int CT_X = 64, CT_Y = 4, CT_PAD = 40;
+template <int NJ, bool ACT, bool BIAS>
 __global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ X, const bf16* __restrict__ Wt,
                                                  const float* __restrict__ bias, bf16* __restrict__ Y,
-                                                 int N, int H, int W, int Cin, int Cout) {
-    constexpr int NJ = CO_T / 16;
-    const long long M = (long long)N * H * W;
+                                                 int N, int H, int W, int Cin, int Cout, int ntx, int nty) {
+    __shared__ __attribute__((aligned(16))) bf16 sIn[CT_Y + 2][CT_X + 2][CT_PAD];
+    __shared__ __attribute__((aligned(16))) bf16 sW[9][16 * NJ][CT_PAD];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int row = lane & 15, kq = lane >> 4;
-    const long long m0 = (long long)blockIdx.x * 64 + wave * 16;
-    const int co0 = blockIdx.y * CO_T;
-    const long long m = m0 + row;
-    const bool mvalid = m < M;
-    const long long mc = mvalid ? m : 0;
-    const int n = (int)(mc / ((long long)H * W));
-    const int rem = (int)(mc % ((long long)H * W));
-    const int y = rem / W, x = rem % W;
-    f32x4 acc[NJ];
+    int t = blockIdx.x;
+    const int tx = t % ntx;
+    t /= ntx;
+    const int ty = t % nty, n = t / nty;
+    const int x0 = tx * CT_X, y0 = ty * CT_Y;
+    const int co0 = blockIdx.y * 16 * NJ;
+    f32x4 acc[4][NJ];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const bf16x8 zero = {};
-    for (int ky = 0; ky < 3; ++ky) {
-        for (int kx = 0; kx < 3; ++kx) {
-            const int yy = y + ky - 1, xx = x + kx - 1;
-            const bool ok = mvalid && yy >= 0 && yy < H && xx >= 0 && xx < W;
-            const size_t xo = ok ? (((size_t)n * H + yy) * W + xx) * Cin : 0;
-            const bf16* xp = X + xo + kq * 8;
-            const bf16* wp = Wt + ((size_t)(ky * 3 + kx) * Cout + co0 + row) * Cin + kq * 8;
-            for (int ci = 0; ci < Cin; ci += 32) {
-                bf16x8 a = ok ? *(const bf16x8*)(xp + ci) : zero;
+    for (int bb = 0; bb < 4; ++bb)
 #pragma unroll
-                for (int j = 0; j < NJ; ++j) {
-                    bf16x8 b = *(const bf16x8*)(wp + (size_t)j * 16 * Cin + ci);
-                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
+        for (int j = 0; j < NJ; ++j) acc[bb][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int ci = 0; ci < Cin; ci += 32) {
+        __syncthreads();  // the previous chunk's operands have been read
+        // issue every staging load before the first LDS write
+        constexpr int NI = ((CT_Y + 2) * (CT_X + 2) * 4 + 255) / 256, NWL = (9 * 16 * NJ * 4 + 255) / 256;
+        bf16x8 vin[NI], vw[NWL];
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+            const int i = threadIdx.x + 256 * k;
+            const int g = i & 3, pix = i >> 2;
+            const int yy = pix / (CT_X + 2), xx = pix % (CT_X + 2);
+            const int gy = y0 + yy - 1, gx = x0 + xx - 1;
+            vin[k] = bf16x8{};
+            if (i < (CT_Y + 2) * (CT_X + 2) * 4 && gy >= 0 && gy < H && gx >= 0 && gx < W)
+                vin[k] = *(const bf16x8*)(X + (((size_t)n * H + gy) * W + gx) * Cin + ci + 8 * g);
+        }
+#pragma unroll
+        for (int k = 0; k < NWL; ++k) {
+            const int i = threadIdx.x + 256 * k;
+            const int g = i & 3, q = i >> 2;
+            const int co = q % (16 * NJ), sft = q / (16 * NJ);
+            if (i < 9 * 16 * NJ * 4)
+                vw[k] = *(const bf16x8*)(Wt + ((size_t)sft * Cout + co0 + co) * Cin + ci + 8 * g);
+        }
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+            const int i = threadIdx.x + 256 * k;
+            const int g = i & 3, pix = i >> 2;
+            if (i < (CT_Y + 2) * (CT_X + 2) * 4)
+                *(bf16x8*)&sIn[pix / (CT_X + 2)][pix % (CT_X + 2)][8 * g] = vin[k];
+        }
+#pragma unroll
+        for (int k = 0; k < NWL; ++k) {
+            const int i = threadIdx.x + 256 * k;
+            const int g = i & 3, q = i >> 2;
+            if (i < 9 * 16 * NJ * 4) *(bf16x8*)&sW[q / (16 * NJ)][q % (16 * NJ)][8 * g] = vw[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky) {
+#pragma unroll
+            for (int kx = 0; kx < 3; ++kx) {
+                bf16x8 bv[NJ];
+#pragma unroll
+                for (int j = 0; j < NJ; ++j) bv[j] = *(const bf16x8*)&sW[ky * 3 + kx][16 * j + row][8 * kq];
+#pragma unroll
+                for (int bb = 0; bb < 4; ++bb) {
+                    const bf16x8 av = *(const bf16x8*)&sIn[wave + ky][16 * bb + row + kx][8 * kq];
+#pragma unroll
+                    for (int j = 0; j < NJ; ++j)
+                        acc[bb][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[j], acc[bb][j], 0, 0, 0);
                 }
             }
         }
     }
+    const int y = y0 + wave;
+    if (y >= H) return;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
         const int co = co0 + j * 16 + row;
-        const float bv = BIAS ? bias[co] : 0.f;
+        const float bval = BIAS ? bias[co] : 0.f;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const long long mm = m0 + 4 * kq + r;
-            if (mm < M) {
-                float v = acc[j][r] + bv;
-                if (ACT) v = v > 0.f ? v : LEAK * v;
-                Y[mm * Cout + co] = f2bf(v);
+        for (int bb = 0; bb < 4; ++bb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int px = x0 + 16 * bb + 4 * kq + r;
+                if (px < W) {
+                    float v = acc[bb][j][r] + bval;
+                    if (ACT) v = v > 0.f ? v : LEAK * v;
+                    Y[(((size_t)n * H + y) * W + px) * Cout + co] = f2bf(v);
+                }
             }
+    }
+}
+
+template <int NJ, bool ACT, bool BIAS>
+void launch_conv_t(hipStream_t st, const bf16* in, const bf16* wt, const float* bias, bf16* out, int B, int H, int W,
+                   int Cin, int Cout) {
+    const int ntx = (W + CT_X - 1) / CT_X, nty = (H + CT_Y - 1) / CT_Y;
+    dim3 grid((unsigned)(ntx * nty * B), (unsigned)(Cout / (16 * NJ)));
+    hipLaunchKernelGGL((k_conv3x3<NJ, ACT, BIAS>), grid, dim3(256), 0, st, in, wt, bias, out, B, H, W, Cin, Cout,
+                       ntx, nty);
+}
+
+// Y = conv(X, Wt) (+ bias, leaky ReLU); Cin and Cout multiples of 32
+void launch_conv(hipStream_t st, const bf16* in, const bf16* wt, const float* bias, bf16* out, int B, int H, int W,
+                 int Cin, int Cout, bool act) {
+    const bool wide = Cout % 64 == 0;
+    if (bias) {
+        if (wide) {
+            if (act) launch_conv_t<4, true, true>(st, in, wt, bias, out, B, H, W, Cin, Cout);
+            else launch_conv_t<4, false, true>(st, in, wt, bias, out, B, H, W, Cin, Cout);
+        } else {
+            if (act) launch_conv_t<2, true, true>(st, in, wt, bias, out, B, H, W, Cin, Cout);
+            else launch_conv_t<2, false, true>(st, in, wt, bias, out, B, H, W, Cin, Cout);
         }
+    } else {
+        if (wide) launch_conv_t<4, false, false>(st, in, wt, nullptr, out, B, H, W, Cin, Cout);
+        else launch_conv_t<2, false, false>(st, in, wt, nullptr, out, B, H, W, Cin, Cout);
     }
 }
 
 // ---------------------------------------------------------------------------
 // 3x3 convolution, weight gradient:  dW[s][co][ci] += sum_m dP[m][co] X_s[m][ci]
-// (X_s = X shifted by s, zero outside).  Workgroup: one shift, a 32x32
-// (co, ci) tile, a chunk of pixels; pixel tiles of 32 are staged through LDS
-// transposed so that each lane reads 8 consecutive pixels of one channel.
+// (X_s = X shifted by s, zero outside).  A k-step is a segment of 32
+// pixels of one image row; the segment's dP (transposed, [co][px]) and the
+// three input rows around it, stored once per column shift kx (transposed,
+// [s][ci][px]), are staged in LDS, so one dP operand serves all 9 shifts.
+// Workgroup: a CO_T x CI_T (co, ci) tile, all 9 shifts, a run of k-steps;
+// wave w owns a fixed set of 16 x 16 blocks and accumulates them in
+// registers, then adds them to dW with FP32 atomics.
 // ---------------------------------------------------------------------------
-constexpr int WG_CHUNK = 2048;
+constexpr int WG_PX = 32;
+template <int CO_T, int CI_T>
 __global__ __launch_bounds__(256) void k_conv3x3_wgrad(const bf16* __restrict__ X, const bf16* __restrict__ dP,
                                                        float* __restrict__ dW, int N, int H, int W, int Cin,
-                                                       int Cout) {
-    __shared__ __attribute__((aligned(16))) bf16 sA[32][40];  // [co][pixel]
-    __shared__ __attribute__((aligned(16))) bf16 sB[32][40];  // [ci][pixel]
-    const long long M = (long long)N * H * W;
-    const int s = blockIdx.z, ky = s / 3, kx = s % 3;
-    const int nci = Cin / 32;
-    const int co0 = (blockIdx.y / nci) * 32, ci0 = (blockIdx.y % nci) * 32;
-    const long long mbeg = (long long)blockIdx.x * WG_CHUNK;
-    const long long mend = mbeg + WG_CHUNK < M ? mbeg + WG_CHUNK : M;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int wr = wave >> 1, wc = wave & 1;  // this wave's 16x16 block of the tile
-    const int t = threadIdx.x;
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (long long mb = mbeg; mb < mend; mb += 32) {
-        // stage: thread t < 128 loads 8 channels of pixel (t % 32), group t / 32
-        if (t < 128) {
-            const int p = t & 31, g = t >> 5;  // g: which 8 of the 32 channels
-            const long long m = mb + p;
-            bf16x8 va = {}, vb = {};
-            if (m < mend) {
-                va = *(const bf16x8*)(dP + m * Cout + co0 + g * 8);
-                const int n = (int)(m / ((long long)H * W));
-                const int rem = (int)(m % ((long long)H * W));
-                const int yy = rem / W + ky - 1, xx = rem % W + kx - 1;
-                if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-                    vb = *(const bf16x8*)(X + (((size_t)n * H + yy) * W + xx) * Cin + ci0 + g * 8);
-            }
+                                                       int Cout, int nseg, int per_wg) {
+    constexpr int NCO = CO_T / 16, NCI = CI_T / 16;
+    // wave w: ci block w % NCI, co blocks w / NCI + k (4 / NCI) .. (all 9 shifts)
+    constexpr int WCI = NCI >= 4 ? NCI / 4 : 1;           // ci blocks per wave
+    constexpr int WCO = NCI >= 4 ? NCO : NCO * NCI / 4;   // co blocks per wave
+    constexpr int NACC = 9 * WCO * WCI;
+    __shared__ __attribute__((aligned(16))) bf16 sA[CO_T][WG_PX + 8];
+    __shared__ __attribute__((aligned(16))) bf16 sX[9][CI_T][WG_PX + 8];
+    const int nci_t = Cin / CI_T;
+    const int co0 = (blockIdx.y / nci_t) * CO_T, ci0 = (blockIdx.y % nci_t) * CI_T;
+    const long long total = (long long)N * H * nseg;
+    const long long kbeg = (long long)blockIdx.x * per_wg;
+    const long long kend = kbeg + per_wg < total ? kbeg + per_wg : total;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int row = lane & 15, kq = lane >> 4;
+    // this wave's blocks
+    int cb_first, cb_step, ib_first;
+    if (NCI >= 4) {
+        ib_first = wave * WCI;
+        cb_first = 0;
+        cb_step = 1;
+    } else {  // NCI in {1, 2}: 4 / NCI waves share the ci blocks, co blocks interleaved
+        ib_first = wave % NCI;
+        cb_first = wave / NCI;
+        cb_step = 4 / NCI;
+    }
+    f32x4 acc[NACC];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                sA[g * 8 + e][p] = va[e];
-                sB[g * 8 + e][p] = vb[e];
+    for (int i = 0; i < NACC; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (long long ks = kbeg; ks < kend; ++ks) {
+        const int seg = (int)(ks % nseg);
+        const long long ny = ks / nseg;
+        const int y = (int)(ny % H), n = (int)(ny / H);
+        const int xs = seg * WG_PX;
+        __syncthreads();  // the previous step's operands have been read
+        // issue every staging load before the first LDS write
+        constexpr int NA = (WG_PX * (CO_T / 8) + 255) / 256, NX = (3 * (WG_PX + 2) * (CI_T / 8) + 255) / 256;
+        bf16x8 va[NA], vx[NX];
+#pragma unroll
+        for (int k = 0; k < NA; ++k) {
+            const int v = tid + 256 * k;
+            const int g = v % (CO_T / 8), px = v / (CO_T / 8);
+            const int x = xs + px;
+            va[k] = bf16x8{};
+            if (v < WG_PX * (CO_T / 8) && x < W)
+                va[k] = *(const bf16x8*)(dP + (((size_t)n * H + y) * W + x) * Cout + co0 + 8 * g);
+        }
+#pragma unroll
+        for (int k = 0; k < NX; ++k) {
+            const int v = tid + 256 * k;
+            const int g = v % (CI_T / 8), q = v / (CI_T / 8);
+            const int xx = q % (WG_PX + 2), ky = q / (WG_PX + 2);
+            const int gy = y + ky - 1, gx = xs + xx - 1;
+            vx[k] = bf16x8{};
+            if (v < 3 * (WG_PX + 2) * (CI_T / 8) && gy >= 0 && gy < H && gx >= 0 && gx < W)
+                vx[k] = *(const bf16x8*)(X + (((size_t)n * H + gy) * W + gx) * Cin + ci0 + 8 * g);
+        }
+#pragma unroll
+        for (int k = 0; k < NA; ++k) {
+            const int v = tid + 256 * k;
+            const int g = v % (CO_T / 8), px = v / (CO_T / 8);
+            if (v < WG_PX * (CO_T / 8))
+#pragma unroll
+                for (int e = 0; e < 8; ++e) sA[8 * g + e][px] = va[k][e];
+        }
+#pragma unroll
+        for (int k = 0; k < NX; ++k) {
+            const int v = tid + 256 * k;
+            const int g = v % (CI_T / 8), q = v / (CI_T / 8);
+            const int xx = q % (WG_PX + 2), ky = q / (WG_PX + 2);
+            if (v < 3 * (WG_PX + 2) * (CI_T / 8)) {
+#pragma unroll
+                for (int kx = 0; kx < 3; ++kx) {
+                    const int px = xx - kx;  // pixel xs + px takes input column xs + px + kx - 1
+                    if (px >= 0 && px < WG_PX) {
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) sX[ky * 3 + kx][8 * g + e][px] = vx[k][e];
+                    }
+                }
             }
         }
         __syncthreads();
-        const int row = lane & 15, kq = lane >> 4;
-        bf16x8 a = *(const bf16x8*)&sA[wr * 16 + row][kq * 8];
-        bf16x8 b = *(const bf16x8*)&sB[wc * 16 + row][kq * 8];
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
-        __syncthreads();
-    }
-    const int row = lane & 15, kq = lane >> 4;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int co = co0 + wr * 16 + 4 * kq + r, ci = ci0 + wc * 16 + row;
-        atomicAdd(&dW[((size_t)s * Cout + co) * Cin + ci], acc[r]);
+        for (int c = 0; c < WCO; ++c) {
+            const int cb = cb_first + c * cb_step;
+            const bf16x8 av = *(const bf16x8*)&sA[cb * 16 + row][8 * kq];
+#pragma unroll
+            for (int i = 0; i < WCI; ++i) {
+                const int ib = ib_first + i;
+#pragma unroll
+                for (int sft = 0; sft < 9; ++sft) {
+                    const bf16x8 bv = *(const bf16x8*)&sX[sft][ib * 16 + row][8 * kq];
+                    f32x4& ac = acc[(c * WCI + i) * 9 + sft];
+                    ac = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, ac, 0, 0, 0);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < WCO; ++c) {
+        const int cb = cb_first + c * cb_step;
+#pragma unroll
+        for (int i = 0; i < WCI; ++i) {
+            const int ci = ci0 + (ib_first + i) * 16 + row;
+#pragma unroll
+            for (int sft = 0; sft < 9; ++sft)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int co = co0 + cb * 16 + 4 * kq + r;
+                    atomicAdd(&dW[((size_t)sft * Cout + co) * Cin + ci], acc[(c * WCI + i) * 9 + sft][r]);
+                }
+        }
     }
 }
 
-// bias gradient: db[c] += sum_m dP[m][c]
+void launch_wgrad(hipStream_t st, const bf16* X, const bf16* dP, float* dW, int N, int H, int W, int Cin,
+                  int Cout, int num_cu) {
+    const int nseg = (W + WG_PX - 1) / WG_PX;
+    const long long total = (long long)N * H * nseg;
+    const bool big = Cin % 64 == 0 && Cout % 64 == 0;
+    const int tiles = big ? (Cout / 64) * (Cin / 64) : (Cout / 32) * (Cin / 32);
+    // about two workgroups per compute unit in all, at least 8 k-steps each
+    long long want = (2ll * num_cu + tiles - 1) / tiles;
+    long long per = (total + want - 1) / want;
+    if (per < 8) per = 8;
+    const unsigned nwg = (unsigned)((total + per - 1) / per);
+    dim3 grid(nwg, (unsigned)tiles);
+    if (big)
+        hipLaunchKernelGGL((k_conv3x3_wgrad<64, 64>), grid, dim3(256), 0, st, X, dP, dW, N, H, W, Cin, Cout, nseg,
+                           (int)per);
+    else
+        hipLaunchKernelGGL((k_conv3x3_wgrad<32, 32>), grid, dim3(256), 0, st, X, dP, dW, N, H, W, Cin, Cout, nseg,
+                           (int)per);
+}
+
+// bias gradient: db[c] += sum_m dP[m][c].  Thread: 8 channels (one vector)
+// of every (256 / (C / 8))-th pixel of the block's pixel range; the block
+// reduces through LDS and adds C values with atomics.
 __global__ __launch_bounds__(256) void k_bias_grad(const bf16* __restrict__ dP, float* __restrict__ db, long long M,
                                                    int C) {
-    const int c = threadIdx.x % C;  // C in {32, 64, 128, 256}
-    const int lanes = 256 / C < 1 ? 1 : 256 / C;
-    const int sub = threadIdx.x / C;
-    if (sub >= lanes) return;
+    __shared__ float red[256][9];
+    const int G = C / 8, lanes = 256 / G;  // C in {32, 64, 128, 256}
+    const int g = threadIdx.x % G, sub = threadIdx.x / G;
     const long long per = (M + gridDim.x - 1) / gridDim.x;
     const long long beg = blockIdx.x * per, end = beg + per < M ? beg + per : M;
-    float acc = 0.f;
-    for (long long m = beg + sub; m < end; m += lanes) acc += bf2f(dP[m * C + c]);
-    atomicAdd(&db[c], acc);
+    float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (long long m = beg + sub; m < end; m += lanes) {
+        const bf16x8 v = *(const bf16x8*)(dP + m * C + 8 * g);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) acc[e] += bf2f(v[e]);
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) red[threadIdx.x][e] = acc[e];
+    __syncthreads();
+    if (threadIdx.x < C) {
+        const int gg = threadIdx.x / 8, e = threadIdx.x % 8;
+        float s = 0.f;
+        for (int k = 0; k < lanes; ++k) s += red[k * G + gg][e];
+        atomicAdd(&db[threadIdx.x], s);
+    }
 }
 
-// leaky ReLU backward from the stored output: dY *= (Y > 0 ? 1 : LEAK)
-__global__ void k_leaky_bwd(const bf16* __restrict__ Y, bf16* __restrict__ dY, long long n) {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    float g = bf2f(dY[i]);
-    dY[i] = f2bf(bf2f(Y[i]) > 0.f ? g : LEAK * g);
+// leaky ReLU backward from the stored output: dY *= (Y > 0 ? 1 : LEAK), 8 per thread
+__global__ void k_leaky_bwd(const bf16* __restrict__ Y, bf16* __restrict__ dY, long long n8) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n8) return;
+    const bf16x8 y = ((const bf16x8*)Y)[i];
+    bf16x8 d = ((bf16x8*)dY)[i];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const float g = bf2f(d[e]);
+        d[e] = f2bf(bf2f(y[e]) > 0.f ? g : LEAK * g);
+    }
+    ((bf16x8*)dY)[i] = d;
 }
 
-// 2x2 average pooling and its adjoint
+// 2x2 average pooling and its adjoint; thread: one pixel, 8 channels
 __global__ void k_pool2(const bf16* __restrict__ X, bf16* __restrict__ Y, int N, int H, int W, int C) {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int Ho = H / 2, Wo = W / 2;
-    if (i >= (long long)N * Ho * Wo * C) return;
-    const int c = (int)(i % C);
-    long long p = i / C;
-    const int xo = (int)(p % Wo), yo = (int)((p / Wo) % Ho), n = (int)(p / ((long long)Wo * Ho));
-    const size_t b = (((size_t)n * H + 2 * yo) * W + 2 * xo) * C + c;
-    float s = bf2f(X[b]) + bf2f(X[b + C]) + bf2f(X[b + (size_t)W * C]) + bf2f(X[b + (size_t)W * C + C]);
-    Y[i] = f2bf(0.25f * s);
+    const int Ho = H / 2, Wo = W / 2, G = C / 8;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)N * Ho * Wo * G) return;
+    const int g = (int)(i % G);
+    const int p = (int)(i / G);
+    const int xo = p % Wo, yo = (p / Wo) % Ho, n = p / (Wo * Ho);
+    const size_t b = (((size_t)n * H + 2 * yo) * W + 2 * xo) * C + 8 * g;
+    const bf16x8 a0 = *(const bf16x8*)(X + b), a1 = *(const bf16x8*)(X + b + C);
+    const bf16x8 a2 = *(const bf16x8*)(X + b + (size_t)W * C), a3 = *(const bf16x8*)(X + b + (size_t)W * C + C);
+    bf16x8 o;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) o[e] = f2bf(0.25f * (bf2f(a0[e]) + bf2f(a1[e]) + bf2f(a2[e]) + bf2f(a3[e])));
+    *(bf16x8*)(Y + (size_t)p * C + 8 * g) = o;
 }
-// dX (full resolution) += dY / 4 broadcast; `accumulate` adds to dX
+// dX (full resolution) = dY / 4 broadcast; `accumulate` adds to dX
 __global__ void k_pool2_bwd(const bf16* __restrict__ dY, bf16* __restrict__ dX, int N, int H, int W, int C,
                             int accumulate) {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (long long)N * H * W * C) return;
-    const int c = (int)(i % C);
-    long long p = i / C;
-    const int x = (int)(p % W), y = (int)((p / W) % H), n = (int)(p / ((long long)W * H));
-    float g = 0.25f * bf2f(dY[(((size_t)n * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c]);
-    dX[i] = f2bf(accumulate ? bf2f(dX[i]) + g : g);
+    const int G = C / 8;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)N * H * W * G) return;
+    const int g = (int)(i % G);
+    const int p = (int)(i / G);
+    const int x = p % W, y = (p / W) % H, n = p / (W * H);
+    const bf16x8 d = *(const bf16x8*)(dY + (((size_t)n * (H / 2) + y / 2) * (W / 2) + x / 2) * C + 8 * g);
+    bf16* out = dX + (size_t)p * C + 8 * g;
+    bf16x8 o = accumulate ? *(const bf16x8*)out : bf16x8{};
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const float gv = 0.25f * bf2f(d[e]);
+        o[e] = f2bf(accumulate ? bf2f(o[e]) + gv : gv);
+    }
+    *(bf16x8*)out = o;
 }
 
-// up2(A) concatenated with S along channels: out[.., 0:Ca] = A(y/2, x/2), out[.., Ca:] = S
+// up2(A) concatenated with S along channels: out[.., 0:Ca] = A(y/2, x/2),
+// out[.., Ca:] = S; thread: one pixel, 8 channels
 __global__ void k_up2_concat(const bf16* __restrict__ A, const bf16* __restrict__ S, bf16* __restrict__ O, int N,
                              int H, int W, int Ca, int Cs) {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int C = Ca + Cs;
-    if (i >= (long long)N * H * W * C) return;
-    const int c = (int)(i % C);
-    long long p = i / C;
-    const int x = (int)(p % W), y = (int)((p / W) % H), n = (int)(p / ((long long)W * H));
-    O[i] = c < Ca ? A[(((size_t)n * (H / 2) + y / 2) * (W / 2) + x / 2) * Ca + c] : S[(size_t)p * Cs + (c - Ca)];
+    const int C = Ca + Cs, G = C / 8;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)N * H * W * G) return;
+    const int c = 8 * (int)(i % G);
+    const int p = (int)(i / G);
+    const int x = p % W, y = (p / W) % H, n = p / (W * H);
+    const bf16x8 v = c < Ca ? *(const bf16x8*)(A + (((size_t)n * (H / 2) + y / 2) * (W / 2) + x / 2) * Ca + c)
+                            : *(const bf16x8*)(S + (size_t)p * Cs + (c - Ca));
+    *(bf16x8*)(O + (size_t)p * C + c) = v;
 }
-// adjoint: dA (low res) = sum of the four children's first Ca channels; dS = rest
+// adjoint: dA (low res) = sum of the four children's first Ca channels; dS = the rest
 __global__ void k_up2_concat_bwd(const bf16* __restrict__ dO, bf16* __restrict__ dA, bf16* __restrict__ dS,
                                  int N, int H, int W, int Ca, int Cs) {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int C = Ca + Cs;
-    const int Ho = H / 2, Wo = W / 2;
-    const long long nA = (long long)N * Ho * Wo * Ca, nS = (long long)N * H * W * Cs;
+    const int C = Ca + Cs, Ho = H / 2, Wo = W / 2, GA = Ca / 8, GS = Cs / 8;
+    const long long nA = (long long)N * Ho * Wo * GA, nS = (long long)N * H * W * GS;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < nA) {
-        const int c = (int)(i % Ca);
-        long long p = i / Ca;
-        const int xo = (int)(p % Wo), yo = (int)((p / Wo) % Ho), n = (int)(p / ((long long)Wo * Ho));
+        const int c = 8 * (int)(i % GA);
+        const int p = (int)(i / GA);
+        const int xo = p % Wo, yo = (p / Wo) % Ho, n = p / (Wo * Ho);
         const size_t b = (((size_t)n * H + 2 * yo) * W + 2 * xo) * C + c;
-        float s = bf2f(dO[b]) + bf2f(dO[b + C]) + bf2f(dO[b + (size_t)W * C]) + bf2f(dO[b + (size_t)W * C + C]);
-        dA[i] = f2bf(s);
+        const bf16x8 a0 = *(const bf16x8*)(dO + b), a1 = *(const bf16x8*)(dO + b + C);
+        const bf16x8 a2 = *(const bf16x8*)(dO + b + (size_t)W * C), a3 = *(const bf16x8*)(dO + b + (size_t)W * C + C);
+        bf16x8 o;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) o[e] = f2bf(bf2f(a0[e]) + bf2f(a1[e]) + bf2f(a2[e]) + bf2f(a3[e]));
+        *(bf16x8*)(dA + (size_t)p * Ca + c) = o;
     } else if (i < nA + nS) {
-        long long k = i - nA;
-        const int c = (int)(k % Cs);
-        long long p = k / Cs;
-        dS[k] = dO[(size_t)p * C + Ca + c];
+        const long long k = i - nA;
+        const int c = 8 * (int)(k % GS);
+        const int p = (int)(k / GS);
+        *(bf16x8*)(dS + (size_t)p * Cs + c) = *(const bf16x8*)(dO + (size_t)p * C + Ca + c);
     }
 }
 
@@ -244,21 +447,23 @@ __global__ void k_flip(const bf16* __restrict__ Wt, bf16* __restrict__ Wf, int C
 }
 
 // input packing: planar FP32 fields -> normalised NHWC bf16 with 32 channels
+// (channels 5..31 zero); thread: one pixel
 __global__ void k_pack(const float* __restrict__ F, bf16* __restrict__ X, int N, int H, int W, float m0, float m1,
                        float m2, float m3, float m4, float s0, float s1, float s2, float s3, float s4) {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (long long)N * H * W * 32) return;
-    const int c = (int)(i & 31);
-    long long p = i >> 5;
     const long long hw = (long long)H * W;
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= (long long)N * hw) return;
     const int n = (int)(p / hw);
     const long long q = p % hw;
-    float v = 0.f;
-    if (c < 5) {
-        const float mean[5] = {m0, m1, m2, m3, m4}, inv[5] = {1.f / s0, 1.f / s1, 1.f / s2, 1.f / s3, 1.f / s4};
-        v = (F[((size_t)n * 5 + c) * hw + q] - mean[c]) * inv[c];
-    }
-    X[i] = f2bf(v);
+    const float mean[5] = {m0, m1, m2, m3, m4}, inv[5] = {1.f / s0, 1.f / s1, 1.f / s2, 1.f / s3, 1.f / s4};
+    bf16x8 v = {};
+#pragma unroll
+    for (int c = 0; c < 5; ++c) v[c] = f2bf((F[((size_t)n * 5 + c) * hw + q] - mean[c]) * inv[c]);
+    bf16x8* out = (bf16x8*)(X + p * 32);
+    out[0] = v;
+    out[1] = bf16x8{};
+    out[2] = bf16x8{};
+    out[3] = bf16x8{};
 }
 
 // 1x1 head, loss and their gradients.  pred[m][o] = bh[o] + sum_c A[m][c] Wh[o][c];
@@ -340,17 +545,43 @@ __global__ __launch_bounds__(256) void k_head(const bf16* __restrict__ A, const 
         atomicAdd(threadIdx.x == 0 ? loss : &dbh[threadIdx.x - 1], s);
     }
 }
-// head weight gradient: dWh[o][c] += sum_m dpred[m][o] A[m][c]; thread t < 160 owns (o, c)
+// head weight gradient: dWh[o][c] += sum_m dpred[m][o] A[m][c].  Thread:
+// channels 8g..8g+7 of every 64th pixel of the block's range (g = t % 4);
+// the block reduces its 160 sums through LDS and adds them with atomics.
 __global__ __launch_bounds__(256) void k_head_wgrad(const bf16* __restrict__ A, const float* __restrict__ dpred,
                                                     float* __restrict__ dWh, long long M) {
-    const int t = threadIdx.x;
-    if (t >= 160) return;
-    const int o = t / 32, c = t % 32;
+    __shared__ float red[64][161];
+    const int g = threadIdx.x & 3, sub = threadIdx.x >> 2;
     const long long per = (M + gridDim.x - 1) / gridDim.x;
     const long long beg = blockIdx.x * per, end = beg + per < M ? beg + per : M;
-    float s = 0.f;
-    for (long long m = beg; m < end; ++m) s += dpred[m * 5 + o] * bf2f(A[m * 32 + c]);
-    atomicAdd(&dWh[o * 32 + c], s);
+    float acc[5][8];
+#pragma unroll
+    for (int o = 0; o < 5; ++o)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) acc[o][e] = 0.f;
+    for (long long m = beg + sub; m < end; m += 64) {
+        const bf16x8 a = *(const bf16x8*)(A + m * 32 + 8 * g);
+#pragma unroll
+        for (int o = 0; o < 5; ++o) {
+            const float d = dpred[m * 5 + o];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) acc[o][e] += d * bf2f(a[e]);
+        }
+    }
+    // fold the four channel groups of a pixel lane into one row of 160
+    for (int gg = 0; gg < 4; ++gg) {
+        if (g == gg)
+#pragma unroll
+            for (int o = 0; o < 5; ++o)
+#pragma unroll
+                for (int e = 0; e < 8; ++e) red[sub][o * 32 + 8 * gg + e] = acc[o][e];
+    }
+    __syncthreads();
+    if (threadIdx.x < 160) {
+        float s = 0.f;
+        for (int k = 0; k < 64; ++k) s += red[k][threadIdx.x];
+        atomicAdd(&dWh[threadIdx.x], s);
+    }
 }
 
 __global__ void k_fill(float* __restrict__ p, long long n, float v) {
@@ -482,6 +713,7 @@ struct sur_net {
     hipStream_t st;
     float mean[5], std[5], rstd[5], lw[5];
     int t = 0;
+    int num_cu = 256;  // compute units of the device (work split of the weight gradient)
 };
 
 static size_t params_bytes(size_t P) {
@@ -501,18 +733,7 @@ static bf16* ACT(sur_net* h, bool grad, size_t off) { return (bf16*)(h->work + (
 static void conv_fwd(sur_net* h, int k, const bf16* in, bf16* out, bool act, int B) {
     const Layer& l = h->L[k];
     int Hl = h->H >> l.level, Wl = h->W >> l.level;
-    long long M = (long long)B * Hl * Wl;
-    const bf16* wt = h->wb + l.w_off;
-    const float* bias = h->master + l.b_off;
-    const bool wide = l.cout % 64 == 0;
-    dim3 grid(nb(M, 64), wide ? l.cout / 64 : l.cout / 32);
-    if (wide) {
-        if (act) hipLaunchKernelGGL((k_conv3x3<64, true, true>), grid, dim3(256), 0, h->st, in, wt, bias, out, B, Hl, Wl, l.cin_p, l.cout);
-        else hipLaunchKernelGGL((k_conv3x3<64, false, true>), grid, dim3(256), 0, h->st, in, wt, bias, out, B, Hl, Wl, l.cin_p, l.cout);
-    } else {
-        if (act) hipLaunchKernelGGL((k_conv3x3<32, true, true>), grid, dim3(256), 0, h->st, in, wt, bias, out, B, Hl, Wl, l.cin_p, l.cout);
-        else hipLaunchKernelGGL((k_conv3x3<32, false, true>), grid, dim3(256), 0, h->st, in, wt, bias, out, B, Hl, Wl, l.cin_p, l.cout);
-    }
+    launch_conv(h->st, in, h->wb + l.w_off, h->master + l.b_off, out, B, Hl, Wl, l.cin_p, l.cout, act);
 }
 
 // the input of conv layer k in the forward sequence
@@ -537,7 +758,7 @@ static void forward(sur_net* h, int B) {
     for (int lv = 0; lv < 4; ++lv) {
         if (lv > 0) {
             int Hs = h->H >> (lv - 1), Ws = h->W >> (lv - 1), C = LEVEL_CH[lv - 1];
-            hipLaunchKernelGGL(k_pool2, dim3(nb((long long)B * (Hs / 2) * (Ws / 2) * C)), dim3(256), 0, h->st,
+            hipLaunchKernelGGL(k_pool2, dim3(nb((long long)B * (Hs / 2) * (Ws / 2) * (C / 8))), dim3(256), 0, h->st,
                                ACT(h, false, a.conv_out[2 * lv - 1]), ACT(h, false, a.pool[lv]), B, Hs, Ws, C);
         }
         conv_fwd(h, 2 * lv, conv_input(h, 2 * lv, false), ACT(h, false, a.conv_out[2 * lv]), true, B);
@@ -547,7 +768,7 @@ static void forward(sur_net* h, int B) {
     for (int i = 2; i >= 0; --i) {
         int k = 8 + 2 * (2 - i);
         int Hl = h->H >> i, Wl = h->W >> i, Ca = h->L[prev].cout, Cs = LEVEL_CH[i];
-        hipLaunchKernelGGL(k_up2_concat, dim3(nb((long long)B * Hl * Wl * (Ca + Cs))), dim3(256), 0, h->st,
+        hipLaunchKernelGGL(k_up2_concat, dim3(nb((long long)B * Hl * Wl * ((Ca + Cs) / 8))), dim3(256), 0, h->st,
                            ACT(h, false, a.conv_out[prev]), ACT(h, false, a.conv_out[2 * i + 1]),
                            ACT(h, false, a.cat[i]), B, Hl, Wl, Ca, Cs);
         conv_fwd(h, k, conv_input(h, k, false), ACT(h, false, a.conv_out[k]), true, B);
@@ -565,24 +786,17 @@ static void conv_bwd(sur_net* h, int k, int B) {
     int Hl = h->H >> l.level, Wl = h->W >> l.level;
     long long M = (long long)B * Hl * Wl;
     bf16* dOut = ACT(h, true, a.conv_out[k]);
-    hipLaunchKernelGGL(k_leaky_bwd, dim3(nb(M * l.cout)), dim3(256), 0, h->st, ACT(h, false, a.conv_out[k]), dOut,
-                       M * l.cout);
-    hipLaunchKernelGGL(k_conv3x3_wgrad, dim3(nb(M, WG_CHUNK), (l.cout / 32) * (l.cin_p / 32), 9), dim3(256), 0,
-                       h->st, conv_input(h, k, false), (const bf16*)dOut, h->grad + l.w_off, B, Hl, Wl, l.cin_p,
-                       l.cout);
-    hipLaunchKernelGGL(k_bias_grad, dim3(256), dim3(256), 0, h->st, (const bf16*)dOut, h->grad + l.b_off, M, l.cout);
+    hipLaunchKernelGGL(k_leaky_bwd, dim3(nb(M * l.cout / 8)), dim3(256), 0, h->st, ACT(h, false, a.conv_out[k]), dOut,
+                       M * l.cout / 8);
+    launch_wgrad(h->st, conv_input(h, k, false), (const bf16*)dOut, h->grad + l.w_off, B, Hl, Wl, l.cin_p, l.cout,
+                 h->num_cu);
+    const unsigned nbias = (unsigned)std::min<long long>(1024, std::max<long long>(1, M / 512));
+    hipLaunchKernelGGL(k_bias_grad, dim3(nbias), dim3(256), 0, h->st, (const bf16*)dOut, h->grad + l.b_off, M, l.cout);
     if (k == 0) return;
     hipLaunchKernelGGL(k_flip, dim3(nb(9ll * l.cin_p * l.cout)), dim3(256), 0, h->st, h->wb + l.w_off,
                        h->wf + l.w_off, l.cin_p, l.cout);
     bf16* dIn = (bf16*)conv_input(h, k, true);
-    const bool wide = l.cin_p % 64 == 0;
-    dim3 grid(nb(M, 64), wide ? l.cin_p / 64 : l.cin_p / 32);
-    if (wide)
-        hipLaunchKernelGGL((k_conv3x3<64, false, false>), grid, dim3(256), 0, h->st, (const bf16*)dOut,
-                           h->wf + l.w_off, (const float*)nullptr, dIn, B, Hl, Wl, l.cout, l.cin_p);
-    else
-        hipLaunchKernelGGL((k_conv3x3<32, false, false>), grid, dim3(256), 0, h->st, (const bf16*)dOut,
-                           h->wf + l.w_off, (const float*)nullptr, dIn, B, Hl, Wl, l.cout, l.cin_p);
+    launch_conv(h->st, (const bf16*)dOut, h->wf + l.w_off, nullptr, dIn, B, Hl, Wl, l.cout, l.cin_p, false);
 }
 
 static void backward(sur_net* h, int B) {
@@ -599,7 +813,7 @@ static void backward(sur_net* h, int B) {
         // dA -> gradient of the producer's output; dS -> gradient of the skip,
         // kept aside in the skip's own gradient slot for the encoder pass
         hipLaunchKernelGGL(k_up2_concat_bwd,
-                           dim3(nb((long long)B * (Hl / 2) * (Wl / 2) * Ca + (long long)B * Hl * Wl * Cs)), dim3(256), 0,
+                           dim3(nb((long long)B * (Hl / 2) * (Wl / 2) * (Ca / 8) + (long long)B * Hl * Wl * (Cs / 8))), dim3(256), 0,
                            h->st, (const bf16*)ACT(h, true, a.cat[i]), ACT(h, true, a.conv_out[src]),
                            ACT(h, true, a.conv_out[2 * i + 1]), B, Hl, Wl, Ca, Cs);
         prevk = src;
@@ -612,7 +826,7 @@ static void backward(sur_net* h, int B) {
         conv_bwd(h, 2 * lv, B);
         if (lv > 0) {
             int Hs = h->H >> (lv - 1), Ws = h->W >> (lv - 1), C = LEVEL_CH[lv - 1];
-            hipLaunchKernelGGL(k_pool2_bwd, dim3(nb((long long)B * Hs * Ws * C)), dim3(256), 0, h->st,
+            hipLaunchKernelGGL(k_pool2_bwd, dim3(nb((long long)B * Hs * Ws * (C / 8))), dim3(256), 0, h->st,
                                (const bf16*)ACT(h, true, a.pool[lv]), ACT(h, true, a.conv_out[2 * lv - 1]), B, Hs,
                                Ws, C, 1);
         }
@@ -638,6 +852,12 @@ int sur_create(int B, int H, int W, void* params, size_t pbytes, void* work, siz
     if (!params || pbytes < params_bytes(P)) return fail(-2, "parameter block too small");
     if (!work || wbytes < workspace_bytes(B, H, W)) return fail(-2, "workspace too small");
     sur_net* h = new (std::nothrow) sur_net();
+    if (h) {
+        int dev = 0, ncu = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+            h->num_cu = ncu;
+    }
     if (!h) return fail(-2, "host allocation failed");
     h->B = B;
     h->H = H;
@@ -722,7 +942,7 @@ int sur_set_loss_weights(sur_handle h, const float* w5) {
 }
 
 static void pack(sur_net* h, int b, const float* x) {
-    hipLaunchKernelGGL(k_pack, dim3(nb((long long)b * h->H * h->W * 32)), dim3(256), 0, h->st, x,
+    hipLaunchKernelGGL(k_pack, dim3(nb((long long)b * h->H * h->W)), dim3(256), 0, h->st, x,
                        ACT(h, false, h->fwd.x0), b, h->H, h->W, h->mean[0], h->mean[1], h->mean[2], h->mean[3],
                        h->mean[4], h->std[0], h->std[1], h->std[2], h->std[3], h->std[4]);
 }
@@ -759,7 +979,8 @@ int sur_gradients(sur_handle h, int b, const float* x, const float* y, float* lo
     hipLaunchKernelGGL(k_head, dim3(nb(M)), dim3(256), 0, h->st, A, h->master + head, h->master + head + 160, x, y,
                        h->dpred, ACT(h, true, h->fwd.conv_out[13]), (double*)nullptr, h->scal,
                        h->grad + head + 160, b, h->H, h->W, head_args(h, b));
-    hipLaunchKernelGGL(k_head_wgrad, dim3(512), dim3(256), 0, h->st, A, (const float*)h->dpred, h->grad + head, M);
+    const unsigned nhead = (unsigned)std::min<long long>(1024, std::max<long long>(1, M / 256));
+    hipLaunchKernelGGL(k_head_wgrad, dim3(nhead), dim3(256), 0, h->st, A, (const float*)h->dpred, h->grad + head, M);
     backward(h, b);
     HIP_TRY(hipGetLastError());
     float l = 0.f;
@@ -820,21 +1041,12 @@ int sur_conv_check(int op, int B, int H, int W, int Cin, int Cout, const float* 
     if (e == hipSuccess) e = hipMemset(dgw, 0, nw * 4);
     if (e == hipSuccess) {
         if (op == 0) {
-            dim3 g(nb((long long)M, 64), Cout % 64 == 0 ? Cout / 64 : Cout / 32);
-            if (Cout % 64 == 0)
-                hipLaunchKernelGGL((k_conv3x3<64, false, true>), g, dim3(256), 0, 0, dx, dw, dbias, dout, B, H, W, Cin, Cout);
-            else
-                hipLaunchKernelGGL((k_conv3x3<32, false, true>), g, dim3(256), 0, 0, dx, dw, dbias, dout, B, H, W, Cin, Cout);
+            launch_conv(0, dx, dw, dbias, dout, B, H, W, Cin, Cout, false);
         } else if (op == 1) {
             hipLaunchKernelGGL(k_flip, dim3(nb((long long)nw)), dim3(256), 0, 0, dw, dwf, Cin, Cout);
-            dim3 g(nb((long long)M, 64), Cin % 64 == 0 ? Cin / 64 : Cin / 32);
-            if (Cin % 64 == 0)
-                hipLaunchKernelGGL((k_conv3x3<64, false, false>), g, dim3(256), 0, 0, dy, dwf, (const float*)nullptr, dout, B, H, W, Cout, Cin);
-            else
-                hipLaunchKernelGGL((k_conv3x3<32, false, false>), g, dim3(256), 0, 0, dy, dwf, (const float*)nullptr, dout, B, H, W, Cout, Cin);
+            launch_conv(0, dy, dwf, nullptr, dout, B, H, W, Cout, Cin, false);
         } else {
-            hipLaunchKernelGGL(k_conv3x3_wgrad, dim3(nb((long long)M, WG_CHUNK), (Cout / 32) * (Cin / 32), 9), dim3(256),
-                               0, 0, dx, dy, dgw, B, H, W, Cin, Cout);
+            launch_wgrad(0, dx, dy, dgw, B, H, W, Cin, Cout, 256);
         }
         e = hipGetLastError();
     }
