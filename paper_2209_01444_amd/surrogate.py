@@ -3,7 +3,7 @@ training of the U-Net with the library's own kernels, and the hybrid loop
 that alternates network jumps of K main steps with lattice Boltzmann
 segments, using the lattice Boltzmann solver as judge and fallback.
 
-    python -m paper_2209_01444_amd.surrogate --size 512 --train-seeds 16 --iters 1500
+    python -m paper_2209_01444_amd.surrogate --size 512 --train-seeds 32
 
 Hybrid loop (per cycle): checkpoint the solver on the device; read the
 fields (phi, C, theta, ux, uy); jump: fields + network residual (or, for the
@@ -239,15 +239,15 @@ def compare(h, p):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--size", type=int, default=512)
-    ap.add_argument("--train-seeds", type=int, default=16)
+    ap.add_argument("--train-seeds", type=int, default=32)
     ap.add_argument("--t0", type=int, default=500)
-    ap.add_argument("--pairs", type=int, default=25)
+    ap.add_argument("--pairs", type=int, default=95)
     ap.add_argument("--K", type=int, default=100)
-    ap.add_argument("--L", type=int, default=100)
-    ap.add_argument("--iters", type=int, default=1500)
-    ap.add_argument("--batch", type=int, default=4)
-    ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--T", type=int, default=3000)
+    ap.add_argument("--L", default="100", help="lattice Boltzmann steps after each jump; a comma list runs each")
+    ap.add_argument("--iters", type=int, default=16000)
+    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--lr", type=float, default=4e-4, help="peak of the cosine schedule (1e-3 diverged)")
+    ap.add_argument("--T", type=int, default=10000)
     ap.add_argument("--tol", type=float, default=0.02)
     ap.add_argument("--seed", type=int, default=5)
     ap.add_argument("--save", default="", help="write the trained FP32 parameters (.npy) here")
@@ -302,26 +302,28 @@ def main():
     v_series = [(t1, ((b - a) / (t1 - t0)).round(6).tolist())
                 for (t0, a), (t1, b) in zip(plain["series"][:-1], plain["series"][1:])]
     print(json.dumps({"plain_tip_v": v_series}), flush=True)
-    hyb = run_hybrid(cfg, noise, args.T, args.t0, args.K, args.L, net, args.tol, restart=args.restart)
-    base = run_hybrid(cfg, noise, args.T, args.t0, args.K, args.L, None, args.tol, restart=args.restart)
-    exact = run_hybrid(cfg, noise, args.T, args.t0, args.K, args.L, None, args.tol, jump="lb",
-                       restart=args.restart)
-    exact_eq = run_hybrid(cfg, noise, args.T, args.t0, args.K, args.L, None, args.tol, jump="lb",
-                          restart="equilibrium")
+    Ls = [int(v) for v in str(args.L).split(",")]
     res = {
         "size": n, "train_pairs": int(X.shape[0]), "iters": args.iters, "train_seconds": t_train,
         "loss_weights": lw.tolist(),
         "loss_first": losses[0], "loss_last": float(np.mean(losses[-50:])), "forward_ms": fwd_ms,
         "forward_TFLOPs": 85.0e9 * (n / 512) ** 2 / (fwd_ms * 1e-3) / 1e12,
-        "plain_seconds": plain["seconds"], "T": args.T, "K": args.K, "L": args.L, "tol": args.tol,
-        "with_network": compare(hyb, plain), "without_network": compare(base, plain),
-        "jump_errors_with_network": [round(e, 4) if np.isfinite(e) else None for e in hyb["jump_errors"]],
-        "jump_errors_exact_lb": [round(e, 4) if np.isfinite(e) else None for e in exact["jump_errors"]],
-        "jump_errors_exact_lb_equilibrium_restart": [round(e, 4) if np.isfinite(e) else None
-                                                     for e in exact_eq["jump_errors"]],
-        "restart": args.restart, "with_exact_lb_jump": compare(exact, plain),
-        "val_mse": val, "val_mse_identity": val_identity,
+        "plain_seconds": plain["seconds"], "T": args.T, "K": args.K, "tol": args.tol, "restart": args.restart,
+        "val_mse": val, "val_mse_identity": val_identity, "by_L": {},
     }
+    for L in Ls:
+        hyb = run_hybrid(cfg, noise, args.T, args.t0, args.K, L, net, args.tol, restart=args.restart)
+        r = {"with_network": compare(hyb, plain),
+             "jump_errors_with_network": [round(e, 4) if np.isfinite(e) else None for e in hyb["jump_errors"]]}
+        if L == Ls[0]:
+            base = run_hybrid(cfg, noise, args.T, args.t0, args.K, L, None, args.tol, restart=args.restart)
+            exact = run_hybrid(cfg, noise, args.T, args.t0, args.K, L, None, args.tol, jump="lb",
+                               restart=args.restart)
+            r["without_network"] = compare(base, plain)
+            r["with_exact_lb_jump"] = compare(exact, plain)
+            r["jump_errors_exact_lb"] = [round(e, 4) if np.isfinite(e) else None for e in exact["jump_errors"]]
+        res["by_L"][L] = r
+        print(json.dumps({"L": L, **r}), flush=True)
     print(json.dumps(res), flush=True)
 
 
