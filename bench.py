@@ -156,6 +156,8 @@ def main():
     flow_bytes = ab["flow"] * nodes * subs_per_launch
     achieved = flow_bytes / (flow_ms * 1e-3) / 1e9
     wl = f"thermosolutal_flow_{cfg['nx']}x{cfg['ny']}_{cfg['precision']}"
+    # FP32 arithmetic fuses with the wave-row tile kernel, FP64 arithmetic with the LDS tile kernel
+    fused_name = "k_flow_tb" if cfg["precision"] in ("f64", "f32m") else "k_flow_tbw"
     red = solver.reduce(allow_nonfinite=True)
 
     line = {
@@ -176,11 +178,11 @@ def main():
                    "algorithmic_bytes_per_node_step": ab["step"], "parallelism": "single GPU"},
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_flow_tb (fused flow sub-steps)" if subs_per_launch > 1 else "k_flow (flow sub-step)",
+            "kernel": f"{fused_name} (fused flow sub-steps)" if subs_per_launch > 1 else "k_flow (flow sub-step)",
             "substeps_per_launch": subs_per_launch,
             "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4),
-            "traffic": traffic_from_profiles("k_flow_tb" if subs_per_launch > 1 else "k_flow", wl),
+            "traffic": traffic_from_profiles(fused_name if subs_per_launch > 1 else "k_flow", wl),
             "avg_launch_ms": round(flow_ms, 5), "bytes_per_launch": flow_bytes,
         },
         "kernels": {
