@@ -223,6 +223,24 @@ def test_small_and_ragged_grids(dlb, nx, ny, walls, fuse):
     compare(s.fields(), o.fields(), 1e-10, label=f"{nx}x{ny}")
 
 
+@pytest.mark.parametrize("nx,ny,walls,fuse", [(16, 16, 1, 5), (17, 19, 0, 5), (50, 23, 1, 5), (40, 37, 1, 3),
+                                              (65, 21, 1, 5), (64, 64, 0, 5), (119, 61, 1, 5)])
+def test_small_grids_fp32_fused_kernel(dlb, nx, ny, walls, fuse):
+    """The FP32 wave-row fused kernel on grids where one tile holds both
+    x walls (nx <= 54 at K = 5), both y walls (ny <= 22), or ragged edges:
+    against the unfused path (same arithmetic) and against the oracle."""
+    _say(f"case: FP32 fused kernel, small grid {nx}x{ny} walls={walls} fuse={fuse}")
+    cfg = dict(W.pure_diffusion_128("f32"), nx=nx, ny=ny, seed_x=nx / 2 - 0.3, seed_y=ny / 2 + 0.2,
+               seed_R=3.0, walls=walls, use_ns=1, n_sub=15, nu=0.3, u_in=(0.01, 0.004),
+               flow_fuse=fuse)
+    fused = dlb.Solver(cfg).init_seed().step(40)
+    unfused = dlb.Solver(dict(cfg, flow_fuse=1)).init_seed().step(40)
+    compare(fused.fields(), unfused.fields(), 2e-5, label=f"fused vs unfused {nx}x{ny}")
+    o = O.Oracle(cfg).init_seed().step(40)
+    compare(fused.fields(), o.fields(), 1e-4, fields=("phi", "C", "U", "theta", "ux", "uy"),
+            label=f"fused vs oracle {nx}x{ny}")
+
+
 def test_zero_steps_and_uniform_liquid(dlb):
     _say("case: step(0) and uniform liquid")
     cfg = dict(W.pure_diffusion_128("f64"), nx=32, ny=32)
