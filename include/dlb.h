@@ -80,6 +80,10 @@ typedef struct dlb_params {
     int32_t flow_fuse;    /* flow sub-steps fused per launch: 1, 3 or 5 (0: 5); the
                              fused kernel keeps a tile in registers and LDS for
                              that many sub-steps; results equal the unfused ones */
+    int32_t phi_static;   /* 1: phi, C and theta stay as set (no phi/C/theta
+                             update); each main step is n_sub flow sub-steps past
+                             the frozen diffuse solid -- the stationary-cylinder
+                             problem of Sec. 4.1.  Not available in batches     */
     double W0, tau0;      /* interface width and kinetic time (Sec. 2)              */
     double eps4, orient;  /* anisotropy strength and crystal orientation (rad)      */
     double lambda, Mcinf, k;   /* coupling, M c_inf, partition coefficient          */
@@ -161,12 +165,14 @@ int64_t dlb_step_count(dlb_handle h);
  * synchronises. */
 int dlb_get_fields(dlb_handle h, uint32_t mask, void* out, int out_on_device, int out_f32);
 
-/* Reductions in FP64 on the device; synchronises.  out[0..16]:
+/* Reductions in FP64 on the device; synchronises.  out[0..18] (19 doubles):
  *   0 sum C, 1 sum H, 2 solid fraction sum((1+phi)/2)/(nx ny), 3 non-finite
- *   count, 4-5 hydrodynamic force (Sec. 3.4) -sum [1-q(phi)] f, 6 torque about
- *   the solid centroid (flow sub-step units), 7-10 tip position s_k of arm k
- *   (angle orient + k pi/2 from the seed centre), 11-14 tip radius rho_k,
- *   15-16 solid centroid.
+ *   count, 4-5 hydrodynamic force (Sec. 3.4) -sum [1-q(phi)] f over all nodes,
+ *   6 torque about the solid centroid (flow sub-step units), 7-10 tip
+ *   position s_k of arm k (angle orient + k pi/2 from the seed centre), 11-14
+ *   tip radius rho_k, 15-16 solid centroid, 17-18 the force in the literal
+ *   form of Sec. 3.4, -sum f over the nodes covered by the solid (phi > 0),
+ *   f = -u* (u_s = 0, sub-step units).
  * Tip: psi = atanh(phi) (phi clamped to |phi| <= 1 - 2^-30) sampled every
  * 1 lu along the arm ray by bilinear interpolation of the node values of
  * psi; s is the outermost sample pair psi_j > 0 >= psi_{j+1}, refined

@@ -658,10 +658,18 @@ static void swap_ptr(double** a, double** b) {
     *b = t;
 }
 
+static void flow_substeps(orc_state* s);
+
 static void main_step(orc_state* s) {
     const orc_params* p = &s->p;
     int N = s->N, nx = s->nx, ny = s->ny;
     compute_macros(s);
+    if (p->phi_static) {
+        /* frozen diffuse solid (Sec. 4.1): only the flow lattice steps */
+        if (p->use_ns) flow_substeps(s);
+        s->step += 1;
+        return;
+    }
 
 #pragma omp parallel for schedule(static)
     for (int x = 0; x < N; ++x) collide_pct_node(s, x);
@@ -695,7 +703,16 @@ static void main_step(orc_state* s) {
 
     /* Flow lattice: n_sub sub-steps with phi frozen at phi^t (Sec. 3.4,
      * two-time-scaling of Sec. 4). */
-    if (p->use_ns) {
+    if (p->use_ns) flow_substeps(s);
+    s->hist_valid = 1;
+    s->step += 1;
+}
+
+/* n_sub flow sub-steps at the phi of the last compute_macros */
+static void flow_substeps(orc_state* s) {
+    const orc_params* p = &s->p;
+    int N = s->N, nx = s->nx, ny = s->ny;
+    {
         for (int sub = 0; sub < p->n_sub; ++sub) {
             fill_flow_walls(s, s->h, s->phi);
 #pragma omp parallel for schedule(static)
@@ -718,8 +735,6 @@ static void main_step(orc_state* s) {
             swap_ptr(&s->h, &s->hn);
         }
     }
-    s->hist_valid = 1;
-    s->step += 1;
 }
 
 int orc_step(orc_state* s, long n) {
@@ -1025,10 +1040,12 @@ int orc_reduce(orc_state* s, double* out) {
     }
     cx /= sphi;
     cy /= sphi;
-    double T = 0;
+    double T = 0, Fsx = 0, Fsy = 0;
     if (p->use_ns) {
         /* Eq. (hydrodynamic force/torque), reading: summed over all nodes of
-         * the force actually applied, [1 - q(phi)] f, sub-step units. */
+         * the force actually applied, [1 - q(phi)] f, sub-step units; the
+         * literal form, f summed over the nodes covered by the solid
+         * (phi > 0), is reported as well.  f = (u_s - u*)/dt' with u_s = 0. */
         for (int x = 0; x < N; ++x) {
             double hx[9], us[2], Fb[2], u[2], pr;
             for (int i = 0; i < 9; ++i) hx[i] = s->h[(size_t)i * N + x];
@@ -1037,6 +1054,10 @@ int orc_reduce(orc_state* s, double* out) {
             Fy -= Fb[1];
             double rx = (x % s->nx) - cx, ry = (x / s->nx) - cy;
             T -= rx * Fb[1] - ry * Fb[0];
+            if (s->phi[x] > 0.0) {
+                Fsx += us[0]; /* -f = u* */
+                Fsy += us[1];
+            }
         }
     }
     out[0] = sC;
@@ -1052,5 +1073,7 @@ int orc_reduce(orc_state* s, double* out) {
     }
     out[15] = cx;
     out[16] = cy;
+    out[17] = Fsx;
+    out[18] = Fsy;
     return 0;
 }

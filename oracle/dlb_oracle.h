@@ -44,6 +44,9 @@ typedef struct orc_params {
     int h_quintic;    /* 0: h(phi)=phi; 1: h = 15(phi-2phi^3/3+phi^5/5)/8    */
     int c_init_U;     /* 0: initial C uniform = C0; 1: initial U uniform = U0 */
     int grad_max_iter;/* cap on the implicit local-gradient iteration         */
+    int phi_static;   /* 1: phi, C and theta stay as set; only the flow lattice
+                         steps (n_sub sub-steps per main step) past the frozen
+                         diffuse solid: the stationary-cylinder problem      */
     double W0, tau0, eps4, orient, lambda, Mcinf, k, D, alpha, nu, rho0;
     double u_in_x, u_in_y;   /* inflow / initial velocity, lu per main step  */
     double theta0, U0, C0;
@@ -100,11 +103,12 @@ int orc_get_fields(orc_state* s, double* out);
  * pre-collision at the current step; flow slot 0 unshifted (includes rho0). */
 int orc_get_pops(orc_state* s, int lattice, double* out);
 
-/* Reductions, out[0..16]:
+/* Reductions, out[0..18]:
  *   0 sum C, 1 sum H, 2 solid fraction sum((1+phi)/2)/N, 3 non-finite count,
- *   4,5 hydrodynamic force Fx,Fy, 6 torque (flow sub-step units),
- *   7..10 tip position s_k of arms k=0..3, 11..14 tip radius rho_k,
- *   15,16 solid centroid */
+ *   4,5 hydrodynamic force Fx,Fy = -sum [1-q(phi)] f, 6 torque (flow
+ *   sub-step units), 7..10 tip position s_k of arms k=0..3, 11..14 tip
+ *   radius rho_k, 15,16 solid centroid, 17,18 force -sum f over the nodes
+ *   with phi > 0 */
 int orc_reduce(orc_state* s, double* out);
 
 /* ---- single-node primitives, exposed for the pins ---- */

@@ -689,6 +689,7 @@ struct InitFields {
     unsigned flags;          // DLB_KEEP_FLOW (1) | DLB_KEEP_NONEQ (2)
     int hist_valid;          // KEEP_NONEQ: hist holds rates (see k_restart_prep)
     const double* phi_old;   // KEEP_NONEQ: phi of the current state (k_restart_prep)
+    int phi_static;          // frozen solid: the flow sub-steps read phi from hist[0]
 };
 
 constexpr unsigned KEEP_FLOW = 1u, KEEP_NONEQ = 2u;
@@ -896,6 +897,9 @@ __global__ __launch_bounds__(BLOCK) void k_set_fields(const KParams kp, const In
             hist[5 * P + idx] = HT(H * suy - (double)hist[5 * P + idx]);
         }
     }
+    // frozen solid: phi of the flow sub-steps, as a main step would leave it
+    // (a wall node carries its inward neighbour's value)
+    if (in.phi_static) hist[idx] = HT((WALLS && is_wall(kp, x, y)) ? in.phi[inward_idx(kp, x, y)] : phi);
 }
 
 // ---------------------------------------------------------------------------
@@ -925,6 +929,7 @@ __device__ __forceinline__ void node_macros(const KParams& kp, const typename CF
     m[4] = m[5] = m[6] = 0.0;
     m[7] = H;
     m[8] = m[9] = 0.0;  // interface force (sub-step units)
+    m[10] = m[11] = 0.0;  // f = u_s - u* = -u* (sub-step units)
     if constexpr (NS) {
         T h[9];
         flow_node<T, S, WALLS>(kp, flow, x, y, idx, phi, h);
@@ -934,6 +939,8 @@ __device__ __forceinline__ void node_macros(const KParams& kp, const typename CF
         m[6] = kp.nsub_d * kp.nsub_d * fm.p;
         m[8] = fm.Fx;
         m[9] = fm.Fy;
+        m[10] = -fm.mx;
+        m[11] = -fm.my;
     }
 }
 
@@ -944,7 +951,7 @@ __global__ __launch_bounds__(BLOCK) void k_fields(const KParams kp,
                                                   uint32_t mask, void* __restrict__ out, int f32) {
     int x, y;
     if (!node_of_thread(kp, x, y)) return;
-    double m[10];
+    double m[12];
     node_macros<CF, NS, WALLS>(kp, pop, flow, x, y, m);
     size_t N = (size_t)kp.nx * kp.ny, idx = (size_t)y * kp.nx + x;
     int slot = 0;
@@ -975,9 +982,9 @@ template <int NR> __device__ __forceinline__ void block_sum(double* v) {
         }
 }
 
-static constexpr int NRED = 10;
+static constexpr int NRED = 11;
 // partial sums per workgroup: C, H, (1+phi)/2, non-finite, x w, y w, Fx, Fy,
-// x Fy - y Fx, (unused)
+// x Fy - y Fx, and f summed over the nodes with phi > 0 (x, y)
 template <class CF, bool NS, bool WALLS>
 __global__ __launch_bounds__(BLOCK) void k_reduce_partial(const KParams kp,
                                                           const typename CF::S* __restrict__ pop,
@@ -986,7 +993,7 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_partial(const KParams kp,
     double v[NRED] = {0};
     int x, y;
     if (node_of_thread(kp, x, y)) {
-        double m[10];
+        double m[12];
         node_macros<CF, NS, WALLS>(kp, pop, flow, x, y, m);
         double w = 0.5 * (1.0 + m[0]);
         v[0] = m[1];
@@ -1000,6 +1007,10 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_partial(const KParams kp,
         v[6] = m[8];
         v[7] = m[9];
         v[8] = x * m[9] - y * m[8];
+        if (m[0] > 0.0) {
+            v[9] = m[10];
+            v[10] = m[11];
+        }
     }
     block_sum<NRED>(v);
     if (threadIdx.x == 0)
@@ -1025,6 +1036,8 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_final(const double* __restrict
         out[6] = -(v[8] - cx * v[7] + cy * v[6]);
         out[15] = cx;
         out[16] = cy;
+        out[17] = -v[9];
+        out[18] = -v[10];
     }
 }
 

@@ -439,3 +439,23 @@ def test_tip_of_a_moving_front_moves_uniformly():
         lin.append(k + pj[k] / (pj[k] - pj[k + 1]))
     np.testing.assert_allclose(np.diff(got), 0.1, atol=1e-9)
     assert np.abs(np.diff(lin) - 0.1).max() > 1e-3
+
+
+def test_static_cylinder_drag_is_symmetric_and_grows_with_the_inflow():
+    """Frozen diffuse cylinder in a uniform inflow: phi never changes, the
+    force is along the flow (Fy and the torque vanish by the mirror symmetry
+    of the set-up) and it grows with the inflow speed."""
+    fx = []
+    for Re in (2.0, 5.0):
+        cfg = W.cylinder_flow(Re, R=3, precision="f64", n_sub=3)
+        cfg["seed_y"] = (cfg["ny"] - 1) / 2  # on the channel's mirror line
+        o = O.Oracle(cfg).init_seed()
+        phi0 = o.fields()["phi"]
+        o.step(40)
+        r = o.reduce()
+        assert np.array_equal(o.fields()["phi"], phi0)
+        assert r["Fx"] > 0
+        assert abs(r["Fy"]) < 1e-12 * r["Fx"] and abs(r["torque"]) < 1e-9 * r["Fx"]
+        fx.append(r["Fx"])
+    assert fx[1] > 2.0 * fx[0]
+
