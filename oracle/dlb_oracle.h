@@ -23,7 +23,11 @@
  *   solute / heat lattices: diffusion, conservation, d_t(Cu)      pinned
  *   flow lattice: viscosity, diffuse solid forcing                pinned
  *   anti-trapping current J_at                                    parity unpinned
- *   non-equilibrium-extrapolation walls                           parity unpinned
+ *   non-equilibrium-extrapolation walls: uniform channel flow steady (pinned);
+ *     beyond it only through the GPU path it matches to 1e-10, whose
+ *     stationary-cylinder drag is within 3.2% of the values printed in
+ *     the table of Sec. 4.1                                       indirect
+ *   restart flags (orc_set_fields_ex): continuation is exact      pinned
  *   tip position / radius measurement                             pinned (geometry)
  */
 #ifndef DLB_ORACLE_H
