@@ -84,6 +84,8 @@ typedef struct dlb_params {
                              update); each main step is n_sub flow sub-steps past
                              the frozen diffuse solid -- the stationary-cylinder
                              problem of Sec. 4.1.  Not available in batches     */
+    int32_t isothermal;   /* 1: theta = theta0 everywhere, no heat lattice (the
+                             isothermal alloy of Sec. 4.3)                       */
     double W0, tau0;      /* interface width and kinetic time (Sec. 2)              */
     double eps4, orient;  /* anisotropy strength and crystal orientation (rad)      */
     double lambda, Mcinf, k;   /* coupling, M c_inf, partition coefficient          */

@@ -67,6 +67,7 @@ int check_params(const dlb_params* p) {
     if (p->bc != DLB_BC_PERIODIC && p->bc != DLB_BC_CHANNEL) return fail(DLB_EINVAL, "unknown bc");
     if (p->use_ns && p->n_sub < 1) return fail(DLB_EINVAL, "n_sub must be >= 1");
     if (p->phi_static != 0 && p->phi_static != 1) return fail(DLB_EINVAL, "phi_static must be 0 or 1");
+    if (p->isothermal != 0 && p->isothermal != 1) return fail(DLB_EINVAL, "isothermal must be 0 or 1");
     if (!(p->W0 > 0 && p->tau0 > 0 && p->D > 0 && p->alpha > 0)) return fail(DLB_EINVAL, "W0, tau0, D, alpha must be > 0");
     if (!(p->k > 0 && p->k < 1)) return fail(DLB_EINVAL, "partition coefficient k must be in (0,1)");
     double W2t = p->W0 * p->W0 / p->tau0;
@@ -159,6 +160,8 @@ static KParams make_kparams(const dlb_params* p, const Layout& L) {
     double tol = p->grad_tol > 0 ? p->grad_tol : (f64 ? 1e-14 : (mixed ? 1e-10 : 1e-6));
     k.grad_tol2 = tol * tol;
     k.walls = p->bc == DLB_BC_CHANNEL;
+    k.use_t = p->isothermal ? 0 : 1;
+    k.theta0 = p->theta0;
     k.nbx = (p->nx + TILE_X - 1) / TILE_X;
     k.nby = (p->ny + TILE_Y - 1) / TILE_Y;
     k.nblocks = L.nblocks;

@@ -121,20 +121,23 @@ __device__ __forceinline__ void pct_node(const KParams& kp, const typename CF::S
     const bool wall = WALLS && is_wall(kp, x, y);
     const size_t src = wall ? inward_idx(kp, x, y) : idx;
 
-    T f[5], n[5], g[5];
+    T f[5], n[5], g[5] = {T(0), T(0), T(0), T(0), T(0)};
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
         f[i] = ld_pop<T>(pin, i * P + src, kp.shift[i]);
         n[i] = ld_pop<T>(pin, (5 + i) * P + src, kp.shift[5 + i]);
-        g[i] = ld_pop<T>(pin, (10 + i) * P + src, kp.shift[10 + i]);
     }
-    // macroscopic fields of time t (Sec. 3.1-3.3)
+    if (kp.use_t)
+#pragma unroll
+        for (int i = 0; i < 5; ++i) g[i] = ld_pop<T>(pin, (10 + i) * P + src, kp.shift[10 + i]);
+    // macroscopic fields of time t (Sec. 3.1-3.3); isothermal runs (no heat
+    // lattice) keep theta = theta0, H = theta0 - h(phi)/2
     const T phi = (((f[0] + f[1]) + f[2]) + f[3]) + f[4];
     const T C = (((n[0] + n[1]) + n[2]) + n[3]) + n[4];
-    const T H = (((g[0] + g[1]) + g[2]) + g[3]) + g[4];
     const T k = T(kp.k);
     const T hphi = h_of(phi, kp.h_quintic);
-    const T theta = H + T(0.5) * hphi;
+    const T H = kp.use_t ? (((g[0] + g[1]) + g[2]) + g[3]) + g[4] : T(kp.theta0) - T(0.5) * hphi;
+    const T theta = kp.use_t ? H + T(0.5) * hphi : T(kp.theta0);
     const T U = (T(2) * C / (T(1) + k - (T(1) - k) * phi) - T(1)) / (T(1) - k);
 
     // melt velocity of time t in main-step units: N_sub (3 - phi)/4 u*
@@ -250,7 +253,7 @@ __device__ __forceinline__ void pct_node(const KParams& kp, const typename CF::S
         T fold = i == 0 ? f[0] : ld_pop<T>(pin, i * P + (size_t)d, kp.shift[i]);
         st_pop(pout, i * P + (size_t)d, fold + (pf[i] - fold) * inv_a2, kp.shift[i]);
         st_pop(pout, (5 + i) * P + (size_t)d, pn[i], kp.shift[5 + i]);
-        st_pop(pout, (10 + i) * P + (size_t)d, pg[i], kp.shift[10 + i]);
+        if (kp.use_t) st_pop(pout, (10 + i) * P + (size_t)d, pg[i], kp.shift[10 + i]);
     }
 }
 
@@ -922,6 +925,7 @@ __device__ __forceinline__ void node_macros(const KParams& kp, const typename CF
         H += ld_pop<T>(pop, (10 + i) * P + src, kp.shift[10 + i]);
     }
     T k = T(kp.k);
+    if (!kp.use_t) H = T(kp.theta0) - T(0.5) * h_of(phi, kp.h_quintic);  // isothermal
     m[0] = phi;
     m[1] = C;
     m[2] = (T(2) * C / (T(1) + k - (T(1) - k) * phi) - T(1)) / (T(1) - k);

@@ -25,6 +25,8 @@ struct KParams {
     int nx, ny;
     long long plane;        // elements per SoA plane (>= nx*ny, 64-element multiple)
     int n_sub, h_quintic, grad_iters, walls;
+    int use_t;              // 0: isothermal, theta = theta0 (no heat lattice)
+    double theta0;
     int nbx, nby, nblocks;  // tile grid of the node kernels
     double W0, W2t;         // W0, W0^2/tau0
     double inv_tau0, eps4, co, so;

@@ -1,11 +1,19 @@
-"""Thermal dendrite at the paper's resolution (Sec. 4.2): tip velocity and
-radius against the steady value the paper reports (V d0 / alpha = 0.0166;
-0.017 from the Green's-function solution it cites).
+"""Dendrites at the paper's resolution.
 
-    python -m paper_2209_01444_amd.dendrite
+Thermal (Sec. 4.2): tip velocity and radius against the steady value the
+paper reports (V d0 / alpha = 0.0166; 0.017 from the Green's-function
+solution it cites).  Each record gives, every `every` main steps, t/tau0,
+the dimensionless tip velocity V d0/alpha of each arm over the last window,
+and rho_tip/d0.
 
-Each record gives, every `every` main steps, t/tau0, the dimensionless tip
-velocity V d0/alpha of arm 0 over the last window, and rho_tip/d0.
+Solutal, isothermal (Sec. 4.3): the concentration frozen into the solid on
+the central dendrite axis against the Gibbs-Thomson relation the paper
+checks, c_s/c_l^0 = k [1 - (1 - k) d0/r_tip], with r_tip the tip radius when
+the tip passed that point.  In the model's variables c_s/c_l^0 is C in the
+solid (C = k (1 + (1 - k) U) at phi = 1) and U = -d0 kappa at a curved
+interface of an isothermal alloy.
+
+    python -m paper_2209_01444_amd.dendrite [--solutal]
 """
 from __future__ import annotations
 
@@ -19,6 +27,8 @@ from paper_2209_01444_amd import dlb, workloads
 
 PAPER_V = 0.0166  # steady V d0 / alpha of Sec. 4.2
 D0_OVER_W0 = 0.1385
+# Sec. 4.3 prints d0 = 0.2762 W0 next to lambda = 3.191; a1 W0 / lambda gives 0.2770 W0
+D0_SOLUTAL = 0.8839 / 3.191
 
 
 def run(steps: int = 16000, every: int = 500, precision: str = "f32", L: int = 512) -> dict:
@@ -47,13 +57,65 @@ def run(steps: int = 16000, every: int = 500, precision: str = "f32", L: int = 5
             "paper_V": PAPER_V, "series": series}
 
 
+def run_solutal(steps: int = 40000, every: int = 200, precision: str = "f32", L: int = 1000,
+                skip_w0: float = 8.0) -> dict:
+    """Grow the isothermal alloy dendrite, recording arm 0's tip position and
+    radius every `every` steps; then compare C on the central axis, from
+    skip_w0 W0 outside the initial seed to skip_w0 W0 behind the final tip,
+    with the Gibbs-Thomson value at the tip radius of the passage time."""
+    import torch
+
+    cfg = workloads.solutal_dendrite(precision, L)
+    W0, k = cfg["W0"], cfg["k"]
+    d0 = D0_SOLUTAL * W0
+    s = dlb.Solver(cfg).init_seed(None)
+    torch.cuda.synchronize()
+    t_hist, s_hist, r_hist = [], [], []
+    el, t = 0.0, 0
+    while t < steps:
+        n = min(every, steps - t)
+        t0 = time.perf_counter()
+        s.step(n)
+        torch.cuda.synchronize()
+        el += time.perf_counter() - t0
+        t += n
+        r = s.reduce()
+        t_hist.append(t)
+        s_hist.append(float(r["tip_s"][0]))
+        r_hist.append(float(r["tip_rho"][0]))
+    f = s.fields()
+    yc, xc = int(round(cfg["seed_y"])), cfg["seed_x"]
+    row = f["C"][yc]
+    s_arr, r_arr = np.array(s_hist), np.array(r_hist)
+    x0 = int(np.ceil(xc + cfg["seed_R"] + skip_w0 * W0))
+    x1 = int(np.floor(xc + s_arr[-1] - skip_w0 * W0))
+    xs = np.arange(x0, x1 + 1)
+    # tip radius when the tip passed each x (the tip position grows monotonically)
+    rho = np.interp(xs - xc, s_arr, r_arr)
+    pred = k * (1.0 - (1.0 - k) * d0 / rho)
+    meas = row[xs]
+    err = meas / pred - 1.0
+    return {"workload": cfg["name"], "precision": precision, "steps": steps, "seconds": el,
+            "MLUPS": L * L * steps / el / 1e6, "t_tau0": steps / cfg["tau0"], "tip_s": s_arr[-1],
+            "rho_final_d0": r_arr[-1] / d0, "axis_range_lu": [int(x0 - xc), int(x1 - xc)],
+            "Cs_measured_mean": float(meas.mean()), "Cs_gibbs_thomson_mean": float(pred.mean()),
+            "max_rel_err": float(np.abs(err).max()), "mean_rel_err": float(err.mean()),
+            "trapping_free_value_k": k,
+            "profile": [[int(x - xc), round(float(m), 5), round(float(q), 5)]
+                        for x, m, q in zip(xs[::10], meas[::10], pred[::10])]}
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--steps", type=int, default=16000)
-    ap.add_argument("--every", type=int, default=500)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--every", type=int, default=None)
     ap.add_argument("--precision", default="f32")
+    ap.add_argument("--solutal", action="store_true")
     args = ap.parse_args()
-    print(json.dumps(run(args.steps, args.every, args.precision)), flush=True)
+    if args.solutal:
+        print(json.dumps(run_solutal(args.steps or 40000, args.every or 200, args.precision)), flush=True)
+    else:
+        print(json.dumps(run(args.steps or 16000, args.every or 500, args.precision)), flush=True)
 
 
 if __name__ == "__main__":

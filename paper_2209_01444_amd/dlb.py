@@ -29,7 +29,7 @@ class DlbError(RuntimeError):
 class DlbParams(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
         "nx", "ny", "use_ns", "bc", "n_sub", "h_quintic", "c_init_U", "precision", "grad_iters",
-        "flow_fuse", "phi_static")] + [(n, ctypes.c_double) for n in (
+        "flow_fuse", "phi_static", "isothermal")] + [(n, ctypes.c_double) for n in (
             "W0", "tau0", "eps4", "orient", "lambda_", "Mcinf", "k", "D", "alpha", "nu", "rho0",
             "u_in_x", "u_in_y", "theta0", "U0", "C0", "seed_R", "seed_x", "seed_y", "noise_amp",
             "grad_tol")]
@@ -122,8 +122,8 @@ def make_params(cfg: dict) -> DlbParams:
         if key not in c:
             raise KeyError(f"unknown parameter {key!r}")
         c[key] = val
-    if not (c["use_c"] and c["use_t"]):
-        raise ValueError("the GPU solver always runs the solute and heat lattices")
+    if not c["use_c"]:
+        raise ValueError("the GPU solver always runs the solute lattice")
     p = DlbParams()
     p.nx, p.ny = int(c["nx"]), int(c["ny"])
     p.use_ns = int(c["use_ns"])
@@ -135,6 +135,7 @@ def make_params(cfg: dict) -> DlbParams:
     p.grad_iters = int(c["grad_iters"])
     p.flow_fuse = int(c["flow_fuse"])
     p.phi_static = int(c["phi_static"])
+    p.isothermal = 0 if c["use_t"] else 1
     for name in ("W0", "tau0", "eps4", "orient", "lambda_", "Mcinf", "k", "D", "alpha", "nu", "rho0",
                  "theta0", "U0", "C0", "seed_R", "noise_amp", "grad_tol"):
         setattr(p, name, float(c[name]))

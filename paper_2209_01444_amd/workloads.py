@@ -92,6 +92,20 @@ def thermal_dendrite(precision: str = "f32", L: int = 512, W0: float = 2.5) -> d
         C0=1.0, seed_R=10.0, seed_x=L / 2.0, seed_y=L / 2.0, noise_amp=0.0, precision=precision)
 
 
+def solutal_dendrite(precision: str = "f32", L: int = 1000, W0: float = 2.5) -> dict:
+    """Isothermal alloy dendrite at the paper's resolution (Sec. 4.3):
+    L x L nodes, dx = 0.4 W0, dt = 0.02 tau0 (W0 = 2.5 lu, tau0 = 50 steps),
+    eps4 = 0.02, theta = 0 (no heat lattice), U0 = -0.55 (uniform initial
+    supersaturation), D = 2 W0^2/tau0, Mc_inf = 1, k = 0.15, lambda = 3.191,
+    seed R = 10 dx at the centre, zero-gradient walls, no flow."""
+    tau0 = W0 * W0 / 0.125
+    return dict(
+        name=f"solutal_dendrite_{L}", nx=L, ny=L, use_c=1, use_t=0, use_ns=0, walls=1, n_sub=1,
+        c_init_U=1, W0=W0, tau0=tau0, eps4=0.02, orient=0.0, lambda_=3.191, Mcinf=1.0, k=0.15,
+        D=2.0 * W0 * W0 / tau0, alpha=0.1, nu=0.1, rho0=1.0, u_in=(0.0, 0.0), theta0=0.0, U0=-0.55,
+        C0=1.0, seed_R=10.0, seed_x=L / 2.0, seed_y=L / 2.0, noise_amp=0.0, precision=precision)
+
+
 def cylinder_flow(Re: float, R: int = 20, precision: str = "f32", n_sub: int = 15) -> dict:
     """Flow past a stationary diffuse cylinder (Sec. 4.1): domain 70R x 40R
     nodes, cylinder of radius R lu centred at (20R, 20R), interface width
