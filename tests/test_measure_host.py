@@ -1,0 +1,48 @@
+"""Host-side measurement helpers (no GPU): the cylinder's drag coefficient
+and recirculation length, and the workloads' derived parameters."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2209_01444_amd import cylinder, workloads
+
+
+def test_cylinder_workload_matches_the_paper_setup():
+    cfg = workloads.cylinder_flow(40, R=20)
+    assert (cfg["nx"], cfg["ny"]) == (1400, 800)          # 70 R x 40 R on the paper's mesh
+    assert (cfg["seed_x"], cfg["seed_y"]) == (400.0, 400.0)
+    u0 = cfg["u_in"][0] / cfg["n_sub"]
+    nu = cfg["nu"] / cfg["n_sub"]
+    assert u0 == pytest.approx(0.1) and 1.0 / (3.0 * nu + 0.5) == pytest.approx(1.25)
+    assert 2 * u0 * cfg["seed_R"] / nu == pytest.approx(40.0)   # Re = 2 u0 R / nu
+
+
+def test_drag_coefficient_uses_the_sub_step_inflow():
+    cfg = workloads.cylinder_flow(20, R=20)
+    u0 = 0.05
+    red = {"Fx": 2.153 * 1.0 * 20 * u0 * u0, "Fx_solid": 0.0}
+    assert cylinder.drag_coefficient(red, cfg) == pytest.approx(2.153)
+
+
+def test_recirculation_length_from_a_synthetic_wake():
+    cfg = workloads.cylinder_flow(20, R=20)
+    ny, nx = cfg["ny"], cfg["nx"]
+    x = np.arange(nx, dtype=float)
+    rear = cfg["seed_x"] + cfg["seed_R"]
+    L = 37.3
+    row = np.where(x < rear, 0.0, np.tanh((x - rear - L) / 5.0))  # backward flow until rear + L
+    ux = np.zeros((ny, nx))
+    ux[int(cfg["seed_y"])] = row
+    assert cylinder.recirculation_length(ux, cfg) == pytest.approx(L / cfg["seed_R"], abs=1e-3)
+    ux[int(cfg["seed_y"])] = 1.0
+    assert cylinder.recirculation_length(ux, cfg) == 0.0
+
+
+def test_dendrite_workloads_use_the_paper_scales():
+    th = workloads.thermal_dendrite()
+    assert 1.0 / th["W0"] == pytest.approx(0.4) and th["tau0"] * 0.008 == pytest.approx(1.0)  # dx = 0.4 W0, dt = 0.008 tau0
+    assert th["alpha"] == pytest.approx(4 * th["W0"] ** 2 / th["tau0"])
+    so = workloads.solutal_dendrite()
+    assert 1.0 / so["W0"] == pytest.approx(0.4) and so["tau0"] * 0.02 == pytest.approx(1.0) and so["use_t"] == 0
+    assert so["D"] == pytest.approx(2 * so["W0"] ** 2 / so["tau0"])
