@@ -188,6 +188,8 @@ static KParams make_kparams(const dlb_params* p, const Layout& L) {
     k.seed_y = p->seed_y;
     k.noise_amp = p->noise_amp;
     if (p->precision == DLB_F16S || p->precision == DLB_BF16S) rest_shifts(p, k.shift);
+    for (int j = 0; j < 2; ++j)  // wave-row fused tiles, K = 3 and 5 (-1: no valid shift)
+        k.tbw_dy[j] = tbw_row_shift(p->ny, j ? 5 : 3, k.walls != 0, &k.tbw_nby[j]);
     return k;
 }
 
@@ -232,7 +234,8 @@ template <class CF, bool NS, bool W> struct OpsImpl {
         using T = typename CF::T;
         using G = TbGeom<T>;
         constexpr int OX = G::EX - 2 * K, OY = G::EY - 2 * K;
-        int nbx = (kp.nx + OX - 1) / OX, nby = (kp.ny + OY - 1) / OY;
+        const int nbx = (kp.nx + OX - 1) / OX;
+        const int nby = sizeof(T) == 4 ? kp.tbw_nby[K == 5] : (kp.ny + OY - 1) / OY;
         if constexpr (sizeof(T) == 4)
             hipLaunchKernelGGL((k_flow_tbw<CF, W, K>), dim3(nbx * nby), dim3(G::THREADS), 0, st, kp,
                                (const S*)hin, (S*)hout, (const H*)phi, nbx, nbx * nby);
@@ -446,6 +449,10 @@ int dlb_create(const dlb_params* p, void* dev_state, size_t bytes, void* hip_str
     s->p = *p;
     s->L = L;
     s->kp = make_kparams(p, L);
+    if (s->kp.tbw_dy[0] < 0 || s->kp.tbw_dy[1] < 0) {  // not reached for ny >= 3
+        delete s;
+        return fail(DLB_EUNSUPPORTED, "no row shift of the fused flow tiles fits this grid height");
+    }
     s->ops = select_ops(p);
     s->base = (char*)dev_state;
     s->bytes = bytes;
@@ -869,7 +876,7 @@ int dlb_batch_create(const dlb_params* ps, int count, void* dev_state, size_t by
         const int Ks[2] = {3, 5};
         for (int L = 0; L < 2; ++L) {
             int OX = EX - 2 * Ks[L], OY = EY - 2 * Ks[L];
-            int nbx = (ps[i].nx + OX - 1) / OX, nby = (ps[i].ny + OY - 1) / OY;
+            int nbx = (ps[i].nx + OX - 1) / OX, nby = f64 ? (ps[i].ny + OY - 1) / OY : m->kp.tbw_nby[L];
             d.tb0[L] = b->total_tb[L];
             d.tb_nbx[L] = nbx;
             b->total_tb[L] += nbx * nby;

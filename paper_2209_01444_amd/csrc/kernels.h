@@ -284,7 +284,7 @@ __device__ __forceinline__ void flow_step_node(const KParams& kp, const typename
     if (WALLS && is_wall(kp, x, y)) phi_f = T(phi_t[inward_idx(kp, x, y)]);
     flow_node<T, S, WALLS>(kp, hin, x, y, idx, phi_f, h);
     T o[9];
-    flow_collide<T>(h, phi, T(kp.s2u), o);
+    flow_collide<T>(h, flow_coef(phi), T(kp.s2u), o);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         long long d = push_dest<WALLS>(kp, x, y, C9X[i], C9Y[i]);
@@ -362,9 +362,10 @@ __device__ __forceinline__ void flow_tb_tile(const KParams& kp, const typename C
         for (int i = 0; i < 9; ++i) h[i] = T(0);
     }
     const T s2 = T(kp.s2u);
+    const FlowCoef<T> fc = flow_coef(phi);
     for (int sub = 0; sub < K; ++sub) {
         T o[9];
-        flow_collide<T>(h, phi, s2, o);
+        flow_collide<T>(h, fc, s2, o);
 #pragma unroll
         for (int i = 0; i < 9; ++i) lds[i][ty][tx] = o[i];
         __syncthreads();
@@ -401,14 +402,51 @@ __device__ __forceinline__ void flow_tb_tile(const KParams& kp, const typename C
 // collision, streaming along x is a one-lane shift of the wave (DPP), along y
 // a move between the thread's own rows; only the first and last row of each
 // wave cross to the neighbouring waves, through a small double-buffered LDS
-// exchange (one barrier per sub-step).  Wall nodes take the inward
-// neighbour's pulled populations: first along x (lane shift), then along y
-// (own rows or an LDS slot), so a corner takes the diagonal one, and rebuild
-// (wall_rebuild).  Arithmetic per node and sub-step is that of k_flow.
+// exchange (one barrier per sub-step).  Arithmetic per node and sub-step is
+// that of k_flow.
+//
+// Walls (channel, edge tiles only) need no further barrier.  The tiling is
+// shifted by kp.tbw_dy rows so that a wall row y = 0 or ny - 1 always lies in
+// the same wave as its inward row: its nodes take that row's pulled
+// populations from the thread's own registers.  The wall columns x = 0 and
+// nx - 1 are then rebuilt by one pass per wave: the lane of the inward column
+// writes its R rows to a per-wave LDS slot, lanes 0-7 rebuild one (side,
+// row) pair each (a corner from the row inward of it: the diagonal
+// neighbour), and the wall lane reads the results back.
 // ---------------------------------------------------------------------------
 struct TbWave {
     static constexpr int NW = 8, R = 4, EX = 64, EY = NW * R;
 };
+
+// Row shift of the wave-row tiling for K fused sub-steps (tile origin
+// y = by OY - K - dy): the smallest tile count among shifts dy in [0, 2R)
+// for which every wall row falling into a tile has its inward row in the
+// same wave.  Returns dy (0 without walls) and sets *nby; -1 if none.
+inline int tbw_row_shift(int ny, int K, bool walls, int* nby) {
+    constexpr int R = TbWave::R, EY = TbWave::EY;
+    const int OY = EY - 2 * K;
+    if (!walls) {
+        *nby = (ny + OY - 1) / OY;
+        return 0;
+    }
+    int best = -1, best_n = 0;
+    for (int dy = 0; dy < 2 * R; ++dy) {
+        const int n = (ny + dy + OY - 1) / OY;
+        bool ok = true;
+        for (int by = 0; by < n && ok; ++by) {
+            const int y0 = by * OY - K - dy;
+            const int t = -y0, b = ny - 1 - y0;
+            if (t >= 0 && t < EY) ok = t + 1 < EY && (t + 1) / R == t / R;
+            if (ok && b >= 0 && b < EY) ok = b >= 1 && (b - 1) / R == b / R;
+        }
+        if (ok && (best < 0 || n < best_n)) {
+            best = dy;
+            best_n = n;
+        }
+    }
+    *nby = best_n;
+    return best;
+}
 
 // DPP wave shifts: lane l receives the value of lane l - 1 (from_left) or
 // l + 1 (from_right); the edge lane receives 0 (a stale column).
@@ -417,6 +455,14 @@ __device__ __forceinline__ float lane_from_left(float v) {
 }
 __device__ __forceinline__ float lane_from_right(float v) {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
+}
+
+// orders this wave's LDS writes before its later LDS reads (lanes exchange
+// data through LDS within one wave)
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <class CF, bool WALLS, int K>
@@ -431,10 +477,13 @@ __device__ __forceinline__ void flow_tbw_tile(const KParams& kp, const typename 
     // exchange slots: [buffer][wave][k][lane]; k 0-2 = up-movers (2, 5, 6) of
     // the wave's last row, k 3-5 = down-movers (4, 7, 8) of its first row
     __shared__ float xch[2][NW][6][64];
-    __shared__ float ywall[2][9][64];  // inward rows of the y walls (top, bottom)
+    // wall-column pass: [wave][side (west, east)][row][population], rows
+    // padded to 12 floats
+    __shared__ float xw_in[WALLS ? NW : 1][2][R][12];
+    __shared__ float xw_out[WALLS ? NW : 1][2][R][12];
     const size_t P = (size_t)kp.plane;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int X0 = bx * OX - K, Y0 = by * OY - K;
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int X0 = bx * OX - K, Y0 = by * OY - K - (WALLS ? kp.tbw_dy[K == 5] : 0);
     int gx = X0 + lane;
     bool xin = true;
     if constexpr (WALLS) {
@@ -442,7 +491,17 @@ __device__ __forceinline__ void flow_tbw_tile(const KParams& kp, const typename 
     } else {
         gx = gx < 0 ? gx + kp.nx : (gx >= kp.nx ? gx - kp.nx : gx);
     }
-    T h[R][9], phi[R], phi_f[R];
+    // tile-uniform wall geometry (channel only): wall lanes of x = 0 and
+    // x = nx - 1, local rows of y = 0 and y = ny - 1
+    const bool west_tile = WALLS && X0 <= 0, east_tile = WALLS && X0 + EX - 1 >= kp.nx - 1;
+    const bool xwall_tile = west_tile || east_tile;
+    const int lane_w = -X0, lane_e = kp.nx - 1 - X0;
+    const int top_row = -Y0, bot_row = kp.ny - 1 - Y0;
+    const bool top_tile = WALLS && top_row >= 0 && top_row < EY;
+    const bool bot_tile = WALLS && bot_row >= 0 && bot_row < EY;
+    T h[R][9];
+    T phi_yw = T(0);  // frozen phi inward of this wave's wall row y = 0 or ny - 1
+    FlowCoef<T> fc[R];
     int gy[R];
     bool ex[R];
 #pragma unroll
@@ -456,23 +515,28 @@ __device__ __forceinline__ void flow_tbw_tile(const KParams& kp, const typename 
         }
         gy[r] = y;
         ex[r] = e;
-        phi[r] = phi_f[r] = T(0);
+        T phi = T(0);
         if (e) {
             const size_t idx = (size_t)y * kp.nx + gx;
-            phi[r] = T(phi_t[idx]);
-            phi_f[r] = phi[r];
-            if (WALLS && is_wall(kp, gx, y)) phi_f[r] = T(phi_t[inward_idx(kp, gx, y)]);
-            flow_node<T, S, WALLS>(kp, hin, gx, y, idx, phi_f[r], h[r]);
+            phi = T(phi_t[idx]);
+            T phi_f = phi;
+            if (WALLS && is_wall(kp, gx, y)) phi_f = T(phi_t[inward_idx(kp, gx, y)]);
+            if (WALLS && (y == 0 || y == kp.ny - 1)) phi_yw = phi_f;
+            flow_node<T, S, WALLS>(kp, hin, gx, y, idx, phi_f, h[r]);
         } else {
 #pragma unroll
             for (int i = 0; i < 9; ++i) h[r][i] = T(0);
         }
+        fc[r] = flow_coef(phi);
     }
-    // tile-uniform wall flags (channel only)
-    const bool xwall_tile = WALLS && (X0 <= 0 || X0 + EX - 1 >= kp.nx - 1);
-    const int top_row = -Y0, bot_row = kp.ny - 1 - Y0;  // local rows of y = 0 and y = ny - 1
-    const bool top_tile = WALLS && top_row >= 0 && top_row + 1 < EY;
-    const bool bot_tile = WALLS && bot_row - 1 >= 0 && bot_row < EY;
+    // rebuild lanes of the wall-column pass: lane j < 8 takes side j / R,
+    // row j % R of this wave; the frozen phi of that node's inward neighbour
+    // waits in the padding of its output slot
+    if constexpr (WALLS) {
+        const int xw_side = lane / R, xw_row = lane % R, xw_y = Y0 + w * R + xw_row;
+        if (xwall_tile && lane < 2 * R && (xw_side ? east_tile : west_tile) && xw_y >= 0 && xw_y < kp.ny)
+            xw_out[w][xw_side][xw_row][9] = T(phi_t[inward_idx(kp, xw_side ? kp.nx - 1 : 0, xw_y)]);
+    }
     const T s2 = T(kp.s2u);
 #pragma unroll
     for (int sub = 0; sub < K; ++sub) {
@@ -480,7 +544,7 @@ __device__ __forceinline__ void flow_tbw_tile(const KParams& kp, const typename 
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             T o[9];
-            flow_collide<T>(h[r], phi[r], s2, o);
+            flow_collide<T>(h[r], fc[r], s2, o);
             // x streaming: c_x = +1 from the left lane, c_x = -1 from the right lane
             h[r][0] = o[0];
             h[r][2] = o[2];
@@ -525,60 +589,59 @@ __device__ __forceinline__ void flow_tbw_tile(const KParams& kp, const typename 
             h[R - 1][8] = dn8;
         }
         if constexpr (WALLS) {
-            // wall nodes (edge tiles only): the inward neighbour's pulled
-            // populations, taken along x first (lane shift), then along y
-            if (xwall_tile || top_tile || bot_tile) {
-                const bool west = xin && gx == 0, east = xin && gx == kp.nx - 1;
-                const bool west_tile = X0 <= 0, east_tile = X0 + EX - 1 >= kp.nx - 1;
-                if (top_tile || bot_tile) {
-                    // the thread rows holding y = 1 and y = ny - 2 publish their x-staged values
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        const int lr = w * R + r;
-                        const bool pub_top = top_tile && lr == top_row + 1;
-                        const bool pub_bot = bot_tile && lr == bot_row - 1;
-                        if (pub_top || pub_bot) {  // wave-uniform
-#pragma unroll
-                            for (int i = 0; i < 9; ++i) {
-                                T v = h[r][i];
-                                if (west_tile) {
-                                    T a = lane_from_right(v);
-                                    v = west ? a : v;
-                                }
-                                if (east_tile) {
-                                    T b = lane_from_left(v);
-                                    v = east ? b : v;
-                                }
-                                ywall[pub_top ? 0 : 1][i][lane] = v;
-                            }
-                        }
-                    }
-                    __syncthreads();
-                }
+            // y walls: the inward row is in this wave (row shift of the tiling)
+            if (top_tile || bot_tile) {
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const int lr = w * R + r;
-                    const bool yrow_top = top_tile && lr == top_row, yrow_bot = bot_tile && lr == bot_row;
-                    if (!(xwall_tile || yrow_top || yrow_bot)) continue;  // wave-uniform
+                    const bool yt = top_tile && lr == top_row, yb = bot_tile && lr == bot_row;
+                    if (!(yt || yb)) continue;  // wave-uniform
                     T hf[9];
 #pragma unroll
-                    for (int i = 0; i < 9; ++i) {
-                        T v = h[r][i];
-                        if (west_tile) {
-                            T a = lane_from_right(v);
-                            v = west ? a : v;
-                        }
-                        if (east_tile) {
-                            T b = lane_from_left(v);
-                            v = east ? b : v;
-                        }
-                        if (yrow_top) v = ywall[0][i][lane];
-                        if (yrow_bot) v = ywall[1][i][lane];
-                        hf[i] = v;
-                    }
-                    if (ex[r] && is_wall(kp, gx, gy[r])) wall_rebuild(kp, gx, gy[r], hf, phi_f[r], h[r]);
+                    for (int i = 0; i < 9; ++i) hf[i] = yt ? h[r + 1 < R ? r + 1 : r][i] : h[r >= 1 ? r - 1 : r][i];
+                    if (ex[r]) wall_rebuild(kp, gx, gy[r], hf, phi_yw, h[r]);
                 }
-                if (top_tile || bot_tile) __syncthreads();  // ywall is rewritten next sub-step
+            }
+            // x walls: one rebuild pass per wave through LDS
+            if (xwall_tile) {
+#pragma unroll
+                for (int side = 0; side < 2; ++side) {
+                    if (!(side ? east_tile : west_tile)) continue;  // tile-uniform
+                    const int lane_in = side ? lane_e - 1 : lane_w + 1;
+                    if (lane == lane_in) {
+#pragma unroll
+                        for (int r = 0; r < R; ++r)
+#pragma unroll
+                            for (int i = 0; i < 9; ++i) xw_in[w][side][r][i] = h[r][i];
+                    }
+                }
+                wave_lds_sync();
+                const int xw_side = lane / R, xw_row = lane % R, xw_y = Y0 + w * R + xw_row;
+                if (lane < 2 * R && (xw_side ? east_tile : west_tile) && xw_y >= 0 && xw_y < kp.ny) {
+                    // a corner takes the row inward of it (same wave by the row shift)
+                    const int lr = w * R + xw_row;
+                    const int src = (top_tile && lr == top_row) ? xw_row + 1
+                                                                : ((bot_tile && lr == bot_row) ? xw_row - 1 : xw_row);
+                    T hf[9], hw[9];
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) hf[i] = xw_in[w][xw_side][src][i];
+                    wall_rebuild(kp, xw_side ? kp.nx - 1 : 0, xw_y, hf, T(xw_out[w][xw_side][xw_row][9]), hw);
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) xw_out[w][xw_side][xw_row][i] = hw[i];
+                }
+                wave_lds_sync();
+#pragma unroll
+                for (int side = 0; side < 2; ++side) {
+                    if (!(side ? east_tile : west_tile)) continue;
+                    if (lane == (side ? lane_e : lane_w)) {
+#pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            if (!ex[r]) continue;
+#pragma unroll
+                            for (int i = 0; i < 9; ++i) h[r][i] = xw_out[w][side][r][i];
+                        }
+                    }
+                }
             }
         }
     }
@@ -586,7 +649,7 @@ __device__ __forceinline__ void flow_tbw_tile(const KParams& kp, const typename 
     for (int r = 0; r < R; ++r) {
         const int lr = w * R + r;
         const bool out = lane >= K && lane < EX - K && lr >= K && lr < EY - K;
-        const int ox = bx * OX + (lane - K), oy = by * OY + (lr - K);
+        const int ox = bx * OX + (lane - K), oy = Y0 + lr;
         if (out && ex[r] && !(WALLS && is_wall(kp, gx, gy[r])) && ox < kp.nx && oy < kp.ny) {
             const size_t idx = (size_t)gy[r] * kp.nx + gx;
 #pragma unroll

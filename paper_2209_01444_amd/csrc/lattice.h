@@ -34,6 +34,7 @@ struct KParams {
     double nsub_d, uin_x_sub, uin_y_sub, grad_tol2;
     double seed_R, seed_x, seed_y, noise_amp, orient;
     float shift[24];        // storage shifts (rest-state populations) for 16-bit storage
+    int tbw_dy[2], tbw_nby[2];  // row shift and tile rows of the wave-row fused tiles, K = 3 / 5
 };
 
 static constexpr int TILE_X = 64;
@@ -259,34 +260,61 @@ template <class T> __device__ __forceinline__ FlowMacro<T> flow_macro(const T* h
     return m;
 }
 
-// One MRT collision; returns post-collision populations (shifted h_0).
-template <class T> __device__ __forceinline__ void flow_collide(const T* h, T phi, T s2, T* o) {
-    FlowMacro<T> M = flow_macro(h, phi);
-    T h57 = h[5] + h[7], h68 = h[6] + h[8];
-    T m3 = h[1] + h[3] + (h57 + h68);
-    T m4 = h[2] + h[4] + (h57 + h68);
-    T m5 = h57 - h68;
-    T ux = M.ux, uy = M.uy;
-    T m1 = ux + T(0.5) * M.Fx;  // s1 = 1: relaxed to u, plus (1 - 1/2) F
-    T m2 = uy + T(0.5) * M.Fy;
-    T n3 = m3 - s2 * (m3 - (M.p + ux * ux));
-    T n4 = m4 - s2 * (m4 - (M.p + uy * uy));
-    T n5 = m5 - s2 * (m5 - ux * uy);
-    T n6 = m2 * T(1.0 / 3.0);  // (uy + Fy/2)/3
-    T n7 = m1 * T(1.0 / 3.0);
-    T n8 = (M.p + ux * ux + uy * uy) * T(1.0 / 3.0);
-    // h = M^-1 m (inverse of the Appendix B transform)
-    o[0] = n8 - n3 - n4;
-    T a1 = n3 - n8, a2 = n4 - n8, d1 = m1 - n7, d2 = m2 - n6;
-    o[1] = T(0.5) * (a1 + d1);
-    o[3] = T(0.5) * (a1 - d1);
-    o[2] = T(0.5) * (a2 + d2);
-    o[4] = T(0.5) * (a2 - d2);
-    T b = n6 + n8, c = n8 - n6;
-    o[5] = T(0.25) * (n5 + n7 + b);
-    o[6] = T(0.25) * (-n5 - n7 + b);
-    o[7] = T(0.25) * (n5 - n7 + c);
-    o[8] = T(0.25) * (-n5 + n7 + c);
+// Per-node factors of the flow collision for the frozen phi of the main
+// step: with 1 - q(phi) = (1 + phi)/2 and f = -u*, the velocity is
+// u = u* (3 - phi)/4 and the relaxed first moment u + F/2 = u* (1 - phi)/2.
+template <class T> struct FlowCoef {
+    T cu, c1;
+};
+template <class T> __device__ __forceinline__ FlowCoef<T> flow_coef(T phi) {
+    return {(T(3) - phi) * T(0.25), (T(1) - phi) * T(0.5)};
+}
+
+template <class T> __device__ __forceinline__ T fmadd(T a, T b, T c) {
+    if constexpr (sizeof(T) == 4) return __builtin_fmaf(a, b, c);
+    else return __builtin_fma(a, b, c);
+}
+
+// One MRT collision (Sec. 3.4, Appendix B transform); returns post-collision
+// populations (shifted h_0).  Moments share their partial sums; the inverse
+// transform is written with the halved and quartered moment combinations:
+// since m1 - m1/3 = 2 m1/3, the x-links get (m3' - m8')/2 +- m1/3, and the
+// diagonals (+-m5' +- m7' + m8' +- m6')/4.  Fused multiply-adds are spelled
+// out and nothing else is contracted, so every kernel that inlines this
+// rounds alike.
+template <class T> __device__ __forceinline__ void flow_collide(const T* h, FlowCoef<T> c, T s2, T* o) {
+#pragma clang fp contract(off)
+    const T d57 = h[5] - h[7], d68 = h[6] - h[8];
+    const T s57 = h[5] + h[7], s68 = h[6] + h[8], e = s57 + s68;
+    const T s24 = h[2] + h[4];
+    const T mx = (h[1] - h[3]) + (d57 - d68);
+    const T my = (h[2] - h[4]) + (d57 + d68);
+    const T m3 = (h[1] + h[3]) + e, m4 = s24 + e, m5 = s57 - s68;
+    const T rest = m3 + s24;  // sum of h_1 .. h_8
+    const T ux = mx * c.cu, uy = my * c.cu;
+    const T m1 = mx * c.c1, m2 = my * c.c1;  // s1 = 1: u + F/2
+    const T ux2 = ux * ux, uu = fmadd(uy, uy, ux2);
+    const T p = fmadd(T(-0.4), uu, T(0.6) * rest);
+    const T r2 = T(1) - s2;
+    const T n3 = fmadd(s2, p + ux2, r2 * m3);
+    const T n4 = fmadd(s2, fmadd(uy, uy, p), r2 * m4);
+    const T n5 = fmadd(s2, ux * uy, r2 * m5);
+    const T n6 = m2 * T(1.0 / 3.0), n7 = m1 * T(1.0 / 3.0);
+    const T n8 = (p + uu) * T(1.0 / 3.0);
+    o[0] = (n8 - n3) - n4;
+    const T hn8 = T(-0.5) * n8;
+    const T a1 = fmadd(T(0.5), n3, hn8), a2 = fmadd(T(0.5), n4, hn8);
+    o[1] = a1 + n7;
+    o[3] = a1 - n7;
+    o[2] = a2 + n6;
+    o[4] = a2 - n6;
+    const T q6 = T(0.25) * n6, q7 = T(0.25) * n7;
+    const T b = fmadd(T(0.25), n8, q6), bc = fmadd(T(0.25), n8, -q6);
+    const T t1 = fmadd(T(0.25), n5, q7), t2 = fmadd(T(0.25), n5, -q7);
+    o[5] = b + t1;
+    o[6] = b - t1;
+    o[7] = bc + t2;
+    o[8] = bc - t2;
 }
 
 }  // namespace dlb

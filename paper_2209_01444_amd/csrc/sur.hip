@@ -156,7 +156,10 @@ void launch_conv_t(hipStream_t st, const bf16* in, const bf16* wt, const float* 
 // Y = conv(X, Wt) (+ bias, leaky ReLU); Cin and Cout multiples of 32
 void launch_conv(hipStream_t st, const bf16* in, const bf16* wt, const float* bias, bf16* out, int B, int H, int W,
                  int Cin, int Cout, bool act) {
-    const bool wide = Cout % 64 == 0;
+    // 64 output channels per workgroup, unless that leaves fewer than 512
+    // workgroups (deep levels at small batch): then 32, for twice as many
+    const long long tiles = (long long)((W + CT_X - 1) / CT_X) * ((H + CT_Y - 1) / CT_Y) * B;
+    const bool wide = Cout % 64 == 0 && tiles * (Cout / 64) >= 512;
     if (bias) {
         if (wide) {
             if (act) launch_conv_t<4, true, true>(st, in, wt, bias, out, B, H, W, Cin, Cout);

@@ -224,11 +224,15 @@ def test_small_and_ragged_grids(dlb, nx, ny, walls, fuse):
 
 
 @pytest.mark.parametrize("nx,ny,walls,fuse", [(16, 16, 1, 5), (17, 19, 0, 5), (50, 23, 1, 5), (40, 37, 1, 3),
-                                              (65, 21, 1, 5), (64, 64, 0, 5), (119, 61, 1, 5)])
+                                              (65, 21, 1, 5), (64, 64, 0, 5), (119, 61, 1, 5), (33, 25, 1, 3),
+                                              (70, 24, 1, 5)])
 def test_small_grids_fp32_fused_kernel(dlb, nx, ny, walls, fuse):
     """The FP32 wave-row fused kernel on grids where one tile holds both
-    x walls (nx <= 54 at K = 5), both y walls (ny <= 22), or ragged edges:
-    against the unfused path (same arithmetic) and against the oracle."""
+    x walls (nx <= 54 at K = 5), both y walls (ny <= 22), or ragged edges,
+    and with the tiling shifted by 0, 1 or 2 rows so that the wall row sits
+    with its inward row (ny 23 and 24 at K = 5, 25 at K = 3 also put the
+    bottom wall into the halo of the tile above the last): against the
+    unfused path (same arithmetic) and against the oracle."""
     _say(f"case: FP32 fused kernel, small grid {nx}x{ny} walls={walls} fuse={fuse}")
     cfg = dict(W.pure_diffusion_128("f32"), nx=nx, ny=ny, seed_x=nx / 2 - 0.3, seed_y=ny / 2 + 0.2,
                seed_R=3.0, walls=walls, use_ns=1, n_sub=15, nu=0.3, u_in=(0.01, 0.004),
