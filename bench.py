@@ -46,17 +46,36 @@ def algorithmic_bytes(cfg: dict) -> dict:
     return {"pct": pct, "flow": flow, "step": pct + (cfg["n_sub"] * flow if ns else 0)}
 
 
-def traffic_from_profiles(kernel: str, workload: str) -> float | None:
-    """Counter-measured HBM bytes per launch from a committed summary, only
-    if it was taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+# VALU issue rate of the chip: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64
+# vector instruction per SIMD every 4 cycles
+PEAK_VALU_INSTS_PER_S = 256 * 4 * 2.4e9 / 4
+
+
+def _profile_record(kind: str, kernel: str, workload: str) -> dict | None:
+    """A committed counter summary, only if it was taken on the current
+    kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"{kind}_{kernel}_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
     if rec.get("source_hash") != kernel_source_hash():
         return None
-    return rec.get("bytes_per_launch")
+    return rec
+
+
+def traffic_from_profiles(kernel: str, workload: str) -> float | None:
+    """Counter-measured HBM bytes per launch (FETCH_SIZE and WRITE_SIZE,
+    copy-calibrated)."""
+    rec = _profile_record("traffic", kernel, workload)
+    return rec.get("bytes_per_launch") if rec else None
+
+
+def valu_from_profiles(kernel: str, workload: str) -> float | None:
+    """Counter-measured wave-level VALU instructions per launch
+    (SQ_INSTS_VALU)."""
+    rec = _profile_record("valu", kernel, workload)
+    return rec.get("valu_insts_per_launch") if rec else None
 
 
 def cpu_baseline(cfg, noise, budget_s: float = 12.0) -> dict:
@@ -118,8 +137,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no multi-GPU "
-              "path: see the sharding design in DESIGN.md", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the solver has no multi-GPU "
+              "path, it measures one GPU's share of the workload", file=sys.stderr)
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy()
@@ -158,6 +177,7 @@ def main():
     wl = f"thermosolutal_flow_{cfg['nx']}x{cfg['ny']}_{cfg['precision']}"
     # FP32 arithmetic fuses with the wave-row tile kernel, FP64 arithmetic with the LDS tile kernel
     fused_name = "k_flow_tb" if cfg["precision"] in ("f64", "f32m") else "k_flow_tbw"
+    valu = valu_from_profiles(fused_name if subs_per_launch > 1 else "k_flow", wl)
     red = solver.reduce(allow_nonfinite=True)
 
     line = {
@@ -184,6 +204,8 @@ def main():
             "frac": round(achieved / PEAK_HBM_GBS, 4),
             "traffic": traffic_from_profiles(fused_name if subs_per_launch > 1 else "k_flow", wl),
             "avg_launch_ms": round(flow_ms, 5), "bytes_per_launch": flow_bytes,
+            "valu_issue_frac": (None if valu is None
+                                else round(valu / (flow_ms * 1e-3) / PEAK_VALU_INSTS_PER_S, 4)),
         },
         "kernels": {
             "k_pct": {"avg_ms": round(pct_ms, 5), "GBs": round(ab["pct"] * nodes / (pct_ms * 1e-3) / 1e9, 1)},

@@ -1,0 +1,56 @@
+"""Host-side checks of bench.py: algorithmic byte counts, the single-GPU
+guard and the readers of the committed counter summaries."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_algorithmic_bytes_per_node_step():
+    # FP32 with flow: k_pct moves 15 populations in and out, reads 8 moving
+    # flow populations and reads and writes 6 history planes; each of the
+    # 15 flow sub-steps moves 9 populations in and out and reads phi
+    cfg = {"precision": "f32", "use_ns": 1, "n_sub": 15}
+    ab = bench.algorithmic_bytes(cfg)
+    assert ab["pct"] == 30 * 4 + 8 * 4 + 2 * 6 * 4
+    assert ab["flow"] == 18 * 4 + 4
+    assert ab["step"] == 1340
+    # 16-bit storage halves the population bytes, history stays FP32
+    ab16 = bench.algorithmic_bytes(dict(cfg, precision="f16s"))
+    assert ab16["flow"] == 18 * 2 + 4 and ab16["pct"] == 30 * 2 + 8 * 2 + 48
+    # no flow: 15 populations and 2 history planes
+    ab0 = bench.algorithmic_bytes({"precision": "f64", "use_ns": 0, "n_sub": 1})
+    assert ab0["step"] == ab0["pct"] == 30 * 8 + 2 * 2 * 8
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_valu_issue_peak():
+    # 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles per wave64 instruction
+    assert bench.PEAK_VALU_INSTS_PER_S == pytest.approx(614.4e9)
+
+
+def test_counter_records_follow_the_source_hash(tmp_path, monkeypatch):
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    h = bench.kernel_source_hash()
+    (prof / "traffic_kx_wl.json").write_text(json.dumps({"source_hash": h, "bytes_per_launch": 123.0}))
+    (prof / "valu_kx_wl.json").write_text(json.dumps({"source_hash": h, "valu_insts_per_launch": 7}))
+    (prof / "traffic_ky_wl.json").write_text(json.dumps({"source_hash": "stale", "bytes_per_launch": 1.0}))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: h)
+    assert bench.traffic_from_profiles("kx", "wl") == 123.0
+    assert bench.valu_from_profiles("kx", "wl") == 7
+    assert bench.traffic_from_profiles("ky", "wl") is None  # taken on other sources
+    assert bench.valu_from_profiles("kz", "wl") is None     # absent
