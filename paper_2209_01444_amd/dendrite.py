@@ -13,7 +13,12 @@ the tip passed that point.  In the model's variables c_s/c_l^0 is C in the
 solid (C = k (1 + (1 - k) U) at phi = 1) and U = -d0 kappa at a curved
 interface of an isothermal alloy.
 
-    python -m paper_2209_01444_amd.dendrite [--solutal]
+Thermal with melt flow (Sec. 4.2): inflow W0/tau0 from the west; the
+paper describes the upstream arm outgrowing the others, the vertical arms
+settling at the pure-diffusion velocity and the downstream arm slowing to
+a lower constant velocity.
+
+    python -m paper_2209_01444_amd.dendrite [--solutal | --flow]
 """
 from __future__ import annotations
 
@@ -31,10 +36,13 @@ D0_OVER_W0 = 0.1385
 D0_SOLUTAL = 0.8839 / 3.191
 
 
-def run(steps: int = 16000, every: int = 500, precision: str = "f32", L: int = 512) -> dict:
+def run(steps: int = 16000, every: int = 500, precision: str = "f32", L: int = 512, flow: bool = False) -> dict:
+    """Thermal dendrite; with flow=True the melt-flow case (inflow along +x):
+    arm 0 (+x) grows downstream, arm 2 (-x) upstream, arms 1 and 3 across
+    the flow."""
     import torch
 
-    cfg = workloads.thermal_dendrite(precision, L)
+    cfg = workloads.thermal_dendrite(precision, L, flow=flow)
     d0 = D0_OVER_W0 * cfg["W0"]
     s = dlb.Solver(cfg).init_seed(None)
     torch.cuda.synchronize()
@@ -52,9 +60,13 @@ def run(steps: int = 16000, every: int = 500, precision: str = "f32", L: int = 5
         prev = r["tip_s"]
         series.append({"t_tau0": t / cfg["tau0"], "V": (v * d0 / cfg["alpha"]).round(5).tolist(),
                        "rho_d0": (r["tip_rho"] / d0).round(3).tolist()})
-    return {"workload": cfg["name"], "precision": precision, "steps": steps, "seconds": el,
-            "MLUPS": L * L * steps / el / 1e6, "V_final": float(np.mean(series[-1]["V"])),
-            "paper_V": PAPER_V, "series": series}
+    out = {"workload": cfg["name"], "precision": precision, "steps": steps, "seconds": el,
+           "MLUPS": L * L * steps / el / 1e6, "V_final": float(np.mean(series[-1]["V"])),
+           "paper_V": PAPER_V, "series": series}
+    if flow:
+        v = series[-1]["V"]
+        out.update(V_downstream=v[0], V_upstream=v[2], V_vertical=0.5 * (v[1] + v[3]))
+    return out
 
 
 def run_solutal(steps: int = 40000, every: int = 200, precision: str = "f32", L: int = 1000,
@@ -111,11 +123,13 @@ def main():
     ap.add_argument("--every", type=int, default=None)
     ap.add_argument("--precision", default="f32")
     ap.add_argument("--solutal", action="store_true")
+    ap.add_argument("--flow", action="store_true", help="thermal dendrite with melt flow")
     args = ap.parse_args()
     if args.solutal:
         print(json.dumps(run_solutal(args.steps or 40000, args.every or 200, args.precision)), flush=True)
     else:
-        print(json.dumps(run(args.steps or 16000, args.every or 500, args.precision)), flush=True)
+        print(json.dumps(run(args.steps or 16000, args.every or 500, args.precision, flow=args.flow)),
+              flush=True)
 
 
 if __name__ == "__main__":

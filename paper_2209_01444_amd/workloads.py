@@ -77,19 +77,32 @@ def batched_sweep(count: int = 256, seed: int = 4) -> list[tuple[dict, np.ndarra
     return out
 
 
-def thermal_dendrite(precision: str = "f32", L: int = 512, W0: float = 2.5) -> dict:
+def thermal_dendrite(precision: str = "f32", L: int = 512, W0: float = 2.5, flow: bool = False) -> dict:
     """Thermal dendrite into an undercooled melt at the paper's resolution
     (Sec. 4.2): L x L nodes with dx = 0.4 W0 and dt = 0.008 tau0, i.e.
     W0 = 2.5 lu and tau0 = 125 steps (W0^2/tau0 = 0.05 lu^2/step as in the
     coarser mapping); Delta = 0.55, eps4 = 0.05, Mc_inf = 0, uniform c,
     alpha = 4 W0^2/tau0, lambda = 0.8839/0.1385, seed R = 10 dx at the centre,
-    zero-gradient (symmetry) walls, no flow."""
+    zero-gradient (symmetry) walls, no flow.
+
+    flow=True: the melt-flow case of the same section, inflow u_in = W0/tau0
+    along +x at the west wall, free outflow east, Pr = nu/alpha = 23.1, 15
+    flow sub-steps per main step; the seed sits on the channel's centre
+    line ((L - 1)/2) so that the two vertical arms mirror each other."""
     tau0 = W0 * W0 / 0.05
+    alpha = 4.0 * W0 * W0 / tau0
+    if not flow:
+        return dict(
+            name=f"thermal_dendrite_{L}", nx=L, ny=L, use_c=1, use_t=1, use_ns=0, walls=1, n_sub=1,
+            W0=W0, tau0=tau0, eps4=0.05, orient=0.0, lambda_=LAMBDA_THERMAL, Mcinf=0.0, k=0.15,
+            D=0.1, alpha=alpha, nu=0.1, rho0=1.0, u_in=(0.0, 0.0), theta0=-0.55, U0=0.0,
+            C0=1.0, seed_R=10.0, seed_x=L / 2.0, seed_y=L / 2.0, noise_amp=0.0, precision=precision)
+    c = (L - 1) / 2.0
     return dict(
-        name=f"thermal_dendrite_{L}", nx=L, ny=L, use_c=1, use_t=1, use_ns=0, walls=1, n_sub=1,
+        name=f"thermal_dendrite_flow_{L}", nx=L, ny=L, use_c=1, use_t=1, use_ns=1, walls=1, n_sub=15,
         W0=W0, tau0=tau0, eps4=0.05, orient=0.0, lambda_=LAMBDA_THERMAL, Mcinf=0.0, k=0.15,
-        D=0.1, alpha=4.0 * W0 * W0 / tau0, nu=0.1, rho0=1.0, u_in=(0.0, 0.0), theta0=-0.55, U0=0.0,
-        C0=1.0, seed_R=10.0, seed_x=L / 2.0, seed_y=L / 2.0, noise_amp=0.0, precision=precision)
+        D=0.1, alpha=alpha, nu=23.1 * alpha, rho0=1.0, u_in=(W0 / tau0, 0.0), theta0=-0.55, U0=0.0,
+        C0=1.0, seed_R=10.0, seed_x=c, seed_y=c, noise_amp=0.0, precision=precision)
 
 
 def solutal_dendrite(precision: str = "f32", L: int = 1000, W0: float = 2.5) -> dict:

@@ -270,7 +270,7 @@ def test_cylinder_drag_matches_the_paper(dlb, Re):
     """Pin of the flow lattice and the diffuse fluid-solid force against the
     paper's table of Sec. 4.1 (stationary cylinder, R = 20 lu on the paper's
     1400 x 800 mesh): C_d = 2.153 / 1.598 and L_W = 1.853 / 4.491 at Re =
-    20 / 40.  This build gives C_d 2.6% / 3.2% and L_W 10% / 9% above them;
+    20 / 40.  The solver gives C_d 2.6% / 3.2% and L_W 10% / 9% above them;
     the bars are 5% and 15%.  (The literal alternative reading of the force,
     f summed over the solid nodes only, gives C_d 27% low.)"""
     from paper_2209_01444_amd import cylinder
@@ -287,7 +287,7 @@ def test_thermal_dendrite_tip_velocity_matches_the_paper(dlb):
     printed in Sec. 4.2: the thermal dendrite at the paper's resolution
     (512 x 512, dx = 0.4 W0, dt = 0.008 tau0, Delta = 0.55, eps4 = 0.05)
     reaches a steady tip velocity V d0/alpha = 0.0166 (0.017 from the
-    Green's-function solution).  This build gives 0.0167 over t = 100..148
+    Green's-function solution).  The solver gives 0.0167 over t = 100..148
     tau0; the bar is 3% on the window 112..128 tau0."""
     from paper_2209_01444_amd import dendrite
     _say("case: thermal dendrite 512x512 FP32, 16000 steps")
@@ -297,6 +297,27 @@ def test_thermal_dendrite_tip_velocity_matches_the_paper(dlb):
     assert abs(v / dendrite.PAPER_V - 1) < 0.03
     # fourfold symmetry at orientation 0: the four arms agree
     assert np.ptp(r["series"][-1]["V"]) < 1e-3 * v
+
+
+def test_thermal_dendrite_with_melt_flow_follows_the_paper(dlb):
+    """The melt-flow case of Sec. 4.2 (inflow W0/tau0 from the west, Pr =
+    23.1, 15 flow sub-steps per main step) at 512 x 512 to t = 128 tau0,
+    against what the section describes: the upstream arm (-x) grows fastest
+    and speeds up, the arms across the flow settle at the pure-diffusion tip
+    velocity (0.0166), and the downstream arm (+x) slows below them.  The
+    solver gives 0.0255 upstream, 0.0168 across and 0.0114 downstream at
+    t = 128 tau0."""
+    from paper_2209_01444_amd import dendrite
+    _say("case: thermal dendrite with melt flow 512x512 FP32, 16000 steps")
+    r = dendrite.run(16000, 2000, "f32", flow=True)
+    up, across, down = r["V_upstream"], r["V_vertical"], r["V_downstream"]
+    _say(f"  V d0/alpha at 128 tau0: upstream {up:.5f}, across {across:.5f}, downstream {down:.5f}")
+    assert up > 1.3 * across and down < 0.8 * across
+    assert abs(across / dendrite.PAPER_V - 1) < 0.05
+    mid, last = r["series"][3]["V"], r["series"][-1]["V"]  # t = 64 and 128 tau0
+    assert last[2] > mid[2] and last[0] < mid[0]
+    # the seed sits on the channel's centre line: the arms across the flow mirror each other
+    assert abs(last[1] - last[3]) <= 1e-3 * across
 
 
 @pytest.mark.parametrize("precision,tol", [("f64", 1e-10), ("f32", 1e-4)])
@@ -316,7 +337,7 @@ def test_solutal_dendrite_follows_gibbs_thomson(dlb):
     the isothermal alloy dendrite at the paper's resolution (1000 x 1000,
     dx = 0.4 W0, dt = 0.02 tau0) freezes into the solid on its central axis
     the concentration c_s/c_l^0 = k [1 - (1 - k) d0/r_tip] that the paper
-    checks.  This build: mean deviation 0.3%, at most 0.9% (without the
+    checks.  The solver: mean deviation 0.3%, at most 0.9% (without the
     anti-trapping current the solid traps solute: 18% mean deviation)."""
     from paper_2209_01444_amd import dendrite
     _say("case: solutal dendrite 1000x1000 FP32, 40000 steps, Gibbs-Thomson on the axis")

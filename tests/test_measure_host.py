@@ -46,3 +46,17 @@ def test_dendrite_workloads_use_the_paper_scales():
     so = workloads.solutal_dendrite()
     assert 1.0 / so["W0"] == pytest.approx(0.4) and so["tau0"] * 0.02 == pytest.approx(1.0) and so["use_t"] == 0
     assert so["D"] == pytest.approx(2 * so["W0"] ** 2 / so["tau0"])
+
+
+def test_thermal_dendrite_flow_workload():
+    # Sec. 4.2 with melt flow: inflow W0/tau0, Pr = nu/alpha = 23.1, seed on
+    # the channel's centre line, 15 flow sub-steps with a stable rate
+    fl = workloads.thermal_dendrite(flow=True)
+    th = workloads.thermal_dendrite()
+    assert fl["u_in"] == (pytest.approx(fl["W0"] / fl["tau0"]), 0.0) and fl["use_ns"] == 1
+    assert fl["nu"] / fl["alpha"] == pytest.approx(23.1)
+    assert fl["seed_x"] == fl["seed_y"] == (fl["nx"] - 1) / 2
+    assert all(fl[k] == th[k] for k in ("W0", "tau0", "alpha", "lambda_", "eps4", "theta0", "seed_R"))
+    s2 = 1.0 / (3.0 * fl["nu"] / fl["n_sub"] + 0.5)
+    assert 0.0 < s2 < 2.0
+    assert fl["u_in"][0] / fl["n_sub"] * 3 ** 0.5 < 0.1  # Mach number per sub-step
