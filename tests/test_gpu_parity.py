@@ -164,6 +164,23 @@ def test_thermosolutal_flow_parity_ragged(dlb, precision, tol, steps):
         assert rg[key] == pytest.approx(ro[key], rel=max(tol, 1e-12) * 10, abs=1e-12), key
 
 
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_quintic_interpolation_parity(dlb, precision, tol):
+    """The quintic h(phi) = 15(phi - 2 phi^3/3 + phi^5/5)/8 that Sec. 2
+    offers beside h = phi, in the heat equilibrium and in theta = H +
+    h(phi)/2, on the coupled channel case: GPU against the oracle."""
+    nx, ny = 64, 48
+    _say(f"case: quintic h(phi), thermosolutal flow {nx}x{ny} channel {precision}, 200 steps")
+    cfg, noise = _flow_case(nx, ny, precision)
+    cfg = dict(cfg, h_quintic=1)
+    o = O.Oracle(cfg).init_seed(noise).step(200)
+    s = dlb.Solver(cfg).init_seed(noise).step(200)
+    compare(s.fields(), o.fields(), tol, label=f"quintic {precision}")
+    # the interpolation matters: h = phi gives a different temperature field
+    lin = O.Oracle(dict(cfg, h_quintic=0)).init_seed(noise).step(200)
+    assert np.abs(lin.fields()["theta"] - o.fields()["theta"]).max() > 1e-3
+
+
 @pytest.mark.parametrize("precision", ["f64", "f32", "f16s"])
 @pytest.mark.parametrize("walls", [1, 0])
 def test_fused_flow_substeps_match_single_substeps(dlb, precision, walls):
