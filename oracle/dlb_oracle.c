@@ -292,6 +292,28 @@ void orc_local_gradient(const orc_params* p, double m1x, double m1y, double* out
     out[5] = (double)it;
 }
 
+/* Isotropic nine-point gradient of a node field: with the D2Q9 weights w_i
+ * and cs^2 = 1/3, grad F = (1/cs^2) sum_i w_i c_i F(x + c_i) + O(dx^2).
+ * Neighbours wrap on periodic grids and are clamped on channel grids. */
+void orc_stencil_gradient(const orc_params* p, const double* F, int x, int y, double* out) {
+    int nx = p->nx, ny = p->ny;
+    double gx = 0.0, gy = 0.0;
+    for (int i = 1; i < 9; ++i) {
+        int xx = x + C9X[i], yy = y + C9Y[i];
+        if (p->walls) {
+            xx = xx < 0 ? 0 : (xx > nx - 1 ? nx - 1 : xx);
+            yy = yy < 0 ? 0 : (yy > ny - 1 ? ny - 1 : yy);
+        } else {
+            xx = (xx % nx + nx) % nx;
+            yy = (yy % ny + ny) % ny;
+        }
+        gx += 3.0 * W9[i] * C9X[i] * F[yy * nx + xx];
+        gy += 3.0 * W9[i] * C9Y[i] * F[yy * nx + xx];
+    }
+    out[0] = gx;
+    out[1] = gy;
+}
+
 /* ---------------------------------------------------------------------------
  * Flow lattice macros and collision (Sec. 3.4), in sub-step units dt' = 1.
  *   u* = sum c_i h_i + dt/2 F   (external force F = 0, reading)
@@ -559,7 +581,26 @@ static void collide_pct_node(orc_state* s, int x) {
         m1y += C5Y[i] * f[i];
     }
     double lg[6];
-    orc_local_gradient(p, m1x, m1y, lg);
+    if (p->grad_stencil) {
+        /* ablation: grad phi from the node values of phi at time t; a wall
+         * node, a copy of its inward neighbour, takes that node's gradient */
+        int xi = x % s->nx, yi = x / s->nx;
+        if (is_wall(s, xi, yi)) {
+            int f = inward(s, xi, yi);
+            xi = f % s->nx;
+            yi = f / s->nx;
+        }
+        orc_stencil_gradient(p, s->phi, xi, yi, lg);
+        if (lg[0] * lg[0] + lg[1] * lg[1] < GRAD_GUARD) {
+            lg[0] = lg[1] = 0.0;
+            lg[2] = p->fixed_as > 0.0 ? p->fixed_as : 1.0;
+            lg[3] = lg[4] = 0.0;
+        } else {
+            aniso_or_hook(p, lg[0], lg[1], &lg[2], &lg[3], &lg[4]);
+        }
+    } else {
+        orc_local_gradient(p, m1x, m1y, lg);
+    }
     double gx = lg[0], gy = lg[1], a = lg[2], Nx = lg[3], Ny = lg[4];
     double a2 = a * a;
     double s1 = s1_phi(p, a);
@@ -759,20 +800,9 @@ int orc_set_fields(orc_state* s, const double* phi, const double* Cin, const dou
  * (periodic wrap, or clamped at the channel walls). */
 static void cd_first_moment(const orc_state* s, const double* F, int x, int y, double* V) {
     const orc_params* p = &s->p;
-    int nx = s->nx, ny = s->ny;
-    double gx = 0.0, gy = 0.0;
-    for (int i = 1; i < 9; ++i) {
-        int xx = x + C9X[i], yy = y + C9Y[i];
-        if (p->walls) {
-            xx = xx < 0 ? 0 : (xx > nx - 1 ? nx - 1 : xx);
-            yy = yy < 0 ? 0 : (yy > ny - 1 ? ny - 1 : yy);
-        } else {
-            xx = wrap(xx, nx);
-            yy = wrap(yy, ny);
-        }
-        gx += 3.0 * W9[i] * C9X[i] * F[yy * nx + xx];
-        gy += 3.0 * W9[i] * C9Y[i] * F[yy * nx + xx];
-    }
+    double g[2];
+    orc_stencil_gradient(p, F, x, y, g);
+    double gx = g[0], gy = g[1];
     V[0] = V[1] = 0.0;
     if (gx * gx + gy * gy >= GRAD_GUARD) {
         double a, Nx, Ny;

@@ -31,6 +31,8 @@
  *     stationary-cylinder drag is within 3.2% of the values printed in
  *     the table of Sec. 4.1                                       indirect
  *   restart flags (orc_set_fields_ex): continuation is exact      pinned
+ *   stencil-gradient ablation (grad_stencil): exact on quadratics,
+ *     stationary planar fronts at second order                    pinned
  *   tip position / radius measurement                             pinned (geometry)
  */
 #ifndef DLB_ORACLE_H
@@ -54,6 +56,9 @@ typedef struct orc_params {
     int phi_static;   /* 1: phi, C and theta stay as set; only the flow lattice
                          steps (n_sub sub-steps per main step) past the frozen
                          diffuse solid: the stationary-cylinder problem      */
+    int grad_stencil; /* 0: the local gradient of Sec. 3.1 (the method);
+                         1: ablation, grad phi from the isotropic nine-point
+                         difference of the node values of phi               */
     double W0, tau0, eps4, orient, lambda, Mcinf, k, D, alpha, nu, rho0;
     double u_in_x, u_in_y;   /* inflow / initial velocity, lu per main step  */
     double theta0, U0, C0;
@@ -131,6 +136,10 @@ void orc_force_flow(double Fx, double Fy, double* out9);
 void orc_anisotropy(double eps4, double orient, double gx, double gy, double* out3);
 /* out: gx, gy, a_s, Nx, Ny, iterations */
 void orc_local_gradient(const orc_params* p, double m1x, double m1y, double* out6);
+/* Stencil gradient at node (x, y) of the node field phi (nx*ny): the
+ * isotropic difference 3 sum_i w_i c_i phi(x + c_i) with the D2Q9 weights
+ * (periodic wrap, or clamped at the channel walls); out: gx, gy. */
+void orc_stencil_gradient(const orc_params* p, const double* phi, int x, int y, double* out2);
 /* One flow collision at a node (sub-step units): pre-collision h (9, slot 0
  * unshifted), frozen phi -> post-collision populations; aux[0..3] = u*, u. */
 void orc_collide_flow(const orc_params* p, const double* h, double phi,

@@ -66,7 +66,7 @@ def test_fourfold_symmetry_at_zero_orientation(pure_diffusion_run):
 # Phase field: stationary planar fronts (lambda = 0)
 # ---------------------------------------------------------------------------
 
-def _planar(angle, W0, eps=0.05):
+def _planar(angle, W0, eps=0.05, grad_stencil=0):
     L = int(32 * W0) if angle == 0 else int(24 * W0)
     tau0 = 20.0 * W0 * W0  # diffusive scaling: W0^2/tau0 fixed
     a = 1 + eps if angle == 0 else 1 - eps
@@ -82,7 +82,7 @@ def _planar(angle, W0, eps=0.05):
         Ls = L / math.sqrt(2)
     exact = -np.tanh((s - Ls / 4) / w) * np.tanh((s - 3 * Ls / 4) / w)
     cfg = dict(nx=nx, ny=ny, use_c=0, use_t=0, use_ns=0, W0=W0, tau0=tau0, lambda_=0.0,
-               theta0=0.0, eps4=eps)
+               theta0=0.0, eps4=eps, grad_stencil=grad_stencil)
     o = O.Oracle(cfg).set_fields(exact)
     o.step(int(10 * tau0))
     return np.abs(o.fields()["phi"] - exact).max()

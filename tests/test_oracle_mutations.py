@@ -16,8 +16,15 @@ SRC = os.path.join(ROOT, "oracle", "dlb_oracle.c")
 T = "tests/test_oracle_dynamics.py::"
 TT = "tests/test_oracle_tables.py::"
 TR = "tests/test_oracle_restart.py::"
+TS = "tests/test_oracle_stencil.py::"
 
 MUTATIONS = [
+    ("stencil gradient: sign of the y part", "gy += 3.0 * W9[i] * C9Y[i] * F[yy * nx + xx];",
+     "gy -= 3.0 * W9[i] * C9Y[i] * F[yy * nx + xx];", TS + "test_stencil_is_exact_on_quadratics"),
+    ("stencil gradient: 1/cs^2 taken as 2", "gx += 3.0 * W9[i] * C9X[i] * F[yy * nx + xx];",
+     "gx += 2.0 * W9[i] * C9X[i] * F[yy * nx + xx];", TS + "test_stencil_is_exact_on_quadratics"),
+    ("stencil mode without anisotropy", "aniso_or_hook(p, lg[0], lg[1], &lg[2], &lg[3], &lg[4]);",
+     "lg[2] = 1.0, lg[3] = lg[4] = 0.0;", TS + "test_planar_front_is_stationary_with_the_stencil_gradient"),
     ("no d_t F^phi term (Remark 2)", "acc += F[i] + 0.5 * a2 * dF[i];", "acc += F[i];",
      T + "test_phase_field_mode_decay_with_fixed_anisotropy"),
     ("plain streaming for phi", "(s->pf[o + src] - s->f[o + d]) / s->a2[src]",
