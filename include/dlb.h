@@ -86,6 +86,11 @@ typedef struct dlb_params {
                              problem of Sec. 4.1.  Not available in batches     */
     int32_t isothermal;   /* 1: theta = theta0 everywhere, no heat lattice (the
                              isothermal alloy of Sec. 4.3)                       */
+    int32_t grad_stencil; /* 0: grad phi by the local scheme of Sec. 3.1 (the
+                             method); 1: ablation, grad phi from the isotropic
+                             nine-point difference of the node values of phi
+                             (one extra plane in the state).  Not available in
+                             batches                                             */
     double W0, tau0;      /* interface width and kinetic time (Sec. 2)              */
     double eps4, orient;  /* anisotropy strength and crystal orientation (rad)      */
     double lambda, Mcinf, k;   /* coupling, M c_inf, partition coefficient          */

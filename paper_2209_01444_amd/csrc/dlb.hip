@@ -55,7 +55,7 @@ size_t history_bytes(int precision) { return precision == DLB_F64 ? 8 : 4; }
 
 struct Layout {
     size_t plane;  // elements per plane
-    size_t pop[2], flow[2], hist, red, redout, total;
+    size_t pop[2], flow[2], hist, phin, red, redout, total;
     int nblocks;
 };
 
@@ -68,6 +68,7 @@ int check_params(const dlb_params* p) {
     if (p->use_ns && p->n_sub < 1) return fail(DLB_EINVAL, "n_sub must be >= 1");
     if (p->phi_static != 0 && p->phi_static != 1) return fail(DLB_EINVAL, "phi_static must be 0 or 1");
     if (p->isothermal != 0 && p->isothermal != 1) return fail(DLB_EINVAL, "isothermal must be 0 or 1");
+    if (p->grad_stencil != 0 && p->grad_stencil != 1) return fail(DLB_EINVAL, "grad_stencil must be 0 or 1");
     if (!(p->W0 > 0 && p->tau0 > 0 && p->D > 0 && p->alpha > 0)) return fail(DLB_EINVAL, "W0, tau0, D, alpha must be > 0");
     if (!(p->k > 0 && p->k < 1)) return fail(DLB_EINVAL, "partition coefficient k must be in (0,1)");
     double W2t = p->W0 * p->W0 / p->tau0;
@@ -106,6 +107,8 @@ Layout layout_of(const dlb_params* p) {
     }
     L.hist = off;
     off = align256(off + (p->use_ns ? 6 : 2) * L.plane * cb);
+    L.phin = off;  // phi at time t for the stencil-gradient ablation
+    if (p->grad_stencil) off = align256(off + L.plane * cb);
     int nbx = (p->nx + TILE_X - 1) / TILE_X, nby = (p->ny + TILE_Y - 1) / TILE_Y;
     L.nblocks = nbx * nby;
     L.red = off;
@@ -190,6 +193,7 @@ static KParams make_kparams(const dlb_params* p, const Layout& L) {
     if (p->precision == DLB_F16S || p->precision == DLB_BF16S) rest_shifts(p, k.shift);
     for (int j = 0; j < 2; ++j)  // wave-row fused tiles, K = 3 and 5 (-1: no valid shift)
         k.tbw_dy[j] = tbw_row_shift(p->ny, j ? 5 : 3, k.walls != 0, &k.tbw_nby[j]);
+    k.grad_stencil = p->grad_stencil;  // k.phin is set once the state buffer is known
     return k;
 }
 
@@ -198,6 +202,7 @@ static KParams make_kparams(const dlb_params* p, const Layout& L) {
 // ---------------------------------------------------------------------------
 struct Ops {
     void (*pct)(const KParams&, const void*, void*, const void*, void*, int, hipStream_t, dim3);
+    void (*phi_plane)(const KParams&, const void*, void*, hipStream_t, dim3);
     void (*flow)(const KParams&, const void*, void*, const void*, hipStream_t, dim3);
     // K fused sub-steps (K in {3, 5}); returns false if K is not built
     bool (*flow_tb)(int, const KParams&, const void*, void*, const void*, hipStream_t);
@@ -222,6 +227,9 @@ template <class CF, bool NS, bool W> struct OpsImpl {
                     int hv, hipStream_t st, dim3 grid) {
         hipLaunchKernelGGL((k_pct<CF, NS, W>), grid, dim3(BLOCK), 0, st, kp, (const S*)pin, (S*)pout,
                            (const S*)hin, (H*)hist, hv);
+    }
+    static void phi_plane(const KParams& kp, const void* pin, void* phin, hipStream_t st, dim3 grid) {
+        hipLaunchKernelGGL((k_phi_plane<CF, W>), grid, dim3(BLOCK), 0, st, kp, (const S*)pin, (H*)phin);
     }
     static void flow(const KParams& kp, const void* hin, void* hout, const void* phi, hipStream_t st,
                      dim3 grid) {
@@ -274,7 +282,7 @@ template <class CF, bool NS, bool W> struct OpsImpl {
     static void tips(const KParams& kp, const void* pop, double* out, hipStream_t st) {
         hipLaunchKernelGGL((k_tips<CF, W>), dim3(4), dim3(448), 0, st, kp, (const S*)pop, out);
     }
-    static Ops ops() { return Ops{pct, flow, flow_tb, set_fields, restart_prep, fields, reduce, tips}; }
+    static Ops ops() { return Ops{pct, phi_plane, flow, flow_tb, set_fields, restart_prep, fields, reduce, tips}; }
 
     // batched persistent launches
     static void b_pct(const SeedDesc* d, int count, int total, int cur, int fcur, int blocks,
@@ -361,6 +369,7 @@ struct dlb_solver {
 static void enqueue_step(dlb_solver* s, hipEvent_t* ev) {
     if (ev) (void)hipEventRecord(ev[0], s->stream);
     if (!s->p.phi_static) {
+        if (s->p.grad_stencil) s->ops.phi_plane(s->kp, s->pop(s->pop_cur), s->base + s->L.phin, s->stream, s->grid);
         s->ops.pct(s->kp, s->pop(s->pop_cur), s->pop(1 - s->pop_cur), s->flow(s->flow_cur), s->hist(),
                    s->hist_valid, s->stream, s->grid);
         s->pop_cur ^= 1;
@@ -455,6 +464,7 @@ int dlb_create(const dlb_params* p, void* dev_state, size_t bytes, void* hip_str
     }
     s->ops = select_ops(p);
     s->base = (char*)dev_state;
+    s->kp.phin = p->grad_stencil ? s->base + L.phin : nullptr;
     s->bytes = bytes;
     s->stream = (hipStream_t)hip_stream;
     s->grid = dim3(L.nblocks);
@@ -772,6 +782,7 @@ static int batch_layout(const dlb_params* ps, int count, std::vector<size_t>* of
         int rc = check_params(&ps[i]);
         if (rc) return rc;
         if (ps[i].phi_static) return fail(DLB_EUNSUPPORTED, "phi_static is not available in batches");
+        if (ps[i].grad_stencil) return fail(DLB_EUNSUPPORTED, "grad_stencil is not available in batches");
         if (!batch_compatible(&ps[0], &ps[i]))
             return fail(DLB_EINVAL, "batch members must share precision, use_ns, bc and n_sub");
         if (offs) offs->push_back(off);

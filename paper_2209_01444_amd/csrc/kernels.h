@@ -104,6 +104,55 @@ __device__ __forceinline__ void flow_node(const KParams& kp, const S* __restrict
     wall_rebuild(kp, x, y, hf, phi_f, h);
 }
 
+// Ablation of the local scheme: grad phi from the isotropic nine-point
+// difference (1/cs^2) sum_i w_i c_i phi(x + c_i) of the node values of phi
+// at time t (the plane kp.phin, written by k_phi_plane), with the bulk guard
+// and anisotropy of the local scheme.  A wall node, a copy of its inward
+// neighbour, takes that neighbour's gradient.
+template <class T, class HT, bool WALLS>
+__device__ __forceinline__ void stencil_gradient(const KParams& kp, int x, int y, T& gx, T& gy, T& a, T& Nx,
+                                                 T& Ny) {
+    const HT* __restrict__ ph = (const HT*)kp.phin;
+    if (WALLS) {
+        x = x < 1 ? 1 : (x > kp.nx - 2 ? kp.nx - 2 : x);
+        y = y < 1 ? 1 : (y > kp.ny - 2 ? kp.ny - 2 : y);
+    }
+    // neighbours x +- 1, y +- 1 (periodic wrap; on channel grids x and y are
+    // interior here, so the neighbours exist)
+    const int xe = x + 1 < kp.nx ? x + 1 : 0, xw = x > 0 ? x - 1 : kp.nx - 1;
+    const int yn = y + 1 < kp.ny ? y + 1 : 0, ys = y > 0 ? y - 1 : kp.ny - 1;
+    const size_t r0 = (size_t)y * kp.nx, rn = (size_t)yn * kp.nx, rs = (size_t)ys * kp.nx;
+    const T e = T(ph[r0 + xe]), w = T(ph[r0 + xw]), n = T(ph[rn + x]), so = T(ph[rs + x]);
+    const T ne = T(ph[rn + xe]), nw = T(ph[rn + xw]), sw = T(ph[rs + xw]), se = T(ph[rs + xe]);
+    // 3 w_axis = 1/3, 3 w_diagonal = 1/12
+    gx = (e - w) * T(1.0 / 3.0) + ((ne - nw) + (se - sw)) * T(1.0 / 12.0);
+    gy = (n - so) * T(1.0 / 3.0) + ((ne + nw) - (se + sw)) * T(1.0 / 12.0);
+    if (gx * gx + gy * gy < T(GRAD_GUARD)) {
+        gx = gy = T(0);
+        a = T(1);
+        Nx = Ny = T(0);
+    } else {
+        anisotropy(kp, gx, gy, a, Nx, Ny);
+    }
+}
+
+// phi at time t per node into the plane phin (grad_stencil only); a wall
+// node carries its inward neighbour's value (zero gradient)
+template <class CF, bool WALLS>
+__global__ __launch_bounds__(BLOCK) void k_phi_plane(const KParams kp, const typename CF::S* __restrict__ pin,
+                                                     typename CF::H* __restrict__ phin) {
+    using T = typename CF::T;
+    int x, y;
+    if (!node_of_thread(kp, x, y)) return;
+    const size_t P = (size_t)kp.plane;
+    const size_t idx = (size_t)y * kp.nx + x;
+    const size_t src = (WALLS && is_wall(kp, x, y)) ? inward_idx(kp, x, y) : idx;
+    T f[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) f[i] = ld_pop<T>(pin, i * P + src, kp.shift[i]);
+    phin[idx] = typename CF::H((((f[0] + f[1]) + f[2]) + f[3]) + f[4]);
+}
+
 // ---------------------------------------------------------------------------
 // K1: phi, C, theta main step.
 // ---------------------------------------------------------------------------
@@ -155,7 +204,10 @@ __device__ __forceinline__ void pct_node(const KParams& kp, const typename CF::S
 
     // local gradient, anisotropy (Sec. 2, Sec. 3.1)
     T gx, gy, a, Nx, Ny;
-    local_gradient<T>(kp, f[1] - f[3], f[2] - f[4], gx, gy, a, Nx, Ny);
+    if (kp.grad_stencil)
+        stencil_gradient<T, HT, WALLS>(kp, x, y, gx, gy, a, Nx, Ny);
+    else
+        local_gradient<T>(kp, f[1] - f[3], f[2] - f[4], gx, gy, a, Nx, Ny);
     const T a2 = a * a;
     const T inv_a2 = T(1) / a2;
     const T W2t = T(kp.W2t);

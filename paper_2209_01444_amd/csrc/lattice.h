@@ -35,6 +35,8 @@ struct KParams {
     double seed_R, seed_x, seed_y, noise_amp, orient;
     float shift[24];        // storage shifts (rest-state populations) for 16-bit storage
     int tbw_dy[2], tbw_nby[2];  // row shift and tile rows of the wave-row fused tiles, K = 3 / 5
+    int grad_stencil;           // 1: grad phi from the nine-point stencil of the plane phin
+    const void* phin;           // phi at time t per node (history type), grad_stencil only
 };
 
 static constexpr int TILE_X = 64;

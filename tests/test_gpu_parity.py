@@ -181,6 +181,27 @@ def test_quintic_interpolation_parity(dlb, precision, tol):
     assert np.abs(lin.fields()["theta"] - o.fields()["theta"]).max() > 1e-3
 
 
+@pytest.mark.parametrize("case,precision,tol", [("periodic", "f64", 1e-10), ("channel", "f64", 1e-10),
+                                               ("channel", "f32", 1e-4)])
+def test_stencil_gradient_ablation_parity(dlb, case, precision, tol):
+    """grad_stencil = 1 (grad phi from the nine-point stencil of the node
+    values of phi instead of the local scheme of Sec. 3.1): GPU against the
+    oracle on a periodic seed and on the coupled channel case."""
+    _say(f"case: stencil gradient, {case} {precision}")
+    if case == "periodic":
+        cfg = dict(W.pure_diffusion_128(precision), nx=64, ny=64, seed_x=32.0, seed_y=32.0, grad_stencil=1)
+        noise = None
+    else:
+        cfg, noise = _flow_case(64, 48, precision)
+        cfg = dict(cfg, grad_stencil=1)
+    o = O.Oracle(cfg).init_seed(noise).step(200)
+    s = dlb.Solver(cfg).init_seed(noise).step(200)
+    compare(s.fields(), o.fields(), tol, label=f"stencil {case} {precision}")
+    # the ablation changes the result at the discretisation level
+    local = O.Oracle(dict(cfg, grad_stencil=0)).init_seed(noise).step(200)
+    assert np.abs(local.fields()["phi"] - o.fields()["phi"]).max() > 1e-6
+
+
 @pytest.mark.parametrize("precision", ["f64", "f32", "f16s"])
 @pytest.mark.parametrize("walls", [1, 0])
 def test_fused_flow_substeps_match_single_substeps(dlb, precision, walls):
@@ -552,3 +573,7 @@ def test_batch_autotune_and_member_rules(dlb):
     b.step(5)
     r = b.members[2].reduce()
     assert r["nonfinite"] == 0
+    # solver options that batches do not carry are refused
+    for opt in ({"phi_static": 1}, {"grad_stencil": 1}):
+        with pytest.raises(dlb.DlbError):
+            dlb.Batch([dict(cases[0][0], **opt)])
