@@ -133,6 +133,8 @@ def main():
     ap.add_argument("--flow-fuse", type=int, default=0, help="flow sub-steps per launch (0: library default)")
     ap.add_argument("--timed-launch-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--grad-stencil", action="store_true",
+                    help="stencil-gradient ablation of the local scheme (not the method's default)")
     ap.add_argument("--calibrate-copy", action="store_true")
     args = ap.parse_args()
 
@@ -150,6 +152,7 @@ def main():
 
     cfg, noise = workloads.thermosolutal_flow(args.size, args.size, seed=2, precision=args.precision)
     cfg["flow_fuse"] = args.flow_fuse
+    cfg["grad_stencil"] = int(args.grad_stencil)
     solver = dlb.Solver(cfg).init_seed(noise)
     nodes = cfg["nx"] * cfg["ny"]
 
@@ -195,7 +198,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl, "nx": cfg["nx"], "ny": cfg["ny"], "n_sub": cfg["n_sub"],
                    "lattices": "phi D2Q5 + C D2Q5 + theta D2Q5 + flow D2Q9",
-                   "algorithmic_bytes_per_node_step": ab["step"], "parallelism": "single GPU"},
+                   "algorithmic_bytes_per_node_step": ab["step"], "parallelism": "single GPU",
+                   "grad_phi": "stencil (ablation)" if args.grad_stencil else "local (Sec. 3.1)"},
         "roofline": {
             "bound": "hbm",
             "kernel": f"{fused_name} (fused flow sub-steps)" if subs_per_launch > 1 else "k_flow (flow sub-step)",

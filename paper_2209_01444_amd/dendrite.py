@@ -18,7 +18,7 @@ paper describes the upstream arm outgrowing the others, the vertical arms
 settling at the pure-diffusion velocity and the downstream arm slowing to
 a lower constant velocity.
 
-    python -m paper_2209_01444_amd.dendrite [--solutal | --flow]
+    python -m paper_2209_01444_amd.dendrite [--solutal | --flow] [--stencil]
 """
 from __future__ import annotations
 
@@ -36,13 +36,15 @@ D0_OVER_W0 = 0.1385
 D0_SOLUTAL = 0.8839 / 3.191
 
 
-def run(steps: int = 16000, every: int = 500, precision: str = "f32", L: int = 512, flow: bool = False) -> dict:
+def run(steps: int = 16000, every: int = 500, precision: str = "f32", L: int = 512, flow: bool = False,
+        grad_stencil: int = 0) -> dict:
     """Thermal dendrite; with flow=True the melt-flow case (inflow along +x):
     arm 0 (+x) grows downstream, arm 2 (-x) upstream, arms 1 and 3 across
-    the flow."""
+    the flow.  grad_stencil=1: the stencil-gradient ablation of the local
+    scheme."""
     import torch
 
-    cfg = workloads.thermal_dendrite(precision, L, flow=flow)
+    cfg = dict(workloads.thermal_dendrite(precision, L, flow=flow), grad_stencil=grad_stencil)
     d0 = D0_OVER_W0 * cfg["W0"]
     s = dlb.Solver(cfg).init_seed(None)
     torch.cuda.synchronize()
@@ -124,12 +126,13 @@ def main():
     ap.add_argument("--precision", default="f32")
     ap.add_argument("--solutal", action="store_true")
     ap.add_argument("--flow", action="store_true", help="thermal dendrite with melt flow")
+    ap.add_argument("--stencil", action="store_true", help="stencil-gradient ablation of the local scheme")
     args = ap.parse_args()
     if args.solutal:
         print(json.dumps(run_solutal(args.steps or 40000, args.every or 200, args.precision)), flush=True)
     else:
-        print(json.dumps(run(args.steps or 16000, args.every or 500, args.precision, flow=args.flow)),
-              flush=True)
+        print(json.dumps(run(args.steps or 16000, args.every or 500, args.precision, flow=args.flow,
+                             grad_stencil=int(args.stencil))), flush=True)
 
 
 if __name__ == "__main__":
