@@ -464,7 +464,9 @@ __device__ __forceinline__ void flow_tb_tile(const KParams& kp, const typename C
 // nx - 1 are then rebuilt by one pass per wave: the lane of the inward column
 // writes its R rows to a per-wave LDS slot, lanes 0-7 rebuild one (side,
 // row) pair each (a corner from the row inward of it: the diagonal
-// neighbour), and the wall lane reads the results back.
+// neighbour), and the wall lane reads the results back.  Tiles whose
+// extended region holds no wall node run the variant without walls
+// (flow_tbw_tile_any).
 // ---------------------------------------------------------------------------
 struct TbWave {
     static constexpr int NW = 8, R = 4, EX = 64, EY = NW * R;
@@ -517,6 +519,21 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// LDS of a wave-row tile, one block per workgroup whichever tile variant
+// runs: exchange slots [buffer][wave][k][lane] (k 0-2 the up-movers 2, 5, 6
+// of the wave's last row, k 3-5 the down-movers 4, 7, 8 of its first row)
+// and the wall-column pass [wave][side (west, east)][row][population],
+// rows padded to 12 floats
+struct TbwLds {
+    float xch[2][TbWave::NW][6][64];
+    float xw_in[TbWave::NW][2][TbWave::R][12];
+    float xw_out[TbWave::NW][2][TbWave::R][12];
+};
+__device__ __forceinline__ TbwLds& tbw_lds() {
+    __shared__ TbwLds l;
+    return l;
+}
+
 template <class CF, bool WALLS, int K>
 __device__ __forceinline__ void flow_tbw_tile(const KParams& kp, const typename CF::S* __restrict__ hin,
                                               typename CF::S* __restrict__ hout,
@@ -526,16 +543,13 @@ __device__ __forceinline__ void flow_tbw_tile(const KParams& kp, const typename 
     static_assert(sizeof(T) == 4, "wave-row tile is for FP32 arithmetic");
     constexpr int NW = TbWave::NW, R = TbWave::R, EX = TbWave::EX, EY = TbWave::EY;
     constexpr int OX = EX - 2 * K, OY = EY - 2 * K;
-    // exchange slots: [buffer][wave][k][lane]; k 0-2 = up-movers (2, 5, 6) of
-    // the wave's last row, k 3-5 = down-movers (4, 7, 8) of its first row
-    __shared__ float xch[2][NW][6][64];
-    // wall-column pass: [wave][side (west, east)][row][population], rows
-    // padded to 12 floats
-    __shared__ float xw_in[WALLS ? NW : 1][2][R][12];
-    __shared__ float xw_out[WALLS ? NW : 1][2][R][12];
+    TbwLds& lds = tbw_lds();
+    auto& xch = lds.xch;
+    auto& xw_in = lds.xw_in;
+    auto& xw_out = lds.xw_out;
     const size_t P = (size_t)kp.plane;
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int X0 = bx * OX - K, Y0 = by * OY - K - (WALLS ? kp.tbw_dy[K == 5] : 0);
+    const int X0 = bx * OX - K, Y0 = by * OY - K - kp.tbw_dy[K == 5];  // tbw_dy = 0 without walls
     int gx = X0 + lane;
     bool xin = true;
     if constexpr (WALLS) {
@@ -710,6 +724,24 @@ __device__ __forceinline__ void flow_tbw_tile(const KParams& kp, const typename 
     }
 }
 
+// A wave-row tile of a channel grid whose extended region holds no wall
+// node runs the tile code without walls (no bounds or wall tests, fewer
+// registers live): same arithmetic, same results.
+template <class CF, bool WALLS, int K>
+__device__ __forceinline__ void flow_tbw_tile_any(const KParams& kp, const typename CF::S* __restrict__ hin,
+                                                  typename CF::S* __restrict__ hout,
+                                                  const typename CF::H* __restrict__ phi_t, int bx, int by) {
+    if constexpr (WALLS) {
+        constexpr int EX = TbWave::EX, EY = TbWave::EY, OX = EX - 2 * K, OY = EY - 2 * K;
+        const int X0 = bx * OX - K, Y0 = by * OY - K - kp.tbw_dy[K == 5];
+        if (X0 >= 1 && X0 + EX - 1 <= kp.nx - 2 && Y0 >= 1 && Y0 + EY - 1 <= kp.ny - 2) {
+            flow_tbw_tile<CF, false, K>(kp, hin, hout, phi_t, bx, by);
+            return;
+        }
+    }
+    flow_tbw_tile<CF, WALLS, K>(kp, hin, hout, phi_t, bx, by);
+}
+
 // Tile geometry of the fused flow launch per arithmetic type: the wave-row
 // tile for FP32, the LDS tile for FP64.
 template <class T> struct TbGeom;
@@ -727,7 +759,7 @@ __device__ __forceinline__ void flow_fused_tile(const KParams& kp, const typenam
                                                 const typename CF::H* __restrict__ phi_t, int bx, int by) {
     using T = typename CF::T;
     if constexpr (sizeof(T) == 4)
-        flow_tbw_tile<CF, WALLS, K>(kp, hin, hout, phi_t, bx, by);
+        flow_tbw_tile_any<CF, WALLS, K>(kp, hin, hout, phi_t, bx, by);
     else
         flow_tb_tile<CF, WALLS, TbTile<T>::EX, TbTile<T>::EY, K>(kp, hin, hout, phi_t, bx, by);
 }
@@ -771,7 +803,7 @@ __global__ __launch_bounds__(64 * TbWave::NW) void k_flow_tbw(const KParams kp,
                                                                int nbx, int nblocks) {
     int bx, by;
     tbw_tile_of<WALLS>(blockIdx.x, nbx, nblocks / nbx, bx, by);
-    flow_tbw_tile<CF, WALLS, K>(kp, hin, hout, phi_t, bx, by);
+    flow_tbw_tile_any<CF, WALLS, K>(kp, hin, hout, phi_t, bx, by);
 }
 
 template <class CF, bool WALLS, int EX, int EY, int K>
