@@ -70,11 +70,12 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ X, con
     for (int bb = 0; bb < 4; ++bb)
 #pragma unroll
         for (int j = 0; j < NJ; ++j) acc[bb][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int ci = 0; ci < Cin; ci += 32) {
-        __syncthreads();  // the previous chunk's operands have been read
-        // issue every staging load before the first LDS write
-        constexpr int NI = ((CT_Y + 2) * (CT_X + 2) * 4 + 255) / 256, NWL = (9 * 16 * NJ * 4 + 255) / 256;
-        bf16x8 vin[NI], vw[NWL];
+    // chunk staging, software-pipelined: the global loads of chunk c + 1 are
+    // issued right after chunk c reaches LDS, so they are in flight while
+    // the matrix cores work on chunk c
+    constexpr int NI = ((CT_Y + 2) * (CT_X + 2) * 4 + 255) / 256, NWL = (9 * 16 * NJ * 4 + 255) / 256;
+    bf16x8 vin[NI], vw[NWL];
+    auto load_chunk = [&](int ci) {
 #pragma unroll
         for (int k = 0; k < NI; ++k) {
             const int i = threadIdx.x + 256 * k;
@@ -93,6 +94,10 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ X, con
             if (i < 9 * 16 * NJ * 4)
                 vw[k] = *(const bf16x8*)(Wt + ((size_t)sft * Cout + co0 + co) * Cin + ci + 8 * g);
         }
+    };
+    load_chunk(0);
+    for (int ci = 0; ci < Cin; ci += 32) {
+        __syncthreads();  // the previous chunk's operands have been read
 #pragma unroll
         for (int k = 0; k < NI; ++k) {
             const int i = threadIdx.x + 256 * k;
@@ -107,6 +112,7 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ X, con
             if (i < 9 * 16 * NJ * 4) *(bf16x8*)&sW[q / (16 * NJ)][q % (16 * NJ)][8 * g] = vw[k];
         }
         __syncthreads();
+        if (ci + 32 < Cin) load_chunk(ci + 32);
 #pragma unroll
         for (int ky = 0; ky < 3; ++ky) {
 #pragma unroll
