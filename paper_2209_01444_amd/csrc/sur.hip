@@ -223,15 +223,15 @@ __global__ __launch_bounds__(256) void k_conv3x3_wgrad(const bf16* __restrict__ 
     f32x4 acc[NACC];
 #pragma unroll
     for (int i = 0; i < NACC; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (long long ks = kbeg; ks < kend; ++ks) {
+    // k-step staging, software-pipelined: the global loads of step ks + 1
+    // are issued once step ks is in LDS, in flight during its products
+    constexpr int NA = (WG_PX * (CO_T / 8) + 255) / 256, NX = (3 * (WG_PX + 2) * (CI_T / 8) + 255) / 256;
+    bf16x8 va[NA], vx[NX];
+    auto load_step = [&](long long ks) {
         const int seg = (int)(ks % nseg);
         const long long ny = ks / nseg;
         const int y = (int)(ny % H), n = (int)(ny / H);
         const int xs = seg * WG_PX;
-        __syncthreads();  // the previous step's operands have been read
-        // issue every staging load before the first LDS write
-        constexpr int NA = (WG_PX * (CO_T / 8) + 255) / 256, NX = (3 * (WG_PX + 2) * (CI_T / 8) + 255) / 256;
-        bf16x8 va[NA], vx[NX];
 #pragma unroll
         for (int k = 0; k < NA; ++k) {
             const int v = tid + 256 * k;
@@ -251,6 +251,10 @@ __global__ __launch_bounds__(256) void k_conv3x3_wgrad(const bf16* __restrict__ 
             if (v < 3 * (WG_PX + 2) * (CI_T / 8) && gy >= 0 && gy < H && gx >= 0 && gx < W)
                 vx[k] = *(const bf16x8*)(X + (((size_t)n * H + gy) * W + gx) * Cin + ci0 + 8 * g);
         }
+    };
+    if (kbeg < kend) load_step(kbeg);
+    for (long long ks = kbeg; ks < kend; ++ks) {
+        __syncthreads();  // the previous step's operands have been read
 #pragma unroll
         for (int k = 0; k < NA; ++k) {
             const int v = tid + 256 * k;
@@ -276,6 +280,7 @@ __global__ __launch_bounds__(256) void k_conv3x3_wgrad(const bf16* __restrict__ 
             }
         }
         __syncthreads();
+        if (ks + 1 < kend) load_step(ks + 1);
 #pragma unroll
         for (int c = 0; c < WCO; ++c) {
             const int cb = cb_first + c * cb_step;
