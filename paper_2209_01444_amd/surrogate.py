@@ -244,7 +244,7 @@ def main():
     ap.add_argument("--pairs", type=int, default=95)
     ap.add_argument("--K", type=int, default=100)
     ap.add_argument("--L", default="100", help="lattice Boltzmann steps after each jump; a comma list runs each")
-    ap.add_argument("--iters", type=int, default=16000)
+    ap.add_argument("--iters", type=int, default=32000)
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--lr", type=float, default=4e-4, help="peak of the cosine schedule (1e-3 diverged)")
     ap.add_argument("--T", type=int, default=10000)
