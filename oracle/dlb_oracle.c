@@ -238,6 +238,9 @@ void orc_anisotropy(double eps, double orient, double gx, double gy, double* out
  * ------------------------------------------------------------------------- */
 #define GRAD_GUARD 1e-12
 
+/* heat sub-steps per main step (multi-time-scaling), at least one */
+static int heat_sub(const orc_params* p) { return p->n_sub_t > 1 ? p->n_sub_t : 1; }
+
 static double s1_phi(const orc_params* p, double as) {
     double W2t = p->W0 * p->W0 / p->tau0;
     return 1.0 / (as * as * W2t * 3.0 + 0.5);
@@ -419,7 +422,9 @@ orc_state* orc_create(const orc_params* p) {
     }
     double s1 = s1_phi(p, 1.0);
     double s1c = 1.0 / (3.0 * p->D * (1.0 - p->k) + 0.5);
-    double s1t = 1.0 / (3.0 * p->alpha + 0.5);
+    /* multi-time-scaling of the heat lattice: n_sub_t sub-steps of dt/n_sub_t,
+     * diffusivity alpha/n_sub_t per sub-step (reading) */
+    double s1t = 1.0 / (3.0 * p->alpha / heat_sub(p) + 0.5);
     double rates[4] = {s1, p->use_c ? s1c : 1.0, p->use_t ? s1t : 1.0, p->use_ns ? s2_flow(p) : 1.0};
     for (int i = 0; i < 4; ++i)
         if (!(rates[i] > 0.0 && rates[i] < 2.0)) {
@@ -676,8 +681,8 @@ static void collide_pct_node(orc_state* s, int x) {
             s->pn[(size_t)i * N + x] = acc;
         }
     }
-    /* ---- heat lattice, Sec. 3.3 ---- */
-    if (p->use_t) {
+    /* ---- heat lattice, Sec. 3.3 (here unless it takes sub-steps) ---- */
+    if (p->use_t && heat_sub(p) == 1) {
         double gv[5], geq[5], GT[5];
         for (int i = 0; i < 5; ++i) gv[i] = s->g[(size_t)i * N + x];
         orc_eq_heat(theta, ph, p->h_quintic, ux, uy, geq);
@@ -700,6 +705,58 @@ static void swap_ptr(double** a, double** b) {
 }
 
 static void flow_substeps(orc_state* s);
+
+/* Heat lattice in n_sub_t sub-steps of dt' = dt/n_sub_t (multi-time-scaling,
+ * reading): phi frozen at phi^t as for the flow sub-steps; per sub-step the
+ * diffusivity is alpha/n_sub_t (in the relaxation rate), the advecting
+ * velocity u^t/n_sub_t, and the correction G = (1/2) c.d_t'(H u') takes the
+ * main step's backward difference of H u in sub-step units,
+ * d_t(H u)/n_sub_t^2, in every sub-step.  Walls: zero gradient, as for one
+ * step. */
+static void heat_substeps(orc_state* s) {
+    const orc_params* p = &s->p;
+    int N = s->N, nx = s->nx, ny = s->ny;
+    const int ns = heat_sub(p);
+    for (int sub = 0; sub < ns; ++sub) {
+        fill_cde_walls(s, s->g);
+#pragma omp parallel for schedule(static)
+        for (int x = 0; x < N; ++x) {
+            double gv[5], geq[5], GT[5], H = 0.0;
+            for (int i = 0; i < 5; ++i) {
+                gv[i] = s->g[(size_t)i * N + x];
+                H += gv[i];
+            }
+            double ph = s->phi[x];
+            double theta = H + 0.5 * h_of(ph, p->h_quintic);
+            double dHu[2] = {0.0, 0.0};
+            if (s->hist_valid) {
+                dHu[0] = (s->Hu[x] - s->Hu_prev[x]) / ((double)ns * ns);
+                dHu[1] = (s->Hu[N + x] - s->Hu_prev[N + x]) / ((double)ns * ns);
+            }
+            orc_eq_heat(theta, ph, p->h_quintic, s->ux[x] / ns, s->uy[x] / ns, geq);
+            for (int i = 0; i < 5; ++i) GT[i] = W5[i] * (3.0 * (C5X[i] * dHu[0] + C5Y[i] * dHu[1]));
+            for (int i = 0; i < 5; ++i) {
+                double acc = gv[i];
+                for (int j = 0; j < 5; ++j) {
+                    acc -= s->L.L5t[i * 5 + j] * (gv[j] - geq[j]);
+                    acc += ((i == j ? 1.0 : 0.0) - 0.5 * s->L.L5t[i * 5 + j]) * GT[j];
+                }
+                s->pg[(size_t)i * N + x] = acc;
+            }
+        }
+#pragma omp parallel for schedule(static)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                if (is_wall(s, x, y)) continue;
+                int d = y * nx + x;
+                for (int i = 0; i < 5; ++i) {
+                    int src = wrap(y - C5Y[i], ny) * nx + wrap(x - C5X[i], nx);
+                    s->gn[(size_t)i * N + d] = s->pg[(size_t)i * N + src];
+                }
+            }
+        swap_ptr(&s->g, &s->gn);
+    }
+}
 
 static void main_step(orc_state* s) {
     const orc_params* p = &s->p;
@@ -729,12 +786,15 @@ static void main_step(orc_state* s) {
                 size_t o = (size_t)i * N;
                 s->fn[o + d] = s->f[o + d] + (s->pf[o + src] - s->f[o + d]) / s->a2[src];
                 if (p->use_c) s->nn[o + d] = s->pn[o + src];
-                if (p->use_t) s->gn[o + d] = s->pg[o + src];
+                if (p->use_t && heat_sub(p) == 1) s->gn[o + d] = s->pg[o + src];
             }
         }
     swap_ptr(&s->f, &s->fn);
     swap_ptr(&s->n, &s->nn);
-    swap_ptr(&s->g, &s->gn);
+    if (heat_sub(p) == 1)
+        swap_ptr(&s->g, &s->gn);
+    else if (p->use_t)
+        heat_substeps(s);
 
     /* history <- time-t values */
     memcpy(s->phi_prev, s->phi, sizeof(double) * N);
@@ -886,10 +946,12 @@ int orc_set_fields_ex(orc_state* s, const double* phi, const double* Cin, const 
             } else {
                 for (int i = 0; i < 5; ++i) s->n[(size_t)i * N + id] = e5[i];
             }
-            orc_eq_heat(th, ph, p->h_quintic, u[0], u[1], e5);
+            /* heat populations carry the velocity of their own time unit */
+            const double ht = heat_sub(p);
+            orc_eq_heat(th, ph, p->h_quintic, u[0] / ht, u[1] / ht, e5);
             if (keep_neq) {
                 /* keep g - g^eq (Sec. 3.3) */
-                orc_eq_heat(s->theta[id], s->phi[id], p->h_quintic, s->ux[id], s->uy[id], o5);
+                orc_eq_heat(s->theta[id], s->phi[id], p->h_quintic, s->ux[id] / ht, s->uy[id] / ht, o5);
                 for (int i = 0; i < 5; ++i) s->g[(size_t)i * N + id] += e5[i] - o5[i];
             } else {
                 for (int i = 0; i < 5; ++i) s->g[(size_t)i * N + id] = e5[i];

@@ -33,6 +33,7 @@
  *   restart flags (orc_set_fields_ex): continuation is exact      pinned
  *   stencil-gradient ablation (grad_stencil): exact on quadratics,
  *     stationary planar fronts at second order                    pinned
+ *   heat sub-steps (n_sub_t): diffusion rate, advected mode       pinned
  *   tip position / radius measurement                             pinned (geometry)
  */
 #ifndef DLB_ORACLE_H
@@ -59,6 +60,8 @@ typedef struct orc_params {
     int grad_stencil; /* 0: the local gradient of Sec. 3.1 (the method);
                          1: ablation, grad phi from the isotropic nine-point
                          difference of the node values of phi               */
+    int n_sub_t;      /* heat sub-steps per main step (multi-time-scaling for
+                         Le = alpha/D != 1); 0 or 1: one                      */
     double W0, tau0, eps4, orient, lambda, Mcinf, k, D, alpha, nu, rho0;
     double u_in_x, u_in_y;   /* inflow / initial velocity, lu per main step  */
     double theta0, U0, C0;

@@ -36,7 +36,7 @@ def build(verbose: bool = False) -> str:
 class OrcParams(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int) for n in (
         "nx", "ny", "use_c", "use_t", "use_ns", "walls", "n_sub", "h_quintic", "c_init_U",
-        "grad_max_iter", "phi_static", "grad_stencil")] + [(n, ctypes.c_double) for n in (
+        "grad_max_iter", "phi_static", "grad_stencil", "n_sub_t")] + [(n, ctypes.c_double) for n in (
             "W0", "tau0", "eps4", "orient", "lambda_", "Mcinf", "k", "D", "alpha", "nu", "rho0",
             "u_in_x", "u_in_y", "theta0", "U0", "C0", "seed_R", "seed_x", "seed_y", "noise_amp",
             "grad_tol", "fixed_as")]
@@ -90,7 +90,7 @@ def load():
 
 DEFAULTS = dict(
     nx=64, ny=64, use_c=1, use_t=1, use_ns=0, walls=0, n_sub=1, h_quintic=0, c_init_U=0,
-    grad_max_iter=100, phi_static=0, grad_stencil=0, W0=1.0, tau0=20.0, eps4=0.05, orient=0.0, lambda_=0.0, Mcinf=0.0,
+    grad_max_iter=100, phi_static=0, grad_stencil=0, n_sub_t=1, W0=1.0, tau0=20.0, eps4=0.05, orient=0.0, lambda_=0.0, Mcinf=0.0,
     k=0.15, D=0.1, alpha=0.1, nu=0.1, rho0=1.0, u_in=(0.0, 0.0), theta0=0.0, U0=0.0, C0=1.0,
     seed_R=8.0, seed_x=None, seed_y=None, noise_amp=0.0, grad_tol=1e-14, fixed_as=0.0,
 )

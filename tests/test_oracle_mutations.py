@@ -17,8 +17,15 @@ T = "tests/test_oracle_dynamics.py::"
 TT = "tests/test_oracle_tables.py::"
 TR = "tests/test_oracle_restart.py::"
 TS = "tests/test_oracle_stencil.py::"
+TH = "tests/test_oracle_heat_substeps.py::"
 
 MUTATIONS = [
+    ("heat sub-steps: velocity in main-step units", "s->ux[x] / ns, s->uy[x] / ns, geq", "s->ux[x], s->uy[x], geq",
+     TH + "test_advected_heat_mode_with_sub_steps"),
+    ("heat sub-steps: diffusivity not rescaled", "1.0 / (3.0 * p->alpha / heat_sub(p) + 0.5)",
+     "1.0 / (3.0 * p->alpha + 0.5)", TH + "test_heat_mode_decays_at_alpha_per_main_step"),
+    ("heat sub-steps: d_t(Hu) in main-step units", "(s->Hu[x] - s->Hu_prev[x]) / ((double)ns * ns)",
+     "(s->Hu[x] - s->Hu_prev[x]) / (double)ns", TH + "test_advected_heat_mode_with_sub_steps"),
     ("stencil gradient: sign of the y part", "gy += 3.0 * W9[i] * C9Y[i] * F[yy * nx + xx];",
      "gy -= 3.0 * W9[i] * C9Y[i] * F[yy * nx + xx];", TS + "test_stencil_is_exact_on_quadratics"),
     ("stencil gradient: 1/cs^2 taken as 2", "gx += 3.0 * W9[i] * C9X[i] * F[yy * nx + xx];",
