@@ -91,6 +91,12 @@ typedef struct dlb_params {
                              nine-point difference of the node values of phi
                              (one extra plane in the state).  Not available in
                              batches                                             */
+    int32_t n_sub_t;      /* heat sub-steps per main step (multi-time-scaling for
+                             a Lewis number alpha/D != 1): the heat lattice takes
+                             n_sub_t steps of dt/n_sub_t with phi frozen at its
+                             time-t value, diffusivity alpha/n_sub_t per
+                             sub-step.  0 or 1: one step inside the phi/C/theta
+                             update.  Not available in batches                   */
     double W0, tau0;      /* interface width and kinetic time (Sec. 2)              */
     double eps4, orient;  /* anisotropy strength and crystal orientation (rad)      */
     double lambda, Mcinf, k;   /* coupling, M c_inf, partition coefficient          */

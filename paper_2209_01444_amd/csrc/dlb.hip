@@ -55,7 +55,7 @@ size_t history_bytes(int precision) { return precision == DLB_F64 ? 8 : 4; }
 
 struct Layout {
     size_t plane;  // elements per plane
-    size_t pop[2], flow[2], hist, phin, red, redout, total;
+    size_t pop[2], flow[2], hist, phin, aux, heat, red, redout, total;
     int nblocks;
 };
 
@@ -69,12 +69,14 @@ int check_params(const dlb_params* p) {
     if (p->phi_static != 0 && p->phi_static != 1) return fail(DLB_EINVAL, "phi_static must be 0 or 1");
     if (p->isothermal != 0 && p->isothermal != 1) return fail(DLB_EINVAL, "isothermal must be 0 or 1");
     if (p->grad_stencil != 0 && p->grad_stencil != 1) return fail(DLB_EINVAL, "grad_stencil must be 0 or 1");
+    if (p->n_sub_t < 0 || p->n_sub_t > 256) return fail(DLB_EINVAL, "n_sub_t must be in [0, 256]");
     if (!(p->W0 > 0 && p->tau0 > 0 && p->D > 0 && p->alpha > 0)) return fail(DLB_EINVAL, "W0, tau0, D, alpha must be > 0");
     if (!(p->k > 0 && p->k < 1)) return fail(DLB_EINVAL, "partition coefficient k must be in (0,1)");
     double W2t = p->W0 * p->W0 / p->tau0;
     double lo = 1.0 - p->eps4, hi = 1.0 + p->eps4;  // range of a_s
+    const double nt = p->n_sub_t > 1 ? p->n_sub_t : 1;  // heat sub-steps
     double rates[4] = {1.0 / (3.0 * lo * lo * W2t + 0.5), 1.0 / (3.0 * p->D * (1.0 - p->k) + 0.5),
-                       1.0 / (3.0 * p->alpha + 0.5), 1.0};
+                       1.0 / (3.0 * p->alpha / nt + 0.5), 1.0};
     double r2 = 1.0 / (3.0 * hi * hi * W2t + 0.5);
     if (p->use_ns) {
         if (!(p->nu > 0)) return fail(DLB_EINVAL, "nu must be > 0");
@@ -109,6 +111,11 @@ Layout layout_of(const dlb_params* p) {
     off = align256(off + (p->use_ns ? 6 : 2) * L.plane * cb);
     L.phin = off;  // phi at time t for the stencil-gradient ablation
     if (p->grad_stencil) off = align256(off + L.plane * cb);
+    const bool heat_split = p->n_sub_t > 1 && !p->isothermal;
+    L.aux = off;  // u and d_t(Hu) of time t for the heat sub-steps
+    if (heat_split) off = align256(off + 4 * L.plane * cb);
+    L.heat = off;  // five heat planes: intermediate heat sub-steps
+    if (heat_split) off = align256(off + 5 * L.plane * sb);
     int nbx = (p->nx + TILE_X - 1) / TILE_X, nby = (p->ny + TILE_Y - 1) / TILE_Y;
     L.nblocks = nbx * nby;
     L.red = off;
@@ -180,7 +187,8 @@ static KParams make_kparams(const dlb_params* p, const Layout& L) {
     k.k = p->k;
     k.invD = 1.0 / p->D;
     k.s1c = 1.0 / (3.0 * p->D * (1.0 - p->k) + 0.5);
-    k.s1t = 1.0 / (3.0 * p->alpha + 0.5);
+    k.n_sub_t = (p->n_sub_t > 1 && !p->isothermal) ? p->n_sub_t : 1;  // k.aux is set with the buffer
+    k.s1t = 1.0 / (3.0 * p->alpha / k.n_sub_t + 0.5);
     k.s2u = p->use_ns ? 1.0 / (3.0 * p->nu / p->n_sub + 0.5) : 1.0;
     k.jat = p->W0 / (2.0 * std::sqrt(2.0));
     k.nsub_d = k.n_sub;
@@ -203,6 +211,7 @@ static KParams make_kparams(const dlb_params* p, const Layout& L) {
 struct Ops {
     void (*pct)(const KParams&, const void*, void*, const void*, void*, int, hipStream_t, dim3);
     void (*phi_plane)(const KParams&, const void*, void*, hipStream_t, dim3);
+    void (*heat_sub)(const KParams&, const void*, void*, const void*, hipStream_t, dim3);
     void (*flow)(const KParams&, const void*, void*, const void*, hipStream_t, dim3);
     // K fused sub-steps (K in {3, 5}); returns false if K is not built
     bool (*flow_tb)(int, const KParams&, const void*, void*, const void*, hipStream_t);
@@ -230,6 +239,11 @@ template <class CF, bool NS, bool W> struct OpsImpl {
     }
     static void phi_plane(const KParams& kp, const void* pin, void* phin, hipStream_t st, dim3 grid) {
         hipLaunchKernelGGL((k_phi_plane<CF, W>), grid, dim3(BLOCK), 0, st, kp, (const S*)pin, (H*)phin);
+    }
+    static void heat_sub(const KParams& kp, const void* gin, void* gout, const void* hist, hipStream_t st,
+                         dim3 grid) {
+        hipLaunchKernelGGL((k_heat_sub<CF, W>), grid, dim3(BLOCK), 0, st, kp, (const S*)gin, (S*)gout,
+                           (const H*)hist);
     }
     static void flow(const KParams& kp, const void* hin, void* hout, const void* phi, hipStream_t st,
                      dim3 grid) {
@@ -282,7 +296,9 @@ template <class CF, bool NS, bool W> struct OpsImpl {
     static void tips(const KParams& kp, const void* pop, double* out, hipStream_t st) {
         hipLaunchKernelGGL((k_tips<CF, W>), dim3(4), dim3(448), 0, st, kp, (const S*)pop, out);
     }
-    static Ops ops() { return Ops{pct, phi_plane, flow, flow_tb, set_fields, restart_prep, fields, reduce, tips}; }
+    static Ops ops() {
+        return Ops{pct, phi_plane, heat_sub, flow, flow_tb, set_fields, restart_prep, fields, reduce, tips};
+    }
 
     // batched persistent launches
     static void b_pct(const SeedDesc* d, int count, int total, int cur, int fcur, int blocks,
@@ -372,6 +388,21 @@ static void enqueue_step(dlb_solver* s, hipEvent_t* ev) {
         if (s->p.grad_stencil) s->ops.phi_plane(s->kp, s->pop(s->pop_cur), s->base + s->L.phin, s->stream, s->grid);
         s->ops.pct(s->kp, s->pop(s->pop_cur), s->pop(1 - s->pop_cur), s->flow(s->flow_cur), s->hist(),
                    s->hist_valid, s->stream, s->grid);
+        if (s->kp.n_sub_t > 1) {
+            // heat sub-steps from the current buffer's heat planes to the new
+            // buffer's, alternating with the scratch planes so the last one
+            // lands in the new buffer
+            const size_t off = 10 * s->L.plane * storage_bytes(s->p.precision);
+            char* from = (char*)s->pop(s->pop_cur) + off;
+            char* dst = (char*)s->pop(1 - s->pop_cur) + off;
+            char* scr = s->base + s->L.heat;
+            const int nt = s->kp.n_sub_t;
+            for (int j = 0; j < nt; ++j) {
+                char* to = ((nt - 1 - j) % 2 == 0) ? dst : scr;
+                s->ops.heat_sub(s->kp, from, to, s->hist(), s->stream, s->grid);
+                from = to;
+            }
+        }
         s->pop_cur ^= 1;
         s->hist_valid = 1;
     }
@@ -465,6 +496,7 @@ int dlb_create(const dlb_params* p, void* dev_state, size_t bytes, void* hip_str
     s->ops = select_ops(p);
     s->base = (char*)dev_state;
     s->kp.phin = p->grad_stencil ? s->base + L.phin : nullptr;
+    s->kp.aux = s->kp.n_sub_t > 1 ? s->base + L.aux : nullptr;
     s->bytes = bytes;
     s->stream = (hipStream_t)hip_stream;
     s->grid = dim3(L.nblocks);
@@ -783,6 +815,7 @@ static int batch_layout(const dlb_params* ps, int count, std::vector<size_t>* of
         if (rc) return rc;
         if (ps[i].phi_static) return fail(DLB_EUNSUPPORTED, "phi_static is not available in batches");
         if (ps[i].grad_stencil) return fail(DLB_EUNSUPPORTED, "grad_stencil is not available in batches");
+        if (ps[i].n_sub_t > 1) return fail(DLB_EUNSUPPORTED, "n_sub_t > 1 is not available in batches");
         if (!batch_compatible(&ps[0], &ps[i]))
             return fail(DLB_EINVAL, "batch members must share precision, use_ns, bc and n_sub");
         if (offs) offs->push_back(off);

@@ -153,6 +153,61 @@ __global__ __launch_bounds__(BLOCK) void k_phi_plane(const KParams kp, const typ
     phin[idx] = typename CF::H((((f[0] + f[1]) + f[2]) + f[3]) + f[4]);
 }
 
+// Heat collision (Sec. 3.3) with S = diag(1, s1T, s1T, 1, 1), in closed
+// form; Hu and d_t(Hu) in the time unit of the lattice's step.
+template <class T>
+__device__ __forceinline__ void heat_collide(T s1t, const T* g, T H, T theta, T Hux, T Huy, T dHx, T dHy, T* pg) {
+    const T gf = T(1) - T(0.5) * s1t;  // (1 - s1/2) (1/3)(3 d_t(Hu))
+    const T m1x = (g[1] - g[3]) - s1t * ((g[1] - g[3]) - Hux) + gf * dHx;
+    const T m1y = (g[2] - g[4]) - s1t * ((g[2] - g[4]) - Huy) + gf * dHy;
+    const T m3 = theta * T(1.0 / 3.0);
+    pg[0] = H - T(2) * m3;
+    pg[1] = T(0.5) * (m3 + m1x);
+    pg[3] = T(0.5) * (m3 - m1x);
+    pg[2] = T(0.5) * (m3 + m1y);
+    pg[4] = T(0.5) * (m3 - m1y);
+}
+
+// One heat sub-step (multi-time-scaling for Le != 1: n_sub_t sub-steps of
+// dt/n_sub_t per main step, after k_pct): phi frozen at phi^t (hist[0]),
+// diffusivity alpha/n_sub_t (kp.s1t), velocity u^t/n_sub_t and the d_t(Hu)
+// correction d_t(Hu)/n_sub_t^2 from the planes k_pct wrote (kp.aux);
+// push-streamed like k_pct, wall nodes taking their inward neighbour's heat
+// populations and their own velocity.
+// gin, gout: the five heat planes of a population buffer or the scratch.
+template <class CF, bool WALLS>
+__global__ __launch_bounds__(BLOCK) void k_heat_sub(const KParams kp, const typename CF::S* __restrict__ gin,
+                                                    typename CF::S* __restrict__ gout,
+                                                    const typename CF::H* __restrict__ hist) {
+    using T = typename CF::T;
+    using HT = typename CF::H;
+    int x, y;
+    if (!node_of_thread(kp, x, y)) return;
+    const size_t P = (size_t)kp.plane;
+    const size_t idx = (size_t)y * kp.nx + x;
+    const size_t src = (WALLS && is_wall(kp, x, y)) ? inward_idx(kp, x, y) : idx;
+    T g[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) g[i] = ld_pop<T>(gin, i * P + src, kp.shift[10 + i]);
+    const T H = (((g[0] + g[1]) + g[2]) + g[3]) + g[4];
+    const T phi = T(hist[idx]);
+    const T theta = H + T(0.5) * h_of(phi, kp.h_quintic);
+    // the node's own melt velocity (a wall node's comes from its rebuilt
+    // flow populations, as in k_pct)
+    const HT* __restrict__ aux = (const HT*)kp.aux;
+    const T inv = T(1) / T(kp.n_sub_t);
+    const T ux = T(aux[idx]) * inv, uy = T(aux[P + idx]) * inv;
+    const T dHx = T(aux[2 * P + idx]) * (inv * inv), dHy = T(aux[3 * P + idx]) * (inv * inv);
+    T pg[5];
+    heat_collide<T>(T(kp.s1t), g, H, theta, H * ux, H * uy, dHx, dHy, pg);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        long long d = push_dest<WALLS>(kp, x, y, C5X[i], C5Y[i]);
+        if (d < 0) continue;
+        st_pop(gout, i * P + (size_t)d, pg[i], kp.shift[10 + i]);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // K1: phi, C, theta main step.
 // ---------------------------------------------------------------------------
@@ -282,19 +337,17 @@ __device__ __forceinline__ void pct_node(const KParams& kp, const typename CF::S
         pn[4] = T(0.5) * (m3 - m1y);
     }
 
-    // ---- heat lattice (Sec. 3.3): S = diag(1, s1T, s1T, 1, 1) ----
+    // ---- heat lattice (Sec. 3.3), here unless it takes sub-steps ----
     T pg[5];
-    {
-        const T s1t = T(kp.s1t);
-        const T gf = T(1) - T(0.5) * s1t;  // (1 - s1/2) (1/3)(3 d_t(Hu))
-        const T m1x = (g[1] - g[3]) - s1t * ((g[1] - g[3]) - Hux) + gf * dHx;
-        const T m1y = (g[2] - g[4]) - s1t * ((g[2] - g[4]) - Huy) + gf * dHy;
-        const T m3 = theta * T(1.0 / 3.0);
-        pg[0] = H - T(2) * m3;
-        pg[1] = T(0.5) * (m3 + m1x);
-        pg[3] = T(0.5) * (m3 - m1x);
-        pg[2] = T(0.5) * (m3 + m1y);
-        pg[4] = T(0.5) * (m3 - m1y);
+    heat_collide<T>(T(kp.s1t), g, H, theta, Hux, Huy, dHx, dHy, pg);
+    const bool heat_here = kp.use_t && kp.n_sub_t == 1;
+    if (kp.use_t && kp.n_sub_t > 1) {
+        // inputs of the heat sub-steps (k_heat_sub): u and d_t(Hu) of time t
+        HT* __restrict__ aux = (HT*)kp.aux;
+        aux[idx] = HT(ux);
+        aux[P + idx] = HT(uy);
+        aux[2 * P + idx] = HT(dHx);
+        aux[3 * P + idx] = HT(dHy);
     }
 
     // ---- streaming (push).  phi: f(y,t+1) = f(y,t) + (post - f(y,t)) / a_s^2 ----
@@ -305,7 +358,7 @@ __device__ __forceinline__ void pct_node(const KParams& kp, const typename CF::S
         T fold = i == 0 ? f[0] : ld_pop<T>(pin, i * P + (size_t)d, kp.shift[i]);
         st_pop(pout, i * P + (size_t)d, fold + (pf[i] - fold) * inv_a2, kp.shift[i]);
         st_pop(pout, (5 + i) * P + (size_t)d, pn[i], kp.shift[5 + i]);
-        if (kp.use_t) st_pop(pout, (10 + i) * P + (size_t)d, pg[i], kp.shift[10 + i]);
+        if (heat_here) st_pop(pout, (10 + i) * P + (size_t)d, pg[i], kp.shift[10 + i]);
     }
 }
 
@@ -1017,10 +1070,12 @@ __global__ __launch_bounds__(BLOCK) void k_set_fields(const KParams kp, const In
     } else {
         for (int i = 0; i < 5; ++i) st_pop(pop, (5 + i) * P + idx, e[i], kp.shift[5 + i]);
     }
-    eq_heat<double>(th, phi, kp.h_quintic, ux, uy, e);
+    // heat populations carry the velocity of their own step (n_sub_t sub-steps)
+    const double ht = kp.n_sub_t;
+    eq_heat<double>(th, phi, kp.h_quintic, ux / ht, uy / ht, e);
     if (keep_neq) {
         double tho = Ho + 0.5 * h_of(phio, kp.h_quintic);
-        eq_heat<double>(tho, phio, kp.h_quintic, uox, uoy, eo);
+        eq_heat<double>(tho, phio, kp.h_quintic, uox / ht, uoy / ht, eo);
         for (int i = 0; i < 5; ++i) st_pop(pop, (10 + i) * P + idx, go[i] + (e[i] - eo[i]), kp.shift[10 + i]);
     } else {
         for (int i = 0; i < 5; ++i) st_pop(pop, (10 + i) * P + idx, e[i], kp.shift[10 + i]);

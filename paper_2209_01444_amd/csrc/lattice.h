@@ -37,6 +37,8 @@ struct KParams {
     int tbw_dy[2], tbw_nby[2];  // row shift and tile rows of the wave-row fused tiles, K = 3 / 5
     int grad_stencil;           // 1: grad phi from the nine-point stencil of the plane phin
     const void* phin;           // phi at time t per node (history type), grad_stencil only
+    int n_sub_t;                // heat sub-steps per main step (1: within k_pct)
+    void* aux;                  // u, d_t(Hu) of time t (4 planes, history type), n_sub_t > 1 only
 };
 
 static constexpr int TILE_X = 64;

@@ -202,6 +202,25 @@ def test_stencil_gradient_ablation_parity(dlb, case, precision, tol):
     assert np.abs(local.fields()["phi"] - o.fields()["phi"]).max() > 1e-6
 
 
+@pytest.mark.parametrize("case,precision,tol,nt", [("channel", "f64", 1e-10, 4), ("channel", "f32", 1e-4, 3),
+                                                   ("periodic", "f64", 1e-10, 8)])
+def test_heat_sub_steps_parity(dlb, case, precision, tol, nt):
+    """n_sub_t heat sub-steps per main step (multi-time-scaling for Le !=
+    1), GPU against the oracle: the coupled channel case with alpha raised
+    tenfold (Le = 10), and a periodic seed at alpha = 2."""
+    _say(f"case: heat sub-steps n_sub_t={nt}, {case} {precision}")
+    if case == "periodic":
+        cfg = dict(W.pure_diffusion_128(precision), nx=64, ny=64, seed_x=32.0, seed_y=32.0, alpha=2.0,
+                   n_sub_t=nt)
+        noise = None
+    else:
+        cfg, noise = _flow_case(64, 48, precision)
+        cfg = dict(cfg, alpha=10 * cfg["alpha"], n_sub_t=nt)
+    o = O.Oracle(cfg).init_seed(noise).step(150)
+    s = dlb.Solver(cfg).init_seed(noise).step(150)
+    compare(s.fields(), o.fields(), tol, label=f"heat sub-steps {case} {precision}")
+
+
 @pytest.mark.parametrize("precision", ["f64", "f32", "f16s"])
 @pytest.mark.parametrize("walls", [1, 0])
 def test_fused_flow_substeps_match_single_substeps(dlb, precision, walls):
@@ -574,6 +593,6 @@ def test_batch_autotune_and_member_rules(dlb):
     r = b.members[2].reduce()
     assert r["nonfinite"] == 0
     # solver options that batches do not carry are refused
-    for opt in ({"phi_static": 1}, {"grad_stencil": 1}):
+    for opt in ({"phi_static": 1}, {"grad_stencil": 1}, {"n_sub_t": 2}):
         with pytest.raises(dlb.DlbError):
             dlb.Batch([dict(cases[0][0], **opt)])
