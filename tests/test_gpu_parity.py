@@ -264,6 +264,22 @@ def test_channel_mirror_symmetry_full_size(dlb):
     np.testing.assert_allclose(-f["uy"][::-1, :], f["uy"], atol=1e-13)
 
 
+def test_channel_mirror_symmetry_full_size_fp32_fused(dlb):
+    """The same property in the benchmark's launch configuration (FP32,
+    five fused flow sub-steps per launch, wave-row tiles with the row shift
+    of the channel walls and the wall-free interior variant): the mirrored
+    rows of the tiling are computed by different tiles and wall code, so a
+    mistake in either breaks the symmetry."""
+    _say("case: channel mirror symmetry 1024x1024 FP32 fused, 300 steps")
+    cfg, _ = _flow_case(1024, 1024, "f32")
+    cfg.update(orient=0.0, seed_y=511.5, noise_amp=0.0)
+    s = dlb.Solver(cfg).init_seed().step(300)
+    f = s.fields()
+    for name in ("phi", "C", "theta", "ux", "p"):
+        np.testing.assert_allclose(f[name][::-1, :], f[name], atol=1e-5 * max(1, np.abs(f[name]).max()))
+    np.testing.assert_allclose(-f["uy"][::-1, :], f["uy"], atol=1e-5 * np.abs(f["ux"]).max())
+
+
 # ---------------------------------------------------------------------------
 # Edge cases and runtime behaviour
 # ---------------------------------------------------------------------------
