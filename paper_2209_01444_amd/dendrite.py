@@ -18,7 +18,10 @@ paper describes the upstream arm outgrowing the others, the vertical arms
 settling at the pure-diffusion velocity and the downstream arm slowing to
 a lower constant velocity.
 
-    python -m paper_2209_01444_amd.dendrite [--solutal | --flow] [--stencil]
+Solutal with melt flow (Sec. 4.3): the same comparison of the arms; the
+section gives no inflow or viscosity for it (workloads.solutal_dendrite).
+
+    python -m paper_2209_01444_amd.dendrite [--solutal] [--flow] [--stencil]
 """
 from __future__ import annotations
 
@@ -69,6 +72,35 @@ def run(steps: int = 16000, every: int = 500, precision: str = "f32", L: int = 5
         v = series[-1]["V"]
         out.update(V_downstream=v[0], V_upstream=v[2], V_vertical=0.5 * (v[1] + v[3]))
     return out
+
+
+def run_solutal_flow(steps: int = 30000, every: int = 3000, precision: str = "f32", L: int = 1000) -> dict:
+    """Solutal dendrite with melt flow (Sec. 4.3): tip velocity V d0/D and
+    radius of the four arms; arm 0 downstream (+x), arm 2 upstream."""
+    import torch
+
+    cfg = workloads.solutal_dendrite(precision, L, flow=True)
+    d0 = D0_SOLUTAL * cfg["W0"]
+    s = dlb.Solver(cfg).init_seed(None)
+    torch.cuda.synchronize()
+    prev = s.reduce()["tip_s"]
+    series, el, t = [], 0.0, 0
+    while t < steps:
+        n = min(every, steps - t)
+        t0 = time.perf_counter()
+        s.step(n)
+        torch.cuda.synchronize()
+        el += time.perf_counter() - t0
+        t += n
+        r = s.reduce()
+        v = (r["tip_s"] - prev) / n
+        prev = r["tip_s"]
+        series.append({"t_tau0": t / cfg["tau0"], "V": (v * d0 / cfg["D"]).round(5).tolist(),
+                       "rho_d0": (r["tip_rho"] / d0).round(3).tolist()})
+    v = series[-1]["V"]
+    return {"workload": cfg["name"], "precision": precision, "steps": steps, "seconds": el,
+            "MLUPS": L * L * steps / el / 1e6, "V_downstream": v[0], "V_upstream": v[2],
+            "V_vertical": 0.5 * (v[1] + v[3]), "series": series}
 
 
 def run_solutal(steps: int = 40000, every: int = 200, precision: str = "f32", L: int = 1000,
@@ -128,7 +160,9 @@ def main():
     ap.add_argument("--flow", action="store_true", help="thermal dendrite with melt flow")
     ap.add_argument("--stencil", action="store_true", help="stencil-gradient ablation of the local scheme")
     args = ap.parse_args()
-    if args.solutal:
+    if args.solutal and args.flow:
+        print(json.dumps(run_solutal_flow(args.steps or 30000, args.every or 3000, args.precision)), flush=True)
+    elif args.solutal:
         print(json.dumps(run_solutal(args.steps or 40000, args.every or 200, args.precision)), flush=True)
     else:
         print(json.dumps(run(args.steps or 16000, args.every or 500, args.precision, flow=args.flow,

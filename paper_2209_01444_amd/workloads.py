@@ -105,18 +105,28 @@ def thermal_dendrite(precision: str = "f32", L: int = 512, W0: float = 2.5, flow
         C0=1.0, seed_R=10.0, seed_x=c, seed_y=c, noise_amp=0.0, precision=precision)
 
 
-def solutal_dendrite(precision: str = "f32", L: int = 1000, W0: float = 2.5) -> dict:
+def solutal_dendrite(precision: str = "f32", L: int = 1000, W0: float = 2.5, flow: bool = False) -> dict:
     """Isothermal alloy dendrite at the paper's resolution (Sec. 4.3):
     L x L nodes, dx = 0.4 W0, dt = 0.02 tau0 (W0 = 2.5 lu, tau0 = 50 steps),
     eps4 = 0.02, theta = 0 (no heat lattice), U0 = -0.55 (uniform initial
     supersaturation), D = 2 W0^2/tau0, Mc_inf = 1, k = 0.15, lambda = 3.191,
-    seed R = 10 dx at the centre, zero-gradient walls, no flow."""
+    seed R = 10 dx at the centre, zero-gradient walls, no flow.
+
+    flow=True: the melt-flow case of the same section, which states neither
+    inflow nor viscosity: the thermal case's inflow W0/tau0 and melt
+    (nu = 23.1 x 4 W0^2/tau0, i.e. the same fluid), 15 flow sub-steps, the
+    seed on the channel's centre line."""
     tau0 = W0 * W0 / 0.125
-    return dict(
-        name=f"solutal_dendrite_{L}", nx=L, ny=L, use_c=1, use_t=0, use_ns=0, walls=1, n_sub=1,
-        c_init_U=1, W0=W0, tau0=tau0, eps4=0.02, orient=0.0, lambda_=3.191, Mcinf=1.0, k=0.15,
-        D=2.0 * W0 * W0 / tau0, alpha=0.1, nu=0.1, rho0=1.0, u_in=(0.0, 0.0), theta0=0.0, U0=-0.55,
-        C0=1.0, seed_R=10.0, seed_x=L / 2.0, seed_y=L / 2.0, noise_amp=0.0, precision=precision)
+    base = dict(
+        nx=L, ny=L, use_c=1, use_t=0, walls=1, c_init_U=1, W0=W0, tau0=tau0, eps4=0.02, orient=0.0,
+        lambda_=3.191, Mcinf=1.0, k=0.15, D=2.0 * W0 * W0 / tau0, alpha=0.1, rho0=1.0, theta0=0.0, U0=-0.55,
+        C0=1.0, seed_R=10.0, noise_amp=0.0, precision=precision)
+    if not flow:
+        return dict(base, name=f"solutal_dendrite_{L}", use_ns=0, n_sub=1, nu=0.1, u_in=(0.0, 0.0),
+                    seed_x=L / 2.0, seed_y=L / 2.0)
+    c = (L - 1) / 2.0
+    return dict(base, name=f"solutal_dendrite_flow_{L}", use_ns=1, n_sub=15,
+                nu=23.1 * 4.0 * W0 * W0 / tau0, u_in=(W0 / tau0, 0.0), seed_x=c, seed_y=c)
 
 
 def cylinder_flow(Re: float, R: int = 20, precision: str = "f32", n_sub: int = 15) -> dict:

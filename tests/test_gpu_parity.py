@@ -405,6 +405,26 @@ def test_isothermal_alloy_matches_oracle(dlb, precision, tol):
     assert np.all(s.fields()["theta"] == 0.0)
 
 
+def test_solutal_dendrite_with_melt_flow_follows_the_paper(dlb):
+    """The melt-flow case of Sec. 4.3 at the paper's resolution (1000^2, to
+    t = 600 tau0, the last time the section shows; inflow and viscosity are
+    not given there: the thermal case's W0/tau0 and melt), against its
+    description: the upstream arm outgrows the others, and while the
+    upstream tip radius falls to a low value the radii of the tips across
+    and down the flow grow again after a small decrease."""
+    from paper_2209_01444_amd import dendrite
+    _say("case: solutal dendrite with melt flow 1000x1000 FP32, 30000 steps")
+    r = dendrite.run_solutal_flow(30000, 3000, "f32")
+    up, across, down = r["V_upstream"], r["V_vertical"], r["V_downstream"]
+    _say(f"  V d0/D at 600 tau0: upstream {up:.5f}, across {across:.5f}, downstream {down:.5f}")
+    assert up > 1.5 * across and down < 0.6 * across
+    first, mid, last = r["series"][0], r["series"][2], r["series"][-1]  # t = 60, 180 and 600 tau0
+    rho_f, rho_m, rho_l = first["rho_d0"], mid["rho_d0"], last["rho_d0"]
+    assert rho_l[2] < rho_f[2] and rho_l[2] < rho_l[1] and rho_l[2] < rho_l[0]  # upstream radius falls, stays low
+    assert rho_l[0] > rho_m[0] and rho_l[1] > rho_m[1]  # downstream and across radii grow again
+    assert abs(last["V"][1] - last["V"][3]) <= 1e-3 * across  # arms across the flow mirror each other
+
+
 def test_solutal_dendrite_follows_gibbs_thomson(dlb):
     """Pin of the solute lattice and the anti-trapping current (Sec. 4.3):
     the isothermal alloy dendrite at the paper's resolution (1000 x 1000,

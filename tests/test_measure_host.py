@@ -60,3 +60,15 @@ def test_thermal_dendrite_flow_workload():
     s2 = 1.0 / (3.0 * fl["nu"] / fl["n_sub"] + 0.5)
     assert 0.0 < s2 < 2.0
     assert fl["u_in"][0] / fl["n_sub"] * 3 ** 0.5 < 0.1  # Mach number per sub-step
+
+
+def test_solutal_dendrite_flow_workload():
+    # Sec. 4.3 with melt flow: the section gives no inflow or viscosity; the
+    # thermal case's inflow W0/tau0 and melt (nu = 23.1 x 4 W0^2/tau0)
+    fl = workloads.solutal_dendrite(flow=True)
+    so = workloads.solutal_dendrite()
+    assert fl["u_in"] == (pytest.approx(fl["W0"] / fl["tau0"]), 0.0) and fl["use_ns"] == 1
+    assert fl["nu"] == pytest.approx(23.1 * 4 * fl["W0"] ** 2 / fl["tau0"])
+    assert fl["seed_x"] == fl["seed_y"] == (fl["nx"] - 1) / 2
+    assert all(fl[k] == so[k] for k in ("W0", "tau0", "D", "lambda_", "eps4", "U0", "k", "Mcinf", "use_t"))
+    assert 0.0 < 1.0 / (3.0 * fl["nu"] / fl["n_sub"] + 0.5) < 2.0
