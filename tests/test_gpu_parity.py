@@ -221,6 +221,19 @@ def test_heat_sub_steps_parity(dlb, case, precision, tol, nt):
     compare(s.fields(), o.fields(), tol, label=f"heat sub-steps {case} {precision}")
 
 
+def test_heat_sub_steps_with_16bit_storage(dlb):
+    """The heat sub-steps store their intermediate planes with the heat
+    lattice's rest-state shifts: FP16-shifted storage follows the FP32 run
+    to the storage tolerance of the fused-flow test."""
+    _say("case: heat sub-steps n_sub_t=3 with FP16-shifted storage")
+    runs = {}
+    for precision in ("f32", "f16s"):
+        cfg, noise = _flow_case(96, 78, precision)
+        cfg = dict(cfg, alpha=10 * cfg["alpha"], n_sub_t=3)
+        runs[precision] = dlb.Solver(cfg).init_seed(noise).step(30).fields()
+    compare(runs["f16s"], runs["f32"], 6e-2, label="f16s vs f32, heat sub-steps")
+
+
 @pytest.mark.parametrize("precision", ["f64", "f32", "f16s"])
 @pytest.mark.parametrize("walls", [1, 0])
 def test_fused_flow_substeps_match_single_substeps(dlb, precision, walls):
