@@ -6,14 +6,20 @@
 //   pop[2][15]  phi (0-4), solute (5-9), heat (10-14) populations, ping-pong
 //   flow[2][9]  flow populations (h_0 stored as h_0 - rho0), ping-pong
 //   hist[6]     phi, Q, (C u)x, (C u)y, (H u)x, (H u)y of the previous step
+//   options:    phin (phi^t, grad_stencil); aux[4] (u, d_t(Hu) of time t)
+//               and five scratch heat planes (n_sub_t > 1)
 //
 // One main step (Jacobi order: every lattice reads the fields of time t):
 //   k_pct      phi, C, theta collide at every node and push-stream; the
 //              phi lattice uses the modified streaming of Remark 2 / Sec. 3.1;
 //              the history planes are overwritten with the time-t values, so
 //              hist[0] holds phi^t for the flow sub-steps that follow.
+//              (k_phi_plane runs before it for the stencil-gradient option;
+//              k_heat_sub x n_sub_t after it when the heat lattice takes
+//              sub-steps.)
 //   k_flow     x N_sub: D2Q9 MRT collision with the diffuse force of
-//              Sec. 3.4 at frozen phi^t, push-streamed.
+//              Sec. 3.4 at frozen phi^t, push-streamed; or K sub-steps per
+//              launch in k_flow_tbw (FP32 arithmetic) / k_flow_tb (FP64).
 // Wall nodes of the channel configuration are never stored: whoever reads
 // one rebuilds it from its inward neighbour (zero gradient for phi, C, H;
 // non-equilibrium extrapolation for the flow).
