@@ -420,6 +420,15 @@ orc_state* orc_create(const orc_params* p) {
         set_err("n_sub < 1");
         return NULL;
     }
+    if (p->walls < 0 || p->walls > 2) {
+        set_err("walls must be 0, 1 or 2");
+        return NULL;
+    }
+    if (p->walls == 2 && (p->use_ns || p->grad_stencil || heat_sub(p) > 1 || p->phi_static)) {
+        set_err("far-field walls need the flow lattice off, the local gradient, one heat step "
+                "and a moving phi");
+        return NULL;
+    }
     double s1 = s1_phi(p, 1.0);
     double s1c = 1.0 / (3.0 * p->D * (1.0 - p->k) + 0.5);
     /* multi-time-scaling of the heat lattice: n_sub_t sub-steps of dt/n_sub_t,
@@ -478,15 +487,49 @@ static inline int inward(const orc_state* s, int x, int y) {
  * x_f each time they are needed (before every collision and every macro
  * evaluation) by non-equilibrium extrapolation (Sec. 4 preamble):
  *   f(x_b) = f^eq(Psi_b, u_b) + [f(x_f) - f^eq(Psi_f, u_f)].
- * phi, C, H lattices: zero-gradient Psi_b = Psi_f with u_b = u_f, which makes
- * the rebuild a copy of x_f's populations. */
-static void fill_cde_walls(orc_state* s, double* pop) {
+ * walls = 1, phi, C, H lattices: zero gradient Psi_b = Psi_f with u_b = u_f,
+ * which makes the rebuild a copy of x_f's populations.
+ * walls = 2, far field (Sec. 4.4: Dirichlet phi = -1, U = U0, theta = theta0
+ * on the outer boundary): Psi_b is the far-field liquid, phi = -1 with the C
+ * of the initial far field and theta0, at u = 0 (the flow lattice is off in
+ * this configuration).  lattice: 0 phi, 1 C, 2 H. */
+static double far_field_C(const orc_params* p) {
+    /* the initial C at phi = -1: uniform C0, or the C of U = U0 */
+    return p->c_init_U ? 0.5 * (1.0 + p->k + (1.0 - p->k)) * (1.0 + (1.0 - p->k) * p->U0) : p->C0;
+}
+static void fill_cde_walls(orc_state* s, double* pop, int lattice) {
     if (!s->p.walls) return;
+    const orc_params* p = &s->p;
+    const size_t N = (size_t)s->N;
     for (int y = 0; y < s->ny; ++y)
         for (int x = 0; x < s->nx; ++x) {
             if (!is_wall(s, x, y)) continue;
             int b = y * s->nx + x, f = inward(s, x, y);
-            for (int i = 0; i < 5; ++i) pop[(size_t)i * s->N + b] = pop[(size_t)i * s->N + f];
+            double d[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+            if (p->walls == 2) {
+                double phf = 0.0, Cf = 0.0, Hf = 0.0, eb[5], ef[5];
+                for (int i = 0; i < 5; ++i) {
+                    phf += s->f[i * N + f];
+                    if (p->use_c) Cf += s->n[i * N + f];
+                    if (p->use_t) Hf += s->g[i * N + f];
+                }
+                if (lattice == 0) {
+                    orc_eq_phi(-1.0, eb);
+                    orc_eq_phi(phf, ef);
+                } else if (lattice == 1) {
+                    double Cb = far_field_C(p);
+                    double Ub = (2.0 * Cb / (1.0 + p->k - (1.0 - p->k) * -1.0) - 1.0) / (1.0 - p->k);
+                    double Uf = (2.0 * Cf / (1.0 + p->k - (1.0 - p->k) * phf) - 1.0) / (1.0 - p->k);
+                    orc_eq_solute(Cb, -1.0, Ub, 0.0, 0.0, eb);
+                    orc_eq_solute(Cf, phf, Uf, 0.0, 0.0, ef);
+                } else {
+                    double thf = Hf + 0.5 * h_of(phf, p->h_quintic);
+                    orc_eq_heat(p->theta0, -1.0, p->h_quintic, 0.0, 0.0, eb);
+                    orc_eq_heat(thf, phf, p->h_quintic, 0.0, 0.0, ef);
+                }
+                for (int i = 0; i < 5; ++i) d[i] = eb[i] - ef[i];
+            }
+            for (int i = 0; i < 5; ++i) pop[(size_t)i * N + b] = pop[(size_t)i * N + f] + d[i];
         }
 }
 
@@ -531,9 +574,9 @@ static void fill_flow_walls(orc_state* s, double* h, const double* phi) {
 static void compute_macros(orc_state* s) {
     const orc_params* p = &s->p;
     int N = s->N;
-    fill_cde_walls(s, s->f);
-    if (p->use_c) fill_cde_walls(s, s->n);
-    if (p->use_t) fill_cde_walls(s, s->g);
+    fill_cde_walls(s, s->f, 0);
+    if (p->use_c) fill_cde_walls(s, s->n, 1);
+    if (p->use_t) fill_cde_walls(s, s->g, 2);
 #pragma omp parallel for schedule(static)
     for (int x = 0; x < N; ++x) {
         double ph = 0.0, C = 0.0, H = 0.0;
@@ -718,7 +761,7 @@ static void heat_substeps(orc_state* s) {
     int N = s->N, nx = s->nx, ny = s->ny;
     const int ns = heat_sub(p);
     for (int sub = 0; sub < ns; ++sub) {
-        fill_cde_walls(s, s->g);
+        fill_cde_walls(s, s->g, 2);
 #pragma omp parallel for schedule(static)
         for (int x = 0; x < N; ++x) {
             double gv[5], geq[5], GT[5], H = 0.0;

@@ -34,6 +34,8 @@
  *   stencil-gradient ablation (grad_stencil): exact on quadratics,
  *     stationary planar fronts at second order                    pinned
  *   heat sub-steps (n_sub_t): diffusion rate, advected mode       pinned
+ *   far-field walls (walls = 2): sine modes vanishing on the wall
+ *     ring decay at the diffusion rate; relaxation to the far field pinned
  *   tip position / radius measurement                             pinned (geometry)
  */
 #ifndef DLB_ORACLE_H
@@ -49,7 +51,10 @@ typedef struct orc_params {
     int use_t;        /* heat lattice on (else theta = theta0 everywhere)     */
     int use_ns;       /* flow lattice on (else u = 0)                         */
     int walls;        /* 0: periodic; 1: channel (west inflow, east outflow,
-                         free-slip north/south, zero-gradient phi/C/H)        */
+                         free-slip north/south, zero-gradient phi/C/H);
+                         2: far field (Sec. 4.4): the wall ring holds phi = -1,
+                         the initial far-field C and theta0 by extrapolation;
+                         flow lattice off, local gradient, one heat step    */
     int n_sub;        /* flow sub-steps per main step (two-time-scaling N)    */
     int h_quintic;    /* 0: h(phi)=phi; 1: h = 15(phi-2phi^3/3+phi^5/5)/8    */
     int c_init_U;     /* 0: initial C uniform = C0; 1: initial U uniform = U0 */

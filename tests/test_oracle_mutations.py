@@ -18,8 +18,16 @@ TT = "tests/test_oracle_tables.py::"
 TR = "tests/test_oracle_restart.py::"
 TS = "tests/test_oracle_stencil.py::"
 TH = "tests/test_oracle_heat_substeps.py::"
+TF = "tests/test_oracle_farfield.py::"
 
 MUTATIONS = [
+    ("far field: the wall copies its neighbour", "for (int i = 0; i < 5; ++i) d[i] = eb[i] - ef[i];",
+     "for (int i = 0; i < 5; ++i) d[i] = 0.0;", TF + "test_relaxes_to_the_far_field_zero_gradient_walls_do_not"),
+    ("far field: sign of the equilibrium shift", "for (int i = 0; i < 5; ++i) d[i] = eb[i] - ef[i];",
+     "for (int i = 0; i < 5; ++i) d[i] = ef[i] - eb[i];", TF + "test_dirichlet_mode_decays_at_the_diffusion_rate"),
+    ("far field: C of U0 without the 1 - k factor",
+     "* (1.0 + (1.0 - p->k) * p->U0) : p->C0;", "* (1.0 + p->U0) : p->C0;",
+     TF + "test_relaxes_to_the_far_field_zero_gradient_walls_do_not"),
     ("heat sub-steps: velocity in main-step units", "s->ux[x] / ns, s->uy[x] / ns, geq", "s->ux[x], s->uy[x], geq",
      TH + "test_advected_heat_mode_with_sub_steps"),
     ("heat sub-steps: diffusivity not rescaled", "1.0 / (3.0 * p->alpha / heat_sub(p) + 0.5)",
