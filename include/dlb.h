@@ -65,7 +65,15 @@ enum {
      * phi, C, H: zero gradient (a copy of x_f).  Flow: west x=0 inflow
      * u_b = u_in, p_b = p_f; east x=nx-1 du/dx = 0 with p_b = 0 (u_b,y = 0 at
      * its corners); north/south free slip u_b = (u_f,x, 0), p_b = p_f. */
-    DLB_BC_CHANNEL = 1
+    DLB_BC_CHANNEL = 1,
+    /* Far field (Sec. 4.4: Dirichlet phi = -1, U = U0, theta = theta0 on the
+     * outer boundary): the outermost ring are wall nodes as in the channel;
+     * their phi, C and H populations are rebuilt toward the far-field liquid,
+     *   f(x_b) = f^eq(Psi_inf, 0) + f(x_f) - f^eq(Psi_f, 0),
+     * Psi_inf = (phi = -1, C of the initial far field, theta0), u = 0.
+     * Requires use_ns = 0, grad_stencil = 0, n_sub_t <= 1 and phi_static = 0
+     * (DLB_EUNSUPPORTED otherwise); not available in batches. */
+    DLB_BC_FARFIELD = 2
 };
 
 typedef struct dlb_params {

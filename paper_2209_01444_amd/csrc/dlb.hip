@@ -64,12 +64,16 @@ int check_params(const dlb_params* p) {
     if (p->nx < 16 || p->ny < 16) return fail(DLB_EINVAL, "grid must be at least 16x16");
     if ((long long)p->nx * p->ny > (1ll << 31)) return fail(DLB_EINVAL, "grid too large");
     if (storage_bytes(p->precision) == 0) return fail(DLB_EINVAL, "unknown precision");
-    if (p->bc != DLB_BC_PERIODIC && p->bc != DLB_BC_CHANNEL) return fail(DLB_EINVAL, "unknown bc");
+    if (p->bc != DLB_BC_PERIODIC && p->bc != DLB_BC_CHANNEL && p->bc != DLB_BC_FARFIELD)
+        return fail(DLB_EINVAL, "unknown bc");
     if (p->use_ns && p->n_sub < 1) return fail(DLB_EINVAL, "n_sub must be >= 1");
     if (p->phi_static != 0 && p->phi_static != 1) return fail(DLB_EINVAL, "phi_static must be 0 or 1");
     if (p->isothermal != 0 && p->isothermal != 1) return fail(DLB_EINVAL, "isothermal must be 0 or 1");
     if (p->grad_stencil != 0 && p->grad_stencil != 1) return fail(DLB_EINVAL, "grad_stencil must be 0 or 1");
     if (p->n_sub_t < 0 || p->n_sub_t > 256) return fail(DLB_EINVAL, "n_sub_t must be in [0, 256]");
+    if (p->bc == DLB_BC_FARFIELD && (p->use_ns || p->grad_stencil || p->n_sub_t > 1 || p->phi_static))
+        return fail(DLB_EUNSUPPORTED,
+                    "far-field walls need use_ns = 0, grad_stencil = 0, n_sub_t <= 1 and phi_static = 0");
     if (!(p->W0 > 0 && p->tau0 > 0 && p->D > 0 && p->alpha > 0)) return fail(DLB_EINVAL, "W0, tau0, D, alpha must be > 0");
     if (!(p->k > 0 && p->k < 1)) return fail(DLB_EINVAL, "partition coefficient k must be in (0,1)");
     double W2t = p->W0 * p->W0 / p->tau0;
@@ -169,7 +173,11 @@ static KParams make_kparams(const dlb_params* p, const Layout& L) {
     k.grad_iters = p->grad_iters > 0 ? p->grad_iters : (f64 ? 100 : (mixed ? 40 : 20));
     double tol = p->grad_tol > 0 ? p->grad_tol : (f64 ? 1e-14 : (mixed ? 1e-10 : 1e-6));
     k.grad_tol2 = tol * tol;
-    k.walls = p->bc == DLB_BC_CHANNEL;
+    k.walls = p->bc != DLB_BC_PERIODIC;
+    k.farfield = p->bc == DLB_BC_FARFIELD;
+    // far-field liquid: the initial C at phi = -1 (uniform C0, or that of U0)
+    k.ff_C = p->c_init_U ? 1.0 + (1.0 - p->k) * p->U0 : p->C0;
+    k.ff_U = (k.ff_C - 1.0) / (1.0 - p->k);
     k.use_t = p->isothermal ? 0 : 1;
     k.theta0 = p->theta0;
     k.nbx = (p->nx + TILE_X - 1) / TILE_X;
@@ -333,7 +341,7 @@ template <class CF> static BatchOps bops_for(bool ns, bool walls) {
 }
 
 static BatchOps select_bops(const dlb_params* p) {
-    bool ns = p->use_ns != 0, walls = p->bc == DLB_BC_CHANNEL;
+    bool ns = p->use_ns != 0, walls = p->bc != DLB_BC_PERIODIC;
     switch (p->precision) {
         case DLB_F64: return bops_for<CfgF64>(ns, walls);
         case DLB_F32: return bops_for<CfgF32>(ns, walls);
@@ -344,7 +352,7 @@ static BatchOps select_bops(const dlb_params* p) {
 }
 
 static Ops select_ops(const dlb_params* p) {
-    bool ns = p->use_ns != 0, walls = p->bc == DLB_BC_CHANNEL;
+    bool ns = p->use_ns != 0, walls = p->bc != DLB_BC_PERIODIC;
     switch (p->precision) {
         case DLB_F64: return ops_for<CfgF64>(ns, walls);
         case DLB_F32: return ops_for<CfgF32>(ns, walls);
@@ -814,6 +822,7 @@ static int batch_layout(const dlb_params* ps, int count, std::vector<size_t>* of
         int rc = check_params(&ps[i]);
         if (rc) return rc;
         if (ps[i].phi_static) return fail(DLB_EUNSUPPORTED, "phi_static is not available in batches");
+        if (ps[i].bc == DLB_BC_FARFIELD) return fail(DLB_EUNSUPPORTED, "far-field walls are not available in batches");
         if (ps[i].grad_stencil) return fail(DLB_EUNSUPPORTED, "grad_stencil is not available in batches");
         if (ps[i].n_sub_t > 1) return fail(DLB_EUNSUPPORTED, "n_sub_t > 1 is not available in batches");
         if (!batch_compatible(&ps[0], &ps[i]))

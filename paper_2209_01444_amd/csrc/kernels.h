@@ -20,9 +20,10 @@
 //   k_flow     x N_sub: D2Q9 MRT collision with the diffuse force of
 //              Sec. 3.4 at frozen phi^t, push-streamed; or K sub-steps per
 //              launch in k_flow_tbw (FP32 arithmetic) / k_flow_tb (FP64).
-// Wall nodes of the channel configuration are never stored: whoever reads
-// one rebuilds it from its inward neighbour (zero gradient for phi, C, H;
-// non-equilibrium extrapolation for the flow).
+// Wall nodes of the channel and far-field configurations are never stored:
+// whoever reads one rebuilds it from its inward neighbour (zero gradient, or
+// the far-field liquid, for phi, C, H; non-equilibrium extrapolation for the
+// flow).
 #pragma once
 
 #include "lattice.h"
@@ -46,6 +47,36 @@ __device__ __forceinline__ long long push_dest(const KParams& kp, int x, int y, 
         dy = dy < 0 ? dy + kp.ny : (dy >= kp.ny ? dy - kp.ny : dy);
     }
     return (long long)dy * kp.nx + dx;
+}
+
+// Far-field walls (Sec. 4.4; the flow lattice is off): the wall node's phi,
+// C and H populations are those of its inward neighbour moved by the change
+// of the equilibrium, at u = 0, from the neighbour's fields to the far-field
+// liquid phi = -1, C = ff_C, theta = theta0 (non-equilibrium extrapolation).
+template <class T>
+__device__ __forceinline__ void farfield_rebuild(const KParams& kp, T* f, T* n, T* g) {
+#pragma clang fp contract(off)
+    const T phi = (((f[0] + f[1]) + f[2]) + f[3]) + f[4];
+    const T C = (((n[0] + n[1]) + n[2]) + n[3]) + n[4];
+    const T k = T(kp.k);
+    const T U = (T(2) * C / (T(1) + k - (T(1) - k) * phi) - T(1)) / (T(1) - k);
+    T eb[5], ef[5];
+    eq_phi<T>(T(-1), eb);
+    eq_phi<T>(phi, ef);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) f[i] = f[i] + (eb[i] - ef[i]);
+    eq_solute<T>(T(kp.ff_C), T(-1), T(kp.ff_U), T(0), T(0), eb);
+    eq_solute<T>(C, phi, U, T(0), T(0), ef);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) n[i] = n[i] + (eb[i] - ef[i]);
+    if (kp.use_t) {
+        const T H = (((g[0] + g[1]) + g[2]) + g[3]) + g[4];
+        const T theta = H + T(0.5) * h_of(phi, kp.h_quintic);
+        eq_heat<T>(T(kp.theta0), T(-1), kp.h_quintic, T(0), T(0), eb);
+        eq_heat<T>(theta, phi, kp.h_quintic, T(0), T(0), ef);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) g[i] = g[i] + (eb[i] - ef[i]);
+    }
 }
 
 // Non-equilibrium extrapolation (Sec. 4 preamble) of the wall node (x, y)
@@ -240,6 +271,9 @@ __device__ __forceinline__ void pct_node(const KParams& kp, const typename CF::S
     if (kp.use_t)
 #pragma unroll
         for (int i = 0; i < 5; ++i) g[i] = ld_pop<T>(pin, (10 + i) * P + src, kp.shift[10 + i]);
+    if constexpr (WALLS && !NS) {
+        if (wall && kp.farfield) farfield_rebuild<T>(kp, f, n, g);
+    }
     // macroscopic fields of time t (Sec. 3.1-3.3); isothermal runs (no heat
     // lattice) keep theta = theta0, H = theta0 - h(phi)/2
     const T phi = (((f[0] + f[1]) + f[2]) + f[3]) + f[4];
@@ -976,7 +1010,7 @@ __global__ __launch_bounds__(BLOCK) void k_restart_prep(const KParams kp,
         C += ld_pop<double>(pop, (5 + i) * P + src, kp.shift[5 + i]);
         H += ld_pop<double>(pop, (10 + i) * P + src, kp.shift[10 + i]);
     }
-    phi_old[idx] = phi;
+    phi_old[idx] = (wall && kp.farfield) ? -1.0 : phi;
     if (!hist_valid || wall) return;
     const double k = kp.k;
     const double U = (2.0 * C / (1.0 + k - (1.0 - k) * phi) - 1.0) / (1.0 - k);
@@ -1132,6 +1166,13 @@ __device__ __forceinline__ void node_macros(const KParams& kp, const typename CF
         C += ld_pop<T>(pop, (5 + i) * P + src, kp.shift[5 + i]);
         H += ld_pop<T>(pop, (10 + i) * P + src, kp.shift[10 + i]);
     }
+    if constexpr (WALLS && !NS) {
+        if (kp.farfield && is_wall(kp, x, y)) {  // the far-field liquid
+            phi = T(-1);
+            C = T(kp.ff_C);
+            H = T(kp.theta0) - T(0.5) * h_of(T(-1), kp.h_quintic);
+        }
+    }
     T k = T(kp.k);
     if (!kp.use_t) H = T(kp.theta0) - T(0.5) * h_of(phi, kp.h_quintic);  // isothermal
     m[0] = phi;
@@ -1258,6 +1299,7 @@ __device__ __forceinline__ double node_phi(const KParams& kp, const typename CF:
                                            int x, int y) {
     using T = typename CF::T;
     const size_t P = (size_t)kp.plane;
+    if (WALLS && kp.farfield && is_wall(kp, x, y)) return -1.0;
     size_t idx = (WALLS && is_wall(kp, x, y)) ? inward_idx(kp, x, y) : (size_t)y * kp.nx + x;
     T s = 0;
 #pragma unroll

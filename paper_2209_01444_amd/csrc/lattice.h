@@ -39,6 +39,8 @@ struct KParams {
     const void* phin;           // phi at time t per node (history type), grad_stencil only
     int n_sub_t;                // heat sub-steps per main step (1: within k_pct)
     void* aux;                  // u, d_t(Hu) of time t (4 planes, history type), n_sub_t > 1 only
+    int farfield;               // walls hold the far-field liquid (flow lattice off)
+    double ff_C, ff_U;          // far-field C and U (phi = -1)
 };
 
 static constexpr int TILE_X = 64;

@@ -21,7 +21,15 @@ a lower constant velocity.
 Solutal with melt flow (Sec. 4.3): the same comparison of the arms; the
 section gives no inflow or viscosity for it (workloads.solutal_dendrite).
 
-    python -m paper_2209_01444_amd.dendrite [--solutal] [--flow] [--stencil]
+Thermosolutal with pure diffusion (Sec. 4.4): 2400^2 with far-field walls to
+t D/d0^2 = 470000; the tip velocity V d0/D and radius of the four arms, the
+selection parameter 2 D d0/(rho^2 V), and phi, U, theta along the central
+axis at the end (the section compares these with other authors' curves,
+which the text does not reproduce).  With melt flow, to t D/d0^2 = 150000:
+the section describes a fast upstream arm, clearly growing arms across the
+flow and a suppressed downstream arm.
+
+    python -m paper_2209_01444_amd.dendrite [--solutal] [--thermosolutal] [--flow] [--stencil]
 """
 from __future__ import annotations
 
@@ -37,6 +45,7 @@ PAPER_V = 0.0166  # steady V d0 / alpha of Sec. 4.2
 D0_OVER_W0 = 0.1385
 # Sec. 4.3 prints d0 = 0.2762 W0 next to lambda = 3.191; a1 W0 / lambda gives 0.2770 W0
 D0_SOLUTAL = 0.8839 / 3.191
+D0_THERMOSOLUTAL = 0.8839 / 3.1913  # 0.2770 W0, as Sec. 4.4 prints
 
 
 def run(steps: int = 16000, every: int = 500, precision: str = "f32", L: int = 512, flow: bool = False,
@@ -151,16 +160,83 @@ def run_solutal(steps: int = 40000, every: int = 200, precision: str = "f32", L:
                         for x, m, q in zip(xs[::10], meas[::10], pred[::10])]}
 
 
+def run_thermosolutal(t_end: float = 470000.0, records: int = 20, precision: str = "f32", L: int = 2400,
+                      profile_step: int = 4, verbose: bool = True, flow: bool = False) -> dict:
+    """Thermosolutal dendrite with pure diffusion (Sec. 4.4) to t D/d0^2 =
+    t_end, recorded `records` times: per arm the tip velocity V d0/D over the
+    last window, rho_tip/d0 and the selection parameter 2 D d0/(rho^2 V);
+    at the end phi, U and theta along the +x axis from the seed centre to the
+    wall (every profile_step nodes), with x measured from the tip.
+    flow=True: the melt-flow run (inflow along +x: arm 0 downstream, arm 2
+    upstream, arms 1 and 3 across the flow)."""
+    import sys
+
+    import torch
+
+    cfg = workloads.thermosolutal_dendrite(precision, L, flow=flow)
+    d0 = D0_THERMOSOLUTAL * cfg["W0"]
+    D = cfg["D"]
+    steps = int(round(t_end * d0 * d0 / D))
+    s = dlb.Solver(cfg).init_seed(None)
+    torch.cuda.synchronize()
+    prev = s.reduce()["tip_s"]
+    series, el, t = [], 0.0, 0
+    for j in range(records):
+        n = (steps * (j + 1)) // records - t
+        t0 = time.perf_counter()
+        s.step(n)
+        torch.cuda.synchronize()
+        el += time.perf_counter() - t0
+        t += n
+        r = s.reduce()
+        v = (r["tip_s"] - prev) / n
+        prev = r["tip_s"]
+        rho = r["tip_rho"]
+        series.append({"tD_d0sq": round(t * D / (d0 * d0)), "V": (v * d0 / D).round(8).tolist(),
+                       "rho_d0": (rho / d0).round(3).tolist(),
+                       "sigma": (2.0 * D * d0 / (rho * rho * v)).round(4).tolist(),
+                       "tip_lu": r["tip_s"].round(2).tolist(), "nonfinite": int(r["nonfinite"])})
+        if verbose:
+            print(f"[thermosolutal] step {t}/{steps}: {json.dumps(series[-1])}", file=sys.stderr, flush=True)
+    f = s.fields()
+    yc, xc = int(round(cfg["seed_y"])), int(round(cfg["seed_x"]))
+    tip = xc + float(series[-1]["tip_lu"][0])
+    xs = np.arange(xc, L, profile_step)
+    prof = [[round((x - tip) / d0, 2), round(float(f["phi"][yc, x]), 5), round(float(f["U"][yc, x]), 5),
+             round(float(f["theta"][yc, x]), 5)] for x in xs]
+    ring = np.ones((L, L), bool)
+    ring[1:-1, 1:-1] = False
+    last = series[-1]
+    out = {"workload": cfg["name"], "precision": precision, "steps": steps, "t_end_tD_d0sq": t_end,
+           "seconds": el, "MLUPS": L * L * steps / el / 1e6, "d0_lu": d0,
+           "V_final": float(np.mean(last["V"])), "rho_final_d0": float(np.mean(last["rho_d0"])),
+           "sigma_final": float(np.mean(last["sigma"])),
+           "wall_max_dev": {"phi": float(np.abs(f["phi"][ring] + 1.0).max()),
+                            "U": float(np.abs(f["U"][ring] - cfg["U0"]).max()),
+                            "theta": float(np.abs(f["theta"][ring] - cfg["theta0"]).max())},
+           "series": series, "axis_profile_x_d0_phi_U_theta": prof}
+    if flow:
+        v = last["V"]
+        out.update(V_downstream=v[0], V_upstream=v[2], V_vertical=0.5 * (v[1] + v[3]))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--every", type=int, default=None)
     ap.add_argument("--precision", default="f32")
     ap.add_argument("--solutal", action="store_true")
+    ap.add_argument("--thermosolutal", action="store_true", help="Sec. 4.4 pure diffusion, far-field walls")
+    ap.add_argument("--t-end", type=float, default=None,
+                    help="thermosolutal: final t D/d0^2 (470000; 150000 with --flow)")
     ap.add_argument("--flow", action="store_true", help="thermal dendrite with melt flow")
     ap.add_argument("--stencil", action="store_true", help="stencil-gradient ablation of the local scheme")
     args = ap.parse_args()
-    if args.solutal and args.flow:
+    if args.thermosolutal:
+        t_end = args.t_end if args.t_end is not None else (150000.0 if args.flow else 470000.0)
+        print(json.dumps(run_thermosolutal(t_end, 20, args.precision, flow=args.flow)), flush=True)
+    elif args.solutal and args.flow:
         print(json.dumps(run_solutal_flow(args.steps or 30000, args.every or 3000, args.precision)), flush=True)
     elif args.solutal:
         print(json.dumps(run_solutal(args.steps or 40000, args.every or 200, args.precision)), flush=True)

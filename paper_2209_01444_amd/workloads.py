@@ -129,6 +129,34 @@ def solutal_dendrite(precision: str = "f32", L: int = 1000, W0: float = 2.5, flo
                 nu=23.1 * 4.0 * W0 * W0 / tau0, u_in=(W0 / tau0, 0.0), seed_x=c, seed_y=c)
 
 
+def thermosolutal_dendrite(precision: str = "f32", L: int = 2400, W0: float = 2.5, flow: bool = False) -> dict:
+    """Thermosolutal dendrite with pure diffusion at the paper's resolution
+    (Sec. 4.4): L x L nodes, dx = 0.4 W0 (the section gives no dx; Secs. 4.2
+    and 4.3 use 0.4 W0), dt = tau0/55 (W0 = 2.5 lu, tau0 = 55 steps),
+    eps4 = 0.02, theta0 = -0.55, U0 = 0, alpha = D = 2 W0^2/tau0 (Le = 1),
+    Mc_inf = 0.5325, k = 0.15, lambda = 3.1913 (d0 = 0.2770 W0), seed
+    R = 45 dx on the domain's centre, far-field walls (phi = -1, U = 0,
+    theta = -0.55), no flow.
+
+    flow=True: the section's melt-flow run, whose flow boundaries are those
+    of the earlier sections: inflow W0/tau0 along +x at the west wall, free
+    outflow east, free slip north and south, Pr = nu/alpha = 23.1, 15 flow
+    sub-steps; phi, C and H take the channel's zero-gradient walls (the
+    far-field walls are for the flow lattice off; the inflow carries the
+    far-field melt in)."""
+    tau0 = 55.0
+    c = (L - 1) / 2.0
+    alpha = 2.0 * W0 * W0 / tau0
+    base = dict(
+        nx=L, ny=L, use_c=1, use_t=1, n_sub=1, c_init_U=1, W0=W0, tau0=tau0, eps4=0.02, orient=0.0,
+        lambda_=3.1913, Mcinf=0.5325, k=0.15, D=alpha, alpha=alpha, nu=0.1, rho0=1.0, u_in=(0.0, 0.0),
+        theta0=-0.55, U0=0.0, C0=1.0, seed_R=45.0, seed_x=c, seed_y=c, noise_amp=0.0, precision=precision)
+    if not flow:
+        return dict(base, name=f"thermosolutal_dendrite_{L}", use_ns=0, walls=2)
+    return dict(base, name=f"thermosolutal_dendrite_flow_{L}", use_ns=1, walls=1, n_sub=15,
+                nu=23.1 * alpha, u_in=(W0 / tau0, 0.0))
+
+
 def cylinder_flow(Re: float, R: int = 20, precision: str = "f32", n_sub: int = 15) -> dict:
     """Flow past a stationary diffuse cylinder (Sec. 4.1): domain 70R x 40R
     nodes, cylinder of radius R lu centred at (20R, 20R), interface width

@@ -72,6 +72,20 @@ def test_state_bytes_and_validation():
         assert lib.dlb_last_error()
 
 
+def test_far_field_walls_validation():
+    """Far-field walls need the flow lattice off, the local gradient, one
+    heat step and a moving phi; an unknown boundary code is refused."""
+    lib = dlb.load_library()
+    base = dict(W.pure_diffusion_128(), walls=2)
+    p = dlb.make_params(base)
+    assert lib.dlb_state_bytes(ctypes.byref(p)) > 0
+    for bad in (dict(use_ns=1, n_sub=2, nu=0.1), dict(grad_stencil=1), dict(n_sub_t=2), dict(phi_static=1),
+                dict(walls=3)):
+        q = dlb.make_params(dict(base, **bad))
+        assert lib.dlb_state_bytes(ctypes.byref(q)) == 0, bad
+        assert lib.dlb_last_error()
+
+
 def test_strerror_codes():
     lib = dlb.load_library()
     for code in (0, -1, -2, -3, -4, -5):

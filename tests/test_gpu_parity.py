@@ -418,6 +418,70 @@ def test_isothermal_alloy_matches_oracle(dlb, precision, tol):
     assert np.all(s.fields()["theta"] == 0.0)
 
 
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_farfield_walls_match_oracle(dlb, precision, tol):
+    """Far-field walls (Sec. 4.4): a thermosolutal seed next to the west wall
+    of a ragged 70 x 54 grid, whose heat and solute reach the wall ring,
+    against the oracle; the ring holds phi = -1, U0 and theta0."""
+    _say(f"case: far-field walls 70x54 thermosolutal, {precision}")
+    cfg = dict(W.pure_diffusion_128(precision), nx=70, ny=54, walls=2, c_init_U=1, U0=-0.1, theta0=-0.55,
+               Mcinf=0.5325, lambda_=3.19, k=0.15, D=0.2, alpha=0.25, eps4=0.02, seed_R=6.0, seed_x=13.3,
+               seed_y=26.6)
+    o = O.Oracle(cfg).init_seed().step(200)
+    s = dlb.Solver(cfg).init_seed().step(200)
+    gf, of = s.fields(), o.fields()
+    compare(gf, of, tol, fields=("phi", "C", "U", "theta"), label=f"far field {precision}")
+    ring = np.ones((54, 70), bool)
+    ring[1:-1, 1:-1] = False
+    lim = 1e-12 if precision == "f64" else 1e-6
+    assert np.abs(gf["phi"][ring] + 1.0).max() < lim
+    assert np.abs(gf["U"][ring] + 0.1).max() < lim
+    assert np.abs(gf["theta"][ring] + 0.55).max() < lim
+    assert np.abs(gf["theta"][1:-1, 1] + 0.55).max() > 1e-4  # the seed's heat reached the wall
+    r = s.reduce()
+    assert r["nonfinite"] == 0
+
+
+def test_thermosolutal_dendrite_with_far_field_walls(dlb):
+    """Sec. 4.4's pure-diffusion run at its resolution (2400^2, far-field
+    walls, Le = 1) to t D/d0^2 = 100000: the four arms grow alike (the seed
+    sits on the domain's centre, 0 degrees), the tip velocity settles, the
+    ring holds the far field, and ahead of the tip the rejected solute and
+    the latent heat decay toward U0 and theta0."""
+    from paper_2209_01444_amd import dendrite
+    _say("case: thermosolutal dendrite 2400x2400 FP32, far-field walls, to tD/d0^2 = 100000")
+    r = dendrite.run_thermosolutal(100000.0, 5, "f32", verbose=False)
+    last, prev = r["series"][-1], r["series"][-2]
+    _say(f"  V d0/D {last['V']}, rho/d0 {last['rho_d0']}, sigma {last['sigma']}, {r['MLUPS']:.0f} MLUPS")
+    assert all(x["nonfinite"] == 0 for x in r["series"])
+    v = np.array(last["V"])
+    assert v.min() > 0 and (v.max() - v.min()) <= 1e-3 * v.mean()
+    assert abs(np.mean(last["V"]) / np.mean(prev["V"]) - 1) < 0.1
+    assert max(r["wall_max_dev"].values()) < 1e-6
+    prof = np.array(r["axis_profile_x_d0_phi_U_theta"])
+    ahead = prof[prof[:, 0] > 5.0]  # liquid ahead of the tip
+    assert ahead[0, 2] > 0.0 and ahead[0, 3] > -0.55
+    assert np.all(np.diff(ahead[:, 2]) <= 1e-6) and np.all(np.diff(ahead[:, 3]) <= 1e-6)
+
+
+def test_thermosolutal_dendrite_with_melt_flow_follows_the_paper(dlb):
+    """Sec. 4.4's melt-flow run at its resolution (2400^2, inflow W0/tau0,
+    Pr = 23.1) to t D/d0^2 = 50000, against its description: the upstream
+    arm grows fast, the arms across the flow grow clearly, and the
+    downstream arm is suppressed (slow, with a blunt tip)."""
+    from paper_2209_01444_amd import dendrite
+    _say("case: thermosolutal dendrite with melt flow 2400x2400 FP32, to tD/d0^2 = 50000")
+    r = dendrite.run_thermosolutal(50000.0, 4, "f32", verbose=False, flow=True)
+    up, across, down = r["V_upstream"], r["V_vertical"], r["V_downstream"]
+    last = r["series"][-1]
+    _say(f"  V d0/D upstream {up:.5f}, across {across:.5f}, downstream {down:.5f}; rho/d0 {last['rho_d0']}")
+    assert all(x["nonfinite"] == 0 for x in r["series"])
+    assert up > 2.0 * across and down < 0.5 * across
+    rho = last["rho_d0"]
+    assert rho[0] > 2.0 * rho[1] and rho[2] < rho[1]  # blunt downstream tip, sharp upstream tip
+    assert abs(last["V"][1] - last["V"][3]) <= 1e-3 * across  # arms across the flow mirror each other
+
+
 def test_solutal_dendrite_with_melt_flow_follows_the_paper(dlb):
     """The melt-flow case of Sec. 4.3 at the paper's resolution (1000^2, to
     t = 600 tau0, the last time the section shows; inflow and viscosity are
@@ -642,6 +706,6 @@ def test_batch_autotune_and_member_rules(dlb):
     r = b.members[2].reduce()
     assert r["nonfinite"] == 0
     # solver options that batches do not carry are refused
-    for opt in ({"phi_static": 1}, {"grad_stencil": 1}, {"n_sub_t": 2}):
+    for opt in ({"phi_static": 1}, {"grad_stencil": 1}, {"n_sub_t": 2}, {"walls": 2, "use_ns": 0}):
         with pytest.raises(dlb.DlbError):
             dlb.Batch([dict(cases[0][0], **opt)])
