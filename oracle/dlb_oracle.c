@@ -198,6 +198,20 @@ void orc_force_flow(double Fx, double Fy, double* out) {
     for (int i = 0; i < 9; ++i) out[i] = W9[i] * (3.0 * (C9X[i] * Fx + C9Y[i] * Fy));
 }
 
+/* Sec. 3.4 forcing distribution in full:
+ *   F_i = w_i { c_i.G / cs^2 + varphi (uF + Fu):(c_i c_i - cs^2 I) / (2 cs^4) }
+ * with G = F + [1 - q(phi)] f; (uF + Fu):(cc - cs^2 I) = 2 (c.u)(c.F) - 2 cs^2 u.F. */
+void orc_force_flow_full(double Gx, double Gy, double Fx, double Fy, double ux, double uy,
+                         double varphi, double* out) {
+    const double cs2 = 1.0 / 3.0;
+    for (int i = 0; i < 9; ++i) {
+        double cG = C9X[i] * Gx + C9Y[i] * Gy;
+        double cu = C9X[i] * ux + C9Y[i] * uy, cF = C9X[i] * Fx + C9Y[i] * Fy;
+        double uF = ux * Fx + uy * Fy;
+        out[i] = W9[i] * (cG / cs2 + varphi * (2.0 * cu * cF - 2.0 * cs2 * uF) / (2.0 * cs2 * cs2));
+    }
+}
+
 /* ---------------------------------------------------------------------------
  * Anisotropy (Sec. 2): a_s(n) = (1-3e)[1 + 4e/(1-3e) sum_a n_a^4],
  * n = -grad(phi)/|grad(phi)|;  N_a = |grad phi|^2 a_s d a_s / d(d_a phi).
@@ -324,23 +338,44 @@ void orc_stencil_gradient(const orc_params* p, const double* F, int x, int y, do
  *   u  = u* + dt/2 [1 - q(phi)] f
  *   p  = cs^2/(1-w0) (sum_{i!=0} h_i - w0 u.u/(2cs^2))   (varphi = 0)
  * ------------------------------------------------------------------------- */
-static void flow_macros(const double* h, double phi, double* ustar, double* Fb, double* u, double* p) {
-    double mx = 0.0, my = 0.0, rest = 0.0;
+static double s2_flow(const orc_params* p);
+
+/* External force of the flow sub-steps: F / N_sub^2 (an acceleration, from
+ * main-step to sub-step units). */
+static void sub_force(const orc_params* p, double* F) {
+    double n = p->use_ns ? (double)p->n_sub : 1.0;
+    F[0] = p->force_x / (n * n);
+    F[1] = p->force_y / (n * n);
+}
+
+/* Sec. 3.4 macroscopic quantities (sub-step units, dt' = 1):
+ *   u* = sum c_i h_i + F/2,  f = (u_s - u*)/dt' with u_s = 0,
+ *   u = u* + [1 - q(phi)] f / 2,
+ *   p = cs^2/(1 - w0) (sum_{i>0} h_i - w0 |u|^2/(2 cs^2) + varphi K u.F / cs^2),
+ *   K = 2 (s2 - 3 s4 + s2 s4) / (9 s2 s4)  (Appendix B), s4 = 1. */
+static void flow_macros(const orc_params* p, const double* h, double phi, double* ustar, double* Fb,
+                        double* u, double* pr) {
+    double mx = 0.0, my = 0.0, rest = 0.0, F[2];
     for (int i = 0; i < 9; ++i) {
         mx += C9X[i] * h[i];
         my += C9Y[i] * h[i];
         if (i) rest += h[i];
     }
-    ustar[0] = mx;
-    ustar[1] = my;
+    sub_force(p, F);
+    ustar[0] = mx + 0.5 * F[0];
+    ustar[1] = my + 0.5 * F[1];
     double qt = 0.5 * (1.0 - phi);
-    double fx = (0.0 - mx) / 1.0, fy = (0.0 - my) / 1.0;
+    double fx = (0.0 - ustar[0]) / 1.0, fy = (0.0 - ustar[1]) / 1.0;
     Fb[0] = (1.0 - qt) * fx;
     Fb[1] = (1.0 - qt) * fy;
-    u[0] = mx + 0.5 * Fb[0];
-    u[1] = my + 0.5 * Fb[1];
+    u[0] = ustar[0] + 0.5 * Fb[0];
+    u[1] = ustar[1] + 0.5 * Fb[1];
     double cs2 = 1.0 / 3.0;
-    *p = cs2 / (1.0 - W9[0]) * (rest - W9[0] * (u[0] * u[0] + u[1] * u[1]) / (2.0 * cs2));
+    double s2 = s2_flow(p), s4 = 1.0;
+    double K = 2.0 * (s2 - 3.0 * s4 + s2 * s4) / (9.0 * s2 * s4);
+    *pr = cs2 / (1.0 - W9[0]) *
+          (rest - W9[0] * (u[0] * u[0] + u[1] * u[1]) / (2.0 * cs2) +
+           p->varphi * K * (u[0] * F[0] + u[1] * F[1]) / cs2);
 }
 
 typedef struct {
@@ -350,11 +385,12 @@ typedef struct {
 
 static void collide_flow_node(const orc_params* p, const double* L9, const double* h, double phi,
                               double* post, double* aux) {
-    double us[2], Fb[2], u[2], pr;
-    flow_macros(h, phi, us, Fb, u, &pr);
+    double us[2], Fb[2], u[2], pr, Fe[2];
+    flow_macros(p, h, phi, us, Fb, u, &pr);
+    sub_force(p, Fe);
     double heq[9], F[9];
     orc_eq_flow(p->rho0, pr, u[0], u[1], heq);
-    orc_force_flow(Fb[0], Fb[1], F);
+    orc_force_flow_full(Fe[0] + Fb[0], Fe[1] + Fb[1], Fe[0], Fe[1], u[0], u[1], p->varphi, F);
     for (int i = 0; i < 9; ++i) {
         double acc = h[i];
         for (int j = 0; j < 9; ++j) {
@@ -546,7 +582,7 @@ static void fill_flow_walls(orc_state* s, double* h, const double* phi) {
             int b = y * s->nx + x, f = inward(s, x, y);
             double hf[9], us[2], Fb[2], uf[2], pf;
             for (int i = 0; i < 9; ++i) hf[i] = h[(size_t)i * N + f];
-            flow_macros(hf, phi[f], us, Fb, uf, &pf);
+            flow_macros(&s->p, hf, phi[f], us, Fb, uf, &pf);
             double ub[2], pb;
             if (x == 0) {
                 ub[0] = s->p.u_in_x / s->p.n_sub;
@@ -606,7 +642,7 @@ static void compute_macros(orc_state* s) {
         for (int x = 0; x < N; ++x) {
             double hx[9], us[2], Fb[2], u[2], pr;
             for (int i = 0; i < 9; ++i) hx[i] = s->h[(size_t)i * N + x];
-            flow_macros(hx, s->phi[x], us, Fb, u, &pr);
+            flow_macros(p, hx, s->phi[x], us, Fb, u, &pr);
             s->ux[x] = p->n_sub * u[0];
             s->uy[x] = p->n_sub * u[1];
         }
@@ -921,7 +957,7 @@ static void cd_first_moment(const orc_state* s, const double* F, int x, int y, d
  * phi/C/theta update of a main step evaluates it (Sec. 3.4). */
 static void main_step_velocity(const orc_state* s, const double* h9, double ph, double* u) {
     double us[2], Fb[2], uu[2], pr;
-    flow_macros(h9, ph, us, Fb, uu, &pr);
+    flow_macros(&s->p, h9, ph, us, Fb, uu, &pr);
     u[0] = s->p.n_sub * uu[0];
     u[1] = s->p.n_sub * uu[1];
 }
@@ -1066,7 +1102,7 @@ int orc_get_fields(orc_state* s, double* out) {
         if (p->use_ns) {
             double hx[9], us[2], Fb[2], u[2];
             for (int i = 0; i < 9; ++i) hx[i] = s->h[(size_t)i * N + x];
-            flow_macros(hx, s->phi[x], us, Fb, u, &pr);
+            flow_macros(p, hx, s->phi[x], us, Fb, u, &pr);
             pr *= (double)p->n_sub * p->n_sub;
         }
         out[6 * N + x] = pr;
@@ -1184,7 +1220,7 @@ int orc_reduce(orc_state* s, double* out) {
         for (int x = 0; x < N; ++x) {
             double hx[9], us[2], Fb[2], u[2], pr;
             for (int i = 0; i < 9; ++i) hx[i] = s->h[(size_t)i * N + x];
-            flow_macros(hx, s->phi[x], us, Fb, u, &pr);
+            flow_macros(p, hx, s->phi[x], us, Fb, u, &pr);
             Fx -= Fb[0];
             Fy -= Fb[1];
             double rx = (x % s->nx) - cx, ry = (x / s->nx) - cy;

@@ -34,6 +34,9 @@
  *   stencil-gradient ablation (grad_stencil): exact on quadratics,
  *     stationary planar fronts at second order                    pinned
  *   heat sub-steps (n_sub_t): diffusion rate, advected mode       pinned
+ *   external force F with varphi: population forcing against the
+ *     printed moment vector; uniform acceleration exact; force-driven
+ *     channel flow against the parabola; uniform pressure across it   pinned
  *   far-field walls (walls = 2): sine modes vanishing on the wall
  *     ring decay at the diffusion rate; relaxation to the far field pinned
  *   tip position / radius measurement                             pinned (geometry)
@@ -73,6 +76,10 @@ typedef struct orc_params {
     double seed_R, seed_x, seed_y, noise_amp;
     double grad_tol;  /* relative stopping tolerance of the gradient iteration*/
     double fixed_as;  /* test hook: >0 fixes a_s to this value and N to 0     */
+    double force_x, force_y; /* external body force F (Sec. 3.4), lu per main
+                         step^2; the flow sub-steps take F / N_sub^2          */
+    double varphi;    /* adjustable parameter of the forcing (Sec. 3.4); the
+                         paper's runs use 0                                    */
 } orc_params;
 
 typedef struct orc_state orc_state;
@@ -141,6 +148,11 @@ void orc_eq_solute(double C, double phi, double U, double ux, double uy, double*
 void orc_eq_heat(double theta, double phi, int h_quintic, double ux, double uy, double* out5);
 void orc_eq_flow(double rho0, double p, double ux, double uy, double* out9);
 void orc_force_flow(double Fx, double Fy, double* out9);
+/* The full forcing populations of Sec. 3.4: the first-order part carries
+ * G = F + [1 - q] f, the varphi part (uF + Fu):(cc - cs^2 I)/(2 cs^4) the
+ * external force F and the velocity u. */
+void orc_force_flow_full(double Gx, double Gy, double Fx, double Fy, double ux, double uy,
+                         double varphi, double* out9);
 void orc_anisotropy(double eps4, double orient, double gx, double gy, double* out3);
 /* out: gx, gy, a_s, Nx, Ny, iterations */
 void orc_local_gradient(const orc_params* p, double m1x, double m1y, double* out6);

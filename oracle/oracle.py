@@ -39,7 +39,7 @@ class OrcParams(ctypes.Structure):
         "grad_max_iter", "phi_static", "grad_stencil", "n_sub_t")] + [(n, ctypes.c_double) for n in (
             "W0", "tau0", "eps4", "orient", "lambda_", "Mcinf", "k", "D", "alpha", "nu", "rho0",
             "u_in_x", "u_in_y", "theta0", "U0", "C0", "seed_R", "seed_x", "seed_y", "noise_amp",
-            "grad_tol", "fixed_as")]
+            "grad_tol", "fixed_as", "force_x", "force_y", "varphi")]
 
 
 _lib = None
@@ -81,6 +81,7 @@ def load():
     lib.orc_eq_heat.argtypes = [d, d, ctypes.c_int, d, d, dp]
     lib.orc_eq_flow.argtypes = [d, d, d, d, dp]
     lib.orc_force_flow.argtypes = [d, d, dp]
+    lib.orc_force_flow_full.argtypes = [d, d, d, d, d, d, d, dp]
     lib.orc_anisotropy.argtypes = [d, d, d, d, dp]
     lib.orc_local_gradient.argtypes = [P(OrcParams), d, d, dp]
     lib.orc_collide_flow.argtypes = [P(OrcParams), dp, d, dp, dp]
@@ -93,6 +94,7 @@ DEFAULTS = dict(
     grad_max_iter=100, phi_static=0, grad_stencil=0, n_sub_t=1, W0=1.0, tau0=20.0, eps4=0.05, orient=0.0, lambda_=0.0, Mcinf=0.0,
     k=0.15, D=0.1, alpha=0.1, nu=0.1, rho0=1.0, u_in=(0.0, 0.0), theta0=0.0, U0=0.0, C0=1.0,
     seed_R=8.0, seed_x=None, seed_y=None, noise_amp=0.0, grad_tol=1e-14, fixed_as=0.0,
+    force_x=0.0, force_y=0.0, varphi=0.0,
 )
 
 # keys of a workload dictionary that only concern the GPU library
@@ -248,6 +250,10 @@ def eq_flow(rho0, p, ux, uy):
 
 def force_flow(Fx, Fy):
     o = _vec(9); load().orc_force_flow(Fx, Fy, _dptr(o)); return o
+
+
+def force_flow_full(Gx, Gy, Fx, Fy, ux, uy, varphi):
+    o = _vec(9); load().orc_force_flow_full(Gx, Gy, Fx, Fy, ux, uy, varphi, _dptr(o)); return o
 
 
 def anisotropy(eps4, orient, gx, gy):

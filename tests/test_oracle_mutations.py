@@ -19,8 +19,17 @@ TR = "tests/test_oracle_restart.py::"
 TS = "tests/test_oracle_stencil.py::"
 TH = "tests/test_oracle_heat_substeps.py::"
 TF = "tests/test_oracle_farfield.py::"
+TFO = "tests/test_oracle_force.py::"
 
 MUTATIONS = [
+    ("force: K pressure term dropped", "double K = 2.0 * (s2 - 3.0 * s4 + s2 * s4) / (9.0 * s2 * s4);",
+     "double K = 0.0;", TFO + "test_forced_porous_medium_is_steady"),
+    ("force: u* without F/2", "ustar[0] = mx + 0.5 * F[0];", "ustar[0] = mx;",
+     TFO + "test_forced_porous_medium_is_steady"),
+    ("force: not rescaled to sub-steps", "F[0] = p->force_x / (n * n);", "F[0] = p->force_x / n;",
+     TFO + "test_liquid_accelerates_by_the_force"),
+    ("force: sign of the varphi isotropic part", "(2.0 * cu * cF - 2.0 * cs2 * uF)",
+     "(2.0 * cu * cF + 2.0 * cs2 * uF)", TFO + "test_forcing_populations_match_the_printed_moments"),
     ("far field: the wall copies its neighbour", "for (int i = 0; i < 5; ++i) d[i] = eb[i] - ef[i];",
      "for (int i = 0; i < 5; ++i) d[i] = 0.0;", TF + "test_relaxes_to_the_far_field_zero_gradient_walls_do_not"),
     ("far field: sign of the equilibrium shift", "for (int i = 0; i < 5; ++i) d[i] = eb[i] - ef[i];",
