@@ -115,6 +115,14 @@ typedef struct dlb_params {
     double seed_R, seed_x, seed_y; /* seed radius and centre (lu, node coordinates)  */
     double noise_amp;     /* amplitude applied to the caller's noise field          */
     double grad_tol;      /* relative tolerance of the gradient fixed point (0: default) */
+    double force_x, force_y; /* external body force F of Sec. 3.4 (lu per main
+                             step^2; the flow sub-steps take F/n_sub^2); needs
+                             use_ns = 1 and flow_fuse 0 or 1 (each sub-step is
+                             one launch); not available in batches             */
+    double varphi;        /* adjustable parameter of the forcing (Sec. 3.4): the
+                             second-order force terms (uF + Fu) and the pressure
+                             term varphi K u.F with K = 2(s2 - 3 s4 + s2 s4) /
+                             (9 s2 s4), s4 = 1; the paper's runs use 0         */
 } dlb_params;
 
 typedef struct dlb_solver* dlb_handle;

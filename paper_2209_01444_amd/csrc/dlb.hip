@@ -71,6 +71,12 @@ int check_params(const dlb_params* p) {
     if (p->isothermal != 0 && p->isothermal != 1) return fail(DLB_EINVAL, "isothermal must be 0 or 1");
     if (p->grad_stencil != 0 && p->grad_stencil != 1) return fail(DLB_EINVAL, "grad_stencil must be 0 or 1");
     if (p->n_sub_t < 0 || p->n_sub_t > 256) return fail(DLB_EINVAL, "n_sub_t must be in [0, 256]");
+    const bool forced = p->force_x != 0.0 || p->force_y != 0.0 || p->varphi != 0.0;
+    if (!(std::isfinite(p->force_x) && std::isfinite(p->force_y) && std::isfinite(p->varphi)))
+        return fail(DLB_EINVAL, "force and varphi must be finite");
+    if (forced && !p->use_ns) return fail(DLB_EINVAL, "an external force or varphi needs the flow lattice");
+    if (forced && p->flow_fuse > 1)
+        return fail(DLB_EUNSUPPORTED, "with an external force or varphi each flow sub-step is one launch (flow_fuse 0 or 1)");
     if (p->bc == DLB_BC_FARFIELD && (p->use_ns || p->grad_stencil || p->n_sub_t > 1 || p->phi_static))
         return fail(DLB_EUNSUPPORTED,
                     "far-field walls need use_ns = 0, grad_stencil = 0, n_sub_t <= 1 and phi_static = 0");
@@ -178,6 +184,16 @@ static KParams make_kparams(const dlb_params* p, const Layout& L) {
     // far-field liquid: the initial C at phi = -1 (uniform C0, or that of U0)
     k.ff_C = p->c_init_U ? 1.0 + (1.0 - p->k) * p->U0 : p->C0;
     k.ff_U = (k.ff_C - 1.0) / (1.0 - p->k);
+    // external force per flow sub-step and the varphi pressure term
+    // 3 varphi K with K = 2 (s2 - 3 s4 + s2 s4) / (9 s2 s4), s4 = 1
+    k.force = p->use_ns && (p->force_x != 0.0 || p->force_y != 0.0 || p->varphi != 0.0);
+    k.fx_sub = k.force ? p->force_x / ((double)k.n_sub * k.n_sub) : 0.0;
+    k.fy_sub = k.force ? p->force_y / ((double)k.n_sub * k.n_sub) : 0.0;
+    k.varphi = k.force ? p->varphi : 0.0;
+    {
+        const double s2 = p->use_ns ? 1.0 / (3.0 * p->nu / p->n_sub + 0.5) : 1.0, s4 = 1.0;
+        k.kpf = 3.0 * k.varphi * 2.0 * (s2 - 3.0 * s4 + s2 * s4) / (9.0 * s2 * s4);
+    }
     k.use_t = p->isothermal ? 0 : 1;
     k.theta0 = p->theta0;
     k.nbx = (p->nx + TILE_X - 1) / TILE_X;
@@ -242,6 +258,13 @@ template <class CF, bool NS, bool W> struct OpsImpl {
     using H = typename CF::H;
     static void pct(const KParams& kp, const void* pin, void* pout, const void* hin, void* hist,
                     int hv, hipStream_t st, dim3 grid) {
+        if constexpr (NS) {
+            if (kp.force) {
+                hipLaunchKernelGGL((k_pct_force<CF, W>), grid, dim3(BLOCK), 0, st, kp, (const S*)pin, (S*)pout,
+                                   (const S*)hin, (H*)hist, hv);
+                return;
+            }
+        }
         hipLaunchKernelGGL((k_pct<CF, NS, W>), grid, dim3(BLOCK), 0, st, kp, (const S*)pin, (S*)pout,
                            (const S*)hin, (H*)hist, hv);
     }
@@ -255,6 +278,13 @@ template <class CF, bool NS, bool W> struct OpsImpl {
     }
     static void flow(const KParams& kp, const void* hin, void* hout, const void* phi, hipStream_t st,
                      dim3 grid) {
+        if constexpr (NS) {
+            if (kp.force) {
+                hipLaunchKernelGGL((k_flow_force<CF, W>), grid, dim3(BLOCK), 0, st, kp, (const S*)hin, (S*)hout,
+                                   (const H*)phi);
+                return;
+            }
+        }
         hipLaunchKernelGGL((k_flow<CF, W>), grid, dim3(BLOCK), 0, st, kp, (const S*)hin, (S*)hout,
                            (const H*)phi);
     }
@@ -508,7 +538,7 @@ int dlb_create(const dlb_params* p, void* dev_state, size_t bytes, void* hip_str
     s->bytes = bytes;
     s->stream = (hipStream_t)hip_stream;
     s->grid = dim3(L.nblocks);
-    s->fuse = p->flow_fuse == 0 ? 5 : p->flow_fuse;
+    s->fuse = p->flow_fuse == 0 ? (s->kp.force ? 1 : 5) : p->flow_fuse;
     if (s->fuse != 1 && s->fuse != 3 && s->fuse != 5) {
         delete s;
         return fail(DLB_EINVAL, "flow_fuse must be 0 (default), 1, 3 or 5");
@@ -823,6 +853,8 @@ static int batch_layout(const dlb_params* ps, int count, std::vector<size_t>* of
         if (rc) return rc;
         if (ps[i].phi_static) return fail(DLB_EUNSUPPORTED, "phi_static is not available in batches");
         if (ps[i].bc == DLB_BC_FARFIELD) return fail(DLB_EUNSUPPORTED, "far-field walls are not available in batches");
+        if (ps[i].force_x != 0.0 || ps[i].force_y != 0.0 || ps[i].varphi != 0.0)
+            return fail(DLB_EUNSUPPORTED, "an external force or varphi is not available in batches");
         if (ps[i].grad_stencil) return fail(DLB_EUNSUPPORTED, "grad_stencil is not available in batches");
         if (ps[i].n_sub_t > 1) return fail(DLB_EUNSUPPORTED, "n_sub_t > 1 is not available in batches");
         if (!batch_compatible(&ps[0], &ps[i]))

@@ -83,12 +83,18 @@ __device__ __forceinline__ void farfield_rebuild(const KParams& kp, T* f, T* n, 
 // from the populations hf of its inward neighbour x_f, with the frozen phi
 // there: h = hf + h^eq(p_b, u_b) - h^eq(p_f, u_f), boundary values by wall;
 // the equilibrium (eq_flow) difference is expanded in closed form.
-template <class T>
+template <class T, bool FORCE>
+__device__ __forceinline__ FlowMacro<T> flow_macro_of(const T* h, T phi, const KParams& kp) {
+    if constexpr (FORCE) return flow_macro_force(h, phi, kp);
+    else return flow_macro(h, phi);
+}
+
+template <class T, bool FORCE = false>
 __device__ __forceinline__ void wall_rebuild(const KParams& kp, int x, int y, const T* hf, T phi_f,
                                              T* h) {
     // no contraction: the same rounding in every kernel that inlines this
 #pragma clang fp contract(off)
-    FlowMacro<T> m = flow_macro(hf, phi_f);
+    FlowMacro<T> m = flow_macro_of<T, FORCE>(hf, phi_f, kp);
     T ubx, uby, pb;
     if (x == 0) {  // velocity inlet
         ubx = T(kp.uin_x_sub);
@@ -125,7 +131,7 @@ __device__ __forceinline__ void wall_rebuild(const KParams& kp, int x, int y, co
 
 // Flow populations of node (x, y) at the current sub-step.  Interior nodes
 // load them; wall nodes rebuild them from the inward neighbour x_f.
-template <class T, class S, bool WALLS>
+template <class T, class S, bool WALLS, bool FORCE = false>
 __device__ __forceinline__ void flow_node(const KParams& kp, const S* __restrict__ h_in, int x,
                                           int y, size_t idx, T phi_f, T* h) {
     const size_t P = (size_t)kp.plane;
@@ -138,7 +144,7 @@ __device__ __forceinline__ void flow_node(const KParams& kp, const S* __restrict
     T hf[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) hf[i] = ld_pop<T>(h_in, i * P + f, kp.shift[15 + i]);
-    wall_rebuild(kp, x, y, hf, phi_f, h);
+    wall_rebuild<T, FORCE>(kp, x, y, hf, phi_f, h);
 }
 
 // Ablation of the local scheme: grad phi from the isotropic nine-point
@@ -248,7 +254,7 @@ __global__ __launch_bounds__(BLOCK) void k_heat_sub(const KParams kp, const type
 // ---------------------------------------------------------------------------
 // K1: phi, C, theta main step.
 // ---------------------------------------------------------------------------
-template <class CF, bool NS, bool WALLS>
+template <class CF, bool NS, bool WALLS, bool FORCE = false>
 __device__ __forceinline__ void pct_node(const KParams& kp, const typename CF::S* __restrict__ pin,
                                          typename CF::S* __restrict__ pout,
                                          const typename CF::S* __restrict__ hin,
@@ -286,7 +292,13 @@ __device__ __forceinline__ void pct_node(const KParams& kp, const typename CF::S
 
     // melt velocity of time t in main-step units: N_sub (3 - phi)/4 u*
     T ux = T(0), uy = T(0);
-    if constexpr (NS) {
+    if constexpr (NS && FORCE) {
+        T h[9];
+        flow_node<T, S, WALLS, true>(kp, hin, x, y, idx, phi, h);
+        const FlowMacro<T> fm = flow_macro_force(h, phi, kp);
+        ux = fm.ux * T(kp.nsub_d);
+        uy = fm.uy * T(kp.nsub_d);
+    } else if constexpr (NS) {
         T h[9];
         flow_node<T, S, WALLS>(kp, hin, x, y, idx, phi, h);
         T d57 = h[5] - h[7], d68 = h[6] - h[8];
@@ -412,10 +424,21 @@ __global__ __launch_bounds__(BLOCK) void k_pct(const KParams kp, const typename 
     pct_node<CF, NS, WALLS>(kp, pin, pout, hin, hist, hist_valid, x, y);
 }
 
+// The same with the external force of Sec. 3.4 in the melt velocity.
+template <class CF, bool WALLS>
+__global__ __launch_bounds__(BLOCK) void k_pct_force(const KParams kp, const typename CF::S* __restrict__ pin,
+                                                     typename CF::S* __restrict__ pout,
+                                                     const typename CF::S* __restrict__ hin,
+                                                     typename CF::H* __restrict__ hist, int hist_valid) {
+    int x, y;
+    if (!node_of_thread(kp, x, y)) return;
+    pct_node<CF, true, WALLS, true>(kp, pin, pout, hin, hist, hist_valid, x, y);
+}
+
 // ---------------------------------------------------------------------------
 // K2: one flow sub-step (Sec. 3.4) at frozen phi^t (= hist[0]).
 // ---------------------------------------------------------------------------
-template <class CF, bool WALLS>
+template <class CF, bool WALLS, bool FORCE = false>
 __device__ __forceinline__ void flow_step_node(const KParams& kp, const typename CF::S* __restrict__ hin,
                                                typename CF::S* __restrict__ hout,
                                                const typename CF::H* __restrict__ phi_t, int x, int y) {
@@ -427,9 +450,10 @@ __device__ __forceinline__ void flow_step_node(const KParams& kp, const typename
     T h[9];
     T phi_f = phi;
     if (WALLS && is_wall(kp, x, y)) phi_f = T(phi_t[inward_idx(kp, x, y)]);
-    flow_node<T, S, WALLS>(kp, hin, x, y, idx, phi_f, h);
+    flow_node<T, S, WALLS, FORCE>(kp, hin, x, y, idx, phi_f, h);
     T o[9];
-    flow_collide<T>(h, flow_coef(phi), T(kp.s2u), o);
+    if constexpr (FORCE) flow_collide_force<T>(h, phi, kp, T(kp.s2u), o);
+    else flow_collide<T>(h, flow_coef(phi), T(kp.s2u), o);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         long long d = push_dest<WALLS>(kp, x, y, C9X[i], C9Y[i]);
@@ -445,6 +469,16 @@ __global__ __launch_bounds__(BLOCK) void k_flow(const KParams kp, const typename
     int x, y;
     if (!node_of_thread(kp, x, y)) return;
     flow_step_node<CF, WALLS>(kp, hin, hout, phi_t, x, y);
+}
+
+// One flow sub-step with the external force and varphi of Sec. 3.4.
+template <class CF, bool WALLS>
+__global__ __launch_bounds__(BLOCK) void k_flow_force(const KParams kp, const typename CF::S* __restrict__ hin,
+                                                      typename CF::S* __restrict__ hout,
+                                                      const typename CF::H* __restrict__ phi_t) {
+    int x, y;
+    if (!node_of_thread(kp, x, y)) return;
+    flow_step_node<CF, WALLS, true>(kp, hin, hout, phi_t, x, y);
 }
 
 // ---------------------------------------------------------------------------
@@ -982,6 +1016,10 @@ __device__ __forceinline__ void step_velocity(const KParams& kp, const double* h
     double d57 = h[5] - h[7], d68 = h[6] - h[8];
     double mx = (h[1] - h[3]) + (d57 - d68);
     double my = (h[2] - h[4]) + (d57 + d68);
+    if (kp.force) {  // u* = sum c h + F/2
+        mx += 0.5 * kp.fx_sub;
+        my += 0.5 * kp.fy_sub;
+    }
     double fac = kp.nsub_d * (3.0 - phi) * 0.25;
     ux = mx * fac;
     uy = my * fac;
@@ -1185,8 +1223,14 @@ __device__ __forceinline__ void node_macros(const KParams& kp, const typename CF
     m[10] = m[11] = 0.0;  // f = u_s - u* = -u* (sub-step units)
     if constexpr (NS) {
         T h[9];
-        flow_node<T, S, WALLS>(kp, flow, x, y, idx, phi, h);
-        FlowMacro<T> fm = flow_macro(h, phi);
+        FlowMacro<T> fm;
+        if (kp.force) {
+            flow_node<T, S, WALLS, true>(kp, flow, x, y, idx, phi, h);
+            fm = flow_macro_force(h, phi, kp);
+        } else {
+            flow_node<T, S, WALLS>(kp, flow, x, y, idx, phi, h);
+            fm = flow_macro(h, phi);
+        }
         m[4] = kp.nsub_d * fm.ux;
         m[5] = kp.nsub_d * fm.uy;
         m[6] = kp.nsub_d * kp.nsub_d * fm.p;

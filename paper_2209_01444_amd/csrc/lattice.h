@@ -41,6 +41,9 @@ struct KParams {
     void* aux;                  // u, d_t(Hu) of time t (4 planes, history type), n_sub_t > 1 only
     int farfield;               // walls hold the far-field liquid (flow lattice off)
     double ff_C, ff_U;          // far-field C and U (phi = -1)
+    int force;                  // external force / varphi on: the _force kernels run
+    double fx_sub, fy_sub;      // external force per flow sub-step (F / n_sub^2)
+    double varphi, kpf;         // varphi and 3 varphi K (pressure term, times 1/cs^2)
 };
 
 static constexpr int TILE_X = 64;
@@ -266,6 +269,26 @@ template <class T> __device__ __forceinline__ FlowMacro<T> flow_macro(const T* h
     return m;
 }
 
+// The same with the external force F of Sec. 3.4 (sub-step units):
+// u* = sum c h + F/2, and p gains varphi K u.F / cs^2.
+template <class T>
+__device__ __forceinline__ FlowMacro<T> flow_macro_force(const T* h, T phi, const KParams& kp) {
+#pragma clang fp contract(off)
+    FlowMacro<T> m;
+    const T Fx = T(kp.fx_sub), Fy = T(kp.fy_sub);
+    T d57 = h[5] - h[7], d68 = h[6] - h[8];
+    m.mx = ((h[1] - h[3]) + (d57 - d68)) + T(0.5) * Fx;
+    m.my = ((h[2] - h[4]) + (d57 + d68)) + T(0.5) * Fy;
+    T rest = (h[1] + h[2]) + (h[3] + h[4]) + ((h[5] + h[6]) + (h[7] + h[8]));
+    T solid = T(0.5) * (T(1) + phi);  // 1 - q(phi)
+    m.Fx = -solid * m.mx;
+    m.Fy = -solid * m.my;
+    m.ux = m.mx + T(0.5) * m.Fx;
+    m.uy = m.my + T(0.5) * m.Fy;
+    m.p = T(0.6) * ((rest - T(2.0 / 3.0) * (m.ux * m.ux + m.uy * m.uy)) + T(kp.kpf) * (m.ux * Fx + m.uy * Fy));
+    return m;
+}
+
 // Per-node factors of the flow collision for the frozen phi of the main
 // step: with 1 - q(phi) = (1 + phi)/2 and f = -u*, the velocity is
 // u = u* (3 - phi)/4 and the relaxed first moment u + F/2 = u* (1 - phi)/2.
@@ -317,6 +340,42 @@ template <class T> __device__ __forceinline__ void flow_collide(const T* h, Flow
     const T q6 = T(0.25) * n6, q7 = T(0.25) * n7;
     const T b = fmadd(T(0.25), n8, q6), bc = fmadd(T(0.25), n8, -q6);
     const T t1 = fmadd(T(0.25), n5, q7), t2 = fmadd(T(0.25), n5, -q7);
+    o[5] = b + t1;
+    o[6] = b - t1;
+    o[7] = bc + t2;
+    o[8] = bc - t2;
+}
+
+// The collision with the external force F and varphi (Sec. 3.4, Appendix
+// B): the forcing moments m_F = [0, F + F_b, 2 varphi F_x u, 2 varphi F_y v,
+// varphi (F_x v + F_y u), (F + F_b)/3 (y, x), 2 varphi F.u/3], relaxed with
+// (I - S/2); s0 = s1 = s3 = s4 = 1 as in flow_collide, same inverse.
+template <class T>
+__device__ __forceinline__ void flow_collide_force(const T* h, T phi, const KParams& kp, T s2, T* o) {
+#pragma clang fp contract(off)
+    const FlowMacro<T> m = flow_macro_force(h, phi, kp);
+    const T Fx = T(kp.fx_sub), Fy = T(kp.fy_sub), vp = T(kp.varphi);
+    const T s57 = h[5] + h[7], s68 = h[6] + h[8], e = s57 + s68;
+    const T m3 = (h[1] + h[3]) + e, m4 = (h[2] + h[4]) + e, m5 = s57 - s68;
+    const T ux = m.ux, uy = m.uy, p = m.p;
+    const T uu = ux * ux + uy * uy, uF = ux * Fx + uy * Fy;
+    const T r2 = T(1) - s2, g2 = T(1) - T(0.5) * s2;
+    const T n3 = (r2 * m3 + s2 * (p + ux * ux)) + g2 * (T(2) * vp * Fx * ux);
+    const T n4 = (r2 * m4 + s2 * (p + uy * uy)) + g2 * (T(2) * vp * Fy * uy);
+    const T n5 = (r2 * m5 + s2 * (ux * uy)) + g2 * (vp * (Fx * uy + Fy * ux));
+    const T m1 = ux + T(0.5) * (Fx + m.Fx), m2 = uy + T(0.5) * (Fy + m.Fy);
+    const T n6 = m2 * T(1.0 / 3.0), n7 = m1 * T(1.0 / 3.0);
+    const T n8 = ((p + uu) + vp * uF) * T(1.0 / 3.0);
+    o[0] = (n8 - n3) - n4;
+    const T hn8 = T(-0.5) * n8;
+    const T a1 = T(0.5) * n3 + hn8, a2 = T(0.5) * n4 + hn8;
+    o[1] = a1 + n7;
+    o[3] = a1 - n7;
+    o[2] = a2 + n6;
+    o[4] = a2 - n6;
+    const T q6 = T(0.25) * n6, q7 = T(0.25) * n7;
+    const T b = T(0.25) * n8 + q6, bc = T(0.25) * n8 - q6;
+    const T t1 = T(0.25) * n5 + q7, t2 = T(0.25) * n5 - q7;
     o[5] = b + t1;
     o[6] = b - t1;
     o[7] = bc + t2;

@@ -32,7 +32,7 @@ class DlbParams(ctypes.Structure):
         "flow_fuse", "phi_static", "isothermal", "grad_stencil", "n_sub_t")] + [(n, ctypes.c_double) for n in (
             "W0", "tau0", "eps4", "orient", "lambda_", "Mcinf", "k", "D", "alpha", "nu", "rho0",
             "u_in_x", "u_in_y", "theta0", "U0", "C0", "seed_R", "seed_x", "seed_y", "noise_amp",
-            "grad_tol")]
+            "grad_tol", "force_x", "force_y", "varphi")]
 
 
 KEEP_FLOW, KEEP_NONEQ = 1, 2  # continuation flags of dlb_set_fields_ex
@@ -109,6 +109,7 @@ DEFAULTS = dict(
     grad_iters=0, flow_fuse=0, phi_static=0, grad_stencil=0, n_sub_t=1, W0=1.0, tau0=20.0, eps4=0.05, orient=0.0, lambda_=0.0, Mcinf=0.0, k=0.15, D=0.1,
     alpha=0.1, nu=0.1, rho0=1.0, u_in=(0.0, 0.0), theta0=0.0, U0=0.0, C0=1.0, seed_R=8.0,
     seed_x=None, seed_y=None, noise_amp=0.0, grad_tol=0.0, use_c=1, use_t=1,
+    force_x=0.0, force_y=0.0, varphi=0.0,
 )
 _IGNORED = {"name", "steps"}
 
@@ -139,7 +140,7 @@ def make_params(cfg: dict) -> DlbParams:
     p.grad_stencil = int(c["grad_stencil"])
     p.n_sub_t = int(c["n_sub_t"])
     for name in ("W0", "tau0", "eps4", "orient", "lambda_", "Mcinf", "k", "D", "alpha", "nu", "rho0",
-                 "theta0", "U0", "C0", "seed_R", "noise_amp", "grad_tol"):
+                 "theta0", "U0", "C0", "seed_R", "noise_amp", "grad_tol", "force_x", "force_y", "varphi"):
         setattr(p, name, float(c[name]))
     p.u_in_x, p.u_in_y = float(c["u_in"][0]), float(c["u_in"][1])
     p.seed_x = float(c["nx"] // 2 if c["seed_x"] is None else c["seed_x"])

@@ -86,6 +86,22 @@ def test_far_field_walls_validation():
         assert lib.dlb_last_error()
 
 
+def test_external_force_validation():
+    """An external force or varphi needs the flow lattice and one flow
+    sub-step per launch (flow_fuse 0 or 1)."""
+    lib = dlb.load_library()
+    cfg, _ = W.thermosolutal_flow(64, 64)
+    ok = dlb.make_params(dict(cfg, force_x=1e-5, varphi=1.0))
+    assert lib.dlb_state_bytes(ctypes.byref(ok)) > 0
+    ok1 = dlb.make_params(dict(cfg, varphi=0.5, flow_fuse=1))
+    assert lib.dlb_state_bytes(ctypes.byref(ok1)) > 0
+    for bad in (dict(force_x=1e-5, flow_fuse=5), dict(varphi=1.0, flow_fuse=3),
+                dict(force_y=1e-5, use_ns=0), dict(force_x=float("nan"))):
+        q = dlb.make_params(dict(cfg, **bad))
+        assert lib.dlb_state_bytes(ctypes.byref(q)) == 0, bad
+        assert lib.dlb_last_error()
+
+
 def test_strerror_codes():
     lib = dlb.load_library()
     for code in (0, -1, -2, -3, -4, -5):

@@ -164,6 +164,49 @@ def test_thermosolutal_flow_parity_ragged(dlb, precision, tol, steps):
         assert rg[key] == pytest.approx(ro[key], rel=max(tol, 1e-12) * 10, abs=1e-12), key
 
 
+@pytest.mark.parametrize("case,precision,tol", [("channel", "f64", 1e-10), ("channel", "f32", 1e-4),
+                                                ("periodic", "f64", 1e-10), ("periodic", "f32m", 1e-4)])
+def test_external_force_parity(dlb, case, precision, tol):
+    """External body force with varphi (Sec. 3.4): the coupled flow case with
+    F = (2e-5, -1e-5) lu per main step^2 and varphi = 1 against the oracle,
+    every field including the pressure; each flow sub-step is one launch."""
+    nx, ny = 70, 54
+    _say(f"case: external force {case} {nx}x{ny} {precision}")
+    cfg, noise = _flow_case(nx, ny, precision)
+    cfg = dict(cfg, force_x=2e-5, force_y=-1e-5, varphi=1.0, walls=1 if case == "channel" else 0)
+    o = O.Oracle(cfg).init_seed(noise)
+    s = dlb.Solver(cfg).init_seed(noise)
+    for t in (1, 40, 200):
+        o.step(t - o.step_count)
+        s.step(t - s.step_count)
+        compare(s.fields(), o.fields(), tol, label=f"force {case} {precision} t={t}")
+    ro, rg = o.reduce(), s.reduce()
+    for key in ("Fx", "Fy"):
+        assert rg[key] == pytest.approx(ro[key], rel=max(tol, 1e-12) * 10, abs=1e-12), key
+
+
+def test_force_driven_channel_on_gpu(dlb):
+    """A channel between diffuse solid bands (H = 100, W0 = 1) driven by a
+    body force, FP32, 15 flow sub-steps per main step: in the liquid core
+    the steady profile has the Stokes curvature nu u'' = -F."""
+    _say("case: force-driven channel 16x124, FP32, N_sub = 15")
+    H, nx, n = 100, 16, 15
+    ny = H + 24
+    nu_sub, F_sub = 0.1, 1e-7
+    y = np.arange(ny)
+    yc = (ny - 1) / 2
+    phi = np.repeat(np.tanh((np.abs(y - yc) - H / 2) / np.sqrt(2.0))[:, None], nx, 1)
+    cfg = dict(nx=nx, ny=ny, use_ns=1, n_sub=n, nu=nu_sub * n, phi_static=1, W0=1.0, walls=0,
+               force_x=F_sub * n * n, force_y=0.0, varphi=1.0, lambda_=0.0, precision="f32")
+    s = dlb.Solver(cfg).set_fields(phi)
+    s.step(8000)
+    u = s.fields()["ux"][:, 3] / n  # per sub-step
+    c = int(yc)
+    curv = -nu_sub * (u[c + 1] - 2 * u[c] + u[c - 1]) / F_sub
+    _say(f"  -nu u''/F = {curv:.5f}, u_max = {u.max():.4e} (sharp walls {F_sub * H * H / (8 * nu_sub):.4e})")
+    assert abs(curv - 1) < 2e-3
+
+
 @pytest.mark.parametrize("precision,tol", [("f64", 1e-10), ("f32", 1e-4)])
 def test_quintic_interpolation_parity(dlb, precision, tol):
     """The quintic h(phi) = 15(phi - 2 phi^3/3 + phi^5/5)/8 that Sec. 2
@@ -706,6 +749,7 @@ def test_batch_autotune_and_member_rules(dlb):
     r = b.members[2].reduce()
     assert r["nonfinite"] == 0
     # solver options that batches do not carry are refused
-    for opt in ({"phi_static": 1}, {"grad_stencil": 1}, {"n_sub_t": 2}, {"walls": 2, "use_ns": 0}):
+    for opt in ({"phi_static": 1}, {"grad_stencil": 1}, {"n_sub_t": 2}, {"walls": 2, "use_ns": 0},
+                {"force_x": 1e-5, "flow_fuse": 1}):
         with pytest.raises(dlb.DlbError):
             dlb.Batch([dict(cases[0][0], **opt)])
