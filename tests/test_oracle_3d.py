@@ -1,0 +1,129 @@
+"""Pins of the 3-D oracle (D3Q7 phase-field, solute and heat lattices, the
+d-general anisotropy of Sec. 2, no melt flow).
+
+What fixes it other than itself: the cubic anisotropy's closed values along
+<100>, <110> and <111>; N against finite differences of a_s and orthogonal to
+the gradient; with g_z = 0 the 2-D oracle's (independently written)
+anisotropy; diffusion modes decaying at D k^2 and alpha k^2 at second order;
+the linearised phase-field mode about phi = -1 with a_s fixed; conservation
+of C and H; the cubic symmetry of a centred seed."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O2
+from oracle import oracle3 as O
+
+
+@pytest.mark.parametrize("eps", [0.02, 0.05])
+def test_cubic_anisotropy_closed_values(eps):
+    for g, val in (((1.0, 0, 0), 1 + eps), ((0, -2.0, 0), 1 + eps), ((1, 1, 0), 1 - eps),
+                   ((1, 1, 1), 1 - 5 * eps / 3), ((-1, 1, -1), 1 - 5 * eps / 3)):
+        a = O.anisotropy(eps, *g)
+        assert a[0] == pytest.approx(val, abs=1e-14)
+        if g in ((1.0, 0, 0), (1, 1, 1)):  # extrema: no torque term
+            np.testing.assert_allclose(a[1:], 0.0, atol=1e-14)
+
+
+def test_torque_vector_is_the_gradient_of_a_s():
+    rng = np.random.default_rng(3)
+    eps = 0.05
+    for _ in range(20):
+        g = rng.normal(size=3)
+        a = O.anisotropy(eps, *g)
+        h = 1e-6
+        num = np.array([(O.anisotropy(eps, *(g + h * e))[0] - O.anisotropy(eps, *(g - h * e))[0]) / (2 * h)
+                        for e in np.eye(3)])
+        np.testing.assert_allclose(a[1:], (g @ g) * a[0] * num, rtol=1e-7, atol=1e-12)
+        assert abs(a[1:] @ g) < 1e-13 * np.linalg.norm(g) ** 2
+
+
+def test_planar_anisotropy_equals_the_2d_form():
+    rng = np.random.default_rng(4)
+    for _ in range(20):
+        gx, gy = rng.normal(size=2)
+        a3 = O.anisotropy(0.05, gx, gy, 0.0)
+        a2 = O2.anisotropy(0.05, 0.0, gx, gy)
+        np.testing.assert_allclose(a3[:3], a2, rtol=1e-13, atol=1e-15)
+        assert a3[3] == 0.0
+
+
+def _mode_amp(field, k, axis_len, fn=np.sin):
+    x = np.arange(axis_len)
+    return 2 * np.mean(field * fn(k * x)[None, None, :])
+
+
+@pytest.mark.parametrize("which", ["theta", "U"])
+def test_diffusion_mode_decays_at_the_diffusivity(which):
+    """Liquid (phi = -1), lambda = 0: a mode along x decays at alpha k^2 (theta)
+    or D k^2 (U), at second order in k."""
+    errs = []
+    for nx in (32, 64):
+        k = 2 * math.pi / nx
+        alpha, D = 0.3, 0.2
+        cfg = dict(nx=nx, ny=3, nz=3, alpha=alpha, D=D, k=0.15, lambda_=0.0, theta0=0.0)
+        sn = np.sin(k * np.arange(nx))[None, None, :]
+        th = -0.3 + (0.01 * sn if which == "theta" else 0 * sn)
+        U = 0.01 * sn if which == "U" else 0 * sn
+        C = 1.0 + (1 - 0.15) * U  # C of U at phi = -1
+        o = O.Oracle3(cfg).set_fields(-np.ones((3, 3, nx)), C, th)
+        o.step(5)
+        base = -0.3 if which == "theta" else 0.0
+        a1 = _mode_amp(o.fields()[which] - base, k, nx)
+        n = 40 if nx == 32 else 160
+        o.step(n)
+        a2 = _mode_amp(o.fields()[which] - base, k, nx)
+        diff = alpha if which == "theta" else D
+        errs.append(abs(-math.log(a2 / a1) / n / (diff * k * k) - 1))
+    assert errs[0] < 1e-2 and errs[0] / errs[1] > 3.0, errs
+
+
+@pytest.mark.parametrize("a", [1.0, 1.05])
+def test_phase_field_mode_decay_with_fixed_anisotropy(a):
+    """About phi = -1 with a_s fixed at a and lambda = 0:
+    tau0 a^2 d_t psi = W0^2 a^2 lap psi - 2 psi, so a cosine mode decays at
+    (W0^2 a^2 k^2 + 2)/(tau0 a^2) per step (pins the modified streaming, the
+    source and its time derivative in 3-D)."""
+    W0, tau0, nx = 4.0, 60.0, 32
+    k = 2 * math.pi / nx
+    cfg = dict(nx=nx, ny=3, nz=3, use_t=0, W0=W0, tau0=tau0, lambda_=0.0, theta0=0.0, fixed_as=a)
+    x = np.arange(nx)
+    o = O.Oracle3(cfg).set_fields(-1 + 1e-4 * np.cos(k * x)[None, None, :] + np.zeros((3, 3, 1)))
+    o.step(5)
+    a1 = _mode_amp(o.fields()["phi"] + 1, k, nx, np.cos)
+    n = int(2 * tau0)
+    o.step(n)
+    a2 = _mode_amp(o.fields()["phi"] + 1, k, nx, np.cos)
+    rate = -math.log(a2 / a1) / n
+    exact = (W0**2 * a * a * k * k + 2) / (tau0 * a * a)
+    assert rate / exact - 1 == pytest.approx(0.0, abs=5e-3)
+
+
+@pytest.fixture(scope="module")
+def seed_run():
+    cfg = dict(nx=24, ny=24, nz=24, W0=1.0, tau0=20.0, eps4=0.05, lambda_=3.0, Mcinf=0.5, k=0.15,
+               D=0.2, alpha=0.2, theta0=-0.5, U0=0.0, c_init_U=1, seed_R=5.0, seed_x=12, seed_y=12, seed_z=12)
+    o = O.Oracle3(cfg).init_seed()
+    r0 = o.reduce()
+    o.step(120)
+    return o, r0, o.reduce(), o.fields()
+
+
+def test_seed_conserves_C_and_H(seed_run):
+    _, r0, r1, _ = seed_run
+    assert r1["sum_C"] == pytest.approx(r0["sum_C"], rel=1e-12)
+    assert r1["sum_H"] == pytest.approx(r0["sum_H"], rel=1e-12, abs=1e-9)
+    assert r1["solid_fraction"] > r0["solid_fraction"]  # undercooled: it grows
+
+
+def test_seed_keeps_cubic_symmetry(seed_run):
+    _, _, r1, f = seed_run
+    for key in ("phi", "C", "theta"):
+        a = f[key]
+        c = np.roll(a[::-1, ::-1, ::-1], (1, 1, 1), axis=(0, 1, 2))  # reflection through node 12
+        np.testing.assert_allclose(c, a, atol=1e-12)
+        for perm in ((1, 0, 2), (2, 1, 0), (0, 2, 1), (1, 2, 0)):
+            np.testing.assert_allclose(np.transpose(a, perm), a, atol=1e-12)
+    tips = r1["tip_s"]
+    assert np.ptp(tips) < 1e-9 and tips[0] > 5.0

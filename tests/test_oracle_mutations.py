@@ -94,6 +94,38 @@ MUTATIONS = [
 ]
 
 
+SRC3 = os.path.join(ROOT, "oracle", "dlb3_oracle.c")
+T3 = "tests/test_oracle_3d.py::"
+# mistakes planted in the 3-D oracle (dlb3_oracle.c)
+MUTATIONS_3D = [
+    ("3-D: lattice sound speed 1/3 in s1", "return 1.0 / (as * as * p->W0 * p->W0 / (p->tau0 * CS2) + 0.5);",
+     "return 1.0 / (3.0 * as * as * p->W0 * p->W0 / p->tau0 + 0.5);",
+     T3 + "test_phase_field_mode_decay_with_fixed_anisotropy"),
+    ("3-D: heat rate without 1/cs^2", "static double s1_heat(const o3_params* p) { return 1.0 / (p->alpha / CS2 + 0.5); }",
+     "static double s1_heat(const o3_params* p) { return 1.0 / (3.0 * p->alpha + 0.5); }",
+     T3 + "test_diffusion_mode_decays_at_the_diffusivity"),
+    ("3-D: plain streaming for phi", "(s->pf[o + src] - s->f[o + d]) / s->a2[src];", "(s->pf[o + src] - s->f[o + d]);",
+     T3 + "test_phase_field_mode_decay_with_fixed_anisotropy"),
+    ("3-D: anisotropy strength", "out[1 + a] = g2 * as * (4.0 * eps * dsum);", "out[1 + a] = g2 * as * (3.0 * eps * dsum);",
+     T3 + "test_torque_vector_is_the_gradient_of_a_s"),
+]
+
+
+@pytest.mark.parametrize("label,old,new,pin", MUTATIONS_3D, ids=[m[0] for m in MUTATIONS_3D])
+def test_pin_catches_planted_mistake_3d(tmp_path, label, old, new, pin):
+    src = open(SRC3).read()
+    assert src.count(old) == 1, f"mutation anchor not unique/found: {old!r}"
+    mut_c = tmp_path / "mutant3.c"
+    mut_c.write_text(src.replace(old, new))
+    lib = tmp_path / "libmutant3.so"
+    subprocess.run(["gcc", "-O2", "-std=gnu11", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+                    "-o", str(lib), str(mut_c), "-lm"], check=True)
+    env = dict(os.environ, DLB3_ORACLE_LIB=str(lib))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", pin],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"pin {pin} did not catch: {label}\n{r.stdout[-2000:]}"
+
+
 @pytest.mark.parametrize("label,old,new,pin", MUTATIONS, ids=[m[0] for m in MUTATIONS])
 def test_pin_catches_planted_mistake(tmp_path, label, old, new, pin):
     src = open(SRC).read()
