@@ -1,0 +1,89 @@
+/*
+ * dlb3.h -- C ABI of the three-dimensional phase-field, solute and heat
+ * lattices (D3Q7) of the diffuse-interface lattice Boltzmann method of
+ * Zhan et al., arXiv:2209.01444 (Sec. 2 anisotropy a_s and N for any d,
+ * Secs. 3.1-3.3 with a general lattice sound speed).  No melt flow.
+ * Exported by libdlb.so beside the 2-D solver (dlb.h).
+ *
+ * Lattice: c0 = 0, c1..c3 = +x, +y, +z, c4..c6 = -x, -y, -z; cs^2 = 1/4,
+ * w0 = 1/4, w1..6 = 1/8; S = diag(1, s1, s1, s1, 1, 1, 1) for each lattice.
+ * Crystal axes along the lattice axes.  One main step: every lattice reads
+ * the fields of time t (Jacobi), phi with the modified streaming of Sec. 3.1.
+ *
+ * Ownership: the caller owns the device state buffer (dlb3_state_bytes) and
+ * the stream; the library owns only the small host handle.  Every call is
+ * asynchronous on the stream except those that return host data
+ * (dlb3_get_fields, dlb3_reduce), which synchronise it.
+ * Errors: 0 on success; a negative DLB3_E* code otherwise, with a message
+ * for dlb3_last_error().  No C++ exception crosses the ABI.
+ */
+#ifndef DLB3_H
+#define DLB3_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { DLB3_OK = 0, DLB3_EINVAL = -1, DLB3_ENOMEM = -2, DLB3_EHIP = -3 };
+enum { DLB3_F64 = 0, DLB3_F32 = 1 }; /* storage and arithmetic type */
+
+typedef struct dlb3_params {
+    int32_t nx, ny, nz;   /* grid, >= 8 each                                     */
+    int32_t walls;        /* 0 periodic; 1 zero-gradient walls (outermost layer
+                             of nodes rebuilt as a copy of the inward neighbour) */
+    int32_t use_t;        /* 1 heat lattice; 0 isothermal (theta = theta0)       */
+    int32_t h_quintic;    /* h(phi): 0 phi; 1 15(phi - 2phi^3/3 + phi^5/5)/8     */
+    int32_t c_init_U;     /* initial solute: 0 uniform C0; 1 uniform U0          */
+    int32_t precision;    /* DLB3_F64 or DLB3_F32                                */
+    int32_t grad_iters;   /* cap of the local-gradient fixed point (0: default)  */
+    double W0, tau0, eps4;       /* interface width, kinetic time, anisotropy    */
+    double lambda, Mcinf, k;     /* coupling, M c_inf, partition coefficient     */
+    double D, alpha;             /* solute and heat diffusivities (lu^2/step)    */
+    double theta0, U0, C0;       /* initial temperature, supersaturation, C      */
+    double seed_R, seed_x, seed_y, seed_z; /* spherical seed (lu, node coords)   */
+    double grad_tol;             /* tolerance of the gradient fixed point (0: default) */
+} dlb3_params;
+
+typedef struct dlb3_solver* dlb3_handle;
+
+/* Bytes of device state for p (populations, history, a staging area of
+ * four double planes); 0 if p is invalid (message in dlb3_last_error). */
+size_t dlb3_state_bytes(const dlb3_params* p);
+
+/* Bind a solver to a caller-owned device buffer of at least
+ * dlb3_state_bytes(p) bytes and a hipStream_t (NULL: the null stream). */
+int dlb3_create(const dlb3_params* p, void* dev_state, size_t bytes, void* hip_stream, dlb3_handle* out);
+int dlb3_destroy(dlb3_handle h);
+
+/* Initial condition of Sec. 4 in 3-D: phi = tanh[(R - d)/(sqrt(2) W0)] about
+ * the seed centre, C from C0 or U0, theta0; then dlb3_set_fields. */
+int dlb3_init_seed(dlb3_handle h);
+
+/* Every lattice at equilibrium at the given fields (host arrays of nx*ny*nz
+ * doubles, x fastest then y then z; C and theta nullable: defaults from the
+ * parameters), the phi populations with the first moment that makes the
+ * local scheme return the isotropic D3Q19 central difference of phi.  The
+ * history is reset (time derivatives zero on the next step). */
+int dlb3_set_fields(dlb3_handle h, const double* phi, const double* C, const double* theta);
+
+/* n >= 0 main steps. */
+int dlb3_step(dlb3_handle h, int64_t n);
+
+/* phi, C, U, theta into host out (4 planes of nx*ny*nz doubles). */
+int dlb3_get_fields(dlb3_handle h, double* out);
+
+/* out[0..9]: sum C, sum H, solid fraction sum((1 + phi)/2)/N, non-finite
+ * count, tip distance from the seed node (centre rounded to the nearest node)
+ * along +x, +y, +z, -x, -y, -z (last + to - crossing of phi on the axis,
+ * refined linearly in atanh(phi); -1 if none). */
+int dlb3_reduce(dlb3_handle h, double* out);
+
+const char* dlb3_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

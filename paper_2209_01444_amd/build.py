@@ -10,9 +10,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libdlb.so")
-SOURCES = [os.path.join(CSRC, "dlb.hip")]
+SOURCES = [os.path.join(CSRC, "dlb.hip"), os.path.join(CSRC, "dlb3.hip")]
 DEPS = SOURCES + [os.path.join(CSRC, f) for f in ("lattice.h", "kernels.h", "batch.h")] + [
-    os.path.join(ROOT, "include", "dlb.h")]
+    os.path.join(ROOT, "include", "dlb.h"), os.path.join(ROOT, "include", "dlb3.h")]
 SUR_LIB = os.path.join(LIBDIR, "libsur.so")
 SUR_SOURCES = [os.path.join(CSRC, "sur.hip")]
 

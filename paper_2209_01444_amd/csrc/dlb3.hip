@@ -1,0 +1,638 @@
+// dlb3.hip -- three-dimensional phase-field, solute and heat lattices (D3Q7)
+// of the diffuse-interface lattice Boltzmann method (Zhan et al.,
+// arXiv:2209.01444) on gfx950, and the C ABI of include/dlb3.h.
+//
+// D3Q7 with cs^2 = 1/4 (w0 = 1/4, w1..6 = 1/8), S = diag(1, s1, s1, s1, 1, 1,
+// 1).  With every rate but the first-order ones equal to 1, a collision keeps
+// the equilibrium plus (1 - s1) times the first-moment part of the
+// populations, and the first-order auxiliary term G enters as (1 - s1/2) G;
+// the first-moment part of populations with first moment m is c_i.m/2 on the
+// moving links.  So each lattice's post-collision populations are
+//   rest: w0 (zeroth-order part),  +-a: w1 (zeroth-order part) +- b_a
+// with b_a collecting the first-order terms, written out below.
+//
+// State (caller's buffer, one plane per population, x fastest, planes padded
+// to 64 elements): pop[2][21] (phi 0-6, C 7-13, H 14-20; ping-pong),
+// hist[2] (phi, Q of the previous step), staging[4] double planes (fields in
+// and out, reduction partials).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "dlb3.h"
+
+namespace dlb3 {
+
+static constexpr int BX = 64, BY = 4;
+static constexpr double CS2 = 0.25;
+static constexpr double GUARD = 1e-12;
+
+struct K3 {
+    int nx, ny, nz, nbx, nby;
+    long long plane;
+    int use_t, h_quintic, grad_iters;
+    double W2t, inv_tau0, eps4, lambda, Mcinf, k, invD, s1c, s1t, jat, grad_tol2, theta0;
+};
+
+__device__ __forceinline__ bool node3(const K3& kp, int& x, int& y, int& z) {
+    x = (int)(blockIdx.x % kp.nbx) * BX + threadIdx.x;
+    y = (int)(blockIdx.x / kp.nbx) * BY + threadIdx.y;
+    z = blockIdx.y;
+    return x < kp.nx && y < kp.ny;
+}
+__device__ __forceinline__ size_t id3(const K3& kp, int x, int y, int z) {
+    return ((size_t)z * kp.ny + y) * kp.nx + x;
+}
+__device__ __forceinline__ bool is_wall3(const K3& kp, int x, int y, int z) {
+    return x == 0 || y == 0 || z == 0 || x == kp.nx - 1 || y == kp.ny - 1 || z == kp.nz - 1;
+}
+__device__ __forceinline__ int clampi(int a, int lo, int hi) { return a < lo ? lo : (a > hi ? hi : a); }
+__device__ __forceinline__ size_t inward3(const K3& kp, int x, int y, int z) {
+    return id3(kp, clampi(x, 1, kp.nx - 2), clampi(y, 1, kp.ny - 2), clampi(z, 1, kp.nz - 2));
+}
+
+template <class T> __device__ __forceinline__ T h_of3(T phi, int quintic) {
+    if (!quintic) return phi;
+    T p2 = phi * phi;
+    return T(15) * (phi - T(2) * phi * p2 / T(3) + phi * p2 * p2 / T(5)) / T(8);
+}
+
+// Cubic anisotropy (Sec. 2, d = 3): a_s = 1 - 3e + 4e sum g_a^4/|g|^4,
+// N_a = 16 e a_s (g_a^3 |g|^2 - g_a sum g_b^4)/|g|^4.
+template <class T>
+__device__ __forceinline__ void aniso3(T e, const T* g, T& a, T* N) {
+    T g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+    T P = g[0] * g[0] * g[0] * g[0] + g[1] * g[1] * g[1] * g[1] + g[2] * g[2] * g[2] * g[2];
+    T inv = T(1) / (g2 * g2);
+    a = T(1) - T(3) * e + T(4) * e * P * inv;
+    T c = T(16) * e * a * inv;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) N[d] = c * (g[d] * g[d] * g[d] * g2 - g[d] * P);
+}
+
+// Local gradient of Sec. 3.1 with cs^2 = 1/4: g = -(s1/cs^2)(m1 + W0^2 N/tau0),
+// s1 = 1/(a^2 W0^2/(tau0 cs^2) + 1/2), fixed point from the isotropic guess.
+template <class T>
+__device__ __forceinline__ void local_grad3(const K3& kp, const T* m1, T* g, T& a, T* N) {
+    const T W2t = T(kp.W2t), e = T(kp.eps4), tol2 = T(kp.grad_tol2);
+    T s1 = T(1) / (T(4) * W2t + T(0.5));
+#pragma unroll
+    for (int d = 0; d < 3; ++d) g[d] = T(-4) * s1 * m1[d];
+    a = T(1);
+    N[0] = N[1] = N[2] = T(0);
+    for (int it = 0; it < kp.grad_iters; ++it) {
+        if (g[0] * g[0] + g[1] * g[1] + g[2] * g[2] < T(GUARD)) break;
+        aniso3(e, g, a, N);
+        s1 = T(1) / (T(4) * a * a * W2t + T(0.5));
+        T ng[3], d2 = T(0);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            ng[d] = T(-4) * s1 * (m1[d] + W2t * N[d]);
+            d2 += (ng[d] - g[d]) * (ng[d] - g[d]);
+        }
+        g[0] = ng[0];
+        g[1] = ng[1];
+        g[2] = ng[2];
+        if (d2 <= tol2 * (g[0] * g[0] + g[1] * g[1] + g[2] * g[2])) break;
+    }
+    if (g[0] * g[0] + g[1] * g[1] + g[2] * g[2] < T(GUARD)) {
+        g[0] = g[1] = g[2] = T(0);
+        a = T(1);
+        N[0] = N[1] = N[2] = T(0);
+    } else {
+        aniso3(e, g, a, N);
+    }
+}
+
+// Destination of a push along axis link i (1..6), or -1 (a wall node).
+template <bool WALLS>
+__device__ __forceinline__ long long dest3(const K3& kp, int x, int y, int z, int i) {
+    int d = i <= 3 ? 1 : -1, ax = (i - 1) % 3;
+    int X = x + (ax == 0 ? d : 0), Y = y + (ax == 1 ? d : 0), Z = z + (ax == 2 ? d : 0);
+    if constexpr (WALLS) {
+        if (X < 1 || Y < 1 || Z < 1 || X > kp.nx - 2 || Y > kp.ny - 2 || Z > kp.nz - 2) return -1;
+    } else {
+        X = X < 0 ? X + kp.nx : (X >= kp.nx ? X - kp.nx : X);
+        Y = Y < 0 ? Y + kp.ny : (Y >= kp.ny ? Y - kp.ny : Y);
+        Z = Z < 0 ? Z + kp.nz : (Z >= kp.nz ? Z - kp.nz : Z);
+    }
+    return (long long)id3(kp, X, Y, Z);
+}
+
+// One main step at every node: collide phi, C, theta (Secs. 3.1-3.3), push.
+template <class T, bool WALLS>
+__global__ __launch_bounds__(BX* BY) void k3_step(const K3 kp, const T* __restrict__ pin, T* __restrict__ pout,
+                                                  T* __restrict__ hist, int hist_valid) {
+    int x, y, z;
+    if (!node3(kp, x, y, z)) return;
+    const size_t P = (size_t)kp.plane;
+    const size_t idx = id3(kp, x, y, z);
+    const bool wall = WALLS && is_wall3(kp, x, y, z);
+    const size_t src = wall ? inward3(kp, x, y, z) : idx;
+    T f[7], n[7], g[7];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+        f[i] = pin[i * P + src];
+        n[i] = pin[(7 + i) * P + src];
+        g[i] = kp.use_t ? pin[(14 + i) * P + src] : T(0);
+    }
+    const T phi = ((((((f[0] + f[1]) + f[2]) + f[3]) + f[4]) + f[5]) + f[6]);
+    const T C = ((((((n[0] + n[1]) + n[2]) + n[3]) + n[4]) + n[5]) + n[6]);
+    const T k = T(kp.k);
+    const T hphi = h_of3(phi, kp.h_quintic);
+    const T H = kp.use_t ? ((((((g[0] + g[1]) + g[2]) + g[3]) + g[4]) + g[5]) + g[6]) : T(kp.theta0) - T(0.5) * hphi;
+    const T theta = kp.use_t ? H + T(0.5) * hphi : T(kp.theta0);
+    const T U = (T(2) * C / (T(1) + k - (T(1) - k) * phi) - T(1)) / (T(1) - k);
+
+    const T m1[3] = {f[1] - f[4], f[2] - f[5], f[3] - f[6]};
+    T gr[3], a, N[3];
+    local_grad3<T>(kp, m1, gr, a, N);
+    const T a2 = a * a, inv_a2 = T(1) / a2;
+    const T s1 = T(1) / (T(4) * a2 * T(kp.W2t) + T(0.5));
+
+    const T om = T(1) - phi * phi;
+    const T Q = phi * om - T(kp.lambda) * (theta + T(kp.Mcinf) * U) * om * om;
+    T dQ = T(0), dphi = T(0);
+    if (hist_valid) {
+        dphi = phi - hist[idx];
+        dQ = Q - hist[P + idx];
+    }
+    hist[idx] = phi;
+    hist[P + idx] = Q;
+
+    // phi: rest w0 (phi + A), links w1 (phi + A) +- [(1 - s1) m1/2 - (1 - s1/2) N/(8 a^2)]
+    T pf[7];
+    {
+        const T A = (Q + T(0.5) * a2 * dQ) * T(kp.inv_tau0);
+        const T e = phi + A;
+        const T c1 = (T(1) - s1) * T(0.5), cN = (T(1) - T(0.5) * s1) * T(0.125) * inv_a2;
+        pf[0] = T(0.25) * e;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const T b = c1 * m1[d] - cN * N[d];
+            pf[1 + d] = T(0.125) * e + b;
+            pf[4 + d] = T(0.125) * e - b;
+        }
+    }
+    // anti-trapping current (Sec. 2)
+    T J[3] = {T(0), T(0), T(0)};
+    {
+        const T gn2 = gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2];
+        if (gn2 > T(0)) {
+            const T c = -T(kp.jat) * (T(1) + (T(1) - k) * U) * dphi / sqrt(gn2);
+            J[0] = c * gr[0];
+            J[1] = c * gr[1];
+            J[2] = c * gr[2];
+        }
+    }
+    // solute (u = 0): rest C - (1 - w0) qU, links w1 qU +- [(1 - s1c) m1/2 + (1 - s1c/2) V/8],
+    // V = U grad q + J/D with grad q = -grad phi/2
+    T pn[7];
+    {
+        const T s1c = T(kp.s1c), qU = T(0.5) * (T(1) - phi) * U;
+        const T c1 = (T(1) - s1c) * T(0.5), cV = (T(1) - T(0.5) * s1c) * T(0.125);
+        pn[0] = C - T(0.75) * qU;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const T V = T(-0.5) * U * gr[d] + J[d] * T(kp.invD);
+            const T b = c1 * (n[1 + d] - n[4 + d]) + cV * V;
+            pn[1 + d] = T(0.125) * qU + b;
+            pn[4 + d] = T(0.125) * qU - b;
+        }
+    }
+    // heat (u = 0): rest w0 theta - h/2, links w1 theta +- (1 - s1t) m1/2
+    T pg[7];
+    {
+        const T c1 = (T(1) - T(kp.s1t)) * T(0.5);
+        pg[0] = T(0.25) * theta - T(0.5) * hphi;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const T b = c1 * (g[1 + d] - g[4 + d]);
+            pg[1 + d] = T(0.125) * theta + b;
+            pg[4 + d] = T(0.125) * theta - b;
+        }
+    }
+    // push; phi: f(y, t+1) = f(y, t) + (post - f(y, t)) / a_s^2 (collision site's a_s)
+    if (!wall) {
+        pout[idx] = f[0] + (pf[0] - f[0]) * inv_a2;
+        pout[7 * P + idx] = pn[0];
+        if (kp.use_t) pout[14 * P + idx] = pg[0];
+    }
+#pragma unroll
+    for (int i = 1; i < 7; ++i) {
+        const long long d = dest3<WALLS>(kp, x, y, z, i);
+        if (d < 0) continue;
+        const T fold = pin[i * P + (size_t)d];
+        pout[i * P + (size_t)d] = fold + (pf[i] - fold) * inv_a2;
+        pout[(7 + i) * P + (size_t)d] = pn[i];
+        if (kp.use_t) pout[(14 + i) * P + (size_t)d] = pg[i];
+    }
+}
+
+// Spherical seed into a double plane.
+__global__ __launch_bounds__(BX* BY) void k3_seed(const K3 kp, double R, double cx, double cy, double cz,
+                                                  double W0, double* __restrict__ phi) {
+    int x, y, z;
+    if (!node3(kp, x, y, z)) return;
+    const double dx = x - cx, dy = y - cy, dz = z - cz;
+    phi[id3(kp, x, y, z)] = tanh((R - sqrt(dx * dx + dy * dy + dz * dz)) / (sqrt(2.0) * W0));
+}
+
+// Equilibrium at the given fields; phi populations with the first moment
+// m1 = -(cs^2/s1) grad phi - W0^2 N/tau0 of the isotropic D3Q19 central
+// difference of phi (periodic wrap or clamped at walls).
+template <class T, bool WALLS>
+__global__ __launch_bounds__(BX* BY) void k3_set(const K3 kp, const double* __restrict__ phi,
+                                                 const double* __restrict__ Cin, const double* __restrict__ thin,
+                                                 int c_init_U, double U0, double C0, T* __restrict__ pop) {
+    int x, y, z;
+    if (!node3(kp, x, y, z)) return;
+    const size_t P = (size_t)kp.plane;
+    const size_t idx = id3(kp, x, y, z);
+    double gd[3] = {0.0, 0.0, 0.0};
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int nnz = (dx != 0) + (dy != 0) + (dz != 0);
+                if (nnz == 0 || nnz == 3) continue;
+                const double w = nnz == 1 ? 1.0 / 18.0 : 1.0 / 36.0;
+                int X = x + dx, Y = y + dy, Z = z + dz;
+                if (WALLS) {
+                    X = clampi(X, 0, kp.nx - 1);
+                    Y = clampi(Y, 0, kp.ny - 1);
+                    Z = clampi(Z, 0, kp.nz - 1);
+                } else {
+                    X = (X + kp.nx) % kp.nx;
+                    Y = (Y + kp.ny) % kp.ny;
+                    Z = (Z + kp.nz) % kp.nz;
+                }
+                const double v = phi[id3(kp, X, Y, Z)];
+                gd[0] += 3.0 * w * dx * v;
+                gd[1] += 3.0 * w * dy * v;
+                gd[2] += 3.0 * w * dz * v;
+            }
+    double m1[3] = {0.0, 0.0, 0.0};
+    if (gd[0] * gd[0] + gd[1] * gd[1] + gd[2] * gd[2] >= GUARD) {
+        double a, N[3];
+        aniso3(kp.eps4, gd, a, N);
+        const double s1 = 1.0 / (4.0 * a * a * kp.W2t + 0.5);
+        for (int d = 0; d < 3; ++d) m1[d] = -CS2 * gd[d] / s1 - kp.W2t * N[d];
+    }
+    const double ph = phi[idx];
+    const double k = kp.k;
+    const double C = Cin ? Cin[idx]
+                         : (c_init_U ? 0.5 * (1.0 + k - (1.0 - k) * ph) * (1.0 + (1.0 - k) * U0) : C0);
+    const double th = thin ? thin[idx] : kp.theta0;
+    const double U = (2.0 * C / (1.0 + k - (1.0 - k) * ph) - 1.0) / (1.0 - k);
+    const double qU = 0.5 * (1.0 - ph) * U;
+    const double hp = h_of3(ph, kp.h_quintic);
+    pop[idx] = T(0.25 * ph);
+    pop[7 * P + idx] = T(C - 0.75 * qU);
+    pop[14 * P + idx] = T(kp.use_t ? 0.25 * th - 0.5 * hp : 0.0);
+    for (int d = 0; d < 3; ++d) {
+        pop[(1 + d) * P + idx] = T(0.125 * ph + 0.5 * m1[d]);
+        pop[(4 + d) * P + idx] = T(0.125 * ph - 0.5 * m1[d]);
+        pop[(8 + d) * P + idx] = T(0.125 * qU);
+        pop[(11 + d) * P + idx] = T(0.125 * qU);
+        pop[(15 + d) * P + idx] = T(kp.use_t ? 0.125 * th : 0.0);
+        pop[(18 + d) * P + idx] = T(kp.use_t ? 0.125 * th : 0.0);
+    }
+}
+
+template <class T, bool WALLS>
+__device__ __forceinline__ void macros3(const K3& kp, const T* __restrict__ pop, int x, int y, int z,
+                                        double* m) {
+    const size_t P = (size_t)kp.plane;
+    const size_t src = (WALLS && is_wall3(kp, x, y, z)) ? inward3(kp, x, y, z) : id3(kp, x, y, z);
+    T phi = T(0), C = T(0), H = T(0);
+    for (int i = 0; i < 7; ++i) {
+        phi += pop[i * P + src];
+        C += pop[(7 + i) * P + src];
+        if (kp.use_t) H += pop[(14 + i) * P + src];
+    }
+    const T k = T(kp.k);
+    const T hp = h_of3(phi, kp.h_quintic);
+    if (!kp.use_t) H = T(kp.theta0) - T(0.5) * hp;
+    m[0] = phi;
+    m[1] = C;
+    m[2] = (T(2) * C / (T(1) + k - (T(1) - k) * phi) - T(1)) / (T(1) - k);
+    m[3] = H + T(0.5) * hp;
+    m[4] = H;
+}
+
+template <class T, bool WALLS>
+__global__ __launch_bounds__(BX* BY) void k3_fields(const K3 kp, const T* __restrict__ pop, double* __restrict__ out) {
+    int x, y, z;
+    if (!node3(kp, x, y, z)) return;
+    double m[5];
+    macros3<T, WALLS>(kp, pop, x, y, z, m);
+    const size_t N = (size_t)kp.nx * kp.ny * kp.nz, idx = id3(kp, x, y, z);
+    for (int j = 0; j < 4; ++j) out[j * N + idx] = m[j];
+}
+
+// Per-workgroup partial sums: C, H, (1 + phi)/2, non-finite count.
+template <class T, bool WALLS>
+__global__ __launch_bounds__(BX* BY) void k3_partial(const K3 kp, const T* __restrict__ pop, double* __restrict__ part) {
+    __shared__ double sh[4][BX * BY / 64];
+    int x, y, z;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (node3(kp, x, y, z)) {
+        double m[5];
+        macros3<T, WALLS>(kp, pop, x, y, z, m);
+        v[0] = m[1];
+        v[1] = m[4];
+        v[2] = 0.5 * (1.0 + m[0]);
+        v[3] = (isfinite(m[0]) && isfinite(m[1]) && isfinite(m[3])) ? 0.0 : 1.0;
+    }
+    const int t = threadIdx.y * BX + threadIdx.x, lane = t & 63, wave = t >> 6;
+    for (int r = 0; r < 4; ++r)
+        for (int off = 32; off > 0; off >>= 1) v[r] += __shfl_xor(v[r], off, 64);
+    if (lane == 0)
+        for (int r = 0; r < 4; ++r) sh[r][wave] = v[r];
+    __syncthreads();
+    if (t == 0) {
+        const size_t b = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+        for (int r = 0; r < 4; ++r) {
+            double s = 0.0;
+            for (int w = 0; w < BX * BY / 64; ++w) s += sh[r][w];
+            part[b * 4 + r] = s;
+        }
+    }
+}
+
+// Tips along the six axis directions from the seed node (one thread each).
+template <class T, bool WALLS>
+__global__ void k3_tips(const K3 kp, const T* __restrict__ pop, int cx, int cy, int cz, double* __restrict__ out) {
+    const int arm = threadIdx.x;
+    if (arm >= 6) return;
+    const int sgn = arm < 3 ? 1 : -1, ax = arm % 3;
+    const double lim = 1.0 - 1.0 / 1073741824.0;
+    double best = -1.0, prev = 0.0;
+    for (int j = 0;; ++j) {
+        const int x = cx + (ax == 0 ? sgn * j : 0), y = cy + (ax == 1 ? sgn * j : 0), z = cz + (ax == 2 ? sgn * j : 0);
+        if (x < 0 || y < 0 || z < 0 || x >= kp.nx || y >= kp.ny || z >= kp.nz) break;
+        double m[5];
+        macros3<T, WALLS>(kp, pop, x, y, z, m);
+        double v = m[0] > lim ? lim : (m[0] < -lim ? -lim : m[0]);
+        const double ps = atanh(v);
+        if (j > 0 && prev > 0.0 && ps <= 0.0) best = (j - 1) + prev / (prev - ps);
+        prev = ps;
+    }
+    out[arm] = best;
+}
+
+}  // namespace dlb3
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+using namespace dlb3;
+
+namespace {
+thread_local std::string g_err3;
+int fail3(int code, const std::string& m) {
+    g_err3 = m;
+    return code;
+}
+int hip_fail3(hipError_t e, const char* what) {
+    return fail3(DLB3_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+struct Layout3 {
+    size_t plane, pop[2], hist, stage, total;
+};
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+int check3(const dlb3_params* p) {
+    if (!p) return fail3(DLB3_EINVAL, "null params");
+    if (p->nx < 8 || p->ny < 8 || p->nz < 8) return fail3(DLB3_EINVAL, "grid must be at least 8x8x8");
+    if (p->nz > 65535) return fail3(DLB3_EINVAL, "nz must be at most 65535");
+    if ((double)p->nx * p->ny * p->nz > 2.0e9) return fail3(DLB3_EINVAL, "grid too large");
+    if (p->precision != DLB3_F64 && p->precision != DLB3_F32) return fail3(DLB3_EINVAL, "unknown precision");
+    if (p->walls != 0 && p->walls != 1) return fail3(DLB3_EINVAL, "walls must be 0 or 1");
+    if (!(p->W0 > 0 && p->tau0 > 0 && p->D > 0 && p->alpha > 0)) return fail3(DLB3_EINVAL, "W0, tau0, D, alpha must be > 0");
+    if (!(p->k > 0 && p->k < 1)) return fail3(DLB3_EINVAL, "partition coefficient k must be in (0,1)");
+    if (!(p->eps4 >= 0.0 && p->eps4 < 0.2)) return fail3(DLB3_EINVAL, "eps4 must be in [0, 0.2)");
+    const double W2t = p->W0 * p->W0 / p->tau0;
+    const double rates[3] = {1.0 / (4.0 * (1.0 + p->eps4) * (1.0 + p->eps4) * W2t + 0.5),
+                             1.0 / (4.0 * p->D * (1.0 - p->k) + 0.5), 1.0 / (4.0 * p->alpha + 0.5)};
+    for (double r : rates)
+        if (!(r > 0.0 && r < 2.0)) return fail3(DLB3_EINVAL, "relaxation rate outside (0,2)");
+    return DLB3_OK;
+}
+
+Layout3 layout3(const dlb3_params* p) {
+    Layout3 L{};
+    const size_t N = (size_t)p->nx * p->ny * p->nz;
+    L.plane = (N + 63) & ~size_t(63);
+    const size_t sb = p->precision == DLB3_F64 ? 8 : 4;
+    size_t off = 0;
+    for (int b = 0; b < 2; ++b) {
+        L.pop[b] = off;
+        off = align256(off + 21 * L.plane * sb);
+    }
+    L.hist = off;
+    off = align256(off + 2 * L.plane * sb);
+    L.stage = off;
+    off = align256(off + 4 * L.plane * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+K3 make_k3(const dlb3_params* p, const Layout3& L) {
+    K3 k{};
+    k.nx = p->nx;
+    k.ny = p->ny;
+    k.nz = p->nz;
+    k.nbx = (p->nx + BX - 1) / BX;
+    k.nby = (p->ny + BY - 1) / BY;
+    k.plane = (long long)L.plane;
+    k.use_t = p->use_t ? 1 : 0;
+    k.h_quintic = p->h_quintic;
+    const bool f64 = p->precision == DLB3_F64;
+    k.grad_iters = p->grad_iters > 0 ? p->grad_iters : (f64 ? 100 : 20);
+    const double tol = p->grad_tol > 0 ? p->grad_tol : (f64 ? 1e-14 : 1e-6);
+    k.grad_tol2 = tol * tol;
+    k.W2t = p->W0 * p->W0 / p->tau0;
+    k.inv_tau0 = 1.0 / p->tau0;
+    k.eps4 = p->eps4;
+    k.lambda = p->lambda;
+    k.Mcinf = p->Mcinf;
+    k.k = p->k;
+    k.invD = 1.0 / p->D;
+    k.s1c = 1.0 / (4.0 * p->D * (1.0 - p->k) + 0.5);
+    k.s1t = 1.0 / (4.0 * p->alpha + 0.5);
+    k.jat = p->W0 / (2.0 * std::sqrt(2.0));
+    k.theta0 = p->theta0;
+    return k;
+}
+}  // namespace
+
+struct dlb3_solver {
+    dlb3_params p;
+    Layout3 L;
+    K3 kp;
+    char* base;
+    hipStream_t stream;
+    int cur, hist_valid;
+    dim3 grid, block;
+};
+
+template <class T, bool W> static void launch_step(dlb3_solver* s) {
+    hipLaunchKernelGGL((k3_step<T, W>), s->grid, s->block, 0, s->stream, s->kp, (const T*)(s->base + s->L.pop[s->cur]),
+                       (T*)(s->base + s->L.pop[1 - s->cur]), (T*)(s->base + s->L.hist), s->hist_valid);
+}
+template <class T, bool W> static void launch_set(dlb3_solver* s, const double* phi, const double* C, const double* th) {
+    hipLaunchKernelGGL((k3_set<T, W>), s->grid, s->block, 0, s->stream, s->kp, phi, C, th, s->p.c_init_U, s->p.U0,
+                       s->p.C0, (T*)(s->base + s->L.pop[s->cur]));
+}
+template <class T, bool W> static void launch_fields(dlb3_solver* s, double* out) {
+    hipLaunchKernelGGL((k3_fields<T, W>), s->grid, s->block, 0, s->stream, s->kp, (const T*)(s->base + s->L.pop[s->cur]),
+                       out);
+}
+template <class T, bool W> static void launch_partial(dlb3_solver* s, double* part) {
+    hipLaunchKernelGGL((k3_partial<T, W>), s->grid, s->block, 0, s->stream, s->kp,
+                       (const T*)(s->base + s->L.pop[s->cur]), part);
+}
+template <class T, bool W> static void launch_tips(dlb3_solver* s, int cx, int cy, int cz, double* out) {
+    hipLaunchKernelGGL((k3_tips<T, W>), dim3(1), dim3(64), 0, s->stream, s->kp, (const T*)(s->base + s->L.pop[s->cur]),
+                       cx, cy, cz, out);
+}
+
+#define DISPATCH3(s, fn, ...)                                                     \
+    do {                                                                          \
+        if ((s)->p.precision == DLB3_F64) {                                       \
+            if ((s)->p.walls) fn<double, true>(s, ##__VA_ARGS__);                 \
+            else fn<double, false>(s, ##__VA_ARGS__);                             \
+        } else {                                                                  \
+            if ((s)->p.walls) fn<float, true>(s, ##__VA_ARGS__);                  \
+            else fn<float, false>(s, ##__VA_ARGS__);                              \
+        }                                                                         \
+    } while (0)
+
+extern "C" {
+
+const char* dlb3_last_error(void) { return g_err3.c_str(); }
+
+size_t dlb3_state_bytes(const dlb3_params* p) {
+    if (check3(p) != DLB3_OK) return 0;
+    return layout3(p).total;
+}
+
+int dlb3_create(const dlb3_params* p, void* dev_state, size_t bytes, void* hip_stream, dlb3_handle* out) {
+    int rc = check3(p);
+    if (rc) return rc;
+    if (!out || !dev_state) return fail3(DLB3_EINVAL, "null state or handle pointer");
+    Layout3 L = layout3(p);
+    if (bytes < L.total) return fail3(DLB3_ENOMEM, "state buffer smaller than dlb3_state_bytes");
+    if (((uintptr_t)dev_state) % 256) return fail3(DLB3_EINVAL, "state buffer must be 256-byte aligned");
+    dlb3_solver* s = new (std::nothrow) dlb3_solver();
+    if (!s) return fail3(DLB3_ENOMEM, "host allocation failed");
+    s->p = *p;
+    s->L = L;
+    s->kp = make_k3(p, L);
+    s->base = (char*)dev_state;
+    s->stream = (hipStream_t)hip_stream;
+    s->cur = 0;
+    s->hist_valid = 0;
+    s->grid = dim3(s->kp.nbx * s->kp.nby, p->nz);
+    s->block = dim3(BX, BY);
+    *out = s;
+    return DLB3_OK;
+}
+
+int dlb3_destroy(dlb3_handle h) {
+    delete h;
+    return DLB3_OK;
+}
+
+int dlb3_set_fields(dlb3_handle s, const double* phi, const double* C, const double* theta) {
+    if (!s || !phi) return fail3(DLB3_EINVAL, "null handle or phi");
+    const size_t N = (size_t)s->p.nx * s->p.ny * s->p.nz;
+    double* st = (double*)(s->base + s->L.stage);
+    const double* srcs[3] = {phi, C, theta};
+    for (int j = 0; j < 3; ++j) {
+        if (!srcs[j]) continue;
+        hipError_t e = hipMemcpyAsync(st + j * s->L.plane, srcs[j], N * sizeof(double), hipMemcpyHostToDevice, s->stream);
+        if (e != hipSuccess) return hip_fail3(e, "hipMemcpyAsync");
+    }
+    DISPATCH3(s, launch_set, st, C ? st + s->L.plane : nullptr, theta ? st + 2 * s->L.plane : nullptr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail3(e, "k3_set");
+    // the host arrays must stay valid until the copies ran
+    e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail3(e, "hipStreamSynchronize");
+    s->hist_valid = 0;
+    return DLB3_OK;
+}
+
+int dlb3_init_seed(dlb3_handle s) {
+    if (!s) return fail3(DLB3_EINVAL, "null handle");
+    double* st = (double*)(s->base + s->L.stage);
+    hipLaunchKernelGGL(k3_seed, s->grid, s->block, 0, s->stream, s->kp, s->p.seed_R, s->p.seed_x, s->p.seed_y,
+                       s->p.seed_z, s->p.W0, st);
+    DISPATCH3(s, launch_set, st, nullptr, nullptr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail3(e, "k3_seed/k3_set");
+    s->hist_valid = 0;
+    return DLB3_OK;
+}
+
+int dlb3_step(dlb3_handle s, int64_t n) {
+    if (!s || n < 0) return fail3(DLB3_EINVAL, "null handle or negative step count");
+    for (int64_t t = 0; t < n; ++t) {
+        DISPATCH3(s, launch_step);
+        s->cur ^= 1;
+        s->hist_valid = 1;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail3(e, "k3_step");
+    return DLB3_OK;
+}
+
+int dlb3_get_fields(dlb3_handle s, double* out) {
+    if (!s || !out) return fail3(DLB3_EINVAL, "null handle or output");
+    const size_t N = (size_t)s->p.nx * s->p.ny * s->p.nz;
+    double* st = (double*)(s->base + s->L.stage);
+    DISPATCH3(s, launch_fields, st);
+    hipError_t e = hipMemcpyAsync(out, st, 4 * N * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    if (e != hipSuccess) return hip_fail3(e, "hipMemcpyAsync");
+    e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail3(e, "hipStreamSynchronize");
+    return DLB3_OK;
+}
+
+int dlb3_reduce(dlb3_handle s, double* out) {
+    if (!s || !out) return fail3(DLB3_EINVAL, "null handle or output");
+    double* st = (double*)(s->base + s->L.stage);
+    const size_t nb = (size_t)s->grid.x * s->grid.y;
+    if (4 * nb + 6 > 4 * s->L.plane) return fail3(DLB3_EINVAL, "staging area too small for the reduction");
+    double* tips = st + 4 * nb;
+    DISPATCH3(s, launch_partial, st);
+    const int cx = (int)std::lround(s->p.seed_x), cy = (int)std::lround(s->p.seed_y), cz = (int)std::lround(s->p.seed_z);
+    DISPATCH3(s, launch_tips, cx, cy, cz, tips);
+    double* host = new (std::nothrow) double[4 * nb + 6];
+    if (!host) return fail3(DLB3_ENOMEM, "host allocation failed");
+    hipError_t e = hipMemcpyAsync(host, st, (4 * nb + 6) * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) {
+        delete[] host;
+        return hip_fail3(e, "reduce copy");
+    }
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (size_t b = 0; b < nb; ++b)
+        for (int r = 0; r < 4; ++r) v[r] += host[b * 4 + r];
+    out[0] = v[0];
+    out[1] = v[1];
+    out[2] = v[2] / ((double)s->p.nx * s->p.ny * s->p.nz);
+    out[3] = v[3];
+    for (int a = 0; a < 6; ++a) out[4 + a] = host[4 * nb + a];
+    delete[] host;
+    return DLB3_OK;
+}
+
+}  // extern "C"

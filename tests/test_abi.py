@@ -115,3 +115,18 @@ def test_gpu_solver_refuses_to_run_without_gpu():
         pytest.skip("a GPU is present")
     with pytest.raises(RuntimeError):
         dlb.Solver(W.pure_diffusion_128())
+
+
+def test_3d_abi_exports_and_validation():
+    from paper_2209_01444_amd import dlb3
+    lib = dlb3.load_library()
+    for name in dlb3.EXPORTS:
+        assert hasattr(lib, name), name
+    p = dlb3.make_params(dict(nx=32, ny=30, nz=28, precision="f32"))
+    n32 = lib.dlb3_state_bytes(ctypes.byref(p))
+    # 2 x 21 FP32 population planes, 2 history planes, 4 double staging planes
+    assert n32 >= 32 * 30 * 28 * (42 * 4 + 2 * 4 + 4 * 8)
+    for bad in (dict(nx=4), dict(walls=2), dict(precision=9), dict(D=-1.0), dict(eps4=0.3)):
+        q = dlb3.make_params(dict(dict(nx=32, ny=30, nz=28), **bad))
+        assert lib.dlb3_state_bytes(ctypes.byref(q)) == 0, bad
+        assert lib.dlb3_last_error()
