@@ -11,10 +11,11 @@
 //   rest: w0 (zeroth-order part),  +-a: w1 (zeroth-order part) +- b_a
 // with b_a collecting the first-order terms, written out below.
 //
-// State (caller's buffer, one plane per population, x fastest, planes padded
-// to 64 elements): pop[2][21] (phi 0-6, C 7-13, H 14-20; ping-pong),
-// hist[2] (phi, Q of the previous step), staging[4] double planes (fields in
-// and out, reduction partials).
+// State (caller's buffer): pop[2] (ping-pong), each [nz][21][ny][nx] with the
+// layers padded to 64 elements -- the 21 populations (phi 0-6, C 7-13, H
+// 14-20) of one z-layer lie together, so a workgroup's loads and stores stay
+// within a few megabytes; hist[2][N] (phi, Q of the previous step); staging[4]
+// double planes (fields in and out, reduction partials).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -32,7 +33,8 @@ static constexpr double GUARD = 1e-12;
 
 struct K3 {
     int nx, ny, nz, nbx, nby;
-    long long plane;
+    long long plane;  // elements per history / staging plane (>= N, 64-multiple)
+    long long lp;     // elements per population layer (>= nx ny, 64-multiple)
     int use_t, h_quintic, grad_iters;
     double W2t, inv_tau0, eps4, lambda, Mcinf, k, invD, s1c, s1t, jat, grad_tol2, theta0;
 };
@@ -46,12 +48,16 @@ __device__ __forceinline__ bool node3(const K3& kp, int& x, int& y, int& z) {
 __device__ __forceinline__ size_t id3(const K3& kp, int x, int y, int z) {
     return ((size_t)z * kp.ny + y) * kp.nx + x;
 }
+// Address of population 0 of node (x, y, z); population q is q * lp further.
+__device__ __forceinline__ size_t base3(const K3& kp, int x, int y, int z) {
+    return (size_t)z * 21 * (size_t)kp.lp + (size_t)y * kp.nx + x;
+}
 __device__ __forceinline__ bool is_wall3(const K3& kp, int x, int y, int z) {
     return x == 0 || y == 0 || z == 0 || x == kp.nx - 1 || y == kp.ny - 1 || z == kp.nz - 1;
 }
 __device__ __forceinline__ int clampi(int a, int lo, int hi) { return a < lo ? lo : (a > hi ? hi : a); }
 __device__ __forceinline__ size_t inward3(const K3& kp, int x, int y, int z) {
-    return id3(kp, clampi(x, 1, kp.nx - 2), clampi(y, 1, kp.ny - 2), clampi(z, 1, kp.nz - 2));
+    return base3(kp, clampi(x, 1, kp.nx - 2), clampi(y, 1, kp.ny - 2), clampi(z, 1, kp.nz - 2));
 }
 
 template <class T> __device__ __forceinline__ T h_of3(T phi, int quintic) {
@@ -107,7 +113,8 @@ __device__ __forceinline__ void local_grad3(const K3& kp, const T* m1, T* g, T& 
     }
 }
 
-// Destination of a push along axis link i (1..6), or -1 (a wall node).
+// Population-0 address of the destination of a push along axis link i
+// (1..6), or -1 (a wall node).
 template <bool WALLS>
 __device__ __forceinline__ long long dest3(const K3& kp, int x, int y, int z, int i) {
     int d = i <= 3 ? 1 : -1, ax = (i - 1) % 3;
@@ -119,7 +126,7 @@ __device__ __forceinline__ long long dest3(const K3& kp, int x, int y, int z, in
         Y = Y < 0 ? Y + kp.ny : (Y >= kp.ny ? Y - kp.ny : Y);
         Z = Z < 0 ? Z + kp.nz : (Z >= kp.nz ? Z - kp.nz : Z);
     }
-    return (long long)id3(kp, X, Y, Z);
+    return (long long)base3(kp, X, Y, Z);
 }
 
 // One main step at every node: collide phi, C, theta (Secs. 3.1-3.3), push.
@@ -128,16 +135,16 @@ __global__ __launch_bounds__(BX* BY) void k3_step(const K3 kp, const T* __restri
                                                   T* __restrict__ hist, int hist_valid) {
     int x, y, z;
     if (!node3(kp, x, y, z)) return;
-    const size_t P = (size_t)kp.plane;
-    const size_t idx = id3(kp, x, y, z);
+    const size_t P = (size_t)kp.plane, LP = (size_t)kp.lp;
+    const size_t idx = id3(kp, x, y, z), own = base3(kp, x, y, z);
     const bool wall = WALLS && is_wall3(kp, x, y, z);
-    const size_t src = wall ? inward3(kp, x, y, z) : idx;
+    const size_t src = wall ? inward3(kp, x, y, z) : own;
     T f[7], n[7], g[7];
 #pragma unroll
     for (int i = 0; i < 7; ++i) {
-        f[i] = pin[i * P + src];
-        n[i] = pin[(7 + i) * P + src];
-        g[i] = kp.use_t ? pin[(14 + i) * P + src] : T(0);
+        f[i] = pin[i * LP + src];
+        n[i] = pin[(7 + i) * LP + src];
+        g[i] = kp.use_t ? pin[(14 + i) * LP + src] : T(0);
     }
     const T phi = ((((((f[0] + f[1]) + f[2]) + f[3]) + f[4]) + f[5]) + f[6]);
     const T C = ((((((n[0] + n[1]) + n[2]) + n[3]) + n[4]) + n[5]) + n[6]);
@@ -217,18 +224,18 @@ __global__ __launch_bounds__(BX* BY) void k3_step(const K3 kp, const T* __restri
     }
     // push; phi: f(y, t+1) = f(y, t) + (post - f(y, t)) / a_s^2 (collision site's a_s)
     if (!wall) {
-        pout[idx] = f[0] + (pf[0] - f[0]) * inv_a2;
-        pout[7 * P + idx] = pn[0];
-        if (kp.use_t) pout[14 * P + idx] = pg[0];
+        pout[own] = f[0] + (pf[0] - f[0]) * inv_a2;
+        pout[7 * LP + own] = pn[0];
+        if (kp.use_t) pout[14 * LP + own] = pg[0];
     }
 #pragma unroll
     for (int i = 1; i < 7; ++i) {
         const long long d = dest3<WALLS>(kp, x, y, z, i);
         if (d < 0) continue;
-        const T fold = pin[i * P + (size_t)d];
-        pout[i * P + (size_t)d] = fold + (pf[i] - fold) * inv_a2;
-        pout[(7 + i) * P + (size_t)d] = pn[i];
-        if (kp.use_t) pout[(14 + i) * P + (size_t)d] = pg[i];
+        const T fold = pin[i * LP + (size_t)d];
+        pout[i * LP + (size_t)d] = fold + (pf[i] - fold) * inv_a2;
+        pout[(7 + i) * LP + (size_t)d] = pn[i];
+        if (kp.use_t) pout[(14 + i) * LP + (size_t)d] = pg[i];
     }
 }
 
@@ -250,7 +257,6 @@ __global__ __launch_bounds__(BX* BY) void k3_set(const K3 kp, const double* __re
                                                  int c_init_U, double U0, double C0, T* __restrict__ pop) {
     int x, y, z;
     if (!node3(kp, x, y, z)) return;
-    const size_t P = (size_t)kp.plane;
     const size_t idx = id3(kp, x, y, z);
     double gd[3] = {0.0, 0.0, 0.0};
     for (int dz = -1; dz <= 1; ++dz)
@@ -289,29 +295,30 @@ __global__ __launch_bounds__(BX* BY) void k3_set(const K3 kp, const double* __re
     const double U = (2.0 * C / (1.0 + k - (1.0 - k) * ph) - 1.0) / (1.0 - k);
     const double qU = 0.5 * (1.0 - ph) * U;
     const double hp = h_of3(ph, kp.h_quintic);
-    pop[idx] = T(0.25 * ph);
-    pop[7 * P + idx] = T(C - 0.75 * qU);
-    pop[14 * P + idx] = T(kp.use_t ? 0.25 * th - 0.5 * hp : 0.0);
+    const size_t LP = (size_t)kp.lp, o = base3(kp, x, y, z);
+    pop[o] = T(0.25 * ph);
+    pop[7 * LP + o] = T(C - 0.75 * qU);
+    pop[14 * LP + o] = T(kp.use_t ? 0.25 * th - 0.5 * hp : 0.0);
     for (int d = 0; d < 3; ++d) {
-        pop[(1 + d) * P + idx] = T(0.125 * ph + 0.5 * m1[d]);
-        pop[(4 + d) * P + idx] = T(0.125 * ph - 0.5 * m1[d]);
-        pop[(8 + d) * P + idx] = T(0.125 * qU);
-        pop[(11 + d) * P + idx] = T(0.125 * qU);
-        pop[(15 + d) * P + idx] = T(kp.use_t ? 0.125 * th : 0.0);
-        pop[(18 + d) * P + idx] = T(kp.use_t ? 0.125 * th : 0.0);
+        pop[(1 + d) * LP + o] = T(0.125 * ph + 0.5 * m1[d]);
+        pop[(4 + d) * LP + o] = T(0.125 * ph - 0.5 * m1[d]);
+        pop[(8 + d) * LP + o] = T(0.125 * qU);
+        pop[(11 + d) * LP + o] = T(0.125 * qU);
+        pop[(15 + d) * LP + o] = T(kp.use_t ? 0.125 * th : 0.0);
+        pop[(18 + d) * LP + o] = T(kp.use_t ? 0.125 * th : 0.0);
     }
 }
 
 template <class T, bool WALLS>
 __device__ __forceinline__ void macros3(const K3& kp, const T* __restrict__ pop, int x, int y, int z,
                                         double* m) {
-    const size_t P = (size_t)kp.plane;
-    const size_t src = (WALLS && is_wall3(kp, x, y, z)) ? inward3(kp, x, y, z) : id3(kp, x, y, z);
+    const size_t LP = (size_t)kp.lp;
+    const size_t src = (WALLS && is_wall3(kp, x, y, z)) ? inward3(kp, x, y, z) : base3(kp, x, y, z);
     T phi = T(0), C = T(0), H = T(0);
     for (int i = 0; i < 7; ++i) {
-        phi += pop[i * P + src];
-        C += pop[(7 + i) * P + src];
-        if (kp.use_t) H += pop[(14 + i) * P + src];
+        phi += pop[i * LP + src];
+        C += pop[(7 + i) * LP + src];
+        if (kp.use_t) H += pop[(14 + i) * LP + src];
     }
     const T k = T(kp.k);
     const T hp = h_of3(phi, kp.h_quintic);
@@ -402,7 +409,7 @@ int hip_fail3(hipError_t e, const char* what) {
 }
 
 struct Layout3 {
-    size_t plane, pop[2], hist, stage, total;
+    size_t plane, lp, pop[2], hist, stage, total;
 };
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
@@ -429,11 +436,12 @@ Layout3 layout3(const dlb3_params* p) {
     Layout3 L{};
     const size_t N = (size_t)p->nx * p->ny * p->nz;
     L.plane = (N + 63) & ~size_t(63);
+    L.lp = ((size_t)p->nx * p->ny + 63) & ~size_t(63);
     const size_t sb = p->precision == DLB3_F64 ? 8 : 4;
     size_t off = 0;
     for (int b = 0; b < 2; ++b) {
         L.pop[b] = off;
-        off = align256(off + 21 * L.plane * sb);
+        off = align256(off + (size_t)p->nz * 21 * L.lp * sb);
     }
     L.hist = off;
     off = align256(off + 2 * L.plane * sb);
@@ -451,6 +459,7 @@ K3 make_k3(const dlb3_params* p, const Layout3& L) {
     k.nbx = (p->nx + BX - 1) / BX;
     k.nby = (p->ny + BY - 1) / BY;
     k.plane = (long long)L.plane;
+    k.lp = (long long)L.lp;
     k.use_t = p->use_t ? 1 : 0;
     k.h_quintic = p->h_quintic;
     const bool f64 = p->precision == DLB3_F64;

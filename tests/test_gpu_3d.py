@@ -75,3 +75,22 @@ def test_3d_refusals(dlb3):
     for bad in (dict(nx=4), dict(walls=2), dict(precision=7), dict(tau0=-1.0), dict(k=1.5)):
         with pytest.raises(dlb3.Dlb3Error):
             dlb3.Solver3(dict(_case(0, "f64"), **bad))
+
+
+def test_3d_seed_grows_with_cubic_symmetry(dlb3):
+    """A seed centred on a node of a 65^3 grid with walls, FP32, 400 steps: the six arms
+    stay equal (the grid, seed and anisotropy share the cubic symmetry) and
+    the undercooled seed grows along <100>."""
+    from paper_2209_01444_amd import bench3d
+    cfg = dict(bench3d.workload(65, "f32"), seed_R=6.0)  # centre on node 32
+    s = dlb3.Solver3(cfg).init_seed()
+    r0 = s.reduce()
+    s.step(400)
+    r = s.reduce()
+    _say(f"  tips {r['tip_s']}, solid fraction {r0['solid_fraction']:.5f} -> {r['solid_fraction']:.5f}")
+    assert r["nonfinite"] == 0
+    assert np.ptp(r["tip_s"]) < 1e-3 * r["tip_s"].mean()
+    assert r["tip_s"].min() > r0["tip_s"].max() + 1.0
+    f = s.fields()["phi"]
+    np.testing.assert_allclose(np.transpose(f, (2, 1, 0)), f, atol=1e-5)
+    np.testing.assert_allclose(f[::-1], f, atol=1e-5)
