@@ -24,6 +24,14 @@
  *   - Crystal axes along the lattice axes (no orientation).
  *   - Walls (walls = 1): the outermost layer of nodes, rebuilt as a copy of
  *     the inward neighbour (zero gradient), as in the 2-D channel.
+ *   - Melt flow (use_ns = 1, periodic domain only): D3Q19 (c0 = 0, the six
+ *     faces, the twelve edges; w = 1/3, 1/18, 1/36; cs^2 = 1/3) with the
+ *     equilibrium, pressure, diffuse force and forcing of Sec. 3.4 (varphi =
+ *     0, no external force); MRT in the raw-moment basis 1, c_a, c_a c_b,
+ *     c_a^2 c_b, c_a^2 c_b^2 with s2 on the six second-order moments and 1 on
+ *     all others, as the 2-D flow lattice; n_sub sub-steps per main step at
+ *     the frozen phi of time t, and u = n_sub u' in the solute and heat
+ *     equilibria and in d_t(Cu), d_t(Hu) (two-time-scaling, Sec. 4).
  *
  * Parity status:
  *   anisotropy a_s, N (d-general)                          pinned (closed forms,
@@ -48,6 +56,9 @@ typedef struct o3_params {
     double seed_R, seed_x, seed_y, seed_z;
     double grad_tol;
     double fixed_as;   /* test hook: > 0 fixes a_s and sets N = 0            */
+    int use_ns, n_sub; /* melt flow (periodic only) and its sub-steps        */
+    double nu, rho0;   /* viscosity (main-step units) and density            */
+    double u0x, u0y, u0z; /* initial velocity (main-step units)             */
 } o3_params;
 
 typedef struct o3_state o3_state;
@@ -57,6 +68,21 @@ static const int CY[7] = {0, 0, 1, 0, 0, -1, 0};
 static const int CZ[7] = {0, 0, 0, 1, 0, 0, -1};
 static const double W7[7] = {0.25, 0.125, 0.125, 0.125, 0.125, 0.125, 0.125};
 static const double CS2 = 0.25;
+
+static int C19X[19], C19Y[19], C19Z[19];
+static double W19[19];
+static void init19(void) {
+    static const int e[19][3] = {{0, 0, 0},  {1, 0, 0},   {0, 1, 0},  {0, 0, 1},  {-1, 0, 0}, {0, -1, 0}, {0, 0, -1},
+                                 {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1},
+                                 {1, 0, -1}, {-1, 0, 1},  {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+    for (int i = 0; i < 19; ++i) {
+        C19X[i] = e[i][0];
+        C19Y[i] = e[i][1];
+        C19Z[i] = e[i][2];
+        int n = abs(e[i][0]) + abs(e[i][1]) + abs(e[i][2]);
+        W19[i] = n == 0 ? 1.0 / 3.0 : (n == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+    }
+}
 
 static char g_err[256];
 static void set_err(const char* m) {
@@ -80,7 +106,7 @@ static void m_d3q7(double* M) {
 }
 
 static int invert(const double* A, double* Ainv, int n) {
-    double a[64], b[64];
+    double a[400], b[400];
     memcpy(a, A, sizeof(double) * n * n);
     for (int i = 0; i < n * n; ++i) b[i] = (i / n == i % n) ? 1.0 : 0.0;
     for (int c = 0; c < n; ++c) {
@@ -114,6 +140,65 @@ void o3_lambda(double s1, double* L) {
             for (int q = 0; q < 7; ++q) acc += Mi[i * 7 + q] * s[q] * M[q * 7 + j];
             L[i * 7 + j] = acc;
         }
+}
+
+/* ---- D3Q19 raw-moment transform and Lambda with s2 on the second moments ---- */
+static void m_d3q19(double* M, int* second) {
+    /* rows: 1; cx cy cz; cx^2 cy^2 cz^2 cxcy cxcz cycz; cx^2cy cx^2cz cy^2cx
+     * cy^2cz cz^2cx cz^2cy; cx^2cy^2 cx^2cz^2 cy^2cz^2 */
+    for (int i = 0; i < 19; ++i) {
+        double x = C19X[i], y = C19Y[i], z = C19Z[i];
+        double r[19] = {1, x, y, z, x * x, y * y, z * z, x * y, x * z, y * z, x * x * y, x * x * z, y * y * x,
+                        y * y * z, z * z * x, z * z * y, x * x * y * y, x * x * z * z, y * y * z * z};
+        for (int q = 0; q < 19; ++q) M[q * 19 + i] = r[q];
+    }
+    for (int q = 0; q < 19; ++q) second[q] = (q >= 4 && q <= 9);
+}
+
+void o3_lambda19(double s2, double* L) {
+    init19();
+    double M[361], Mi[361];
+    int second[19];
+    m_d3q19(M, second);
+    invert(M, Mi, 19);
+    for (int i = 0; i < 19; ++i)
+        for (int j = 0; j < 19; ++j) {
+            double acc = 0.0;
+            for (int q = 0; q < 19; ++q) acc += Mi[i * 19 + q] * (second[q] ? s2 : 1.0) * M[q * 19 + j];
+            L[i * 19 + j] = acc;
+        }
+}
+
+/* h^eq of Sec. 3.4 on D3Q19: sigma_0 = (w0 - 1) p/cs^2 + rho0, sigma_i = w_i p/cs^2,
+ * plus w_i [c.u/cs^2 + (c.u)^2/(2 cs^4) - u.u/(2 cs^2)] */
+void o3_eq_flow(double rho0, double p, double ux, double uy, double uz, double* o) {
+    init19();
+    double uu = ux * ux + uy * uy + uz * uz;
+    for (int i = 0; i < 19; ++i) {
+        double cu = C19X[i] * ux + C19Y[i] * uy + C19Z[i] * uz;
+        double sig = i == 0 ? (W19[0] - 1.0) * 3.0 * p + rho0 : W19[i] * 3.0 * p;
+        o[i] = sig + W19[i] * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+    }
+}
+
+/* Flow macros (Sec. 3.4, sub-step units): u* = sum c h, f = -u*, F_b =
+ * [1 - q(phi)] f, u = u* + F_b/2, p = cs^2/(1 - w0) (sum_{i>0} h - w0 |u|^2/(2 cs^2)). */
+static void flow_macros3(const double* h, double phi, double* us, double* Fb, double* u, double* pr) {
+    double m[3] = {0.0, 0.0, 0.0}, rest = 0.0;
+    for (int i = 0; i < 19; ++i) {
+        m[0] += C19X[i] * h[i];
+        m[1] += C19Y[i] * h[i];
+        m[2] += C19Z[i] * h[i];
+        if (i) rest += h[i];
+    }
+    double solid = 1.0 - 0.5 * (1.0 - phi);
+    for (int a = 0; a < 3; ++a) {
+        us[a] = m[a];
+        Fb[a] = solid * (0.0 - m[a]);
+        u[a] = us[a] + 0.5 * Fb[a];
+    }
+    double cs2 = 1.0 / 3.0;
+    *pr = cs2 / (1.0 - W19[0]) * (rest - W19[0] * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) / (2.0 * cs2));
 }
 
 /* ---- anisotropy (Sec. 2), d = 3:
@@ -197,9 +282,12 @@ struct o3_state {
     double *pf, *pn, *pg, *a2;           /* post-collision, a_s^2 */
     double *phi, *C, *U, *H, *theta;     /* macros of time t */
     double *phi_prev, *Q_prev;
+    double *h, *hn, *ph;                 /* flow [19][N] */
+    double *u;                           /* [3][N] velocity of time t, main-step units */
+    double *Cu_prev, *Hu_prev, *Cu_t, *Hu_t; /* [3][N] */
     int hist_valid;
     long step;
-    double L5c[49], L5t[49];
+    double L5c[49], L5t[49], L19[361];
 };
 
 static double* alloc0(long n) { return (double*)calloc((size_t)n, sizeof(double)); }
@@ -207,8 +295,14 @@ static double* alloc0(long n) { return (double*)calloc((size_t)n, sizeof(double)
 o3_state* o3_create(const o3_params* p) {
     if (p->nx < 3 || p->ny < 3 || p->nz < 3) { set_err("grid smaller than 3x3x3"); return NULL; }
     if (p->walls < 0 || p->walls > 1) { set_err("walls must be 0 or 1"); return NULL; }
-    double rates[3] = {s1_phi(p, 1.0 + p->eps4), s1_solute(p), s1_heat(p)};
-    for (int i = 0; i < 3; ++i)
+    if (p->use_ns && (p->walls || p->n_sub < 1 || !(p->nu > 0))) {
+        set_err("melt flow needs a periodic domain, n_sub >= 1 and nu > 0");
+        return NULL;
+    }
+    init19();
+    double s2 = p->use_ns ? 1.0 / (3.0 * p->nu / p->n_sub + 0.5) : 1.0;
+    double rates[4] = {s1_phi(p, 1.0 + p->eps4), s1_solute(p), s1_heat(p), s2};
+    for (int i = 0; i < 4; ++i)
         if (!(rates[i] > 0.0 && rates[i] < 2.0)) { set_err("relaxation rate outside (0,2)"); return NULL; }
     o3_state* s = (o3_state*)calloc(1, sizeof(o3_state));
     s->p = *p;
@@ -220,6 +314,9 @@ o3_state* o3_create(const o3_params* p) {
     s->pf = alloc0(7 * N); s->pn = alloc0(7 * N); s->pg = alloc0(7 * N); s->a2 = alloc0(N);
     s->phi = alloc0(N); s->C = alloc0(N); s->U = alloc0(N); s->H = alloc0(N); s->theta = alloc0(N);
     s->phi_prev = alloc0(N); s->Q_prev = alloc0(N);
+    s->h = alloc0(19 * N); s->hn = alloc0(19 * N); s->ph = alloc0(19 * N); s->u = alloc0(3 * N);
+    s->Cu_prev = alloc0(3 * N); s->Hu_prev = alloc0(3 * N); s->Cu_t = alloc0(3 * N); s->Hu_t = alloc0(3 * N);
+    o3_lambda19(s2, s->L19);
     o3_lambda(s1_solute(p), s->L5c);
     o3_lambda(s1_heat(p), s->L5t);
     return s;
@@ -228,7 +325,8 @@ o3_state* o3_create(const o3_params* p) {
 void o3_destroy(o3_state* s) {
     if (!s) return;
     double* ptrs[] = {s->f, s->n, s->g, s->fn, s->nn, s->gn, s->pf, s->pn, s->pg, s->a2,
-                      s->phi, s->C, s->U, s->H, s->theta, s->phi_prev, s->Q_prev};
+                      s->phi, s->C, s->U, s->H, s->theta, s->phi_prev, s->Q_prev, s->h, s->hn, s->ph,
+                      s->u, s->Cu_prev, s->Hu_prev, s->Cu_t, s->Hu_t};
     for (size_t i = 0; i < sizeof ptrs / sizeof ptrs[0]; ++i) free(ptrs[i]);
     free(s);
 }
@@ -258,14 +356,16 @@ static void fill_walls(o3_state* s, double* pop) {
 }
 
 static void eq_phi(double phi, double* o) { for (int i = 0; i < 7; ++i) o[i] = W7[i] * phi; }
-static void eq_solute(double C, double phi, double U, double* o) {
+/* n^eq and g^eq of Secs. 3.2, 3.3 with the velocity u (main-step units) */
+static void eq_solute(double C, double phi, double U, const double* u, double* o) {
     double qU = 0.5 * (1.0 - phi) * U;
     o[0] = C + (W7[0] - 1.0) * qU;
-    for (int i = 1; i < 7; ++i) o[i] = W7[i] * qU;
+    for (int i = 1; i < 7; ++i) o[i] = W7[i] * qU + W7[i] * (CX[i] * C * u[0] + CY[i] * C * u[1] + CZ[i] * C * u[2]) / CS2;
 }
-static void eq_heat(double theta, double phi, int quintic, double* o) {
+static void eq_heat(double theta, double phi, int quintic, const double* u, double* o) {
+    double H = theta - 0.5 * h_of(phi, quintic);
     o[0] = W7[0] * theta - 0.5 * h_of(phi, quintic);
-    for (int i = 1; i < 7; ++i) o[i] = W7[i] * theta;
+    for (int i = 1; i < 7; ++i) o[i] = W7[i] * theta + W7[i] * (CX[i] * H * u[0] + CY[i] * H * u[1] + CZ[i] * H * u[2]) / CS2;
 }
 
 static void compute_macros(o3_state* s) {
@@ -292,6 +392,15 @@ static void compute_macros(o3_state* s) {
             s->theta[x] = p->theta0;
             s->H[x] = p->theta0 - 0.5 * h_of(ph, p->h_quintic);
         }
+        /* melt velocity of time t in main-step units: n_sub u' */
+        double u[3] = {0.0, 0.0, 0.0};
+        if (p->use_ns) {
+            double h[19], us[3], Fb[3], pr;
+            for (int i = 0; i < 19; ++i) h[i] = s->h[i * N + x];
+            flow_macros3(h, ph, us, Fb, u, &pr);
+            for (int a = 0; a < 3; ++a) u[a] *= p->n_sub;
+        }
+        for (int a = 0; a < 3; ++a) s->u[a * N + x] = u[a];
     }
 }
 
@@ -344,11 +453,22 @@ static void collide_node(o3_state* s, long x) {
         double c = -1.0 / (2.0 * sqrt(2.0)) * p->W0 * (1.0 + (1.0 - p->k) * U) * dphi / gn;
         J[0] = c * gx; J[1] = c * gy; J[2] = c * gz;
     }
-    /* solute lattice (Sec. 3.2), u = 0 */
+    /* velocity of time t and the backward differences of C u and H u */
+    double u[3] = {s->u[x], s->u[N + x], s->u[2 * N + x]}, dCu[3] = {0.0, 0.0, 0.0}, dHu[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < 3; ++a) {
+        s->Cu_t[a * N + x] = s->C[x] * u[a];
+        s->Hu_t[a * N + x] = s->H[x] * u[a];
+        if (s->hist_valid) {
+            dCu[a] = s->Cu_t[a * N + x] - s->Cu_prev[a * N + x];
+            dHu[a] = s->Hu_t[a * N + x] - s->Hu_prev[a * N + x];
+        }
+    }
+    /* solute lattice (Sec. 3.2): G = w c.[d_t(Cu)/cs^2 + U grad q + J/D] */
     double nv[7], neq[7], GC[7];
     for (int i = 0; i < 7; ++i) nv[i] = s->n[i * N + x];
-    eq_solute(s->C[x], ph, U, neq);
-    double V[3] = {U * (-0.5 * gx) + J[0] / p->D, U * (-0.5 * gy) + J[1] / p->D, U * (-0.5 * gz) + J[2] / p->D};
+    eq_solute(s->C[x], ph, U, u, neq);
+    double V[3] = {dCu[0] / CS2 + U * (-0.5 * gx) + J[0] / p->D, dCu[1] / CS2 + U * (-0.5 * gy) + J[1] / p->D,
+                   dCu[2] / CS2 + U * (-0.5 * gz) + J[2] / p->D};
     for (int i = 0; i < 7; ++i) GC[i] = W7[i] * (CX[i] * V[0] + CY[i] * V[1] + CZ[i] * V[2]);
     for (int i = 0; i < 7; ++i) {
         double acc = nv[i];
@@ -358,19 +478,60 @@ static void collide_node(o3_state* s, long x) {
         }
         s->pn[i * N + x] = acc;
     }
-    /* heat lattice (Sec. 3.3), u = 0 */
+    /* heat lattice (Sec. 3.3): G = w c.d_t(Hu)/cs^2 */
     if (p->use_t) {
-        double gv[7], geq[7];
+        double gv[7], geq[7], GT[7];
         for (int i = 0; i < 7; ++i) gv[i] = s->g[i * N + x];
-        eq_heat(th, ph, p->h_quintic, geq);
+        eq_heat(th, ph, p->h_quintic, u, geq);
+        for (int i = 0; i < 7; ++i) GT[i] = W7[i] * (CX[i] * dHu[0] + CY[i] * dHu[1] + CZ[i] * dHu[2]) / CS2;
         for (int i = 0; i < 7; ++i) {
             double acc = gv[i];
-            for (int j = 0; j < 7; ++j) acc -= s->L5t[i * 7 + j] * (gv[j] - geq[j]);
+            for (int j = 0; j < 7; ++j) {
+                acc -= s->L5t[i * 7 + j] * (gv[j] - geq[j]);
+                acc += ((i == j ? 1.0 : 0.0) - 0.5 * s->L5t[i * 7 + j]) * GT[j];
+            }
             s->pg[i * N + x] = acc;
         }
     }
     /* history of time t for the next step */
     s->Q_prev[x] = Q;
+}
+
+/* n_sub flow sub-steps (Sec. 3.4) at the frozen phi of time t (s->phi):
+ * post = h - Lambda (h - h^eq) + (I - Lambda/2) F, F_i = w_i c_i.F_b/cs^2,
+ * then periodic streaming. */
+static void flow_substeps(o3_state* s) {
+    const o3_params* p = &s->p;
+    long N = s->N;
+    int nx = s->nx, ny = s->ny, nz = s->nz;
+    for (int sub = 0; sub < p->n_sub; ++sub) {
+#pragma omp parallel for schedule(static)
+        for (long x = 0; x < N; ++x) {
+            double h[19], us[3], Fb[3], u[3], pr, heq[19], F[19];
+            for (int i = 0; i < 19; ++i) h[i] = s->h[i * N + x];
+            flow_macros3(h, s->phi[x], us, Fb, u, &pr);
+            o3_eq_flow(p->rho0, pr, u[0], u[1], u[2], heq);
+            for (int i = 0; i < 19; ++i) F[i] = W19[i] * 3.0 * (C19X[i] * Fb[0] + C19Y[i] * Fb[1] + C19Z[i] * Fb[2]);
+            for (int i = 0; i < 19; ++i) {
+                double acc = h[i];
+                for (int j = 0; j < 19; ++j) {
+                    acc -= s->L19[i * 19 + j] * (h[j] - heq[j]);
+                    acc += ((i == j ? 1.0 : 0.0) - 0.5 * s->L19[i * 19 + j]) * F[j];
+                }
+                s->ph[i * N + x] = acc;
+            }
+        }
+#pragma omp parallel for schedule(static)
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    long d = id3(s, x, y, z);
+                    for (int i = 0; i < 19; ++i)
+                        s->hn[(long)i * N + d] =
+                            s->ph[(long)i * N + id3(s, wrap(x - C19X[i], nx), wrap(y - C19Y[i], ny), wrap(z - C19Z[i], nz))];
+                }
+        double* t = s->h; s->h = s->hn; s->hn = t;
+    }
 }
 
 int o3_step(o3_state* s, long nsteps) {
@@ -397,10 +558,13 @@ int o3_step(o3_state* s, long nsteps) {
                     }
                 }
         memcpy(s->phi_prev, s->phi, sizeof(double) * N);
+        memcpy(s->Cu_prev, s->Cu_t, sizeof(double) * 3 * N);
+        memcpy(s->Hu_prev, s->Hu_t, sizeof(double) * 3 * N);
         double* tmp;
         tmp = s->f; s->f = s->fn; s->fn = tmp;
         tmp = s->n; s->n = s->nn; s->nn = tmp;
         tmp = s->g; s->g = s->gn; s->gn = tmp;
+        if (s->p.use_ns) flow_substeps(s);
         s->hist_valid = 1;
         s->step += 1;
     }
@@ -413,7 +577,8 @@ int o3_step(o3_state* s, long nsteps) {
  * phi, 3 sum_i w_i c_i phi(x + c_i) (weights 1/18 faces, 1/36 edges;
  * periodic wrap or clamped at the walls): f_i = w_i phi + w_i c_i.m1/cs^2
  * with m1 = -(cs^2/s1) grad phi - W0^2 N/tau0.  History reset. */
-int o3_set_fields(o3_state* s, const double* phi, const double* Cin, const double* thin) {
+int o3_set_fields(o3_state* s, const double* phi, const double* Cin, const double* thin, const double* uxin,
+                  const double* uyin, const double* uzin) {
     const o3_params* p = &s->p;
     long N = s->N;
     int nx = s->nx, ny = s->ny, nz = s->nz;
@@ -460,10 +625,17 @@ int o3_set_fields(o3_state* s, const double* phi, const double* Cin, const doubl
                 eq_phi(ph, e);
                 for (int i = 0; i < 7; ++i)
                     s->f[i * N + id] = e[i] + W7[i] * (CX[i] * V[0] + CY[i] * V[1] + CZ[i] * V[2]) / CS2;
-                eq_solute(C, ph, U, e);
+                double u[3] = {uxin ? uxin[id] : p->u0x, uyin ? uyin[id] : p->u0y, uzin ? uzin[id] : p->u0z};
+                if (!p->use_ns) u[0] = u[1] = u[2] = 0.0;
+                eq_solute(C, ph, U, u, e);
                 for (int i = 0; i < 7; ++i) s->n[i * N + id] = e[i];
-                eq_heat(th, ph, p->h_quintic, e);
+                eq_heat(th, ph, p->h_quintic, u, e);
                 for (int i = 0; i < 7; ++i) s->g[i * N + id] = p->use_t ? e[i] : 0.0;
+                if (p->use_ns) {  /* flow at equilibrium with p = 0 and u' = u/n_sub */
+                    double hq[19];
+                    o3_eq_flow(p->rho0, 0.0, u[0] / p->n_sub, u[1] / p->n_sub, u[2] / p->n_sub, hq);
+                    for (int i = 0; i < 19; ++i) s->h[(long)i * N + id] = hq[i];
+                }
             }
     s->hist_valid = 0;
     return 0;
@@ -482,14 +654,15 @@ int o3_init_seed(o3_state* s) {
                 double d = sqrt(dx * dx + dy * dy + dz * dz);
                 phi[id3(s, x, y, z)] = tanh((p->seed_R - d) / (sqrt(2.0) * p->W0));
             }
-    int rc = o3_set_fields(s, phi, NULL, NULL);
+    int rc = o3_set_fields(s, phi, NULL, NULL, NULL, NULL, NULL);
     free(phi);
     return rc;
 }
 
 long o3_step_count(const o3_state* s) { return s->step; }
 
-/* Four planes of N: phi, C, U, theta (x fastest, then y, then z). */
+/* Eight planes of N: phi, C, U, theta, ux, uy, uz (main-step units), p
+ * (main-step units, n_sub^2 p'); x fastest, then y, then z. */
 int o3_get_fields(o3_state* s, double* out) {
     compute_macros(s);
     long N = s->N;
@@ -497,6 +670,17 @@ int o3_get_fields(o3_state* s, double* out) {
     memcpy(out + N, s->C, sizeof(double) * N);
     memcpy(out + 2 * N, s->U, sizeof(double) * N);
     memcpy(out + 3 * N, s->theta, sizeof(double) * N);
+    memcpy(out + 4 * N, s->u, sizeof(double) * 3 * N);
+    for (long x = 0; x < N; ++x) {
+        double pr = 0.0;
+        if (s->p.use_ns) {
+            double h[19], us[3], Fb[3], u[3];
+            for (int i = 0; i < 19; ++i) h[i] = s->h[i * N + x];
+            flow_macros3(h, s->phi[x], us, Fb, u, &pr);
+            pr *= (double)s->p.n_sub * s->p.n_sub;
+        }
+        out[7 * N + x] = pr;
+    }
     return 0;
 }
 

@@ -33,15 +33,18 @@ class O3Params(ctypes.Structure):
         "nx", "ny", "nz", "use_t", "walls", "h_quintic", "c_init_U", "grad_max_iter")] + [
         (n, ctypes.c_double) for n in (
             "W0", "tau0", "eps4", "lambda_", "Mcinf", "k", "D", "alpha", "theta0", "U0", "C0",
-            "seed_R", "seed_x", "seed_y", "seed_z", "grad_tol", "fixed_as")]
+            "seed_R", "seed_x", "seed_y", "seed_z", "grad_tol", "fixed_as")] + [
+        (n, ctypes.c_int) for n in ("use_ns", "n_sub")] + [(n, ctypes.c_double) for n in (
+            "nu", "rho0", "u0x", "u0y", "u0z")]
 
 
 DEFAULTS = dict(nx=24, ny=24, nz=24, use_t=1, walls=0, h_quintic=0, c_init_U=0, grad_max_iter=100,
                 W0=1.0, tau0=20.0, eps4=0.05, lambda_=0.0, Mcinf=0.0, k=0.15, D=0.1, alpha=0.1,
                 theta0=0.0, U0=0.0, C0=1.0, seed_R=5.0, seed_x=None, seed_y=None, seed_z=None,
-                grad_tol=1e-14, fixed_as=0.0)
+                grad_tol=1e-14, fixed_as=0.0, use_ns=0, n_sub=1, nu=0.1, rho0=1.0, u0x=0.0, u0y=0.0, u0z=0.0)
 _GPU_ONLY = {"precision", "name", "steps"}
 FIELDS = ("phi", "C", "U", "theta")
+FLOW_FIELDS = ("ux", "uy", "uz", "p")
 
 _lib = None
 
@@ -64,7 +67,9 @@ def load():
     lib.o3_destroy.argtypes = [vp]
     lib.o3_last_error.restype = ctypes.c_char_p
     lib.o3_init_seed.argtypes = [vp]
-    lib.o3_set_fields.argtypes = [vp, dp, dp, dp]
+    lib.o3_set_fields.argtypes = [vp, dp, dp, dp, dp, dp, dp]
+    lib.o3_eq_flow.argtypes = [d, d, d, d, d, dp]
+    lib.o3_lambda19.argtypes = [d, dp]
     lib.o3_step.argtypes = [vp, ctypes.c_long]
     lib.o3_get_fields.argtypes = [vp, dp]
     lib.o3_reduce.argtypes = [vp, dp]
@@ -112,6 +117,18 @@ def local_gradient(cfg, m1):
     return o
 
 
+def eq_flow(rho0, p, ux, uy, uz):
+    o = np.zeros(19)
+    load().o3_eq_flow(rho0, p, ux, uy, uz, _dptr(o))
+    return o
+
+
+def lam19(s2):
+    o = np.zeros(361)
+    load().o3_lambda19(s2, _dptr(o))
+    return o.reshape(19, 19)
+
+
 def lam(s1):
     o = np.zeros(49)
     load().o3_lambda(s1, _dptr(o))
@@ -146,8 +163,8 @@ class Oracle3:
         self.lib.o3_init_seed(self.h)
         return self
 
-    def set_fields(self, phi, C=None, theta=None):
-        arrs = [self._plane(a) for a in (phi, C, theta)]
+    def set_fields(self, phi, C=None, theta=None, ux=None, uy=None, uz=None):
+        arrs = [self._plane(a) for a in (phi, C, theta, ux, uy, uz)]
         self._keep = arrs
         self.lib.o3_set_fields(self.h, *[_dptr(a) for a in arrs])
         return self
@@ -162,9 +179,9 @@ class Oracle3:
 
     def fields(self) -> dict:
         N = int(np.prod(self.shape))
-        out = np.zeros(4 * N)
+        out = np.zeros(8 * N)
         self.lib.o3_get_fields(self.h, _dptr(out))
-        return {k: out[i * N:(i + 1) * N].reshape(self.shape) for i, k in enumerate(FIELDS)}
+        return {k: out[i * N:(i + 1) * N].reshape(self.shape) for i, k in enumerate(FIELDS + FLOW_FIELDS)}
 
     def reduce(self) -> dict:
         out = np.zeros(10)

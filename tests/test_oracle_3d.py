@@ -127,3 +127,98 @@ def test_seed_keeps_cubic_symmetry(seed_run):
             np.testing.assert_allclose(np.transpose(a, perm), a, atol=1e-12)
     tips = r1["tip_s"]
     assert np.ptp(tips) < 1e-9 and tips[0] > 5.0
+
+
+# ---------------------------------------------------------------------------
+# 3-D melt flow (D3Q19, periodic)
+# ---------------------------------------------------------------------------
+
+def _c19():
+    e = [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1), (-1, 0, 0), (0, -1, 0), (0, 0, -1), (1, 1, 0), (-1, -1, 0),
+         (1, -1, 0), (-1, 1, 0), (1, 0, 1), (-1, 0, -1), (1, 0, -1), (-1, 0, 1), (0, 1, 1), (0, -1, -1),
+         (0, 1, -1), (0, -1, 1)]
+    return np.array(e, float)
+
+
+def test_d3q19_equilibrium_moments():
+    """Sum h^eq = rho0, sum c h^eq = u, sum c c h^eq = p I + u u (Sec. 3.4)."""
+    c = _c19()
+    rng = np.random.default_rng(9)
+    for _ in range(10):
+        rho0, p = 1.0, rng.uniform(-1e-3, 1e-3)
+        u = rng.uniform(-0.05, 0.05, 3)
+        h = O.eq_flow(rho0, p, *u)
+        assert h.sum() == pytest.approx(rho0, abs=1e-15)
+        np.testing.assert_allclose(c.T @ h, u, atol=1e-16)
+        np.testing.assert_allclose((c.T * h) @ c, p * np.eye(3) + np.outer(u, u), atol=1e-16)
+
+
+def test_d3q19_lambda_relaxes_second_moments_at_s2():
+    """The collision matrix leaves the conserved and higher moments at rate 1
+    and the six second moments c_a c_b at s2: applied to populations whose
+    only nonzero raw moment is one second moment, it scales them by s2."""
+    c = _c19()
+    s2 = 1.3
+    L = O.lam19(s2)
+    w = np.where(np.abs(c).sum(1) == 0, 1 / 3, np.where(np.abs(c).sum(1) == 1, 1 / 18, 1 / 36))
+    # a traceless shear population vector: w_i c_x c_y (moments: only xy and higher-order combos vanish)
+    v = w * c[:, 0] * c[:, 1]
+    np.testing.assert_allclose(L @ v, s2 * v, atol=1e-14)
+    # mass and momentum directions are untouched by Lambda - I's complement: L c_x w = c_x w (rate 1)
+    np.testing.assert_allclose(L @ (w * c[:, 0]), w * c[:, 0], atol=1e-14)
+
+
+def _flow_cfg(n, **kw):
+    cfg = dict(nx=4, ny=n, nz=4, use_ns=1, n_sub=3, nu=0.3, lambda_=0.0, theta0=0.0, alpha=0.1, D=0.1, k=0.15)
+    cfg.update(kw)
+    return cfg
+
+
+def test_shear_wave_decays_at_nu():
+    """Liquid (phi = -1): u_x = A sin(k y) decays at nu k^2 per main step
+    (three sub-steps of nu/3 each), at second order in k."""
+    errs = []
+    for n in (16, 32):
+        k = 2 * math.pi / n
+        y = np.arange(n)
+        ux = 0.01 * np.sin(k * y)[None, :, None] + np.zeros((4, 1, 4))
+        o = O.Oracle3(_flow_cfg(n)).set_fields(-np.ones((4, n, 4)), None, None, ux, 0 * ux, 0 * ux)
+        o.step(2)
+        a1 = 2 * np.mean(o.fields()["ux"] * np.sin(k * y)[None, :, None])
+        m = 20 if n == 16 else 80
+        o.step(m)
+        a2 = 2 * np.mean(o.fields()["ux"] * np.sin(k * y)[None, :, None])
+        errs.append(abs(-math.log(a2 / a1) / m / (0.3 * k * k) - 1))
+    assert errs[0] < 2e-2 and errs[0] / errs[1] > 3.0, errs
+
+
+def test_solid_stops_the_flow():
+    """phi = +1 everywhere: the diffuse force cancels the momentum in the
+    first sub-step, so the melt velocity is zero after one main step."""
+    o = O.Oracle3(_flow_cfg(8, u0x=0.02, u0y=-0.01)).set_fields(np.ones((4, 8, 4)))
+    assert abs(o.fields()["ux"]).max() > 0.005  # u* (3 - phi)/4 of the set velocity, before any step
+    o.step(1)
+    f = o.fields()
+    for key in ("ux", "uy", "uz"):
+        assert np.abs(f[key]).max() < 1e-17
+
+
+def test_advected_heat_mode_keeps_alpha_and_u():
+    """Uniform flow u0 along x through liquid: a theta mode travels at u0 and
+    decays at alpha k^2 (the c.Hu/cs^2 equilibrium with the D3Q7 cs^2 and the
+    d_t(Hu) correction)."""
+    n, u0, alpha = 32, 0.05, 0.1
+    k = 2 * math.pi / n
+    x = np.arange(n)
+    cfg = dict(_flow_cfg(4, nx=n, ny=4, nz=4, u0x=u0, alpha=alpha))
+    th = -0.3 + 0.01 * np.sin(k * x)[None, None, :] + np.zeros((4, 4, 1))
+    o = O.Oracle3(cfg).set_fields(-np.ones((4, 4, n)), None, th)
+    o.step(2)
+    y1 = np.mean((o.fields()["theta"] + 0.3) * np.exp(-1j * k * x)[None, None, :])
+    m = 60
+    o.step(m)
+    y2 = np.mean((o.fields()["theta"] + 0.3) * np.exp(-1j * k * x)[None, None, :])
+    rate = -math.log(abs(y2 / y1)) / m / (alpha * k * k) - 1
+    vel = -np.angle(y2 / y1) / m / k
+    assert abs(rate) < 1e-2
+    assert vel == pytest.approx(u0, rel=1e-2)

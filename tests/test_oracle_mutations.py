@@ -106,6 +106,10 @@ MUTATIONS_3D = [
      T3 + "test_diffusion_mode_decays_at_the_diffusivity"),
     ("3-D: plain streaming for phi", "(s->pf[o + src] - s->f[o + d]) / s->a2[src];", "(s->pf[o + src] - s->f[o + d]);",
      T3 + "test_phase_field_mode_decay_with_fixed_anisotropy"),
+    ("3-D flow: second moments relaxed at 1", "for (int q = 0; q < 19; ++q) second[q] = (q >= 4 && q <= 9);",
+     "for (int q = 0; q < 19; ++q) second[q] = 0;", T3 + "test_shear_wave_decays_at_nu"),
+    ("3-D: heat equilibrium with cs^2 = 1/3", "(CX[i] * H * u[0] + CY[i] * H * u[1] + CZ[i] * H * u[2]) / CS2;",
+     "(CX[i] * H * u[0] + CY[i] * H * u[1] + CZ[i] * H * u[2]) * 3.0;", T3 + "test_advected_heat_mode_keeps_alpha_and_u"),
     ("3-D: anisotropy strength", "out[1 + a] = g2 * as * (4.0 * eps * dsum);", "out[1 + a] = g2 * as * (3.0 * eps * dsum);",
      T3 + "test_torque_vector_is_the_gradient_of_a_s"),
 ]
