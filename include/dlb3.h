@@ -2,13 +2,19 @@
  * dlb3.h -- C ABI of the three-dimensional phase-field, solute and heat
  * lattices (D3Q7) of the diffuse-interface lattice Boltzmann method of
  * Zhan et al., arXiv:2209.01444 (Sec. 2 anisotropy a_s and N for any d,
- * Secs. 3.1-3.3 with a general lattice sound speed).  No melt flow.
+ * Secs. 3.1-3.3 with a general lattice sound speed), and optionally the melt
+ * flow of Sec. 3.4 on D3Q19 in a periodic domain.
  * Exported by libdlb.so beside the 2-D solver (dlb.h).
  *
  * Lattice: c0 = 0, c1..c3 = +x, +y, +z, c4..c6 = -x, -y, -z; cs^2 = 1/4,
  * w0 = 1/4, w1..6 = 1/8; S = diag(1, s1, s1, s1, 1, 1, 1) for each lattice.
  * Crystal axes along the lattice axes.  One main step: every lattice reads
  * the fields of time t (Jacobi), phi with the modified streaming of Sec. 3.1.
+ * Melt flow (use_ns): D3Q19 (c0, six faces, twelve edges; w = 1/3, 1/18,
+ * 1/36; cs^2 = 1/3), equilibrium, pressure and diffuse force of Sec. 3.4
+ * (varphi = 0), MRT with s2 = 1/(3 nu/n_sub + 1/2) on the six second moments
+ * and 1 on the rest; n_sub sub-steps per main step at the frozen phi of time
+ * t; the solute and heat equilibria take u = n_sub u'.
  *
  * Ownership: the caller owns the device state buffer (dlb3_state_bytes) and
  * the stream; the library owns only the small host handle.  Every call is
@@ -45,12 +51,17 @@ typedef struct dlb3_params {
     double theta0, U0, C0;       /* initial temperature, supersaturation, C      */
     double seed_R, seed_x, seed_y, seed_z; /* spherical seed (lu, node coords)   */
     double grad_tol;             /* tolerance of the gradient fixed point (0: default) */
+    int32_t use_ns;              /* 1: melt flow (needs walls = 0)                */
+    int32_t n_sub;               /* flow sub-steps per main step (two-time-scaling) */
+    double nu, rho0;             /* viscosity (lu^2 per main step), density       */
+    double u0[3];                /* initial velocity (lu per main step); the Mach
+                                    number |u0| sqrt(3)/n_sub must stay below 0.3 */
 } dlb3_params;
 
 typedef struct dlb3_solver* dlb3_handle;
 
 /* Bytes of device state for p (populations, history, a staging area of
- * four double planes); 0 if p is invalid (message in dlb3_last_error). */
+ * eight double planes); 0 if p is invalid (message in dlb3_last_error). */
 size_t dlb3_state_bytes(const dlb3_params* p);
 
 /* Bind a solver to a caller-owned device buffer of at least
@@ -63,16 +74,19 @@ int dlb3_destroy(dlb3_handle h);
 int dlb3_init_seed(dlb3_handle h);
 
 /* Every lattice at equilibrium at the given fields (host arrays of nx*ny*nz
- * doubles, x fastest then y then z; C and theta nullable: defaults from the
- * parameters), the phi populations with the first moment that makes the
- * local scheme return the isotropic D3Q19 central difference of phi.  The
- * history is reset (time derivatives zero on the next step). */
-int dlb3_set_fields(dlb3_handle h, const double* phi, const double* C, const double* theta);
+ * doubles, x fastest then y then z; C, theta and the velocity components
+ * nullable: defaults from the parameters), the phi populations with the first
+ * moment that makes the local scheme return the isotropic D3Q19 central
+ * difference of phi; the flow at p = 0 and u' = u/n_sub.  The history is
+ * reset (time derivatives zero on the next step). */
+int dlb3_set_fields(dlb3_handle h, const double* phi, const double* C, const double* theta, const double* ux,
+                    const double* uy, const double* uz);
 
 /* n >= 0 main steps. */
 int dlb3_step(dlb3_handle h, int64_t n);
 
-/* phi, C, U, theta into host out (4 planes of nx*ny*nz doubles). */
+/* phi, C, U, theta, ux, uy, uz (lu per main step; 0 without flow) and p
+ * (main-step units) into host out (8 planes of nx*ny*nz doubles). */
 int dlb3_get_fields(dlb3_handle h, double* out);
 
 /* out[0..9]: sum C, sum H, solid fraction sum((1 + phi)/2)/N, non-finite

@@ -11,11 +11,19 @@
 //   rest: w0 (zeroth-order part),  +-a: w1 (zeroth-order part) +- b_a
 // with b_a collecting the first-order terms, written out below.
 //
+// Melt flow (D3Q19, periodic): every rate but the six second-moment ones is
+// 1, so a collision keeps h^eq + (1 - s2) P2(h - h^eq) + F/2, where P2 maps
+// the non-equilibrium second moments Pi_ab back to populations: Pi_aa puts
+// -Pi_aa on the rest and +Pi_aa/2 on the two faces along a; Pi_ab (a != b)
+// puts +-Pi_ab/4 on the four edges in the ab plane (sign of c_a c_b).
+//
 // State (caller's buffer): pop[2] (ping-pong), each [nz][21][ny][nx] with the
 // layers padded to 64 elements -- the 21 populations (phi 0-6, C 7-13, H
 // 14-20) of one z-layer lie together, so a workgroup's loads and stores stay
-// within a few megabytes; hist[2][N] (phi, Q of the previous step); staging[4]
-// double planes (fields in and out, reduction partials).
+// within a few megabytes; flow[2] (with use_ns), each [nz][19][ny][nx], h_0
+// stored as h_0 - rho0; hist[8][N] (phi, Q, C u, H u of the previous step;
+// after the phi/C/theta kernel hist[0] holds phi of time t for the flow
+// sub-steps); staging[8] double planes (fields in and out, reduction partials).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -37,7 +45,13 @@ struct K3 {
     long long lp;     // elements per population layer (>= nx ny, 64-multiple)
     int use_t, h_quintic, grad_iters;
     double W2t, inv_tau0, eps4, lambda, Mcinf, k, invD, s1c, s1t, jat, grad_tol2, theta0;
+    double nsub_d, s2u;  // flow sub-steps per main step, flow relaxation rate
 };
+
+// D3Q19 links: rest, faces +x +y +z -x -y -z, edges (xy) ++ -- +- -+, (xz) ++ -- +- -+, (yz) ++ -- +- -+
+static constexpr int EX19[19] = {0, 1, 0, 0, -1, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+static constexpr int EY19[19] = {0, 0, 1, 0, 0, -1, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+static constexpr int EZ19[19] = {0, 0, 0, 1, 0, 0, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
 
 __device__ __forceinline__ bool node3(const K3& kp, int& x, int& y, int& z) {
     x = (int)(blockIdx.x % kp.nbx) * BX + threadIdx.x;
@@ -51,6 +65,10 @@ __device__ __forceinline__ size_t id3(const K3& kp, int x, int y, int z) {
 // Address of population 0 of node (x, y, z); population q is q * lp further.
 __device__ __forceinline__ size_t base3(const K3& kp, int x, int y, int z) {
     return (size_t)z * 21 * (size_t)kp.lp + (size_t)y * kp.nx + x;
+}
+// Address of flow population 0 of node (x, y, z) ([nz][19][ny][nx] layers).
+__device__ __forceinline__ size_t fbase3(const K3& kp, int x, int y, int z) {
+    return (size_t)z * 19 * (size_t)kp.lp + (size_t)y * kp.nx + x;
 }
 __device__ __forceinline__ bool is_wall3(const K3& kp, int x, int y, int z) {
     return x == 0 || y == 0 || z == 0 || x == kp.nx - 1 || y == kp.ny - 1 || z == kp.nz - 1;
@@ -130,9 +148,9 @@ __device__ __forceinline__ long long dest3(const K3& kp, int x, int y, int z, in
 }
 
 // One main step at every node: collide phi, C, theta (Secs. 3.1-3.3), push.
-template <class T, bool WALLS>
+template <class T, bool WALLS, bool NS>
 __global__ __launch_bounds__(BX* BY) void k3_step(const K3 kp, const T* __restrict__ pin, T* __restrict__ pout,
-                                                  T* __restrict__ hist, int hist_valid) {
+                                                  const T* __restrict__ hin, T* __restrict__ hist, int hist_valid) {
     int x, y, z;
     if (!node3(kp, x, y, z)) return;
     const size_t P = (size_t)kp.plane, LP = (size_t)kp.lp;
@@ -154,6 +172,24 @@ __global__ __launch_bounds__(BX* BY) void k3_step(const K3 kp, const T* __restri
     const T theta = kp.use_t ? H + T(0.5) * hphi : T(kp.theta0);
     const T U = (T(2) * C / (T(1) + k - (T(1) - k) * phi) - T(1)) / (T(1) - k);
 
+    // melt velocity of time t in main-step units: n_sub (3 - phi)/4 u*
+    T u[3] = {T(0), T(0), T(0)};
+    if constexpr (NS) {
+        const size_t fb = fbase3(kp, x, y, z);
+        T m[3] = {T(0), T(0), T(0)};
+#pragma unroll
+        for (int i = 1; i < 19; ++i) {
+            const T h = hin[i * LP + fb];
+            if (EX19[i]) m[0] += EX19[i] > 0 ? h : -h;
+            if (EY19[i]) m[1] += EY19[i] > 0 ? h : -h;
+            if (EZ19[i]) m[2] += EZ19[i] > 0 ? h : -h;
+        }
+        const T fac = T(kp.nsub_d) * (T(3) - phi) * T(0.25);
+        u[0] = m[0] * fac;
+        u[1] = m[1] * fac;
+        u[2] = m[2] * fac;
+    }
+
     const T m1[3] = {f[1] - f[4], f[2] - f[5], f[3] - f[6]};
     T gr[3], a, N[3];
     local_grad3<T>(kp, m1, gr, a, N);
@@ -169,6 +205,19 @@ __global__ __launch_bounds__(BX* BY) void k3_step(const K3 kp, const T* __restri
     }
     hist[idx] = phi;
     hist[P + idx] = Q;
+    T dCu[3] = {T(0), T(0), T(0)}, dHu[3] = {T(0), T(0), T(0)};
+    if constexpr (NS) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const T Cu = C * u[d], Hu = H * u[d];
+            if (hist_valid) {
+                dCu[d] = Cu - hist[(2 + d) * P + idx];
+                dHu[d] = Hu - hist[(5 + d) * P + idx];
+            }
+            hist[(2 + d) * P + idx] = Cu;
+            hist[(5 + d) * P + idx] = Hu;
+        }
+    }
 
     // phi: rest w0 (phi + A), links w1 (phi + A) +- [(1 - s1) m1/2 - (1 - s1/2) N/(8 a^2)]
     T pf[7];
@@ -195,8 +244,8 @@ __global__ __launch_bounds__(BX* BY) void k3_step(const K3 kp, const T* __restri
             J[2] = c * gr[2];
         }
     }
-    // solute (u = 0): rest C - (1 - w0) qU, links w1 qU +- [(1 - s1c) m1/2 + (1 - s1c/2) V/8],
-    // V = U grad q + J/D with grad q = -grad phi/2
+    // solute: rest C - (1 - w0) qU, links w1 qU +- [Cu/2 + (1 - s1c)(m1 - Cu)/2 + (1 - s1c/2) V/8],
+    // V = d_t(Cu)/cs^2 + U grad q + J/D with grad q = -grad phi/2
     T pn[7];
     {
         const T s1c = T(kp.s1c), qU = T(0.5) * (T(1) - phi) * U;
@@ -204,20 +253,23 @@ __global__ __launch_bounds__(BX* BY) void k3_step(const K3 kp, const T* __restri
         pn[0] = C - T(0.75) * qU;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            const T V = T(-0.5) * U * gr[d] + J[d] * T(kp.invD);
-            const T b = c1 * (n[1 + d] - n[4 + d]) + cV * V;
+            const T Cu = C * u[d];
+            const T V = T(4) * dCu[d] + T(-0.5) * U * gr[d] + J[d] * T(kp.invD);
+            const T b = T(0.5) * Cu + c1 * ((n[1 + d] - n[4 + d]) - Cu) + cV * V;
             pn[1 + d] = T(0.125) * qU + b;
             pn[4 + d] = T(0.125) * qU - b;
         }
     }
-    // heat (u = 0): rest w0 theta - h/2, links w1 theta +- (1 - s1t) m1/2
+    // heat: rest w0 theta - h/2, links w1 theta +- [Hu/2 + (1 - s1t)(m1 - Hu)/2 + (1 - s1t/2) d_t(Hu)/2]
     T pg[7];
     {
-        const T c1 = (T(1) - T(kp.s1t)) * T(0.5);
+        const T s1t = T(kp.s1t);
+        const T c1 = (T(1) - s1t) * T(0.5), cG = (T(1) - T(0.5) * s1t) * T(0.5);
         pg[0] = T(0.25) * theta - T(0.5) * hphi;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            const T b = c1 * (g[1 + d] - g[4 + d]);
+            const T Hu = H * u[d];
+            const T b = T(0.5) * Hu + c1 * ((g[1 + d] - g[4 + d]) - Hu) + cG * dHu[d];
             pg[1 + d] = T(0.125) * theta + b;
             pg[4 + d] = T(0.125) * theta - b;
         }
@@ -239,6 +291,73 @@ __global__ __launch_bounds__(BX* BY) void k3_step(const K3 kp, const T* __restri
     }
 }
 
+// One melt-flow sub-step (Sec. 3.4, D3Q19, periodic) at the frozen phi of
+// time t (hist[0]), push streaming.
+template <class T>
+__global__ __launch_bounds__(BX* BY) void k3_flow(const K3 kp, const T* __restrict__ hin, T* __restrict__ hout,
+                                                  const T* __restrict__ phi_t) {
+    int x, y, z;
+    if (!node3(kp, x, y, z)) return;
+    const size_t LP = (size_t)kp.lp;
+    const size_t fb = fbase3(kp, x, y, z);
+    T h[19];
+#pragma unroll
+    for (int i = 0; i < 19; ++i) h[i] = hin[i * LP + fb];
+    const T phi = phi_t[id3(kp, x, y, z)];
+    T m[3] = {T(0), T(0), T(0)}, rest = T(0);
+#pragma unroll
+    for (int i = 1; i < 19; ++i) {
+        rest += h[i];
+        m[0] += T(EX19[i]) * h[i];
+        m[1] += T(EY19[i]) * h[i];
+        m[2] += T(EZ19[i]) * h[i];
+    }
+    const T solid = T(0.5) * (T(1) + phi);  // 1 - q(phi); f = -u*
+    T Fb[3], u[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        Fb[d] = -solid * m[d];
+        u[d] = m[d] + T(0.5) * Fb[d];
+    }
+    const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const T p = T(0.5) * (rest - T(0.5) * uu);  // cs^2/(1 - w0) (rest - w0 |u|^2/(2 cs^2))
+    T heq[19], Pi[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+        const int ax = EX19[i], ay = EY19[i], az = EZ19[i];
+        const int nn = ax * ax + ay * ay + az * az;
+        const T w = nn == 0 ? T(1.0 / 3.0) : (nn == 1 ? T(1.0 / 18.0) : T(1.0 / 36.0));
+        const T cu = T(ax) * u[0] + T(ay) * u[1] + T(az) * u[2];
+        const T sig = i == 0 ? T(-2) * p : w * T(3) * p;
+        heq[i] = sig + w * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * uu);
+        const T dn = h[i] - heq[i];
+        Pi[0] += T(ax * ax) * dn;
+        Pi[1] += T(ay * ay) * dn;
+        Pi[2] += T(az * az) * dn;
+        Pi[3] += T(ax * ay) * dn;
+        Pi[4] += T(ax * az) * dn;
+        Pi[5] += T(ay * az) * dn;
+    }
+    const T r = T(1) - T(kp.s2u);
+    const int xp = x + 1 == kp.nx ? 0 : x + 1, xm = x == 0 ? kp.nx - 1 : x - 1;
+    const int yp = y + 1 == kp.ny ? 0 : y + 1, ym = y == 0 ? kp.ny - 1 : y - 1;
+    const int zp = z + 1 == kp.nz ? 0 : z + 1, zm = z == 0 ? kp.nz - 1 : z - 1;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+        const int ax = EX19[i], ay = EY19[i], az = EZ19[i];
+        const int nn = ax * ax + ay * ay + az * az;
+        const T w = nn == 0 ? T(1.0 / 3.0) : (nn == 1 ? T(1.0 / 18.0) : T(1.0 / 36.0));
+        T post = heq[i] + T(0.5) * (w * T(3) * (T(ax) * Fb[0] + T(ay) * Fb[1] + T(az) * Fb[2]));
+        if (nn == 0) post += r * -((Pi[0] + Pi[1]) + Pi[2]);
+        else if (nn == 1) post += r * T(0.5) * (ax ? Pi[0] : (ay ? Pi[1] : Pi[2]));
+        else post += r * T(0.25) * (az == 0 ? T(ax * ay) * Pi[3] : (ay == 0 ? T(ax * az) * Pi[4] : T(ay * az) * Pi[5]));
+        const int X = ax > 0 ? xp : (ax < 0 ? xm : x);
+        const int Y = ay > 0 ? yp : (ay < 0 ? ym : y);
+        const int Z = az > 0 ? zp : (az < 0 ? zm : z);
+        hout[i * LP + fbase3(kp, X, Y, Z)] = post;
+    }
+}
+
 // Spherical seed into a double plane.
 __global__ __launch_bounds__(BX* BY) void k3_seed(const K3 kp, double R, double cx, double cy, double cz,
                                                   double W0, double* __restrict__ phi) {
@@ -251,10 +370,13 @@ __global__ __launch_bounds__(BX* BY) void k3_seed(const K3 kp, double R, double 
 // Equilibrium at the given fields; phi populations with the first moment
 // m1 = -(cs^2/s1) grad phi - W0^2 N/tau0 of the isotropic D3Q19 central
 // difference of phi (periodic wrap or clamped at walls).
-template <class T, bool WALLS>
+template <class T, bool WALLS, bool NS>
 __global__ __launch_bounds__(BX* BY) void k3_set(const K3 kp, const double* __restrict__ phi,
                                                  const double* __restrict__ Cin, const double* __restrict__ thin,
-                                                 int c_init_U, double U0, double C0, T* __restrict__ pop) {
+                                                 const double* __restrict__ uxin, const double* __restrict__ uyin,
+                                                 const double* __restrict__ uzin, double u0x, double u0y, double u0z,
+                                                 int c_init_U, double U0, double C0, T* __restrict__ pop,
+                                                 T* __restrict__ flow) {
     int x, y, z;
     if (!node3(kp, x, y, z)) return;
     const size_t idx = id3(kp, x, y, z);
@@ -295,23 +417,42 @@ __global__ __launch_bounds__(BX* BY) void k3_set(const K3 kp, const double* __re
     const double U = (2.0 * C / (1.0 + k - (1.0 - k) * ph) - 1.0) / (1.0 - k);
     const double qU = 0.5 * (1.0 - ph) * U;
     const double hp = h_of3(ph, kp.h_quintic);
+    double u[3] = {0.0, 0.0, 0.0};
+    if (NS) {
+        u[0] = uxin ? uxin[idx] : u0x;
+        u[1] = uyin ? uyin[idx] : u0y;
+        u[2] = uzin ? uzin[idx] : u0z;
+    }
+    const double H = th - 0.5 * hp;
     const size_t LP = (size_t)kp.lp, o = base3(kp, x, y, z);
     pop[o] = T(0.25 * ph);
     pop[7 * LP + o] = T(C - 0.75 * qU);
     pop[14 * LP + o] = T(kp.use_t ? 0.25 * th - 0.5 * hp : 0.0);
     for (int d = 0; d < 3; ++d) {
+        // w1 c.(C u)/cs^2 = +-(C u)/2 on the D3Q7 links
         pop[(1 + d) * LP + o] = T(0.125 * ph + 0.5 * m1[d]);
         pop[(4 + d) * LP + o] = T(0.125 * ph - 0.5 * m1[d]);
-        pop[(8 + d) * LP + o] = T(0.125 * qU);
-        pop[(11 + d) * LP + o] = T(0.125 * qU);
-        pop[(15 + d) * LP + o] = T(kp.use_t ? 0.125 * th : 0.0);
-        pop[(18 + d) * LP + o] = T(kp.use_t ? 0.125 * th : 0.0);
+        pop[(8 + d) * LP + o] = T(0.125 * qU + 0.5 * C * u[d]);
+        pop[(11 + d) * LP + o] = T(0.125 * qU - 0.5 * C * u[d]);
+        pop[(15 + d) * LP + o] = T(kp.use_t ? 0.125 * th + 0.5 * H * u[d] : 0.0);
+        pop[(18 + d) * LP + o] = T(kp.use_t ? 0.125 * th - 0.5 * H * u[d] : 0.0);
+    }
+    if constexpr (NS) {  // flow at p = 0, u' = u/n_sub (h_0 shifted by -rho0)
+        const double v[3] = {u[0] / kp.nsub_d, u[1] / kp.nsub_d, u[2] / kp.nsub_d};
+        const double vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+        const size_t fb = fbase3(kp, x, y, z);
+        for (int i = 0; i < 19; ++i) {
+            const int nn = EX19[i] * EX19[i] + EY19[i] * EY19[i] + EZ19[i] * EZ19[i];
+            const double w = nn == 0 ? 1.0 / 3.0 : (nn == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+            const double cu = EX19[i] * v[0] + EY19[i] * v[1] + EZ19[i] * v[2];
+            flow[i * LP + fb] = T(w * (3.0 * cu + 4.5 * cu * cu - 1.5 * vv));
+        }
     }
 }
 
-template <class T, bool WALLS>
-__device__ __forceinline__ void macros3(const K3& kp, const T* __restrict__ pop, int x, int y, int z,
-                                        double* m) {
+template <class T, bool WALLS, bool NS>
+__device__ __forceinline__ void macros3(const K3& kp, const T* __restrict__ pop, const T* __restrict__ flow, int x,
+                                        int y, int z, double* m) {
     const size_t LP = (size_t)kp.lp;
     const size_t src = (WALLS && is_wall3(kp, x, y, z)) ? inward3(kp, x, y, z) : base3(kp, x, y, z);
     T phi = T(0), C = T(0), H = T(0);
@@ -328,16 +469,37 @@ __device__ __forceinline__ void macros3(const K3& kp, const T* __restrict__ pop,
     m[2] = (T(2) * C / (T(1) + k - (T(1) - k) * phi) - T(1)) / (T(1) - k);
     m[3] = H + T(0.5) * hp;
     m[4] = H;
+    m[5] = m[6] = m[7] = m[8] = 0.0;
+    if constexpr (NS) {  // u = n_sub u' and p = n_sub^2 p' (main-step units)
+        const size_t fb = fbase3(kp, x, y, z);
+        T mm[3] = {T(0), T(0), T(0)}, rest = T(0);
+        for (int i = 1; i < 19; ++i) {
+            const T h = flow[i * LP + fb];
+            rest += h;
+            mm[0] += T(EX19[i]) * h;
+            mm[1] += T(EY19[i]) * h;
+            mm[2] += T(EZ19[i]) * h;
+        }
+        const T fac = (T(3) - phi) * T(0.25);
+        const T u[3] = {mm[0] * fac, mm[1] * fac, mm[2] * fac};
+        const T p = T(0.5) * (rest - T(0.5) * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]));
+        m[5] = kp.nsub_d * u[0];
+        m[6] = kp.nsub_d * u[1];
+        m[7] = kp.nsub_d * u[2];
+        m[8] = kp.nsub_d * kp.nsub_d * p;
+    }
 }
 
-template <class T, bool WALLS>
-__global__ __launch_bounds__(BX* BY) void k3_fields(const K3 kp, const T* __restrict__ pop, double* __restrict__ out) {
+template <class T, bool WALLS, bool NS>
+__global__ __launch_bounds__(BX* BY) void k3_fields(const K3 kp, const T* __restrict__ pop, const T* __restrict__ flow,
+                                                    double* __restrict__ out) {
     int x, y, z;
     if (!node3(kp, x, y, z)) return;
-    double m[5];
-    macros3<T, WALLS>(kp, pop, x, y, z, m);
+    double m[9];
+    macros3<T, WALLS, NS>(kp, pop, flow, x, y, z, m);
     const size_t N = (size_t)kp.nx * kp.ny * kp.nz, idx = id3(kp, x, y, z);
     for (int j = 0; j < 4; ++j) out[j * N + idx] = m[j];
+    for (int j = 0; j < 4; ++j) out[(4 + j) * N + idx] = m[5 + j];
 }
 
 // Per-workgroup partial sums: C, H, (1 + phi)/2, non-finite count.
@@ -347,8 +509,8 @@ __global__ __launch_bounds__(BX* BY) void k3_partial(const K3 kp, const T* __res
     int x, y, z;
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     if (node3(kp, x, y, z)) {
-        double m[5];
-        macros3<T, WALLS>(kp, pop, x, y, z, m);
+        double m[9];
+        macros3<T, WALLS, false>(kp, pop, nullptr, x, y, z, m);
         v[0] = m[1];
         v[1] = m[4];
         v[2] = 0.5 * (1.0 + m[0]);
@@ -381,8 +543,8 @@ __global__ void k3_tips(const K3 kp, const T* __restrict__ pop, int cx, int cy, 
     for (int j = 0;; ++j) {
         const int x = cx + (ax == 0 ? sgn * j : 0), y = cy + (ax == 1 ? sgn * j : 0), z = cz + (ax == 2 ? sgn * j : 0);
         if (x < 0 || y < 0 || z < 0 || x >= kp.nx || y >= kp.ny || z >= kp.nz) break;
-        double m[5];
-        macros3<T, WALLS>(kp, pop, x, y, z, m);
+        double m[9];
+        macros3<T, WALLS, false>(kp, pop, nullptr, x, y, z, m);
         double v = m[0] > lim ? lim : (m[0] < -lim ? -lim : m[0]);
         const double ps = atanh(v);
         if (j > 0 && prev > 0.0 && ps <= 0.0) best = (j - 1) + prev / (prev - ps);
@@ -409,7 +571,7 @@ int hip_fail3(hipError_t e, const char* what) {
 }
 
 struct Layout3 {
-    size_t plane, lp, pop[2], hist, stage, total;
+    size_t plane, lp, pop[2], flow[2], hist, stage, total;
 };
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
@@ -429,6 +591,16 @@ int check3(const dlb3_params* p) {
                              1.0 / (4.0 * p->D * (1.0 - p->k) + 0.5), 1.0 / (4.0 * p->alpha + 0.5)};
     for (double r : rates)
         if (!(r > 0.0 && r < 2.0)) return fail3(DLB3_EINVAL, "relaxation rate outside (0,2)");
+    if (p->use_ns != 0 && p->use_ns != 1) return fail3(DLB3_EINVAL, "use_ns must be 0 or 1");
+    if (p->use_ns) {
+        if (p->walls) return fail3(DLB3_EINVAL, "the 3-D melt flow needs a periodic domain (walls = 0)");
+        if (p->n_sub < 1 || !(p->nu > 0)) return fail3(DLB3_EINVAL, "melt flow needs n_sub >= 1 and nu > 0");
+        const double s2 = 1.0 / (3.0 * p->nu / p->n_sub + 0.5);
+        if (!(s2 > 0.0 && s2 < 2.0)) return fail3(DLB3_EINVAL, "relaxation rate outside (0,2)");
+        const double mach = std::sqrt(p->u0[0] * p->u0[0] + p->u0[1] * p->u0[1] + p->u0[2] * p->u0[2]) /
+                            p->n_sub * std::sqrt(3.0);
+        if (!(mach <= 0.3)) return fail3(DLB3_EINVAL, "initial Mach number |u0| sqrt(3)/n_sub exceeds 0.3");
+    }
     return DLB3_OK;
 }
 
@@ -443,10 +615,14 @@ Layout3 layout3(const dlb3_params* p) {
         L.pop[b] = off;
         off = align256(off + (size_t)p->nz * 21 * L.lp * sb);
     }
+    for (int b = 0; b < 2; ++b) {
+        L.flow[b] = off;
+        if (p->use_ns) off = align256(off + (size_t)p->nz * 19 * L.lp * sb);
+    }
     L.hist = off;
-    off = align256(off + 2 * L.plane * sb);
+    off = align256(off + (p->use_ns ? 8 : 2) * L.plane * sb);
     L.stage = off;
-    off = align256(off + 4 * L.plane * sizeof(double));
+    off = align256(off + 8 * L.plane * sizeof(double));
     L.total = off;
     return L;
 }
@@ -477,6 +653,8 @@ K3 make_k3(const dlb3_params* p, const Layout3& L) {
     k.s1t = 1.0 / (4.0 * p->alpha + 0.5);
     k.jat = p->W0 / (2.0 * std::sqrt(2.0));
     k.theta0 = p->theta0;
+    k.nsub_d = p->use_ns ? p->n_sub : 1;
+    k.s2u = p->use_ns ? 1.0 / (3.0 * p->nu / p->n_sub + 0.5) : 1.0;
     return k;
 }
 }  // namespace
@@ -487,21 +665,54 @@ struct dlb3_solver {
     K3 kp;
     char* base;
     hipStream_t stream;
-    int cur, hist_valid;
+    int cur, fcur, hist_valid;
     dim3 grid, block;
+    const void* pop() const { return base + L.pop[cur]; }
+    const void* flow() const { return p.use_ns ? base + L.flow[fcur] : nullptr; }
 };
 
 template <class T, bool W> static void launch_step(dlb3_solver* s) {
-    hipLaunchKernelGGL((k3_step<T, W>), s->grid, s->block, 0, s->stream, s->kp, (const T*)(s->base + s->L.pop[s->cur]),
-                       (T*)(s->base + s->L.pop[1 - s->cur]), (T*)(s->base + s->L.hist), s->hist_valid);
+    if constexpr (!W) {
+        if (s->p.use_ns) {
+            hipLaunchKernelGGL((k3_step<T, false, true>), s->grid, s->block, 0, s->stream, s->kp, (const T*)s->pop(),
+                               (T*)(s->base + s->L.pop[1 - s->cur]), (const T*)s->flow(), (T*)(s->base + s->L.hist),
+                               s->hist_valid);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k3_step<T, W, false>), s->grid, s->block, 0, s->stream, s->kp, (const T*)s->pop(),
+                       (T*)(s->base + s->L.pop[1 - s->cur]), (const T*)nullptr, (T*)(s->base + s->L.hist),
+                       s->hist_valid);
 }
-template <class T, bool W> static void launch_set(dlb3_solver* s, const double* phi, const double* C, const double* th) {
-    hipLaunchKernelGGL((k3_set<T, W>), s->grid, s->block, 0, s->stream, s->kp, phi, C, th, s->p.c_init_U, s->p.U0,
-                       s->p.C0, (T*)(s->base + s->L.pop[s->cur]));
+template <class T, bool W> static void launch_flow(dlb3_solver* s) {
+    hipLaunchKernelGGL((k3_flow<T>), s->grid, s->block, 0, s->stream, s->kp, (const T*)s->flow(),
+                       (T*)(s->base + s->L.flow[1 - s->fcur]), (const T*)(s->base + s->L.hist));
+}
+template <class T, bool W>
+static void launch_set(dlb3_solver* s, const double* phi, const double* C, const double* th, const double* ux,
+                       const double* uy, const double* uz) {
+    const double* u0 = s->p.u0;
+    if constexpr (!W) {
+        if (s->p.use_ns) {
+            hipLaunchKernelGGL((k3_set<T, false, true>), s->grid, s->block, 0, s->stream, s->kp, phi, C, th, ux, uy, uz,
+                               u0[0], u0[1], u0[2], s->p.c_init_U, s->p.U0, s->p.C0, (T*)(s->base + s->L.pop[s->cur]),
+                               (T*)(s->base + s->L.flow[s->fcur]));
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k3_set<T, W, false>), s->grid, s->block, 0, s->stream, s->kp, phi, C, th, ux, uy, uz, u0[0],
+                       u0[1], u0[2], s->p.c_init_U, s->p.U0, s->p.C0, (T*)(s->base + s->L.pop[s->cur]), (T*)nullptr);
 }
 template <class T, bool W> static void launch_fields(dlb3_solver* s, double* out) {
-    hipLaunchKernelGGL((k3_fields<T, W>), s->grid, s->block, 0, s->stream, s->kp, (const T*)(s->base + s->L.pop[s->cur]),
-                       out);
+    if constexpr (!W) {
+        if (s->p.use_ns) {
+            hipLaunchKernelGGL((k3_fields<T, false, true>), s->grid, s->block, 0, s->stream, s->kp, (const T*)s->pop(),
+                               (const T*)s->flow(), out);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k3_fields<T, W, false>), s->grid, s->block, 0, s->stream, s->kp, (const T*)s->pop(),
+                       (const T*)nullptr, out);
 }
 template <class T, bool W> static void launch_partial(dlb3_solver* s, double* part) {
     hipLaunchKernelGGL((k3_partial<T, W>), s->grid, s->block, 0, s->stream, s->kp,
@@ -547,6 +758,7 @@ int dlb3_create(const dlb3_params* p, void* dev_state, size_t bytes, void* hip_s
     s->base = (char*)dev_state;
     s->stream = (hipStream_t)hip_stream;
     s->cur = 0;
+    s->fcur = 0;
     s->hist_valid = 0;
     s->grid = dim3(s->kp.nbx * s->kp.nby, p->nz);
     s->block = dim3(BX, BY);
@@ -559,17 +771,20 @@ int dlb3_destroy(dlb3_handle h) {
     return DLB3_OK;
 }
 
-int dlb3_set_fields(dlb3_handle s, const double* phi, const double* C, const double* theta) {
+int dlb3_set_fields(dlb3_handle s, const double* phi, const double* C, const double* theta, const double* ux,
+                    const double* uy, const double* uz) {
     if (!s || !phi) return fail3(DLB3_EINVAL, "null handle or phi");
     const size_t N = (size_t)s->p.nx * s->p.ny * s->p.nz;
     double* st = (double*)(s->base + s->L.stage);
-    const double* srcs[3] = {phi, C, theta};
-    for (int j = 0; j < 3; ++j) {
+    const double* srcs[6] = {phi, C, theta, ux, uy, uz};
+    for (int j = 0; j < 6; ++j) {
         if (!srcs[j]) continue;
         hipError_t e = hipMemcpyAsync(st + j * s->L.plane, srcs[j], N * sizeof(double), hipMemcpyHostToDevice, s->stream);
         if (e != hipSuccess) return hip_fail3(e, "hipMemcpyAsync");
     }
-    DISPATCH3(s, launch_set, st, C ? st + s->L.plane : nullptr, theta ? st + 2 * s->L.plane : nullptr);
+    const size_t P = s->L.plane;
+    DISPATCH3(s, launch_set, st, C ? st + P : nullptr, theta ? st + 2 * P : nullptr, ux ? st + 3 * P : nullptr,
+              uy ? st + 4 * P : nullptr, uz ? st + 5 * P : nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail3(e, "k3_set");
     // the host arrays must stay valid until the copies ran
@@ -584,7 +799,7 @@ int dlb3_init_seed(dlb3_handle s) {
     double* st = (double*)(s->base + s->L.stage);
     hipLaunchKernelGGL(k3_seed, s->grid, s->block, 0, s->stream, s->kp, s->p.seed_R, s->p.seed_x, s->p.seed_y,
                        s->p.seed_z, s->p.W0, st);
-    DISPATCH3(s, launch_set, st, nullptr, nullptr);
+    DISPATCH3(s, launch_set, st, nullptr, nullptr, nullptr, nullptr, nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail3(e, "k3_seed/k3_set");
     s->hist_valid = 0;
@@ -597,6 +812,11 @@ int dlb3_step(dlb3_handle s, int64_t n) {
         DISPATCH3(s, launch_step);
         s->cur ^= 1;
         s->hist_valid = 1;
+        if (s->p.use_ns)  // sub-steps at the frozen phi of time t (hist plane 0)
+            for (int j = 0; j < s->p.n_sub; ++j) {
+                DISPATCH3(s, launch_flow);
+                s->fcur ^= 1;
+            }
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail3(e, "k3_step");
@@ -608,7 +828,7 @@ int dlb3_get_fields(dlb3_handle s, double* out) {
     const size_t N = (size_t)s->p.nx * s->p.ny * s->p.nz;
     double* st = (double*)(s->base + s->L.stage);
     DISPATCH3(s, launch_fields, st);
-    hipError_t e = hipMemcpyAsync(out, st, 4 * N * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    hipError_t e = hipMemcpyAsync(out, st, 8 * N * sizeof(double), hipMemcpyDeviceToHost, s->stream);
     if (e != hipSuccess) return hip_fail3(e, "hipMemcpyAsync");
     e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return hip_fail3(e, "hipStreamSynchronize");
@@ -619,7 +839,7 @@ int dlb3_reduce(dlb3_handle s, double* out) {
     if (!s || !out) return fail3(DLB3_EINVAL, "null handle or output");
     double* st = (double*)(s->base + s->L.stage);
     const size_t nb = (size_t)s->grid.x * s->grid.y;
-    if (4 * nb + 6 > 4 * s->L.plane) return fail3(DLB3_EINVAL, "staging area too small for the reduction");
+    if (4 * nb + 6 > 8 * s->L.plane) return fail3(DLB3_EINVAL, "staging area too small for the reduction");
     double* tips = st + 4 * nb;
     DISPATCH3(s, launch_partial, st);
     const int cx = (int)std::lround(s->p.seed_x), cy = (int)std::lround(s->p.seed_y), cz = (int)std::lround(s->p.seed_z);

@@ -12,7 +12,7 @@ from paper_2209_01444_amd import dlb as _dlb
 
 DLB3_OK, DLB3_EINVAL = 0, -1
 PRECISION = {"f64": 0, "f32": 1}
-FIELDS = ("phi", "C", "U", "theta")
+FIELDS = ("phi", "C", "U", "theta", "ux", "uy", "uz", "p")
 EXPORTS = ("dlb3_state_bytes", "dlb3_create", "dlb3_destroy", "dlb3_init_seed", "dlb3_set_fields",
            "dlb3_step", "dlb3_get_fields", "dlb3_reduce", "dlb3_last_error")
 
@@ -28,13 +28,15 @@ class Dlb3Params(ctypes.Structure):
         "nx", "ny", "nz", "walls", "use_t", "h_quintic", "c_init_U", "precision", "grad_iters")] + [
         (n, ctypes.c_double) for n in (
             "W0", "tau0", "eps4", "lambda_", "Mcinf", "k", "D", "alpha", "theta0", "U0", "C0",
-            "seed_R", "seed_x", "seed_y", "seed_z", "grad_tol")]
+            "seed_R", "seed_x", "seed_y", "seed_z", "grad_tol")] + [
+        (n, ctypes.c_int32) for n in ("use_ns", "n_sub")] + [(n, ctypes.c_double) for n in ("nu", "rho0")] + [
+        ("u0", ctypes.c_double * 3)]
 
 
 DEFAULTS = dict(nx=24, ny=24, nz=24, walls=0, use_t=1, h_quintic=0, c_init_U=0, precision="f64",
                 grad_iters=0, W0=1.0, tau0=20.0, eps4=0.05, lambda_=0.0, Mcinf=0.0, k=0.15, D=0.1,
                 alpha=0.1, theta0=0.0, U0=0.0, C0=1.0, seed_R=5.0, seed_x=None, seed_y=None, seed_z=None,
-                grad_tol=0.0)
+                grad_tol=0.0, use_ns=0, n_sub=1, nu=0.1, rho0=1.0, u0x=0.0, u0y=0.0, u0z=0.0)
 _IGNORED = {"name", "steps", "grad_max_iter", "fixed_as"}
 
 _bound = False
@@ -50,7 +52,7 @@ def load_library() -> ctypes.CDLL:
             "dlb3_create": (ctypes.c_int, [P(Dlb3Params), vp, ctypes.c_size_t, vp, P(vp)]),
             "dlb3_destroy": (ctypes.c_int, [vp]),
             "dlb3_init_seed": (ctypes.c_int, [vp]),
-            "dlb3_set_fields": (ctypes.c_int, [vp, dp, dp, dp]),
+            "dlb3_set_fields": (ctypes.c_int, [vp, dp, dp, dp, dp, dp, dp]),
             "dlb3_step": (ctypes.c_int, [vp, ctypes.c_int64]),
             "dlb3_get_fields": (ctypes.c_int, [vp, dp]),
             "dlb3_reduce": (ctypes.c_int, [vp, dp]),
@@ -74,8 +76,10 @@ def make_params(cfg: dict) -> Dlb3Params:
             raise KeyError(f"unknown parameter {key!r}")
         c[key] = val
     p = Dlb3Params()
-    for name in ("nx", "ny", "nz", "walls", "use_t", "h_quintic", "c_init_U", "grad_iters"):
+    for name in ("nx", "ny", "nz", "walls", "use_t", "h_quintic", "c_init_U", "grad_iters", "use_ns", "n_sub"):
         setattr(p, name, int(c[name]))
+    p.nu, p.rho0 = float(c["nu"]), float(c["rho0"])
+    p.u0[0], p.u0[1], p.u0[2] = float(c["u0x"]), float(c["u0y"]), float(c["u0z"])
     p.precision = PRECISION[c["precision"]] if isinstance(c["precision"], str) else int(c["precision"])
     for name in ("W0", "tau0", "eps4", "lambda_", "Mcinf", "k", "D", "alpha", "theta0", "U0", "C0", "seed_R",
                  "grad_tol"):
@@ -135,8 +139,8 @@ class Solver3:
         self.step_count = 0
         return self
 
-    def set_fields(self, phi, C=None, theta=None):
-        arrs = [self._plane(a) for a in (phi, C, theta)]
+    def set_fields(self, phi, C=None, theta=None, ux=None, uy=None, uz=None):
+        arrs = [self._plane(a) for a in (phi, C, theta, ux, uy, uz)]
         self._check(self.lib.dlb3_set_fields(self.handle, *[_dp(a) for a in arrs]))
         self.step_count = 0
         return self
@@ -148,7 +152,7 @@ class Solver3:
 
     def fields(self) -> dict:
         N = int(np.prod(self.shape))
-        out = np.zeros(4 * N)
+        out = np.zeros(8 * N)
         self._check(self.lib.dlb3_get_fields(self.handle, _dp(out)))
         return {k: out[i * N:(i + 1) * N].reshape(self.shape) for i, k in enumerate(FIELDS)}
 

@@ -94,3 +94,30 @@ def test_3d_seed_grows_with_cubic_symmetry(dlb3):
     f = s.fields()["phi"]
     np.testing.assert_allclose(np.transpose(f, (2, 1, 0)), f, atol=1e-5)
     np.testing.assert_allclose(f[::-1], f, atol=1e-5)
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_3d_melt_flow_parity(dlb3, precision, tol):
+    """D3Q19 melt flow (periodic, three sub-steps per main step) past a
+    growing thermosolutal seed on a ragged 37 x 30 x 26 grid, every field
+    including the velocity and pressure, against the oracle."""
+    cfg = dict(_case(0, precision), use_ns=1, n_sub=3, nu=0.45, u0x=0.03, u0y=-0.01, u0z=0.005)
+    _say(f"case: 3-D melt flow 37x30x26 {precision}")
+    o = O.Oracle3(cfg).init_seed()
+    s = dlb3.Solver3(cfg).init_seed()
+    for t in (1, 20, 60):
+        o.step(t - o.step_count)
+        s.step(t - s.step_count)
+        gf, of = s.fields(), o.fields()
+        errs = {k: _rel(gf[k], of[k]) for k in O.FIELDS + O.FLOW_FIELDS}
+        _say(f"  t={t} " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+        bad = {k: v for k, v in errs.items() if v > (10 * tol if k == "p" else tol)}
+        assert not bad, bad
+    assert np.abs(s.fields()["ux"]).max() > 1e-3  # the flow is there
+
+
+def test_3d_flow_needs_a_periodic_domain(dlb3):
+    with pytest.raises(dlb3.Dlb3Error):
+        dlb3.Solver3(dict(_case(1, "f64"), use_ns=1, n_sub=3, nu=0.45))
+    with pytest.raises(dlb3.Dlb3Error):
+        dlb3.Solver3(dict(_case(0, "f64"), use_ns=1, n_sub=1, nu=0.45, u0x=0.5))  # Mach limit
