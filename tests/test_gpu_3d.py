@@ -121,3 +121,20 @@ def test_3d_flow_needs_a_periodic_domain(dlb3):
         dlb3.Solver3(dict(_case(1, "f64"), use_ns=1, n_sub=3, nu=0.45))
     with pytest.raises(dlb3.Dlb3Error):
         dlb3.Solver3(dict(_case(0, "f64"), use_ns=1, n_sub=1, nu=0.45, u0x=0.5))  # Mach limit
+
+
+def test_3d_dendrite_in_melt_flow_grows_upstream(dlb3):
+    """A seed centred on a node of a periodic 96^3 box in a melt flow along
+    +x (15 sub-steps per main step, Pr = 23.1), FP32: the arm facing the
+    flow (-x) outgrows the downstream arm (+x), and the four arms across the
+    flow stay equal (the flow keeps the y and z mirror symmetries)."""
+    from paper_2209_01444_amd import bench3d
+    cfg = dict(bench3d.workload(96, "f32", flow=True), seed_R=8.0, seed_x=48, seed_y=48, seed_z=48, u0x=0.02)
+    s = dlb3.Solver3(cfg).init_seed().step(3000)
+    r = s.reduce()
+    tips = r["tip_s"]  # +x, +y, +z, -x, -y, -z
+    _say(f"  tips {np.round(tips, 3)}")
+    assert r["nonfinite"] == 0
+    down, up, across = tips[0], tips[3], tips[[1, 2, 4, 5]]
+    assert up > down + 1.0
+    assert np.ptp(across) < 1e-2 * across.mean()
