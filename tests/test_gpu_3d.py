@@ -138,3 +138,16 @@ def test_3d_dendrite_in_melt_flow_grows_upstream(dlb3):
     down, up, across = tips[0], tips[3], tips[[1, 2, 4, 5]]
     assert up > down + 1.0
     assert np.ptp(across) < 1e-2 * across.mean()
+
+
+@pytest.mark.parametrize("variant", [dict(use_t=0, theta0=-0.4), dict(h_quintic=1), dict(c_init_U=0, C0=0.9)])
+def test_3d_variant_parity(dlb3, variant):
+    """Isothermal runs, the quintic h(phi) and a uniform initial C, FP64,
+    periodic, against the oracle."""
+    cfg = dict(_case(0, "f64"), nx=24, ny=22, nz=20, seed_x=11.2, seed_y=10.7, seed_z=9.6, **variant)
+    _say(f"case: 3-D variant {variant}")
+    o = O.Oracle3(cfg).init_seed().step(60)
+    s = dlb3.Solver3(cfg).init_seed().step(60)
+    gf, of = s.fields(), o.fields()
+    for k in O.FIELDS:
+        assert _rel(gf[k], of[k]) <= 1e-10, (k, _rel(gf[k], of[k]))
