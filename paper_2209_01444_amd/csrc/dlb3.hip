@@ -40,7 +40,7 @@ static constexpr double CS2 = 0.25;
 static constexpr double GUARD = 1e-12;
 
 struct K3 {
-    int nx, ny, nz, nbx, nby;
+    int nx, ny, nz, nbx, nby, nb;  // grid, tiles per layer in x and y, workgroups
     long long plane;  // elements per history / staging plane (>= N, 64-multiple)
     long long lp;     // elements per population layer (>= nx ny, 64-multiple)
     int use_t, h_quintic, grad_iters;
@@ -53,10 +53,20 @@ static constexpr int EX19[19] = {0, 1, 0, 0, -1, 0, 0, 1, -1, 1, -1, 1, -1, 1, -
 static constexpr int EY19[19] = {0, 0, 1, 0, 0, -1, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
 static constexpr int EZ19[19] = {0, 0, 0, 1, 0, 0, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
 
+// Workgroups are dispatched round-robin over the 8 XCDs; each XCD takes a
+// contiguous range of tiles (a band of z-layers), so the z-neighbour layers
+// a node pushes into and re-reads stay in that XCD's L2.
+__device__ __forceinline__ int xcd_order3(int bid, int nb) {
+    const int q = nb >> 3, r = nb & 7, xcd = bid & 7, slot = bid >> 3;
+    return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + slot;
+}
 __device__ __forceinline__ bool node3(const K3& kp, int& x, int& y, int& z) {
-    x = (int)(blockIdx.x % kp.nbx) * BX + threadIdx.x;
-    y = (int)(blockIdx.x / kp.nbx) * BY + threadIdx.y;
-    z = blockIdx.y;
+    const int t = xcd_order3((int)blockIdx.x, kp.nb);
+    const int nxy = kp.nbx * kp.nby;
+    z = t / nxy;
+    const int rem = t - z * nxy;
+    x = (rem % kp.nbx) * BX + (int)threadIdx.x;
+    y = (rem / kp.nbx) * BY + (int)threadIdx.y;
     return x < kp.nx && y < kp.ny;
 }
 __device__ __forceinline__ size_t id3(const K3& kp, int x, int y, int z) {
@@ -523,7 +533,7 @@ __global__ __launch_bounds__(BX* BY) void k3_partial(const K3 kp, const T* __res
         for (int r = 0; r < 4; ++r) sh[r][wave] = v[r];
     __syncthreads();
     if (t == 0) {
-        const size_t b = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+        const size_t b = blockIdx.x;
         for (int r = 0; r < 4; ++r) {
             double s = 0.0;
             for (int w = 0; w < BX * BY / 64; ++w) s += sh[r][w];
@@ -581,6 +591,8 @@ int check3(const dlb3_params* p) {
     if (p->nx < 8 || p->ny < 8 || p->nz < 8) return fail3(DLB3_EINVAL, "grid must be at least 8x8x8");
     if (p->nz > 65535) return fail3(DLB3_EINVAL, "nz must be at most 65535");
     if ((double)p->nx * p->ny * p->nz > 2.0e9) return fail3(DLB3_EINVAL, "grid too large");
+    if ((double)((p->nx + BX - 1) / BX) * ((p->ny + BY - 1) / BY) * p->nz > 2.0e9)
+        return fail3(DLB3_EINVAL, "too many workgroups");
     if (p->precision != DLB3_F64 && p->precision != DLB3_F32) return fail3(DLB3_EINVAL, "unknown precision");
     if (p->walls != 0 && p->walls != 1) return fail3(DLB3_EINVAL, "walls must be 0 or 1");
     if (!(p->W0 > 0 && p->tau0 > 0 && p->D > 0 && p->alpha > 0)) return fail3(DLB3_EINVAL, "W0, tau0, D, alpha must be > 0");
@@ -634,6 +646,7 @@ K3 make_k3(const dlb3_params* p, const Layout3& L) {
     k.nz = p->nz;
     k.nbx = (p->nx + BX - 1) / BX;
     k.nby = (p->ny + BY - 1) / BY;
+    k.nb = k.nbx * k.nby * p->nz;
     k.plane = (long long)L.plane;
     k.lp = (long long)L.lp;
     k.use_t = p->use_t ? 1 : 0;
@@ -760,7 +773,7 @@ int dlb3_create(const dlb3_params* p, void* dev_state, size_t bytes, void* hip_s
     s->cur = 0;
     s->fcur = 0;
     s->hist_valid = 0;
-    s->grid = dim3(s->kp.nbx * s->kp.nby, p->nz);
+    s->grid = dim3(s->kp.nb);
     s->block = dim3(BX, BY);
     *out = s;
     return DLB3_OK;
