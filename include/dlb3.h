@@ -17,9 +17,10 @@
  * t; the solute and heat equilibria take u = n_sub u'.
  *
  * Ownership: the caller owns the device state buffer (dlb3_state_bytes) and
- * the stream; the library owns only the small host handle.  Every call is
- * asynchronous on the stream except those that return host data
- * (dlb3_get_fields, dlb3_reduce), which synchronise it.
+ * the stream; the library owns only the small host handle.  dlb3_step and
+ * dlb3_init_seed are asynchronous on the stream; dlb3_set_fields (which
+ * copies the caller's host arrays), dlb3_get_fields and dlb3_reduce
+ * synchronise it before they return.  Calls on one handle must not overlap.
  * Errors: 0 on success; a negative DLB3_E* code otherwise, with a message
  * for dlb3_last_error().  No C++ exception crosses the ABI.
  */
