@@ -24,7 +24,7 @@
  *   - Crystal axes along the lattice axes (no orientation).
  *   - Walls (walls = 1): the outermost layer of nodes, rebuilt as a copy of
  *     the inward neighbour (zero gradient), as in the 2-D channel.
- *   - Melt flow (use_ns = 1, periodic domain only): D3Q19 (c0 = 0, the six
+ *   - Melt flow (use_ns = 1): D3Q19 (c0 = 0, the six
  *     faces, the twelve edges; w = 1/3, 1/18, 1/36; cs^2 = 1/3) with the
  *     equilibrium, pressure, diffuse force and forcing of Sec. 3.4 (varphi =
  *     0, no external force); MRT in the raw-moment basis 1, c_a, c_a c_b,
@@ -32,6 +32,14 @@
  *     all others, as the 2-D flow lattice; n_sub sub-steps per main step at
  *     the frozen phi of time t, and u = n_sub u' in the solute and heat
  *     equilibria and in d_t(Cu), d_t(Hu) (two-time-scaling, Sec. 4).
+ *     With walls, the channel of the 2-D runs in 3-D: the wall nodes'
+ *     flow populations are rebuilt by non-equilibrium extrapolation from the
+ *     inward neighbour (Sec. 4 preamble), h_b = h^eq(p_b, u_b) + h_f -
+ *     h^eq(p_f, u_f): west face x = 0 inlet u_b = u0/n_sub, p_b = p_f; east
+ *     face outflow u_b = u_f (its y, z components zeroed where the node also
+ *     lies on a y or z wall), p_b = 0; y and z faces free slip (normal
+ *     component zeroed), p_b = p_f.  phi, C and H keep the zero-gradient copy
+ *     and take the wall node's velocity.
  *
  * Parity status:
  *   anisotropy a_s, N (d-general)                          pinned (closed forms,
@@ -295,8 +303,8 @@ static double* alloc0(long n) { return (double*)calloc((size_t)n, sizeof(double)
 o3_state* o3_create(const o3_params* p) {
     if (p->nx < 3 || p->ny < 3 || p->nz < 3) { set_err("grid smaller than 3x3x3"); return NULL; }
     if (p->walls < 0 || p->walls > 1) { set_err("walls must be 0 or 1"); return NULL; }
-    if (p->use_ns && (p->walls || p->n_sub < 1 || !(p->nu > 0))) {
-        set_err("melt flow needs a periodic domain, n_sub >= 1 and nu > 0");
+    if (p->use_ns && (p->n_sub < 1 || !(p->nu > 0))) {
+        set_err("melt flow needs n_sub >= 1 and nu > 0");
         return NULL;
     }
     init19();
@@ -355,6 +363,45 @@ static void fill_walls(o3_state* s, double* pop) {
             }
 }
 
+/* Flow walls by non-equilibrium extrapolation (see the header comment);
+ * phi is the frozen phi of the sub-step. */
+static void fill_flow_walls3(o3_state* s, double* h, const double* phi) {
+    if (!s->p.walls) return;
+    const o3_params* p = &s->p;
+    long N = s->N;
+    for (int z = 0; z < s->nz; ++z)
+        for (int y = 0; y < s->ny; ++y)
+            for (int x = 0; x < s->nx; ++x) {
+                if (!is_wall(s, x, y, z)) continue;
+                long b = id3(s, x, y, z), f = inward(s, x, y, z);
+                double hf[19], us[3], Fb[3], uf[3], pf;
+                for (int i = 0; i < 19; ++i) hf[i] = h[i * N + f];
+                flow_macros3(hf, phi[f], us, Fb, uf, &pf);
+                double ub[3], pb;
+                const int ywall = (y == 0 || y == s->ny - 1), zwall = (z == 0 || z == s->nz - 1);
+                if (x == 0) {
+                    ub[0] = p->u0x / p->n_sub;
+                    ub[1] = p->u0y / p->n_sub;
+                    ub[2] = p->u0z / p->n_sub;
+                    pb = pf;
+                } else if (x == s->nx - 1) {
+                    ub[0] = uf[0];
+                    ub[1] = ywall ? 0.0 : uf[1];
+                    ub[2] = zwall ? 0.0 : uf[2];
+                    pb = 0.0;
+                } else {
+                    ub[0] = uf[0];
+                    ub[1] = ywall ? 0.0 : uf[1];
+                    ub[2] = zwall ? 0.0 : uf[2];
+                    pb = pf;
+                }
+                double eb[19], ef[19];
+                o3_eq_flow(p->rho0, pb, ub[0], ub[1], ub[2], eb);
+                o3_eq_flow(p->rho0, pf, uf[0], uf[1], uf[2], ef);
+                for (int i = 0; i < 19; ++i) h[i * N + b] = eb[i] + (hf[i] - ef[i]);
+            }
+}
+
 static void eq_phi(double phi, double* o) { for (int i = 0; i < 7; ++i) o[i] = W7[i] * phi; }
 /* n^eq and g^eq of Secs. 3.2, 3.3 with the velocity u (main-step units) */
 static void eq_solute(double C, double phi, double U, const double* u, double* o) {
@@ -392,12 +439,17 @@ static void compute_macros(o3_state* s) {
             s->theta[x] = p->theta0;
             s->H[x] = p->theta0 - 0.5 * h_of(ph, p->h_quintic);
         }
-        /* melt velocity of time t in main-step units: n_sub u' */
+    }
+    /* melt velocity of time t in main-step units: n_sub u' (wall nodes of the
+     * flow lattice rebuilt first, with phi of time t) */
+    if (p->use_ns) fill_flow_walls3(s, s->h, s->phi);
+#pragma omp parallel for schedule(static)
+    for (long x = 0; x < N; ++x) {
         double u[3] = {0.0, 0.0, 0.0};
         if (p->use_ns) {
             double h[19], us[3], Fb[3], pr;
             for (int i = 0; i < 19; ++i) h[i] = s->h[i * N + x];
-            flow_macros3(h, ph, us, Fb, u, &pr);
+            flow_macros3(h, s->phi[x], us, Fb, u, &pr);
             for (int a = 0; a < 3; ++a) u[a] *= p->n_sub;
         }
         for (int a = 0; a < 3; ++a) s->u[a * N + x] = u[a];
@@ -505,6 +557,7 @@ static void flow_substeps(o3_state* s) {
     long N = s->N;
     int nx = s->nx, ny = s->ny, nz = s->nz;
     for (int sub = 0; sub < p->n_sub; ++sub) {
+        fill_flow_walls3(s, s->h, s->phi);
 #pragma omp parallel for schedule(static)
         for (long x = 0; x < N; ++x) {
             double h[19], us[3], Fb[3], u[3], pr, heq[19], F[19];
@@ -525,6 +578,7 @@ static void flow_substeps(o3_state* s) {
         for (int z = 0; z < nz; ++z)
             for (int y = 0; y < ny; ++y)
                 for (int x = 0; x < nx; ++x) {
+                    if (is_wall(s, x, y, z)) continue; /* rebuilt before use */
                     long d = id3(s, x, y, z);
                     for (int i = 0; i < 19; ++i)
                         s->hn[(long)i * N + d] =

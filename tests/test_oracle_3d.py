@@ -222,3 +222,33 @@ def test_advected_heat_mode_keeps_alpha_and_u():
     vel = -np.angle(y2 / y1) / m / k
     assert abs(rate) < 1e-2
     assert vel == pytest.approx(u0, rel=1e-2)
+
+
+def test_uniform_channel_flow_is_steady():
+    """With walls (inlet u0 at x = 0, outflow at the east face, free slip on
+    the y and z faces) a uniform liquid flow at u0 stays uniform: every wall
+    rebuild reproduces the interior equilibrium."""
+    cfg = dict(_flow_cfg(10, nx=12, ny=10, nz=9, walls=1, u0x=0.04, u0y=0.0, u0z=0.0))
+    o = O.Oracle3(cfg).set_fields(-np.ones((9, 10, 12)))
+    o.step(30)
+    f = o.fields()
+    np.testing.assert_allclose(f["ux"], 0.04, atol=1e-13)
+    np.testing.assert_allclose(f["uy"], 0.0, atol=1e-13)
+    np.testing.assert_allclose(f["uz"], 0.0, atol=1e-13)
+    np.testing.assert_allclose(f["p"], 0.0, atol=1e-12)
+
+
+def test_channel_flow_around_a_seed_keeps_the_mirror_symmetry():
+    """A seed on the channel's centre line (y and z mirror planes) in the
+    inflow: the fields stay mirror-symmetric in y and z, and the flow slows
+    in front of the solid."""
+    n = 16
+    cfg = dict(_flow_cfg(n, nx=20, ny=n + 1, nz=n + 1, walls=1, u0x=0.04, lambda_=2.0, theta0=-0.4,
+                         seed_R=3.0, seed_x=9, seed_y=n / 2, seed_z=n / 2, eps4=0.02))
+    o = O.Oracle3(cfg).init_seed()
+    o.step(40)
+    f = o.fields()
+    for key in ("phi", "theta", "ux"):
+        np.testing.assert_allclose(f[key][:, ::-1, :], f[key], atol=1e-12)
+        np.testing.assert_allclose(f[key][::-1, :, :], f[key], atol=1e-12)
+    assert f["ux"][n // 2, n // 2, 5] < 0.04
