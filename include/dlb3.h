@@ -3,7 +3,7 @@
  * lattices (D3Q7) of the diffuse-interface lattice Boltzmann method of
  * Zhan et al., arXiv:2209.01444 (Sec. 2 anisotropy a_s and N for any d,
  * Secs. 3.1-3.3 with a general lattice sound speed), and optionally the melt
- * flow of Sec. 3.4 on D3Q19 in a periodic domain.
+ * flow of Sec. 3.4 on D3Q19 (periodic, or a channel with walls).
  * Exported by libdlb.so beside the 2-D solver (dlb.h).
  *
  * Lattice: c0 = 0, c1..c3 = +x, +y, +z, c4..c6 = -x, -y, -z; cs^2 = 1/4,
@@ -52,7 +52,9 @@ typedef struct dlb3_params {
     double theta0, U0, C0;       /* initial temperature, supersaturation, C      */
     double seed_R, seed_x, seed_y, seed_z; /* spherical seed (lu, node coords)   */
     double grad_tol;             /* tolerance of the gradient fixed point (0: default) */
-    int32_t use_ns;              /* 1: melt flow (needs walls = 0)                */
+    int32_t use_ns;              /* 1: melt flow; with walls the channel: west inlet
+                                    u0, east outflow (p = 0), free slip on the y and
+                                    z faces, by non-equilibrium extrapolation      */
     int32_t n_sub;               /* flow sub-steps per main step (two-time-scaling) */
     double nu, rho0;             /* viscosity (lu^2 per main step), density       */
     double u0[3];                /* initial velocity (lu per main step); the Mach

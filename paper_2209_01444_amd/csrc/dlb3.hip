@@ -46,6 +46,7 @@ struct K3 {
     int use_t, h_quintic, grad_iters;
     double W2t, inv_tau0, eps4, lambda, Mcinf, k, invD, s1c, s1t, jat, grad_tol2, theta0;
     double nsub_d, s2u;  // flow sub-steps per main step, flow relaxation rate
+    double uin[3];       // inlet velocity per sub-step (walls)
 };
 
 // D3Q19 links: rest, faces +x +y +z -x -y -z, edges (xy) ++ -- +- -+, (xz) ++ -- +- -+, (yz) ++ -- +- -+
@@ -86,6 +87,81 @@ __device__ __forceinline__ bool is_wall3(const K3& kp, int x, int y, int z) {
 __device__ __forceinline__ int clampi(int a, int lo, int hi) { return a < lo ? lo : (a > hi ? hi : a); }
 __device__ __forceinline__ size_t inward3(const K3& kp, int x, int y, int z) {
     return base3(kp, clampi(x, 1, kp.nx - 2), clampi(y, 1, kp.ny - 2), clampi(z, 1, kp.nz - 2));
+}
+__device__ __forceinline__ size_t inward_f3(const K3& kp, int x, int y, int z) {
+    return fbase3(kp, clampi(x, 1, kp.nx - 2), clampi(y, 1, kp.ny - 2), clampi(z, 1, kp.nz - 2));
+}
+__device__ __forceinline__ size_t inward_id3(const K3& kp, int x, int y, int z) {
+    return id3(kp, clampi(x, 1, kp.nx - 2), clampi(y, 1, kp.ny - 2), clampi(z, 1, kp.nz - 2));
+}
+
+// D3Q19 flow equilibrium with h_0 shifted by -rho0 (Sec. 3.4, cs^2 = 1/3).
+template <class T> __device__ __forceinline__ T heq19(int i, T p, const T* u) {
+    const int ax = EX19[i], ay = EY19[i], az = EZ19[i];
+    const int nn = ax * ax + ay * ay + az * az;
+    const T w = nn == 0 ? T(1.0 / 3.0) : (nn == 1 ? T(1.0 / 18.0) : T(1.0 / 36.0));
+    const T cu = T(ax) * u[0] + T(ay) * u[1] + T(az) * u[2];
+    const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const T sig = i == 0 ? T(-2) * p : w * T(3) * p;
+    return sig + w * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * uu);
+}
+
+// u and p (sub-step units) of flow populations h at phi: u* = sum c h,
+// u = u* (3 - phi)/4, p = (rest - |u|^2/2)/2.
+template <class T> __device__ __forceinline__ void flow_up3(const T* h, T phi, T* u, T& p) {
+    T m[3] = {T(0), T(0), T(0)}, rest = T(0);
+#pragma unroll
+    for (int i = 1; i < 19; ++i) {
+        rest += h[i];
+        m[0] += T(EX19[i]) * h[i];
+        m[1] += T(EY19[i]) * h[i];
+        m[2] += T(EZ19[i]) * h[i];
+    }
+    const T fac = (T(3) - phi) * T(0.25);
+    u[0] = m[0] * fac;
+    u[1] = m[1] * fac;
+    u[2] = m[2] * fac;
+    p = T(0.5) * (rest - T(0.5) * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]));
+}
+
+// Flow populations of node (x, y, z) at the current sub-step: interior nodes
+// load them; wall nodes rebuild them from the inward neighbour by
+// non-equilibrium extrapolation (Sec. 4 preamble), h = h_f + h^eq(p_b, u_b)
+// - h^eq(p_f, u_f): west face inlet u_b = uin, p_b = p_f; east face u_b =
+// u_f with its y, z components zeroed on y, z walls, p_b = 0; y and z faces
+// free slip, p_b = p_f.  phi_f: phi of the inward neighbour (a wall node
+// carries its neighbour's phi).
+template <class T, bool WALLS>
+__device__ __forceinline__ void flow_node3(const K3& kp, const T* __restrict__ hin, int x, int y, int z, T phi_f,
+                                           T* h) {
+    const size_t LP = (size_t)kp.lp;
+    if (!WALLS || !is_wall3(kp, x, y, z)) {
+        const size_t fb = fbase3(kp, x, y, z);
+#pragma unroll
+        for (int i = 0; i < 19; ++i) h[i] = hin[i * LP + fb];
+        return;
+    }
+    const size_t f = inward_f3(kp, x, y, z);
+    T hf[19];
+#pragma unroll
+    for (int i = 0; i < 19; ++i) hf[i] = hin[i * LP + f];
+    T uf[3], pf;
+    flow_up3(hf, phi_f, uf, pf);
+    const bool yw = y == 0 || y == kp.ny - 1, zw = z == 0 || z == kp.nz - 1;
+    T ub[3], pb;
+    if (x == 0) {
+        ub[0] = T(kp.uin[0]);
+        ub[1] = T(kp.uin[1]);
+        ub[2] = T(kp.uin[2]);
+        pb = pf;
+    } else {
+        ub[0] = uf[0];
+        ub[1] = yw ? T(0) : uf[1];
+        ub[2] = zw ? T(0) : uf[2];
+        pb = x == kp.nx - 1 ? T(0) : pf;
+    }
+#pragma unroll
+    for (int i = 0; i < 19; ++i) h[i] = hf[i] + (heq19(i, pb, ub) - heq19(i, pf, uf));
 }
 
 template <class T> __device__ __forceinline__ T h_of3(T phi, int quintic) {
@@ -185,14 +261,14 @@ __global__ __launch_bounds__(BX* BY) void k3_step(const K3 kp, const T* __restri
     // melt velocity of time t in main-step units: n_sub (3 - phi)/4 u*
     T u[3] = {T(0), T(0), T(0)};
     if constexpr (NS) {
-        const size_t fb = fbase3(kp, x, y, z);
+        T h[19];
+        flow_node3<T, WALLS>(kp, hin, x, y, z, phi, h);
         T m[3] = {T(0), T(0), T(0)};
 #pragma unroll
         for (int i = 1; i < 19; ++i) {
-            const T h = hin[i * LP + fb];
-            if (EX19[i]) m[0] += EX19[i] > 0 ? h : -h;
-            if (EY19[i]) m[1] += EY19[i] > 0 ? h : -h;
-            if (EZ19[i]) m[2] += EZ19[i] > 0 ? h : -h;
+            if (EX19[i]) m[0] += EX19[i] > 0 ? h[i] : -h[i];
+            if (EY19[i]) m[1] += EY19[i] > 0 ? h[i] : -h[i];
+            if (EZ19[i]) m[2] += EZ19[i] > 0 ? h[i] : -h[i];
         }
         const T fac = T(kp.nsub_d) * (T(3) - phi) * T(0.25);
         u[0] = m[0] * fac;
@@ -303,17 +379,15 @@ __global__ __launch_bounds__(BX* BY) void k3_step(const K3 kp, const T* __restri
 
 // One melt-flow sub-step (Sec. 3.4, D3Q19, periodic) at the frozen phi of
 // time t (hist[0]), push streaming.
-template <class T>
+template <class T, bool WALLS>
 __global__ __launch_bounds__(BX* BY) void k3_flow(const K3 kp, const T* __restrict__ hin, T* __restrict__ hout,
                                                   const T* __restrict__ phi_t) {
     int x, y, z;
     if (!node3(kp, x, y, z)) return;
     const size_t LP = (size_t)kp.lp;
-    const size_t fb = fbase3(kp, x, y, z);
-    T h[19];
-#pragma unroll
-    for (int i = 0; i < 19; ++i) h[i] = hin[i * LP + fb];
     const T phi = phi_t[id3(kp, x, y, z)];
+    T h[19];
+    flow_node3<T, WALLS>(kp, hin, x, y, z, phi, h);
     T m[3] = {T(0), T(0), T(0)}, rest = T(0);
 #pragma unroll
     for (int i = 1; i < 19; ++i) {
@@ -361,9 +435,17 @@ __global__ __launch_bounds__(BX* BY) void k3_flow(const K3 kp, const T* __restri
         if (nn == 0) post += r * -((Pi[0] + Pi[1]) + Pi[2]);
         else if (nn == 1) post += r * T(0.5) * (ax ? Pi[0] : (ay ? Pi[1] : Pi[2]));
         else post += r * T(0.25) * (az == 0 ? T(ax * ay) * Pi[3] : (ay == 0 ? T(ax * az) * Pi[4] : T(ay * az) * Pi[5]));
-        const int X = ax > 0 ? xp : (ax < 0 ? xm : x);
-        const int Y = ay > 0 ? yp : (ay < 0 ? ym : y);
-        const int Z = az > 0 ? zp : (az < 0 ? zm : z);
+        int X, Y, Z;
+        if constexpr (WALLS) {  // wall destinations are rebuilt when read
+            X = x + ax;
+            Y = y + ay;
+            Z = z + az;
+            if (X < 1 || Y < 1 || Z < 1 || X > kp.nx - 2 || Y > kp.ny - 2 || Z > kp.nz - 2) continue;
+        } else {
+            X = ax > 0 ? xp : (ax < 0 ? xm : x);
+            Y = ay > 0 ? yp : (ay < 0 ? ym : y);
+            Z = az > 0 ? zp : (az < 0 ? zm : z);
+        }
         hout[i * LP + fbase3(kp, X, Y, Z)] = post;
     }
 }
@@ -481,18 +563,9 @@ __device__ __forceinline__ void macros3(const K3& kp, const T* __restrict__ pop,
     m[4] = H;
     m[5] = m[6] = m[7] = m[8] = 0.0;
     if constexpr (NS) {  // u = n_sub u' and p = n_sub^2 p' (main-step units)
-        const size_t fb = fbase3(kp, x, y, z);
-        T mm[3] = {T(0), T(0), T(0)}, rest = T(0);
-        for (int i = 1; i < 19; ++i) {
-            const T h = flow[i * LP + fb];
-            rest += h;
-            mm[0] += T(EX19[i]) * h;
-            mm[1] += T(EY19[i]) * h;
-            mm[2] += T(EZ19[i]) * h;
-        }
-        const T fac = (T(3) - phi) * T(0.25);
-        const T u[3] = {mm[0] * fac, mm[1] * fac, mm[2] * fac};
-        const T p = T(0.5) * (rest - T(0.5) * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]));
+        T h[19], u[3], p;
+        flow_node3<T, WALLS>(kp, flow, x, y, z, phi, h);
+        flow_up3(h, phi, u, p);
         m[5] = kp.nsub_d * u[0];
         m[6] = kp.nsub_d * u[1];
         m[7] = kp.nsub_d * u[2];
@@ -605,7 +678,6 @@ int check3(const dlb3_params* p) {
         if (!(r > 0.0 && r < 2.0)) return fail3(DLB3_EINVAL, "relaxation rate outside (0,2)");
     if (p->use_ns != 0 && p->use_ns != 1) return fail3(DLB3_EINVAL, "use_ns must be 0 or 1");
     if (p->use_ns) {
-        if (p->walls) return fail3(DLB3_EINVAL, "the 3-D melt flow needs a periodic domain (walls = 0)");
         if (p->n_sub < 1 || !(p->nu > 0)) return fail3(DLB3_EINVAL, "melt flow needs n_sub >= 1 and nu > 0");
         const double s2 = 1.0 / (3.0 * p->nu / p->n_sub + 0.5);
         if (!(s2 > 0.0 && s2 < 2.0)) return fail3(DLB3_EINVAL, "relaxation rate outside (0,2)");
@@ -668,6 +740,7 @@ K3 make_k3(const dlb3_params* p, const Layout3& L) {
     k.theta0 = p->theta0;
     k.nsub_d = p->use_ns ? p->n_sub : 1;
     k.s2u = p->use_ns ? 1.0 / (3.0 * p->nu / p->n_sub + 0.5) : 1.0;
+    for (int a = 0; a < 3; ++a) k.uin[a] = p->use_ns ? p->u0[a] / p->n_sub : 0.0;
     return k;
 }
 }  // namespace
@@ -685,44 +758,38 @@ struct dlb3_solver {
 };
 
 template <class T, bool W> static void launch_step(dlb3_solver* s) {
-    if constexpr (!W) {
-        if (s->p.use_ns) {
-            hipLaunchKernelGGL((k3_step<T, false, true>), s->grid, s->block, 0, s->stream, s->kp, (const T*)s->pop(),
-                               (T*)(s->base + s->L.pop[1 - s->cur]), (const T*)s->flow(), (T*)(s->base + s->L.hist),
-                               s->hist_valid);
-            return;
-        }
+    if (s->p.use_ns) {
+        hipLaunchKernelGGL((k3_step<T, W, true>), s->grid, s->block, 0, s->stream, s->kp, (const T*)s->pop(),
+                           (T*)(s->base + s->L.pop[1 - s->cur]), (const T*)s->flow(), (T*)(s->base + s->L.hist),
+                           s->hist_valid);
+        return;
     }
     hipLaunchKernelGGL((k3_step<T, W, false>), s->grid, s->block, 0, s->stream, s->kp, (const T*)s->pop(),
                        (T*)(s->base + s->L.pop[1 - s->cur]), (const T*)nullptr, (T*)(s->base + s->L.hist),
                        s->hist_valid);
 }
 template <class T, bool W> static void launch_flow(dlb3_solver* s) {
-    hipLaunchKernelGGL((k3_flow<T>), s->grid, s->block, 0, s->stream, s->kp, (const T*)s->flow(),
+    hipLaunchKernelGGL((k3_flow<T, W>), s->grid, s->block, 0, s->stream, s->kp, (const T*)s->flow(),
                        (T*)(s->base + s->L.flow[1 - s->fcur]), (const T*)(s->base + s->L.hist));
 }
 template <class T, bool W>
 static void launch_set(dlb3_solver* s, const double* phi, const double* C, const double* th, const double* ux,
                        const double* uy, const double* uz) {
     const double* u0 = s->p.u0;
-    if constexpr (!W) {
-        if (s->p.use_ns) {
-            hipLaunchKernelGGL((k3_set<T, false, true>), s->grid, s->block, 0, s->stream, s->kp, phi, C, th, ux, uy, uz,
-                               u0[0], u0[1], u0[2], s->p.c_init_U, s->p.U0, s->p.C0, (T*)(s->base + s->L.pop[s->cur]),
-                               (T*)(s->base + s->L.flow[s->fcur]));
-            return;
-        }
+    if (s->p.use_ns) {
+        hipLaunchKernelGGL((k3_set<T, W, true>), s->grid, s->block, 0, s->stream, s->kp, phi, C, th, ux, uy, uz, u0[0],
+                           u0[1], u0[2], s->p.c_init_U, s->p.U0, s->p.C0, (T*)(s->base + s->L.pop[s->cur]),
+                           (T*)(s->base + s->L.flow[s->fcur]));
+        return;
     }
     hipLaunchKernelGGL((k3_set<T, W, false>), s->grid, s->block, 0, s->stream, s->kp, phi, C, th, ux, uy, uz, u0[0],
                        u0[1], u0[2], s->p.c_init_U, s->p.U0, s->p.C0, (T*)(s->base + s->L.pop[s->cur]), (T*)nullptr);
 }
 template <class T, bool W> static void launch_fields(dlb3_solver* s, double* out) {
-    if constexpr (!W) {
-        if (s->p.use_ns) {
-            hipLaunchKernelGGL((k3_fields<T, false, true>), s->grid, s->block, 0, s->stream, s->kp, (const T*)s->pop(),
-                               (const T*)s->flow(), out);
-            return;
-        }
+    if (s->p.use_ns) {
+        hipLaunchKernelGGL((k3_fields<T, W, true>), s->grid, s->block, 0, s->stream, s->kp, (const T*)s->pop(),
+                           (const T*)s->flow(), out);
+        return;
     }
     hipLaunchKernelGGL((k3_fields<T, W, false>), s->grid, s->block, 0, s->stream, s->kp, (const T*)s->pop(),
                        (const T*)nullptr, out);

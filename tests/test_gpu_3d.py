@@ -96,13 +96,16 @@ def test_3d_seed_grows_with_cubic_symmetry(dlb3):
     np.testing.assert_allclose(f[::-1], f, atol=1e-5)
 
 
-@pytest.mark.parametrize("precision,tol", [("f64", 1e-10), ("f32", 1e-4)])
-def test_3d_melt_flow_parity(dlb3, precision, tol):
-    """D3Q19 melt flow (periodic, three sub-steps per main step) past a
-    growing thermosolutal seed on a ragged 37 x 30 x 26 grid, every field
-    including the velocity and pressure, against the oracle."""
-    cfg = dict(_case(0, precision), use_ns=1, n_sub=3, nu=0.45, u0x=0.03, u0y=-0.01, u0z=0.005)
-    _say(f"case: 3-D melt flow 37x30x26 {precision}")
+@pytest.mark.parametrize("walls,precision,tol", [(0, "f64", 1e-10), (0, "f32", 1e-4), (1, "f64", 1e-10),
+                                                 (1, "f32", 1e-4)])
+def test_3d_melt_flow_parity(dlb3, walls, precision, tol):
+    """D3Q19 melt flow (three sub-steps per main step; periodic, or the
+    channel: inlet, outflow, free slip) past a growing thermosolutal seed on
+    a ragged 37 x 30 x 26 grid, every field including the velocity and
+    pressure, against the oracle."""
+    cfg = dict(_case(walls, precision), use_ns=1, n_sub=3, nu=0.45, u0x=0.03, u0y=-0.01 * (1 - walls),
+               u0z=0.005 * (1 - walls))
+    _say(f"case: 3-D melt flow 37x30x26 walls={walls} {precision}")
     o = O.Oracle3(cfg).init_seed()
     s = dlb3.Solver3(cfg).init_seed()
     for t in (1, 20, 60):
@@ -116,11 +119,10 @@ def test_3d_melt_flow_parity(dlb3, precision, tol):
     assert np.abs(s.fields()["ux"]).max() > 1e-3  # the flow is there
 
 
-def test_3d_flow_needs_a_periodic_domain(dlb3):
-    with pytest.raises(dlb3.Dlb3Error):
-        dlb3.Solver3(dict(_case(1, "f64"), use_ns=1, n_sub=3, nu=0.45))
-    with pytest.raises(dlb3.Dlb3Error):
-        dlb3.Solver3(dict(_case(0, "f64"), use_ns=1, n_sub=1, nu=0.45, u0x=0.5))  # Mach limit
+def test_3d_flow_refusals(dlb3):
+    for bad in (dict(u0x=0.5), dict(n_sub=0), dict(nu=0.0), dict(use_ns=2)):
+        with pytest.raises(dlb3.Dlb3Error):
+            dlb3.Solver3(dict(dict(_case(0, "f64"), use_ns=1, n_sub=1, nu=0.45), **bad))
 
 
 def test_3d_dendrite_in_melt_flow_grows_upstream(dlb3):
