@@ -153,3 +153,23 @@ def test_3d_variant_parity(dlb3, variant):
     gf, of = s.fields(), o.fields()
     for k in O.FIELDS:
         assert _rel(gf[k], of[k]) <= 1e-10, (k, _rel(gf[k], of[k]))
+
+
+def test_3d_dendrite_in_channel_flow(dlb3):
+    """A seed on the centre line of a 3-D channel (west inlet 0.02 lu per main
+    step, east outflow, free-slip side walls; 15 sub-steps), FP32: the arm
+    facing the inflow outgrows the downstream arm, the four arms across the
+    flow stay equal, and the side walls keep the normal velocity at zero."""
+    from paper_2209_01444_amd import bench3d
+    cfg = dict(bench3d.workload(97, "f32", flow=True), walls=1, seed_R=8.0, seed_x=48, seed_y=48, seed_z=48,
+               u0x=0.02)
+    s = dlb3.Solver3(cfg).init_seed().step(2000)
+    r = s.reduce()
+    tips = r["tip_s"]
+    _say(f"  tips {np.round(tips, 3)}")
+    assert r["nonfinite"] == 0
+    assert tips[3] > tips[0] + 0.5
+    across = tips[[1, 2, 4, 5]]
+    assert np.ptp(across) < 1e-2 * across.mean()
+    f = s.fields()
+    assert np.abs(f["uy"][:, 0, :]).max() < 1e-7 and np.abs(f["uz"][0]).max() < 1e-7
