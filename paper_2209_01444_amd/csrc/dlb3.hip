@@ -615,6 +615,22 @@ __global__ __launch_bounds__(BX* BY) void k3_partial(const K3 kp, const T* __res
     }
 }
 
+// Final FP64 sums of the per-workgroup partials (one workgroup).
+__global__ __launch_bounds__(256) void k3_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
+    __shared__ double sh[4][4];
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nb; b += 256)
+        for (int r = 0; r < 4; ++r) v[r] += part[(size_t)b * 4 + r];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int r = 0; r < 4; ++r)
+        for (int off = 32; off > 0; off >>= 1) v[r] += __shfl_xor(v[r], off, 64);
+    if (lane == 0)
+        for (int r = 0; r < 4; ++r) sh[r][wave] = v[r];
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int r = 0; r < 4; ++r) out[r] = ((sh[r][0] + sh[r][1]) + sh[r][2]) + sh[r][3];
+}
+
 // Tips along the six axis directions from the seed node (one thread each).
 template <class T, bool WALLS>
 __global__ void k3_tips(const K3 kp, const T* __restrict__ pop, int cx, int cy, int cz, double* __restrict__ out) {
@@ -919,28 +935,21 @@ int dlb3_reduce(dlb3_handle s, double* out) {
     if (!s || !out) return fail3(DLB3_EINVAL, "null handle or output");
     double* st = (double*)(s->base + s->L.stage);
     const size_t nb = (size_t)s->grid.x * s->grid.y;
-    if (4 * nb + 6 > 8 * s->L.plane) return fail3(DLB3_EINVAL, "staging area too small for the reduction");
-    double* tips = st + 4 * nb;
+    if (4 * nb + 10 > 8 * s->L.plane) return fail3(DLB3_EINVAL, "staging area too small for the reduction");
+    double* res = st + 4 * nb;  // 4 sums, then 6 tips
     DISPATCH3(s, launch_partial, st);
+    hipLaunchKernelGGL(k3_final, dim3(1), dim3(256), 0, s->stream, (const double*)st, (int)nb, res);
     const int cx = (int)std::lround(s->p.seed_x), cy = (int)std::lround(s->p.seed_y), cz = (int)std::lround(s->p.seed_z);
-    DISPATCH3(s, launch_tips, cx, cy, cz, tips);
-    double* host = new (std::nothrow) double[4 * nb + 6];
-    if (!host) return fail3(DLB3_ENOMEM, "host allocation failed");
-    hipError_t e = hipMemcpyAsync(host, st, (4 * nb + 6) * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    DISPATCH3(s, launch_tips, cx, cy, cz, res + 4);
+    double host[10];
+    hipError_t e = hipMemcpyAsync(host, res, sizeof host, hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-    if (e != hipSuccess) {
-        delete[] host;
-        return hip_fail3(e, "reduce copy");
-    }
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
-    for (size_t b = 0; b < nb; ++b)
-        for (int r = 0; r < 4; ++r) v[r] += host[b * 4 + r];
-    out[0] = v[0];
-    out[1] = v[1];
-    out[2] = v[2] / ((double)s->p.nx * s->p.ny * s->p.nz);
-    out[3] = v[3];
-    for (int a = 0; a < 6; ++a) out[4 + a] = host[4 * nb + a];
-    delete[] host;
+    if (e != hipSuccess) return hip_fail3(e, "reduce copy");
+    out[0] = host[0];
+    out[1] = host[1];
+    out[2] = host[2] / ((double)s->p.nx * s->p.ny * s->p.nz);
+    out[3] = host[3];
+    for (int a = 0; a < 6; ++a) out[4 + a] = host[4 + a];
     return DLB3_OK;
 }
 
