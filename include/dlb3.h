@@ -35,7 +35,17 @@ extern "C" {
 #endif
 
 enum { DLB3_OK = 0, DLB3_EINVAL = -1, DLB3_ENOMEM = -2, DLB3_EHIP = -3 };
-enum { DLB3_F64 = 0, DLB3_F32 = 1 }; /* storage and arithmetic type */
+/* Population storage / arithmetic type. */
+enum {
+    DLB3_F64 = 0,  /* FP64 storage, arithmetic and history                        */
+    DLB3_F32 = 1,  /* FP32 storage, arithmetic and history                        */
+    DLB3_F16S = 2, /* FP16 storage of each D3Q7 population's difference from its
+                      value in the initial far-field liquid at rest (phi = -1, C
+                      and theta as initialised, moving at u0 with melt flow) and
+                      of the D3Q19 populations (h_0 - rho0); FP32 arithmetic and
+                      history; FP64 reductions and field output                 */
+    DLB3_BF16S = 3 /* as DLB3_F16S with BF16 storage                              */
+};
 
 typedef struct dlb3_params {
     int32_t nx, ny, nz;   /* grid, >= 8 each                                     */
@@ -44,7 +54,7 @@ typedef struct dlb3_params {
     int32_t use_t;        /* 1 heat lattice; 0 isothermal (theta = theta0)       */
     int32_t h_quintic;    /* h(phi): 0 phi; 1 15(phi - 2phi^3/3 + phi^5/5)/8     */
     int32_t c_init_U;     /* initial solute: 0 uniform C0; 1 uniform U0          */
-    int32_t precision;    /* DLB3_F64 or DLB3_F32                                */
+    int32_t precision;    /* DLB3_F64, DLB3_F32, DLB3_F16S or DLB3_BF16S         */
     int32_t grad_iters;   /* cap of the local-gradient fixed point (0: default)  */
     double W0, tau0, eps4;       /* interface width, kinetic time, anisotropy    */
     double lambda, Mcinf, k;     /* coupling, M c_inf, partition coefficient     */

@@ -45,11 +45,12 @@ def run(n: int = 256, precision: str = "f32", steps: int = 200, warmup: int = 20
     ev[1].synchronize()
     ms = ev[0].elapsed_time(ev[1])
     nodes = n ** 3
-    word = 4 if precision == "f32" else 8
+    sp = {"f64": 8, "f32": 4}.get(precision, 2)  # population word
+    hw = 8 if precision == "f64" else 4  # history word (the arithmetic type)
     if flow:  # k3_step also reads the 19 flow populations and 6 more history words each way
-        bytes_per_node = (2 * (21 + 8) + 19) * word + 15 * (2 * 19 + 1) * word
+        bytes_per_node = (2 * 21 + 19) * sp + 2 * 8 * hw + 15 * (2 * 19 * sp + hw)
     else:
-        bytes_per_node = 2 * (21 + 2) * word
+        bytes_per_node = 2 * 21 * sp + 2 * 2 * hw
     r = s.reduce()
     return {"metric": "3-D coupled-lattice MLUPS", "value": round(nodes * steps / (ms * 1e-3) / 1e6, 1),
             "unit": "MLUPS", "precision": precision, "grid": [n, n, n], "steps": steps, "melt_flow": flow,

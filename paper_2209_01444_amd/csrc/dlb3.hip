@@ -24,6 +24,8 @@
 // stored as h_0 - rho0; hist[8][N] (phi, Q, C u, H u of the previous step;
 // after the phi/C/theta kernel hist[0] holds phi of time t for the flow
 // sub-steps); staging[8] double planes (fields in and out, reduction partials).
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -47,7 +49,24 @@ struct K3 {
     double W2t, inv_tau0, eps4, lambda, Mcinf, k, invD, s1c, s1t, jat, grad_tol2, theta0;
     double nsub_d, s2u;  // flow sub-steps per main step, flow relaxation rate
     double uin[3];       // inlet velocity per sub-step (walls)
+    float shift[21];     // 16-bit storage: rest-state value of each D3Q7 population
 };
+
+// Storage and arithmetic: FP64 and FP32 store what they compute; FP16 and
+// BF16 store the difference from the far-field rest state (shift) and
+// compute in FP32.  Flow populations are stored with h_0 - rho0, whose rest
+// state is zero.
+template <class S> struct Arith3 { using T = S; };
+template <> struct Arith3<__half> { using T = float; };
+template <> struct Arith3<__hip_bfloat16> { using T = float; };
+__device__ __forceinline__ double ld3(const double* p, size_t i, float) { return p[i]; }
+__device__ __forceinline__ float ld3(const float* p, size_t i, float) { return p[i]; }
+__device__ __forceinline__ float ld3(const __half* p, size_t i, float sh) { return __half2float(p[i]) + sh; }
+__device__ __forceinline__ float ld3(const __hip_bfloat16* p, size_t i, float sh) { return __bfloat162float(p[i]) + sh; }
+__device__ __forceinline__ void st3(double* p, size_t i, double v, float) { p[i] = v; }
+__device__ __forceinline__ void st3(float* p, size_t i, float v, float) { p[i] = v; }
+__device__ __forceinline__ void st3(__half* p, size_t i, float v, float sh) { p[i] = __float2half(v - sh); }
+__device__ __forceinline__ void st3(__hip_bfloat16* p, size_t i, float v, float sh) { p[i] = __float2bfloat16(v - sh); }
 
 // D3Q19 links: rest, faces +x +y +z -x -y -z, edges (xy) ++ -- +- -+, (xz) ++ -- +- -+, (yz) ++ -- +- -+
 static constexpr int EX19[19] = {0, 1, 0, 0, -1, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
@@ -131,20 +150,20 @@ template <class T> __device__ __forceinline__ void flow_up3(const T* h, T phi, T
 // u_f with its y, z components zeroed on y, z walls, p_b = 0; y and z faces
 // free slip, p_b = p_f.  phi_f: phi of the inward neighbour (a wall node
 // carries its neighbour's phi).
-template <class T, bool WALLS>
-__device__ __forceinline__ void flow_node3(const K3& kp, const T* __restrict__ hin, int x, int y, int z, T phi_f,
+template <class S, bool WALLS, class T = typename Arith3<S>::T>
+__device__ __forceinline__ void flow_node3(const K3& kp, const S* __restrict__ hin, int x, int y, int z, T phi_f,
                                            T* h) {
     const size_t LP = (size_t)kp.lp;
     if (!WALLS || !is_wall3(kp, x, y, z)) {
         const size_t fb = fbase3(kp, x, y, z);
 #pragma unroll
-        for (int i = 0; i < 19; ++i) h[i] = hin[i * LP + fb];
+        for (int i = 0; i < 19; ++i) h[i] = ld3(hin, i * LP + fb, 0.0f);
         return;
     }
     const size_t f = inward_f3(kp, x, y, z);
     T hf[19];
 #pragma unroll
-    for (int i = 0; i < 19; ++i) hf[i] = hin[i * LP + f];
+    for (int i = 0; i < 19; ++i) hf[i] = ld3(hin, i * LP + f, 0.0f);
     T uf[3], pf;
     flow_up3(hf, phi_f, uf, pf);
     const bool yw = y == 0 || y == kp.ny - 1, zw = z == 0 || z == kp.nz - 1;
@@ -234,9 +253,11 @@ __device__ __forceinline__ long long dest3(const K3& kp, int x, int y, int z, in
 }
 
 // One main step at every node: collide phi, C, theta (Secs. 3.1-3.3), push.
-template <class T, bool WALLS, bool NS>
-__global__ __launch_bounds__(BX* BY) void k3_step(const K3 kp, const T* __restrict__ pin, T* __restrict__ pout,
-                                                  const T* __restrict__ hin, T* __restrict__ hist, int hist_valid) {
+template <class S, bool WALLS, bool NS>
+__global__ __launch_bounds__(BX* BY) void k3_step(const K3 kp, const S* __restrict__ pin, S* __restrict__ pout,
+                                                  const S* __restrict__ hin, typename Arith3<S>::T* __restrict__ hist,
+                                                  int hist_valid) {
+    using T = typename Arith3<S>::T;
     int x, y, z;
     if (!node3(kp, x, y, z)) return;
     const size_t P = (size_t)kp.plane, LP = (size_t)kp.lp;
@@ -246,9 +267,9 @@ __global__ __launch_bounds__(BX* BY) void k3_step(const K3 kp, const T* __restri
     T f[7], n[7], g[7];
 #pragma unroll
     for (int i = 0; i < 7; ++i) {
-        f[i] = pin[i * LP + src];
-        n[i] = pin[(7 + i) * LP + src];
-        g[i] = kp.use_t ? pin[(14 + i) * LP + src] : T(0);
+        f[i] = ld3(pin, i * LP + src, kp.shift[i]);
+        n[i] = ld3(pin, (7 + i) * LP + src, kp.shift[7 + i]);
+        g[i] = kp.use_t ? ld3(pin, (14 + i) * LP + src, kp.shift[14 + i]) : T(0);
     }
     const T phi = ((((((f[0] + f[1]) + f[2]) + f[3]) + f[4]) + f[5]) + f[6]);
     const T C = ((((((n[0] + n[1]) + n[2]) + n[3]) + n[4]) + n[5]) + n[6]);
@@ -262,7 +283,7 @@ __global__ __launch_bounds__(BX* BY) void k3_step(const K3 kp, const T* __restri
     T u[3] = {T(0), T(0), T(0)};
     if constexpr (NS) {
         T h[19];
-        flow_node3<T, WALLS>(kp, hin, x, y, z, phi, h);
+        flow_node3<S, WALLS>(kp, hin, x, y, z, phi, h);
         T m[3] = {T(0), T(0), T(0)};
 #pragma unroll
         for (int i = 1; i < 19; ++i) {
@@ -362,32 +383,33 @@ __global__ __launch_bounds__(BX* BY) void k3_step(const K3 kp, const T* __restri
     }
     // push; phi: f(y, t+1) = f(y, t) + (post - f(y, t)) / a_s^2 (collision site's a_s)
     if (!wall) {
-        pout[own] = f[0] + (pf[0] - f[0]) * inv_a2;
-        pout[7 * LP + own] = pn[0];
-        if (kp.use_t) pout[14 * LP + own] = pg[0];
+        st3(pout, own, f[0] + (pf[0] - f[0]) * inv_a2, kp.shift[0]);
+        st3(pout, 7 * LP + own, pn[0], kp.shift[7]);
+        if (kp.use_t) st3(pout, 14 * LP + own, pg[0], kp.shift[14]);
     }
 #pragma unroll
     for (int i = 1; i < 7; ++i) {
         const long long d = dest3<WALLS>(kp, x, y, z, i);
         if (d < 0) continue;
-        const T fold = pin[i * LP + (size_t)d];
-        pout[i * LP + (size_t)d] = fold + (pf[i] - fold) * inv_a2;
-        pout[(7 + i) * LP + (size_t)d] = pn[i];
-        if (kp.use_t) pout[(14 + i) * LP + (size_t)d] = pg[i];
+        const T fold = ld3(pin, i * LP + (size_t)d, kp.shift[i]);
+        st3(pout, i * LP + (size_t)d, fold + (pf[i] - fold) * inv_a2, kp.shift[i]);
+        st3(pout, (7 + i) * LP + (size_t)d, pn[i], kp.shift[7 + i]);
+        if (kp.use_t) st3(pout, (14 + i) * LP + (size_t)d, pg[i], kp.shift[14 + i]);
     }
 }
 
 // One melt-flow sub-step (Sec. 3.4, D3Q19, periodic) at the frozen phi of
 // time t (hist[0]), push streaming.
-template <class T, bool WALLS>
-__global__ __launch_bounds__(BX* BY) void k3_flow(const K3 kp, const T* __restrict__ hin, T* __restrict__ hout,
-                                                  const T* __restrict__ phi_t) {
+template <class S, bool WALLS>
+__global__ __launch_bounds__(BX* BY) void k3_flow(const K3 kp, const S* __restrict__ hin, S* __restrict__ hout,
+                                                  const typename Arith3<S>::T* __restrict__ phi_t) {
+    using T = typename Arith3<S>::T;
     int x, y, z;
     if (!node3(kp, x, y, z)) return;
     const size_t LP = (size_t)kp.lp;
     const T phi = phi_t[id3(kp, x, y, z)];
     T h[19];
-    flow_node3<T, WALLS>(kp, hin, x, y, z, phi, h);
+    flow_node3<S, WALLS>(kp, hin, x, y, z, phi, h);
     T m[3] = {T(0), T(0), T(0)}, rest = T(0);
 #pragma unroll
     for (int i = 1; i < 19; ++i) {
@@ -446,7 +468,7 @@ __global__ __launch_bounds__(BX* BY) void k3_flow(const K3 kp, const T* __restri
             Y = ay > 0 ? yp : (ay < 0 ? ym : y);
             Z = az > 0 ? zp : (az < 0 ? zm : z);
         }
-        hout[i * LP + fbase3(kp, X, Y, Z)] = post;
+        st3(hout, i * LP + fbase3(kp, X, Y, Z), post, 0.0f);
     }
 }
 
@@ -469,6 +491,7 @@ __global__ __launch_bounds__(BX* BY) void k3_set(const K3 kp, const double* __re
                                                  const double* __restrict__ uzin, double u0x, double u0y, double u0z,
                                                  int c_init_U, double U0, double C0, T* __restrict__ pop,
                                                  T* __restrict__ flow) {
+    using A = typename Arith3<T>::T;
     int x, y, z;
     if (!node3(kp, x, y, z)) return;
     const size_t idx = id3(kp, x, y, z);
@@ -517,17 +540,17 @@ __global__ __launch_bounds__(BX* BY) void k3_set(const K3 kp, const double* __re
     }
     const double H = th - 0.5 * hp;
     const size_t LP = (size_t)kp.lp, o = base3(kp, x, y, z);
-    pop[o] = T(0.25 * ph);
-    pop[7 * LP + o] = T(C - 0.75 * qU);
-    pop[14 * LP + o] = T(kp.use_t ? 0.25 * th - 0.5 * hp : 0.0);
+    st3(pop, o, A(0.25 * ph), kp.shift[0]);
+    st3(pop, 7 * LP + o, A(C - 0.75 * qU), kp.shift[7]);
+    st3(pop, 14 * LP + o, A(kp.use_t ? 0.25 * th - 0.5 * hp : 0.0), kp.shift[14]);
     for (int d = 0; d < 3; ++d) {
         // w1 c.(C u)/cs^2 = +-(C u)/2 on the D3Q7 links
-        pop[(1 + d) * LP + o] = T(0.125 * ph + 0.5 * m1[d]);
-        pop[(4 + d) * LP + o] = T(0.125 * ph - 0.5 * m1[d]);
-        pop[(8 + d) * LP + o] = T(0.125 * qU + 0.5 * C * u[d]);
-        pop[(11 + d) * LP + o] = T(0.125 * qU - 0.5 * C * u[d]);
-        pop[(15 + d) * LP + o] = T(kp.use_t ? 0.125 * th + 0.5 * H * u[d] : 0.0);
-        pop[(18 + d) * LP + o] = T(kp.use_t ? 0.125 * th - 0.5 * H * u[d] : 0.0);
+        st3(pop, (1 + d) * LP + o, A(0.125 * ph + 0.5 * m1[d]), kp.shift[1 + d]);
+        st3(pop, (4 + d) * LP + o, A(0.125 * ph - 0.5 * m1[d]), kp.shift[4 + d]);
+        st3(pop, (8 + d) * LP + o, A(0.125 * qU + 0.5 * C * u[d]), kp.shift[8 + d]);
+        st3(pop, (11 + d) * LP + o, A(0.125 * qU - 0.5 * C * u[d]), kp.shift[11 + d]);
+        st3(pop, (15 + d) * LP + o, A(kp.use_t ? 0.125 * th + 0.5 * H * u[d] : 0.0), kp.shift[15 + d]);
+        st3(pop, (18 + d) * LP + o, A(kp.use_t ? 0.125 * th - 0.5 * H * u[d] : 0.0), kp.shift[18 + d]);
     }
     if constexpr (NS) {  // flow at p = 0, u' = u/n_sub (h_0 shifted by -rho0)
         const double v[3] = {u[0] / kp.nsub_d, u[1] / kp.nsub_d, u[2] / kp.nsub_d};
@@ -537,21 +560,22 @@ __global__ __launch_bounds__(BX* BY) void k3_set(const K3 kp, const double* __re
             const int nn = EX19[i] * EX19[i] + EY19[i] * EY19[i] + EZ19[i] * EZ19[i];
             const double w = nn == 0 ? 1.0 / 3.0 : (nn == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
             const double cu = EX19[i] * v[0] + EY19[i] * v[1] + EZ19[i] * v[2];
-            flow[i * LP + fb] = T(w * (3.0 * cu + 4.5 * cu * cu - 1.5 * vv));
+            st3(flow, i * LP + fb, A(w * (3.0 * cu + 4.5 * cu * cu - 1.5 * vv)), 0.0f);
         }
     }
 }
 
-template <class T, bool WALLS, bool NS>
-__device__ __forceinline__ void macros3(const K3& kp, const T* __restrict__ pop, const T* __restrict__ flow, int x,
+template <class S, bool WALLS, bool NS>
+__device__ __forceinline__ void macros3(const K3& kp, const S* __restrict__ pop, const S* __restrict__ flow, int x,
                                         int y, int z, double* m) {
+    using T = typename Arith3<S>::T;
     const size_t LP = (size_t)kp.lp;
     const size_t src = (WALLS && is_wall3(kp, x, y, z)) ? inward3(kp, x, y, z) : base3(kp, x, y, z);
     T phi = T(0), C = T(0), H = T(0);
     for (int i = 0; i < 7; ++i) {
-        phi += pop[i * LP + src];
-        C += pop[(7 + i) * LP + src];
-        if (kp.use_t) H += pop[(14 + i) * LP + src];
+        phi += ld3(pop, i * LP + src, kp.shift[i]);
+        C += ld3(pop, (7 + i) * LP + src, kp.shift[7 + i]);
+        if (kp.use_t) H += ld3(pop, (14 + i) * LP + src, kp.shift[14 + i]);
     }
     const T k = T(kp.k);
     const T hp = h_of3(phi, kp.h_quintic);
@@ -564,7 +588,7 @@ __device__ __forceinline__ void macros3(const K3& kp, const T* __restrict__ pop,
     m[5] = m[6] = m[7] = m[8] = 0.0;
     if constexpr (NS) {  // u = n_sub u' and p = n_sub^2 p' (main-step units)
         T h[19], u[3], p;
-        flow_node3<T, WALLS>(kp, flow, x, y, z, phi, h);
+        flow_node3<S, WALLS>(kp, flow, x, y, z, phi, h);
         flow_up3(h, phi, u, p);
         m[5] = kp.nsub_d * u[0];
         m[6] = kp.nsub_d * u[1];
@@ -682,7 +706,7 @@ int check3(const dlb3_params* p) {
     if ((double)p->nx * p->ny * p->nz > 2.0e9) return fail3(DLB3_EINVAL, "grid too large");
     if ((double)((p->nx + BX - 1) / BX) * ((p->ny + BY - 1) / BY) * p->nz > 2.0e9)
         return fail3(DLB3_EINVAL, "too many workgroups");
-    if (p->precision != DLB3_F64 && p->precision != DLB3_F32) return fail3(DLB3_EINVAL, "unknown precision");
+    if (p->precision < DLB3_F64 || p->precision > DLB3_BF16S) return fail3(DLB3_EINVAL, "unknown precision");
     if (p->walls != 0 && p->walls != 1) return fail3(DLB3_EINVAL, "walls must be 0 or 1");
     if (!(p->W0 > 0 && p->tau0 > 0 && p->D > 0 && p->alpha > 0)) return fail3(DLB3_EINVAL, "W0, tau0, D, alpha must be > 0");
     if (!(p->k > 0 && p->k < 1)) return fail3(DLB3_EINVAL, "partition coefficient k must be in (0,1)");
@@ -709,7 +733,8 @@ Layout3 layout3(const dlb3_params* p) {
     const size_t N = (size_t)p->nx * p->ny * p->nz;
     L.plane = (N + 63) & ~size_t(63);
     L.lp = ((size_t)p->nx * p->ny + 63) & ~size_t(63);
-    const size_t sb = p->precision == DLB3_F64 ? 8 : 4;
+    const size_t sb = p->precision == DLB3_F64 ? 8 : (p->precision == DLB3_F32 ? 4 : 2);
+    const size_t hb = p->precision == DLB3_F64 ? 8 : 4;  // history in the arithmetic type
     size_t off = 0;
     for (int b = 0; b < 2; ++b) {
         L.pop[b] = off;
@@ -720,11 +745,33 @@ Layout3 layout3(const dlb3_params* p) {
         if (p->use_ns) off = align256(off + (size_t)p->nz * 19 * L.lp * sb);
     }
     L.hist = off;
-    off = align256(off + (p->use_ns ? 8 : 2) * L.plane * sb);
+    off = align256(off + (p->use_ns ? 8 : 2) * L.plane * hb);
     L.stage = off;
     off = align256(off + 8 * L.plane * sizeof(double));
     L.total = off;
     return L;
+}
+
+// Rest state of the D3Q7 populations (the 16-bit storage shifts): liquid
+// phi = -1 with the initial far-field solute and temperature, moving at the
+// initial velocity when the melt flows.
+void rest_shifts3(const dlb3_params* p, float* sh) {
+    const double k = p->k, phi = -1.0;
+    const double C = p->c_init_U ? 1.0 + (1.0 - k) * p->U0 : p->C0;
+    const double U = (C - 1.0) / (1.0 - k);  // phi = -1: 1 + k - (1 - k) phi = 2
+    const double qU = 0.5 * (1.0 - phi) * U, hp = -1.0;  // h(-1) = -1 for both forms
+    const double th = p->theta0, H = th - 0.5 * hp;
+    sh[0] = (float)(0.25 * phi);
+    sh[7] = (float)(C - 0.75 * qU);
+    sh[14] = (float)(0.25 * th - 0.5 * hp);
+    for (int d = 0; d < 3; ++d) {
+        const double u = p->use_ns ? p->u0[d] : 0.0;
+        sh[1 + d] = sh[4 + d] = (float)(0.125 * phi);
+        sh[8 + d] = (float)(0.125 * qU + 0.5 * C * u);
+        sh[11 + d] = (float)(0.125 * qU - 0.5 * C * u);
+        sh[15 + d] = (float)(0.125 * th + 0.5 * H * u);
+        sh[18 + d] = (float)(0.125 * th - 0.5 * H * u);
+    }
 }
 
 K3 make_k3(const dlb3_params* p, const Layout3& L) {
@@ -757,6 +804,7 @@ K3 make_k3(const dlb3_params* p, const Layout3& L) {
     k.nsub_d = p->use_ns ? p->n_sub : 1;
     k.s2u = p->use_ns ? 1.0 / (3.0 * p->nu / p->n_sub + 0.5) : 1.0;
     for (int a = 0; a < 3; ++a) k.uin[a] = p->use_ns ? p->u0[a] / p->n_sub : 0.0;
+    if (p->precision == DLB3_F16S || p->precision == DLB3_BF16S) rest_shifts3(p, k.shift);
     return k;
 }
 }  // namespace
@@ -776,17 +824,17 @@ struct dlb3_solver {
 template <class T, bool W> static void launch_step(dlb3_solver* s) {
     if (s->p.use_ns) {
         hipLaunchKernelGGL((k3_step<T, W, true>), s->grid, s->block, 0, s->stream, s->kp, (const T*)s->pop(),
-                           (T*)(s->base + s->L.pop[1 - s->cur]), (const T*)s->flow(), (T*)(s->base + s->L.hist),
-                           s->hist_valid);
+                           (T*)(s->base + s->L.pop[1 - s->cur]), (const T*)s->flow(),
+                           (typename Arith3<T>::T*)(s->base + s->L.hist), s->hist_valid);
         return;
     }
     hipLaunchKernelGGL((k3_step<T, W, false>), s->grid, s->block, 0, s->stream, s->kp, (const T*)s->pop(),
-                       (T*)(s->base + s->L.pop[1 - s->cur]), (const T*)nullptr, (T*)(s->base + s->L.hist),
-                       s->hist_valid);
+                       (T*)(s->base + s->L.pop[1 - s->cur]), (const T*)nullptr,
+                       (typename Arith3<T>::T*)(s->base + s->L.hist), s->hist_valid);
 }
 template <class T, bool W> static void launch_flow(dlb3_solver* s) {
     hipLaunchKernelGGL((k3_flow<T, W>), s->grid, s->block, 0, s->stream, s->kp, (const T*)s->flow(),
-                       (T*)(s->base + s->L.flow[1 - s->fcur]), (const T*)(s->base + s->L.hist));
+                       (T*)(s->base + s->L.flow[1 - s->fcur]), (const typename Arith3<T>::T*)(s->base + s->L.hist));
 }
 template <class T, bool W>
 static void launch_set(dlb3_solver* s, const double* phi, const double* C, const double* th, const double* ux,
@@ -821,12 +869,22 @@ template <class T, bool W> static void launch_tips(dlb3_solver* s, int cx, int c
 
 #define DISPATCH3(s, fn, ...)                                                     \
     do {                                                                          \
-        if ((s)->p.precision == DLB3_F64) {                                       \
+        switch ((s)->p.precision) {                                               \
+        case DLB3_F64:                                                            \
             if ((s)->p.walls) fn<double, true>(s, ##__VA_ARGS__);                 \
             else fn<double, false>(s, ##__VA_ARGS__);                             \
-        } else {                                                                  \
+            break;                                                                \
+        case DLB3_F32:                                                            \
             if ((s)->p.walls) fn<float, true>(s, ##__VA_ARGS__);                  \
             else fn<float, false>(s, ##__VA_ARGS__);                              \
+            break;                                                                \
+        case DLB3_F16S:                                                           \
+            if ((s)->p.walls) fn<__half, true>(s, ##__VA_ARGS__);                 \
+            else fn<__half, false>(s, ##__VA_ARGS__);                             \
+            break;                                                                \
+        default:                                                                  \
+            if ((s)->p.walls) fn<__hip_bfloat16, true>(s, ##__VA_ARGS__);         \
+            else fn<__hip_bfloat16, false>(s, ##__VA_ARGS__);                     \
         }                                                                         \
     } while (0)
 

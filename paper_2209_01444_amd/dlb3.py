@@ -11,7 +11,7 @@ import numpy as np
 from paper_2209_01444_amd import dlb as _dlb
 
 DLB3_OK, DLB3_EINVAL = 0, -1
-PRECISION = {"f64": 0, "f32": 1}
+PRECISION = {"f64": 0, "f32": 1, "f16s": 2, "bf16s": 3}
 FIELDS = ("phi", "C", "U", "theta", "ux", "uy", "uz", "p")
 EXPORTS = ("dlb3_state_bytes", "dlb3_create", "dlb3_destroy", "dlb3_init_seed", "dlb3_set_fields",
            "dlb3_step", "dlb3_get_fields", "dlb3_reduce", "dlb3_last_error")

@@ -130,3 +130,20 @@ def test_3d_abi_exports_and_validation():
         q = dlb3.make_params(dict(dict(nx=32, ny=30, nz=28), **bad))
         assert lib.dlb3_state_bytes(ctypes.byref(q)) == 0, bad
         assert lib.dlb3_last_error()
+
+
+def test_3d_16bit_storage_sizes():
+    """FP16 and BF16 storage hold each population in two bytes; the history
+    stays in FP32 (the arithmetic type)."""
+    from paper_2209_01444_amd import dlb3
+    lib = dlb3.load_library()
+    size = {}
+    for prec in ("f32", "f16s", "bf16s"):
+        p = dlb3.make_params(dict(nx=32, ny=30, nz=28, precision=prec))
+        size[prec] = lib.dlb3_state_bytes(ctypes.byref(p))
+    assert size["f16s"] == size["bf16s"]
+    lp = 32 * 30  # one layer of one population, padded to 64 elements
+    lp = (lp + 63) // 64 * 64
+    assert size["f32"] - size["f16s"] >= 2 * 21 * 28 * lp * 2
+    q = dlb3.make_params(dict(nx=32, ny=30, nz=28, precision=4))
+    assert lib.dlb3_state_bytes(ctypes.byref(q)) == 0

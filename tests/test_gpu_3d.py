@@ -173,3 +173,63 @@ def test_3d_dendrite_in_channel_flow(dlb3):
     assert np.ptp(across) < 1e-2 * across.mean()
     f = s.fields()
     assert np.abs(f["uy"][:, 0, :]).max() < 1e-7 and np.abs(f["uz"][0]).max() < 1e-7
+
+
+# 16-bit storage: a stored difference from the rest state of size up to 1
+# (a solid node's phi and C rest populations) rounds to within 2^-12 (FP16)
+# or 2^-9 (BF16) of it each step; diffusion and relaxation damp what
+# accumulates, so phi, C and theta stay within some tens (FP16) or a few
+# hundred (BF16) such roundings of the FP64 fields over 80 steps (absolute
+# error, all three are of order one).  U = (2C/(1 + k - (1 - k) phi) - 1)/(1 - k)
+# magnifies an error of C by up to 1/(k (1 - k)) in the solid.
+TOL16 = {"f16s": 1e-2, "bf16s": 8e-2}
+
+
+def _abs16(gf, of, k, fields):
+    scale = {"U": 1.0 / (k * (1.0 - k))}
+    return {f: float(np.abs(gf[f] - of[f]).max()) / scale.get(f, 1.0) for f in fields}
+
+
+@pytest.mark.parametrize("walls", [0, 1])
+@pytest.mark.parametrize("precision", ["f16s", "bf16s"])
+def test_3d_parity_16bit_storage(dlb3, walls, precision):
+    """The thermosolutal seed of test_3d_parity with 16-bit shifted storage
+    (FP32 arithmetic) against the FP64 oracle; sums of C and H stay within
+    the rounding of the stored populations."""
+    cfg = _case(walls, precision)
+    tol = TOL16[precision]
+    _say(f"case: 3-D seed 37x30x26 walls={walls} {precision}")
+    o = O.Oracle3(dict(cfg, precision="f64")).init_seed()
+    s = dlb3.Solver3(cfg).init_seed()
+    for t in (1, 20, 80):
+        o.step(t - o.step_count)
+        s.step(t - s.step_count)
+        errs = _abs16(s.fields(), o.fields(), cfg["k"], O.FIELDS)
+        _say(f"  t={t} " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+        assert max(errs.values()) <= tol, errs
+    rg, ro = s.reduce(), o.reduce()
+    for key in ("sum_C", "sum_H"):
+        assert rg[key] == pytest.approx(ro[key], rel=tol / 10, abs=tol), key
+    assert rg["solid_fraction"] == pytest.approx(ro["solid_fraction"], rel=tol)
+    assert rg["nonfinite"] == 0
+
+
+def test_3d_melt_flow_16bit_storage(dlb3):
+    """The periodic melt-flow case with FP16 storage of every lattice
+    against the FP64 oracle, velocity and pressure included."""
+    cfg = dict(_case(0, "f16s"), use_ns=1, n_sub=3, nu=0.45, u0x=0.03, u0y=-0.01, u0z=0.005)
+    tol = TOL16["f16s"]
+    _say("case: 3-D melt flow 37x30x26 walls=0 f16s")
+    o = O.Oracle3(dict(cfg, precision="f64")).init_seed()
+    s = dlb3.Solver3(cfg).init_seed()
+    for t in (1, 20, 60):
+        o.step(t - o.step_count)
+        s.step(t - s.step_count)
+        gf, of = s.fields(), o.fields()
+        errs = _abs16(gf, of, cfg["k"], O.FIELDS)
+        # velocity and pressure relative to their largest magnitude
+        errs.update({k: _rel(gf[k], of[k]) for k in O.FLOW_FIELDS})
+        _say(f"  t={t} " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+        bad = {k: v for k, v in errs.items() if v > (10 * tol if k == "p" else tol)}
+        assert not bad, bad
+
