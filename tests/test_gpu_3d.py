@@ -214,12 +214,15 @@ def test_3d_parity_16bit_storage(dlb3, walls, precision):
     assert rg["nonfinite"] == 0
 
 
-def test_3d_melt_flow_16bit_storage(dlb3):
-    """The periodic melt-flow case with FP16 storage of every lattice
-    against the FP64 oracle, velocity and pressure included."""
-    cfg = dict(_case(0, "f16s"), use_ns=1, n_sub=3, nu=0.45, u0x=0.03, u0y=-0.01, u0z=0.005)
-    tol = TOL16["f16s"]
-    _say("case: 3-D melt flow 37x30x26 walls=0 f16s")
+@pytest.mark.parametrize("walls,precision", [(0, "f16s"), (1, "f16s"), (0, "bf16s"), (1, "bf16s")])
+def test_3d_melt_flow_16bit_storage(dlb3, walls, precision):
+    """The melt-flow case of test_3d_melt_flow_parity (periodic, or the
+    channel) with 16-bit storage of every lattice against the FP64 oracle,
+    velocity and pressure included."""
+    cfg = dict(_case(walls, precision), use_ns=1, n_sub=3, nu=0.45, u0x=0.03, u0y=-0.01 * (1 - walls),
+               u0z=0.005 * (1 - walls))
+    tol = TOL16[precision]
+    _say(f"case: 3-D melt flow 37x30x26 walls={walls} {precision}")
     o = O.Oracle3(dict(cfg, precision="f64")).init_seed()
     s = dlb3.Solver3(cfg).init_seed()
     for t in (1, 20, 60):
