@@ -20,6 +20,9 @@ TS = "tests/test_oracle_stencil.py::"
 TH = "tests/test_oracle_heat_substeps.py::"
 TF = "tests/test_oracle_farfield.py::"
 TFO = "tests/test_oracle_force.py::"
+TC = "tests/test_oracle_coupling_pins.py::"
+# the anti-trapping current of Sec. 2 as the oracle writes it
+JAT = ("double c = -1.0 / (2.0 * sqrt(2.0)) * p->W0 * (1.0 + (1.0 - p->k) * U) * dphi / gnorm;")
 
 MUTATIONS = [
     ("force: K pressure term dropped", "double K = 2.0 * (s2 - 3.0 * s4 + s2 * s4) / (9.0 * s2 * s4);",
@@ -91,11 +94,25 @@ MUTATIONS = [
      TR + "test_restart_at_own_fields_with_both_flags_changes_nothing"),
     ("restart drops the rates", "s->Q_prev[id] = Q - (Qo - s->Q_prev[id]);", "s->Q_prev[id] = Q;",
      TR + "test_restart_at_own_fields_with_both_flags_changes_nothing"),
+    ("anti-trapping current dropped", JAT, "double c = 0.0;", TC + "test_planar_alloy_front_does_not_trap_solute[2]"),
+    ("anti-trapping without 1/(2 sqrt 2)", JAT, JAT.replace("-1.0 / (2.0 * sqrt(2.0))", "-1.0"),
+     TC + "test_planar_alloy_front_does_not_trap_solute[2]"),
+    ("sign of the anti-trapping current", JAT, JAT.replace("-1.0 / (2.0", "1.0 / (2.0"),
+     TC + "test_planar_alloy_front_does_not_trap_solute[2]"),
+    ("anti-trapping with W0^2", JAT, JAT.replace("p->W0 *", "p->W0 * p->W0 *"),
+     TC + "test_planar_alloy_front_does_not_trap_solute[2]"),
+    ("sign of the torque", "T -= rx * Fb[1] - ry * Fb[0];", "T += rx * Fb[1] - ry * Fb[0];",
+     TC + "test_force_and_torque_balance_the_fluid_momentum"),
+    ("torque about the origin", "double rx = (x % s->nx) - cx, ry = (x / s->nx) - cy;",
+     "double rx = (x % s->nx), ry = (x / s->nx);", TC + "test_force_and_torque_balance_the_fluid_momentum"),
+    ("torque with transposed cross product", "T -= rx * Fb[1] - ry * Fb[0];", "T -= rx * Fb[0] - ry * Fb[1];",
+     TC + "test_force_and_torque_balance_the_fluid_momentum"),
 ]
 
 
 SRC3 = os.path.join(ROOT, "oracle", "dlb3_oracle.c")
 T3 = "tests/test_oracle_3d.py::"
+JAT3 = "double c = -1.0 / (2.0 * sqrt(2.0)) * p->W0 * (1.0 + (1.0 - p->k) * U) * dphi / gn;"
 # mistakes planted in the 3-D oracle (dlb3_oracle.c)
 MUTATIONS_3D = [
     ("3-D: lattice sound speed 1/3 in s1", "return 1.0 / (as * as * p->W0 * p->W0 / (p->tau0 * CS2) + 0.5);",
@@ -112,6 +129,14 @@ MUTATIONS_3D = [
      "(CX[i] * H * u[0] + CY[i] * H * u[1] + CZ[i] * H * u[2]) * 3.0;", T3 + "test_advected_heat_mode_keeps_alpha_and_u"),
     ("3-D: anisotropy strength", "out[1 + a] = g2 * as * (4.0 * eps * dsum);", "out[1 + a] = g2 * as * (3.0 * eps * dsum);",
      T3 + "test_torque_vector_is_the_gradient_of_a_s"),
+    ("3-D: anti-trapping current dropped", JAT3, "double c = 0.0;",
+     TC + "test_planar_alloy_front_does_not_trap_solute[3]"),
+    ("3-D: anti-trapping without 1/(2 sqrt 2)", JAT3, JAT3.replace("-1.0 / (2.0 * sqrt(2.0))", "-1.0"),
+     TC + "test_planar_alloy_front_does_not_trap_solute[3]"),
+    ("3-D: sign of the anti-trapping current", JAT3, JAT3.replace("-1.0 / (2.0", "1.0 / (2.0"),
+     TC + "test_planar_alloy_front_does_not_trap_solute[3]"),
+    ("3-D: anti-trapping with W0^2", JAT3, JAT3.replace("p->W0 *", "p->W0 * p->W0 *"),
+     TC + "test_planar_alloy_front_does_not_trap_solute[3]"),
 ]
 
 
