@@ -49,6 +49,14 @@ def algorithmic_bytes(cfg: dict) -> dict:
 # VALU issue rate of the chip: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64
 # vector instruction per SIMD every 4 cycles
 PEAK_VALU_INSTS_PER_S = 256 * 4 * 2.4e9 / 4
+# Vector arithmetic peak without packed FP32 (kept out of the build): 256 CUs
+# x 4 SIMDs x 16 lanes x 2 flops per FMA x 2.4 GHz = 78.6 TFLOP/s, which is
+# also the FP64 vector peak.  (Packed FP32 doubles it to the published 157.3.)
+PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# Flops of one D2Q9 flow node and sub-step as the collision computes it
+# (moments, velocity and pressure, relaxation, inverse transform; an FMA
+# counts 2): 70.  The streaming moves data only.
+FLOW_FLOP_PER_NODE_SUBSTEP = 70
 
 
 def _profile_record(kind: str, kernel: str, workload: str) -> dict | None:
@@ -97,6 +105,57 @@ def cpu_baseline(cfg, noise, budget_s: float = 12.0) -> dict:
                       f"(FP64 oracle, OpenMP), {el:.1f} s"}
 
 
+def measure(cfg: dict, noise, steps: int, warmup: int, timed_launch_steps: int) -> dict:
+    """Whole-step rate and per-kernel launch times (HIP events on the
+    solver's stream) of one workload, inputs resident in HBM."""
+    import torch
+
+    from paper_2209_01444_amd import dlb
+
+    solver = dlb.Solver(cfg).init_seed(noise)
+    nodes = cfg["nx"] * cfg["ny"]
+    solver.step(warmup)
+    solver.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solver.step(steps)
+    solver.sync()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    tk = solver.step_timed(timed_launch_steps)
+    red = solver.reduce(allow_nonfinite=True)
+    out = {"solver": solver, "nodes": nodes, "elapsed": el, "mlups": nodes * steps / el / 1e6,
+           "ms_per_step": el / steps * 1e3, "tk": tk, "reduce": red}
+    out["step_count"] = solver.step_count
+    return out
+
+
+def kernel_rooflines(cfg: dict, m: dict) -> dict:
+    """Per-kernel figures of one measurement: the phi/C/theta kernel against
+    the HBM peak (its algorithmic bytes), the flow launch against the vector
+    arithmetic peak when it fuses several sub-steps (its data stays on chip
+    between them), else against the HBM peak."""
+    ab = algorithmic_bytes(cfg)
+    tk, nodes = m["tk"], m["nodes"]
+    flow_ms = tk["ms_flow"] / max(tk["launches_flow"], 1)
+    pct_ms = tk["ms_pct"] / max(tk["launches_pct"], 1)
+    subs = cfg["n_sub"] * tk["launches_pct"] / max(tk["launches_flow"], 1)
+    pct_gbs = ab["pct"] * nodes / (pct_ms * 1e-3) / 1e9
+    flow = {"avg_ms": round(flow_ms, 5), "substeps": subs}
+    # bytes a flow launch must move at least: its populations and phi in, its populations out
+    flow_min_bytes = ab["flow"] * nodes
+    flow["hbm_min_bytes"] = flow_min_bytes
+    flow["hbm_min_frac"] = round(flow_min_bytes / (flow_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
+    flops = FLOW_FLOP_PER_NODE_SUBSTEP * nodes * subs
+    flow["flop"] = flops
+    flow["TFLOPs"] = round(flops / (flow_ms * 1e-3) / 1e12, 3)
+    flow["alu_frac"] = round(flops / (flow_ms * 1e-3) / 1e12 / PEAK_VALU_TFLOPS, 4)
+    return {"k_pct": {"avg_ms": round(pct_ms, 5), "GBs": round(pct_gbs, 1),
+                      "hbm_frac": round(pct_gbs / PEAK_HBM_GBS, 4), "bytes": ab["pct"] * nodes},
+            "flow_launch": flow,
+            "whole_step_algorithmic_GBs": round(ab["step"] * nodes / (m["ms_per_step"] * 1e-3) / 1e9, 1)}
+
+
 def calibrate_copy(nbytes: int = 1 << 30, reps: int = 5):
     import ctypes
 
@@ -138,6 +197,10 @@ def main():
     ap.add_argument("--n-sub-t", type=int, default=1,
                     help="heat sub-steps per main step (multi-time-scaling variant; the method's default is 1)")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--hbm-size", type=int, default=4096,
+                    help="also measure the workload at this grid size, whose state does not fit the "
+                         "last-level cache (0: skip)")
+    ap.add_argument("--hbm-steps", type=int, default=100)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -156,74 +219,80 @@ def main():
     cfg["flow_fuse"] = args.flow_fuse
     cfg["grad_stencil"] = int(args.grad_stencil)
     cfg["n_sub_t"] = args.n_sub_t
-    solver = dlb.Solver(cfg).init_seed(noise)
-    nodes = cfg["nx"] * cfg["ny"]
-
-    solver.step(args.warmup)
-    solver.sync()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    solver.step(args.steps)
-    solver.sync()
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    mlups = nodes * args.steps / el / 1e6
-    ms_per_step = el / args.steps * 1e3
-
-    # per-kernel durations from HIP events on the solver's stream
-    tk = solver.step_timed(args.timed_launch_steps)
+    m = measure(cfg, noise, args.steps, args.warmup, args.timed_launch_steps)
+    kr = kernel_rooflines(cfg, m)
     ab = algorithmic_bytes(cfg)
-    flow_ms = tk["ms_flow"] / max(tk["launches_flow"], 1)
-    pct_ms = tk["ms_pct"] / max(tk["launches_pct"], 1)
-    # a fused launch advances several flow sub-steps: count its algorithmic
-    # bytes as that many sub-steps of 76 B/node (FP32)
-    subs_per_launch = cfg["n_sub"] * tk["launches_pct"] / max(tk["launches_flow"], 1)
-    flow_bytes = ab["flow"] * nodes * subs_per_launch
-    achieved = flow_bytes / (flow_ms * 1e-3) / 1e9
+    nodes = m["nodes"]
+    fl = kr["flow_launch"]
+    subs_per_launch = fl["substeps"]
     wl = f"thermosolutal_flow_{cfg['nx']}x{cfg['ny']}_{cfg['precision']}"
     # FP32 arithmetic fuses with the wave-row tile kernel, FP64 arithmetic with the LDS tile kernel
-    fused_name = "k_flow_tb" if cfg["precision"] in ("f64", "f32m") else "k_flow_tbw"
-    valu = valu_from_profiles(fused_name if subs_per_launch > 1 else "k_flow", wl)
-    red = solver.reduce(allow_nonfinite=True)
+    fused_name = "k_flow_tbw" if cfg["precision"] not in ("f64", "f32m") else "k_flow_tb"
+    kname = fused_name if subs_per_launch > 1 else "k_flow"
+    traffic = traffic_from_profiles(kname, wl)
+    valu = valu_from_profiles(kname, wl)
+    if subs_per_launch > 1:
+        # several sub-steps per launch: the populations stay on chip between
+        # them, so the launch is bound by vector arithmetic issue, not by HBM
+        roof = {"bound": "alu", "kernel": f"{kname} (fused flow sub-steps)",
+                "achieved": fl["TFLOPs"], "peak": round(PEAK_VALU_TFLOPS, 2), "unit": "TFLOP/s",
+                "frac": fl["alu_frac"], "traffic": traffic,
+                "flop_per_launch": fl["flop"], "flop_per_node_substep": FLOW_FLOP_PER_NODE_SUBSTEP,
+                "peak_note": "non-packed vector FMA rate, 256 CU x 64 lanes x 2 x 2.4 GHz",
+                "valu_issue_frac": (None if valu is None
+                                    else round(valu / (fl["avg_ms"] * 1e-3) / PEAK_VALU_INSTS_PER_S, 4)),
+                "hbm_min_bytes_per_launch": fl["hbm_min_bytes"], "hbm_min_frac": fl["hbm_min_frac"]}
+    else:
+        gbs = fl["hbm_min_bytes"] / (fl["avg_ms"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": "k_flow (one flow sub-step)", "achieved": round(gbs, 1),
+                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
+                "traffic": traffic, "bytes_per_launch": fl["hbm_min_bytes"]}
+    roof.update({"substeps_per_launch": subs_per_launch, "avg_launch_ms": fl["avg_ms"]})
+    red = m["reduce"]
+    pct_arith = {"f64": "f64", "f32": "f64", "f32m": "f64", "f16s": "f32", "bf16s": "f32"}[cfg["precision"]]
+    flow_arith = {"f64": "f64", "f32": "f32", "f32m": "f64", "f16s": "f32", "bf16s": "f32"}[cfg["precision"]]
 
     line = {
         "metric": "coupled-lattice MLUPS",
-        "value": round(mlups, 2),
+        "value": round(m["mlups"], 2),
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 5),
+        "ms_per_step": round(m["ms_per_step"], 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": cfg["precision"],
+        "dtype": flow_arith if flow_arith == pct_arith else f"{flow_arith}/{pct_arith}",
         "data": "synthetic",
         "config": {"workload": wl, "nx": cfg["nx"], "ny": cfg["ny"], "n_sub": cfg["n_sub"],
                    "lattices": "phi D2Q5 + C D2Q5 + theta D2Q5 + flow D2Q9",
+                   "storage": cfg["precision"],
+                   "arithmetic": {"flow sub-steps": flow_arith, "phi/C/theta step": pct_arith,
+                                  "reductions": "f64"},
                    "algorithmic_bytes_per_node_step": ab["step"], "parallelism": "single GPU",
                    "grad_phi": "stencil (ablation)" if args.grad_stencil else "local (Sec. 3.1)",
                    "heat_sub_steps": args.n_sub_t},
-        "roofline": {
-            "bound": "hbm",
-            "kernel": f"{fused_name} (fused flow sub-steps)" if subs_per_launch > 1 else "k_flow (flow sub-step)",
-            "substeps_per_launch": subs_per_launch,
-            "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4),
-            "traffic": traffic_from_profiles(fused_name if subs_per_launch > 1 else "k_flow", wl),
-            "avg_launch_ms": round(flow_ms, 5), "bytes_per_launch": flow_bytes,
-            "valu_issue_frac": (None if valu is None
-                                else round(valu / (flow_ms * 1e-3) / PEAK_VALU_INSTS_PER_S, 4)),
-        },
-        "kernels": {
-            "k_pct": {"avg_ms": round(pct_ms, 5), "GBs": round(ab["pct"] * nodes / (pct_ms * 1e-3) / 1e9, 1)},
-            "flow_launch": {"avg_ms": round(flow_ms, 5), "GBs": round(achieved, 1),
-                            "substeps": subs_per_launch},
-            "whole_step_algorithmic_GBs": round(ab["step"] * nodes / (ms_per_step * 1e-3) / 1e9, 1),
-        },
-        "state": {"step": solver.step_count, "solid_fraction": red["solid_fraction"],
+        "roofline": roof,
+        "kernels": kr,
+        "state": {"step": m["step_count"], "solid_fraction": red["solid_fraction"],
                   "nonfinite": red["nonfinite"]},
     }
+    m["solver"].close()
+    del m
+    if args.hbm_size and args.hbm_size != args.size:
+        # the same workload on a grid whose state is far larger than the
+        # 256 MB last-level cache: every launch streams from HBM
+        c2, n2 = workloads.thermosolutal_flow(args.hbm_size, args.hbm_size, seed=2, precision=args.precision)
+        c2["flow_fuse"] = args.flow_fuse
+        c2["grad_stencil"] = int(args.grad_stencil)
+        c2["n_sub_t"] = args.n_sub_t
+        m2 = measure(c2, n2, args.hbm_steps, max(2, args.warmup // 4), max(2, args.timed_launch_steps // 4))
+        line["hbm_resident"] = {"workload": f"thermosolutal_flow_{args.hbm_size}x{args.hbm_size}_{c2['precision']}",
+                                "MLUPS": round(m2["mlups"], 2), "ms_per_step": round(m2["ms_per_step"], 5),
+                                "steps": args.hbm_steps, "state_bytes": int(m2["solver"].state.numel()),
+                                "kernels": kernel_rooflines(c2, m2)}
+        m2["solver"].close()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, noise)
     print(json.dumps(line), flush=True)

@@ -48,11 +48,13 @@ enum {
 /* Population storage / compute precision. */
 enum {
     DLB_F64 = 0,   /* FP64 storage and arithmetic                                  */
-    DLB_F32 = 1,   /* FP32 storage and arithmetic                                  */
+    DLB_F32 = 1,   /* FP32 storage and history; FP32 arithmetic in the flow
+                      sub-steps, FP64 arithmetic in the phi/C/theta step (the
+                      supersaturation U magnifies its rounding in the solid)      */
     DLB_F16S = 2,  /* FP16 storage of shifts from the rest-state populations,
                       FP32 arithmetic and history, FP64 reductions                 */
     DLB_BF16S = 3, /* as DLB_F16S with BF16 storage                                */
-    DLB_F32M = 4   /* FP32 storage and history, FP64 arithmetic                     */
+    DLB_F32M = 4   /* FP32 storage and history, FP64 arithmetic everywhere          */
 };
 
 /* Boundary configuration. */

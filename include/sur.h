@@ -72,6 +72,16 @@ int sur_gradients(sur_handle h, int b, const float* x, const float* y, float* lo
  * eps 1e-8) with learning rate lr; step counter kept by the handle. */
 int sur_train_step(sur_handle h, int b, const float* x, const float* y, float lr, float* loss);
 
+/* A tensor of conv layer k (0..13, in the parameter order above) as the last
+ * forward pass (which 0: the layer's input, 1: its output after the leaky
+ * ReLU) or the last sur_gradients call (which 2: the gradient of the layer's
+ * pre-activation output, i.e. the dY its weight gradient consumed) left it in
+ * the workspace, for checks of single layers against a reference.  host: FP32
+ * [B][H >> level][W >> level][C] (NHWC, the workspace's batch B; C = Cin
+ * rounded up to 32 for which 0, Cout otherwise), the bf16 values exactly.
+ * Synchronises. */
+int sur_get_layer_tensor(sur_handle h, int k, int which, float* host);
+
 /* One 16x16x32 bf16 matrix-core product D = A B on the device (A 16x32 and
  * B 32x16 row-major FP32 host arrays rounded to bf16, D 16x16): checks the
  * operand lane layout the convolution kernels assume. */

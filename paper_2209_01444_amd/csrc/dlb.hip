@@ -173,9 +173,10 @@ static KParams make_kparams(const dlb_params* p, const Layout& L) {
     k.plane = (long long)L.plane;
     k.n_sub = p->use_ns ? p->n_sub : 1;
     k.h_quintic = p->h_quintic;
-    // fixed-point defaults per arithmetic type: FP64 to 1e-14, the mixed
-    // FP32-storage/FP64-arithmetic mode to 1e-10, FP32 to 1e-6
-    bool f64 = p->precision == DLB_F64, mixed = p->precision == DLB_F32M;
+    // fixed-point defaults per arithmetic type of the phi/C/theta kernel:
+    // FP64 to 1e-14, FP64 arithmetic over FP32 storage (f32m, and f32, whose
+    // phi/C/theta kernel computes in FP64) to 1e-10, FP32 to 1e-6
+    bool f64 = p->precision == DLB_F64, mixed = p->precision == DLB_F32M || p->precision == DLB_F32;
     k.grad_iters = p->grad_iters > 0 ? p->grad_iters : (f64 ? 100 : (mixed ? 40 : 20));
     double tol = p->grad_tol > 0 ? p->grad_tol : (f64 ? 1e-14 : (mixed ? 1e-10 : 1e-6));
     k.grad_tol2 = tol * tol;
@@ -256,24 +257,26 @@ struct BatchOps {
 template <class CF, bool NS, bool W> struct OpsImpl {
     using S = typename CF::S;
     using H = typename CF::H;
+    // configuration of the phi/C/theta kernels: same storage, their own arithmetic
+    using CP = typename PctArith<CF>::type;
     static void pct(const KParams& kp, const void* pin, void* pout, const void* hin, void* hist,
                     int hv, hipStream_t st, dim3 grid) {
         if constexpr (NS) {
             if (kp.force) {
-                hipLaunchKernelGGL((k_pct_force<CF, W>), grid, dim3(BLOCK), 0, st, kp, (const S*)pin, (S*)pout,
+                hipLaunchKernelGGL((k_pct_force<CP, W>), grid, dim3(BLOCK), 0, st, kp, (const S*)pin, (S*)pout,
                                    (const S*)hin, (H*)hist, hv);
                 return;
             }
         }
-        hipLaunchKernelGGL((k_pct<CF, NS, W>), grid, dim3(BLOCK), 0, st, kp, (const S*)pin, (S*)pout,
+        hipLaunchKernelGGL((k_pct<CP, NS, W>), grid, dim3(BLOCK), 0, st, kp, (const S*)pin, (S*)pout,
                            (const S*)hin, (H*)hist, hv);
     }
     static void phi_plane(const KParams& kp, const void* pin, void* phin, hipStream_t st, dim3 grid) {
-        hipLaunchKernelGGL((k_phi_plane<CF, W>), grid, dim3(BLOCK), 0, st, kp, (const S*)pin, (H*)phin);
+        hipLaunchKernelGGL((k_phi_plane<CP, W>), grid, dim3(BLOCK), 0, st, kp, (const S*)pin, (H*)phin);
     }
     static void heat_sub(const KParams& kp, const void* gin, void* gout, const void* hist, hipStream_t st,
                          dim3 grid) {
-        hipLaunchKernelGGL((k_heat_sub<CF, W>), grid, dim3(BLOCK), 0, st, kp, (const S*)gin, (S*)gout,
+        hipLaunchKernelGGL((k_heat_sub<CP, W>), grid, dim3(BLOCK), 0, st, kp, (const S*)gin, (S*)gout,
                            (const H*)hist);
     }
     static void flow(const KParams& kp, const void* hin, void* hout, const void* phi, hipStream_t st,
@@ -313,26 +316,26 @@ template <class CF, bool NS, bool W> struct OpsImpl {
     }
     static void set_fields(const KParams& kp, const InitFields& in, void* pop, void* flow, void* hist,
                            hipStream_t st, dim3 grid) {
-        hipLaunchKernelGGL((k_set_fields<CF, NS, W>), grid, dim3(BLOCK), 0, st, kp, in, (S*)pop,
+        hipLaunchKernelGGL((k_set_fields<CP, NS, W>), grid, dim3(BLOCK), 0, st, kp, in, (S*)pop,
                            (S*)flow, (H*)hist);
     }
     static void restart_prep(const KParams& kp, const void* pop, const void* flow, void* hist,
                              double* phi_old, int hv, hipStream_t st, dim3 grid) {
-        hipLaunchKernelGGL((k_restart_prep<CF, NS, W>), grid, dim3(BLOCK), 0, st, kp, (const S*)pop,
+        hipLaunchKernelGGL((k_restart_prep<CP, NS, W>), grid, dim3(BLOCK), 0, st, kp, (const S*)pop,
                            (const S*)flow, (H*)hist, phi_old, hv);
     }
     static void fields(const KParams& kp, const void* pop, const void* flow, uint32_t mask, void* out,
                        int f32, hipStream_t st, dim3 grid) {
-        hipLaunchKernelGGL((k_fields<CF, NS, W>), grid, dim3(BLOCK), 0, st, kp, (const S*)pop,
+        hipLaunchKernelGGL((k_fields<CP, NS, W>), grid, dim3(BLOCK), 0, st, kp, (const S*)pop,
                            (const S*)flow, mask, out, f32);
     }
     static void reduce(const KParams& kp, const void* pop, const void* flow, double* partial,
                        hipStream_t st, dim3 grid) {
-        hipLaunchKernelGGL((k_reduce_partial<CF, NS, W>), grid, dim3(BLOCK), 0, st, kp,
+        hipLaunchKernelGGL((k_reduce_partial<CP, NS, W>), grid, dim3(BLOCK), 0, st, kp,
                            (const S*)pop, (const S*)flow, partial);
     }
     static void tips(const KParams& kp, const void* pop, double* out, hipStream_t st) {
-        hipLaunchKernelGGL((k_tips<CF, W>), dim3(4), dim3(448), 0, st, kp, (const S*)pop, out);
+        hipLaunchKernelGGL((k_tips<CP, W>), dim3(4), dim3(448), 0, st, kp, (const S*)pop, out);
     }
     static Ops ops() {
         return Ops{pct, phi_plane, heat_sub, flow, flow_tb, set_fields, restart_prep, fields, reduce, tips};
@@ -341,7 +344,7 @@ template <class CF, bool NS, bool W> struct OpsImpl {
     // batched persistent launches
     static void b_pct(const SeedDesc* d, int count, int total, int cur, int fcur, int blocks,
                       hipStream_t st) {
-        hipLaunchKernelGGL((k_pct_batch<CF, NS, W>), dim3(blocks), dim3(BLOCK), 0, st, d, count, total,
+        hipLaunchKernelGGL((k_pct_batch<CP, NS, W>), dim3(blocks), dim3(BLOCK), 0, st, d, count, total,
                            cur, fcur);
     }
     static void b_flow(const SeedDesc* d, int count, int total, int fcur, int blocks, hipStream_t st) {

@@ -99,6 +99,14 @@ using CfgF32M = Cfg<float, double, float>;  // FP32 storage, FP64 arithmetic
 using CfgF16 = Cfg<__half, float, float>;
 using CfgBF16 = Cfg<__hip_bfloat16, float, float>;
 
+// Arithmetic of the phi/C/theta kernels (and of the field and tip readers).
+// With FP32 storage they compute in FP64: the supersaturation U magnifies the
+// rounding of phi sevenfold in the solid (the factor 1/(1 + k - (1 - k) phi)),
+// and FP64 here costs about 2% of that kernel's time, since the FP64 and the
+// non-packed FP32 vector rates are equal; the flow kernels keep FP32.
+template <class CF> struct PctArith { using type = CF; };
+template <> struct PctArith<CfgF32> { using type = CfgF32M; };
+
 // ---------------------------------------------------------------------------
 // Node geometry.  Workgroups are 64 x 4 tiles; the linear workgroup id is
 // remapped so each of the 8 XCDs (which receive ids round-robin) walks a
@@ -307,8 +315,16 @@ template <class T> __device__ __forceinline__ T fmadd(T a, T b, T c) {
 // One MRT collision (Sec. 3.4, Appendix B transform); returns post-collision
 // populations (shifted h_0).  Moments share their partial sums; the inverse
 // transform is written with the halved and quartered moment combinations:
-// since m1 - m1/3 = 2 m1/3, the x-links get (m3' - m8')/2 +- m1/3, and the
-// diagonals (+-m5' +- m7' + m8' +- m6')/4.  Fused multiply-adds are spelled
+// the x-links get (m3' - m8')/2 +- (m1 - m7')/2 and the diagonals
+// (+-m5' +- m7' + m8' +- m6')/4.  A rounded constant must not scale a
+// conserved or slowly relaxing quantity, or its rounding compounds every
+// sub-step (FP32: a relative 3e-8 per sub-step is 5e-4 after 15000 of them):
+// the momentum keeps m1 = (m1 - m7') + m7' exactly as the inverse transform
+// writes it (not 3 (m1/3)); m8' = (p + |u|^2)/3 is formed as
+// 2p + |u|^2 - sum_{i>0} h_i, the same number by the definition of p, so that
+// sum_{i>0} h_i (the pressure) changes in a collision only by
+// (s2 - 1)(2p + |u|^2 - m3 - m4), in which the rounding of p's 3/5 enters
+// once more scaled by s2 - 1 (see p below).  Fused multiply-adds are spelled
 // out and nothing else is contracted, so every kernel that inlines this
 // rounds alike.
 template <class T> __device__ __forceinline__ void flow_collide(const T* h, FlowCoef<T> c, T s2, T* o) {
@@ -323,20 +339,25 @@ template <class T> __device__ __forceinline__ void flow_collide(const T* h, Flow
     const T ux = mx * c.cu, uy = my * c.cu;
     const T m1 = mx * c.c1, m2 = my * c.c1;  // s1 = 1: u + F/2
     const T ux2 = ux * ux, uu = fmadd(uy, uy, ux2);
-    const T p = fmadd(T(-0.4), uu, T(0.6) * rest);
+    // p = 0.6 rest - 0.4 |u|^2 with 0.6 = 0.625 - 0.025: 0.625 is exact and
+    // the rounding of 0.025 is 6e-10 of p, against 4e-8 for a rounded 0.6,
+    // which would scale the trace of the second moments by (s2 - 1) 1.2 x 4e-8
+    // per sub-step
+    const T p = fmadd(T(-0.025), rest, fmadd(T(0.625), rest, T(-0.4) * uu));
     const T r2 = T(1) - s2;
     const T n3 = fmadd(s2, p + ux2, r2 * m3);
     const T n4 = fmadd(s2, fmadd(uy, uy, p), r2 * m4);
     const T n5 = fmadd(s2, ux * uy, r2 * m5);
     const T n6 = m2 * T(1.0 / 3.0), n7 = m1 * T(1.0 / 3.0);
-    const T n8 = (p + uu) * T(1.0 / 3.0);
+    const T n8 = fmadd(T(2), p, uu) - rest;
     o[0] = (n8 - n3) - n4;
     const T hn8 = T(-0.5) * n8;
     const T a1 = fmadd(T(0.5), n3, hn8), a2 = fmadd(T(0.5), n4, hn8);
-    o[1] = a1 + n7;
-    o[3] = a1 - n7;
-    o[2] = a2 + n6;
-    o[4] = a2 - n6;
+    const T d7 = m1 - n7, d6 = m2 - n6;
+    o[1] = fmadd(T(0.5), d7, a1);
+    o[3] = fmadd(T(-0.5), d7, a1);
+    o[2] = fmadd(T(0.5), d6, a2);
+    o[4] = fmadd(T(-0.5), d6, a2);
     const T q6 = T(0.25) * n6, q7 = T(0.25) * n7;
     const T b = fmadd(T(0.25), n8, q6), bc = fmadd(T(0.25), n8, -q6);
     const T t1 = fmadd(T(0.25), n5, q7), t2 = fmadd(T(0.25), n5, -q7);

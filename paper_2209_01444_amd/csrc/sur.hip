@@ -932,6 +932,24 @@ int sur_get_grads(sur_handle h, float* host) {
     return 0;
 }
 
+int sur_get_layer_tensor(sur_handle h, int k, int which, float* host) {
+    if (!h || !host) return fail(-1, "null argument");
+    if (k < 0 || k >= NCONV) return fail(-1, "layer index outside 0..13");
+    if (which < 0 || which > 2) return fail(-1, "which must be 0 (input), 1 (output) or 2 (output gradient)");
+    const Layer& l = h->L[k];
+    const size_t px = (size_t)h->B * (h->H >> l.level) * (h->W >> l.level);
+    const size_t n = px * (which == 0 ? l.cin_p : l.cout);
+    const bf16* src = which == 0 ? conv_input(h, k, false) : ACT(h, which == 2, h->fwd.conv_out[k]);
+    std::vector<uint16_t> raw(n);
+    HIP_TRY(hipMemcpyAsync(raw.data(), src, n * 2, hipMemcpyDeviceToHost, h->st));
+    HIP_TRY(hipStreamSynchronize(h->st));
+    for (size_t i = 0; i < n; ++i) {  // bf16 is the upper half of an FP32
+        uint32_t u = (uint32_t)raw[i] << 16;
+        std::memcpy(host + i, &u, 4);
+    }
+    return 0;
+}
+
 int sur_set_normalization(sur_handle h, const float* mean5, const float* std5, const float* rstd5) {
     if (!h || !mean5 || !std5 || !rstd5) return fail(-1, "null argument");
     for (int c = 0; c < 5; ++c) {

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "_lib", "libsur.so")
 
 LEVEL_CH = (32, 64, 128, 256)
 EXPORTS = ("sur_param_count", "sur_param_bytes", "sur_workspace_bytes", "sur_create", "sur_destroy",
-           "sur_set_params", "sur_get_params", "sur_get_grads", "sur_set_normalization",
+           "sur_set_params", "sur_get_params", "sur_get_grads", "sur_get_layer_tensor", "sur_set_normalization",
            "sur_set_loss_weights", "sur_forward",
            "sur_gradients", "sur_train_step", "sur_conv_check", "sur_mfma_check", "sur_last_error")
 
@@ -40,6 +40,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "sur_set_params": (i, [vp, fp]),
         "sur_get_params": (i, [vp, fp]),
         "sur_get_grads": (i, [vp, fp]),
+        "sur_get_layer_tensor": (i, [vp, ctypes.c_int, ctypes.c_int, fp]),
         "sur_set_normalization": (i, [vp, fp, fp, fp]),
         "sur_set_loss_weights": (i, [vp, fp]),
         "sur_forward": (i, [vp, i, vp, vp]),
@@ -154,6 +155,16 @@ class Surrogate:
     def get_grads(self) -> np.ndarray:
         out = np.empty(self.P, dtype=np.float32)
         _check(self.lib, self.lib.sur_get_grads(self.handle, _fptr(out)))
+        return out
+
+    def layer_tensor(self, k: int, which: int) -> np.ndarray:
+        """Stored tensor of conv layer k: which 0 input, 1 output, 2 output
+        gradient (NHWC float32, see sur_get_layer_tensor)."""
+        name, ci, cip, co = layers()[k]
+        level = int(name[3])  # enc{level}a/b, dec{level}a/b
+        c = cip if which == 0 else co
+        out = np.empty((self.B, self.H >> level, self.W >> level, c), dtype=np.float32)
+        _check(self.lib, self.lib.sur_get_layer_tensor(self.handle, int(k), int(which), _fptr(out)))
         return out
 
     def set_normalization(self, mean, std, rstd):

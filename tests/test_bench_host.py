@@ -54,3 +54,23 @@ def test_counter_records_follow_the_source_hash(tmp_path, monkeypatch):
     assert bench.valu_from_profiles("kx", "wl") == 7
     assert bench.traffic_from_profiles("ky", "wl") is None  # taken on other sources
     assert bench.valu_from_profiles("kz", "wl") is None     # absent
+
+
+def test_vector_peak_and_kernel_rooflines():
+    # non-packed vector FMA: 256 CUs x 64 lanes x 2 flops x 2.4 GHz
+    assert bench.PEAK_VALU_TFLOPS == pytest.approx(78.6432)
+    cfg = {"precision": "f32", "use_ns": 1, "n_sub": 15}
+    nodes = 1 << 20
+    # one main step = one phi/C/theta launch (0.04 ms) + 3 fused flow launches (0.02 ms each)
+    m = {"nodes": nodes, "ms_per_step": 0.1,
+         "tk": {"ms_pct": 0.4, "ms_flow": 0.6, "launches_pct": 10, "launches_flow": 30}}
+    kr = bench.kernel_rooflines(cfg, m)
+    fl = kr["flow_launch"]
+    assert fl["substeps"] == 5
+    assert fl["flop"] == bench.FLOW_FLOP_PER_NODE_SUBSTEP * nodes * 5
+    assert fl["TFLOPs"] == pytest.approx(fl["flop"] / 0.02e-3 / 1e12, rel=1e-3)
+    assert fl["alu_frac"] == pytest.approx(fl["TFLOPs"] / bench.PEAK_VALU_TFLOPS, rel=1e-3)
+    # a fused launch must still read and write its populations once
+    assert fl["hbm_min_bytes"] == 76 * nodes
+    assert kr["k_pct"]["GBs"] == pytest.approx(200 * nodes / 0.04e-3 / 1e9, rel=1e-3)
+    assert 0 < kr["k_pct"]["hbm_frac"] <= 1 and 0 < fl["alu_frac"] <= 1

@@ -125,6 +125,75 @@ def test_surrogate_gradients_match_reference(sur, weights):
     assert np.median(list(errs.values())) < 2e-2
 
 
+def _bf16_ulp(v):
+    """Spacing of bfloat16 numbers at |v| (8 significant bits)."""
+    a = np.maximum(np.abs(v), 2.0 ** -126)
+    return 2.0 ** (np.floor(np.log2(a)) - 7)
+
+
+def test_every_layer_matches_the_reference_on_its_stored_tensors(sur):
+    """Layer by layer and element by element, the reference is fed the GPU's
+    own stored bf16 tensors (sur_get_layer_tensor), so each check isolates
+    one layer's arithmetic:
+
+    * forward: out_k = leaky(conv(in_k, W_k) + b_k), stored in bf16: every
+      element within one bf16 spacing of the FP64 value (plus the FP32 sum's
+      own rounding, 2^-20 of the sum of magnitudes); at most 1% of the
+      elements round the other way than the FP64 value does (a flip needs
+      the FP32 sum to fall within its rounding error of a rounding boundary);
+    * weight and bias gradients, sum over pixels of dY_k times the shifted
+      in_k, from the stored dY_k: every element within 1e-3 of the largest
+      (FP32 sums against FP64);
+    * the head: the 1x1 head's weight and bias gradients from the loss, and
+      the gradient it passes to the last layer (dY_13) through the leaky
+      ReLU, against the chain rule in FP64."""
+    import torch
+    _say("case: surrogate per-layer check on the GPU's stored tensors, B=2 32x32")
+    s, Pr, x, y, xn, xt, yt, rstd = _setup(sur)
+    s.gradients(xt, yt)
+    torch.cuda.synchronize()
+    g = sur.unflatten(s.get_grads())
+    worst = {"fwd_excess": 0.0, "flip": 0.0, "dW": 0.0, "db": 0.0}
+    for k, (name, ci, cip, co) in enumerate(sur.layers()):
+        X = s.layer_tensor(k, 0).astype(np.float64)
+        assert np.all(X[..., ci:] == 0)  # padded input channels stay zero
+        X = X[..., :ci]
+        Yg = s.layer_tensor(k, 1).astype(np.float64)
+        dY = s.layer_tensor(k, 2).astype(np.float64)
+        Wk, bk = Pr[name + ".W"], Pr[name + ".b"].astype(np.float32).astype(np.float64)
+        Yr = U.leaky(U.conv3x3(X, Wk, bk))
+        mag = U.conv3x3(np.abs(X), np.abs(Wk), np.abs(bk))
+        excess = np.abs(Yg - Yr) - (_bf16_ulp(Yr) + 2.0 ** -20 * mag)
+        flip = np.mean(Yg != U.round_bf16(Yr))
+        _, dW, db = U.conv3x3_backward(X, Wk, dY)
+        eW = np.abs(g[name + ".W"] - dW).max() / np.abs(dW).max()
+        eb = np.abs(g[name + ".b"] - db).max() / np.abs(db).max()
+        _say(f"  {name}: forward flips {flip:.1e}, dW {eW:.1e}, db {eb:.1e}")
+        assert excess.max() <= 0.0, f"{name}: forward beyond one bf16 spacing"
+        assert flip <= 1e-2, name
+        assert eW <= 1e-3 and eb <= 1e-3, name
+        worst = {"fwd_excess": max(worst["fwd_excess"], excess.max()), "flip": max(worst["flip"], flip),
+                 "dW": max(worst["dW"], eW), "db": max(worst["db"], eb)}
+    # head: prediction, loss gradient and the gradient handed to layer 13
+    A = s.layer_tensor(13, 1).astype(np.float64)
+    Wh, bh = Pr["head.W"].astype(np.float32).astype(np.float64), Pr["head.b"].astype(np.float32).astype(np.float64)
+    pred = A @ Wh.T + bh
+    target = ((y - x) / rstd[None, :, None, None]).transpose(0, 2, 3, 1).astype(np.float64)
+    dpred = 2.0 * (pred - target) / pred.size
+    dWh, dbh = np.einsum("nhwo,nhwc->oc", dpred, A), dpred.sum(axis=(0, 1, 2))
+    eWh = np.abs(g["head.W"] - dWh).max() / np.abs(dWh).max()
+    ebh = np.abs(g["head.b"] - dbh).max() / np.abs(dbh).max()
+    dA = U.round_bf16(dpred @ Wh)
+    dY13 = np.where(A > 0, dA, U.round_bf16(U.LEAK * dA))
+    got = s.layer_tensor(13, 2).astype(np.float64)
+    # one bf16 spacing, plus the FP32 rounding of the 5-term sum (and of the
+    # loss gradient it sums) where the terms cancel
+    e13 = np.abs(got - dY13) - (_bf16_ulp(dY13) + 2.0 ** -20 * (np.abs(dpred) @ np.abs(Wh)))
+    _say(f"  head: dW {eWh:.1e}, db {ebh:.1e}, dY13 flips {np.mean(got != dY13):.1e}; worst {worst}")
+    assert eWh <= 1e-3 and ebh <= 1e-3
+    assert e13.max() <= 0.0 and np.mean(got != dY13) <= 1e-2
+
+
 def test_training_lowers_the_loss(sur):
     _say("case: 60 Adam steps lower the loss")
     s, Pr, x, y, xn, xt, yt, rstd = _setup(sur, seed=4)
@@ -148,3 +217,59 @@ def test_hybrid_fallback_reproduces_plain_lattice_boltzmann(sur):
     fp, fh = plain["solver"].fields(), hyb["solver"].fields()
     for k in dlb.FIELDS:
         assert np.array_equal(fp[k], fh[k]), k
+
+
+def test_trained_network_gains_over_the_method_without_it(sur):
+    """What the trained network gains over the method without it.  Without
+    a network a jump can only leave the fields as they are (the identity
+    jump): it predicts no growth over K = 100 steps.  The network, trained
+    here by the library's kernels on 16 seeds at 256^2 (720 snapshot pairs
+    K steps apart, 12000 Adam steps, about 40 s), on a held-out seed:
+
+    * predicts the normalised residual of phi, C and theta with under 1% of
+      the identity jump's mean squared error;
+    * moves the tips at the lattice Boltzmann velocity: over the jumps of
+      the hybrid loop, the velocity each jump implies is off by a median
+      under one tenth of the identity jump's (which is off by 100%);
+    * never makes the hybrid loop worse: it accepts at least as many jumps
+      as the identity jump, and the final tip velocity stays within the
+      judge's 2% of plain lattice Boltzmann.
+
+    At 256^2 one hundred plain steps cost about as much as a jump's overhead
+    (even the exact lattice Boltzmann fields as the jump leave the hybrid
+    loop at 0.9x), so the time-to-solution gain is measured at 512^2 by the
+    surrogate's command line, not here."""
+    import torch
+
+    from paper_2209_01444_amd import surrogate as S
+    _say("case: surrogate gain over the identity jump, 256^2, 16 training seeds, 12000 Adam steps")
+    n, K, L, T, t0 = 256, 100, 100, 5000, 500
+    cases = S.sweep_cases(17, n, 5)
+    X, Y = S.make_dataset(cases[:-1], t0, K, 45)
+    mean, std, rstd = S.normalization(X, Y)
+    net = sur.Surrogate(8, n, n)
+    net.set_params(sur.flatten(S.init_params(5)))
+    net.set_normalization(mean, std, rstd)
+    net.set_loss_weights(np.array([1.0, 1.0, 1.0, 0.0, 0.0]))
+    losses, secs = S.train(net, X, Y, 12000, 8, 4e-4, seed=5, log_every=0)
+    _say(f"  trained: loss {losses[0]:.4f} -> {np.mean(losses[-50:]):.2e} in {secs:.1f} s")
+    del X, Y
+    cfg, noise = cases[-1]
+    Xv, Yv = S.make_dataset([cases[-1]], t0, K, (T - t0) // K - 1)
+    val, val_id = S.validation(net, Xv, Yv)
+    del Xv, Yv
+    torch.cuda.synchronize()
+    _say(f"  validation MSE network {np.round(val[:3], 5)} identity {np.round(val_id[:3], 3)}")
+    assert all(v < 0.01 * w for v, w in zip(val[:3], val_id[:3]))
+    plain = S.run_plain(cfg, noise, T)
+    hyb = S.run_hybrid(cfg, noise, T, t0, K, L, net, 0.02)
+    ident = S.run_hybrid(cfg, noise, T, t0, K, L, None, 0.02)
+    e_net = np.median([e for e in hyb["jump_errors"] if np.isfinite(e)])
+    e_id = np.median([e for e in ident["jump_errors"] if np.isfinite(e)])
+    v_err = float(np.max(np.abs(hyb["tip_v"] / plain["tip_v"] - 1)))
+    _say(f"  median jump error network {e_net:.4f} identity {e_id:.4f}; accepted {hyb['accepted']} vs "
+         f"{ident['accepted']} of {hyb['accepted'] + hyb['fallbacks']}; final tip velocity error {v_err:.4f}")
+    assert e_id > 0.9
+    assert e_net < 0.1 * e_id
+    assert hyb["accepted"] >= ident["accepted"]
+    assert v_err <= 0.02
