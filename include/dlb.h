@@ -196,6 +196,21 @@ int64_t dlb_step_count(dlb_handle h);
  * synchronises. */
 int dlb_get_fields(dlb_handle h, uint32_t mask, void* out, int out_on_device, int out_f32);
 
+/* dlb_get_fields for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same fields, mask and layout as dlb_get_fields with out_on_device = 0,
+ * staged through a static device buffer of DLB_NOALLOC_SCRATCH_BYTES that
+ * each GPU holds from the first call until the process ends; no hipMalloc,
+ * hipFree or other allocating call.  out is host memory of
+ * popcount(mask) * nx * ny values (doubles, or floats with out_f32 = 1),
+ * owned by the caller.  Synchronises the solver's stream.
+ * Errors: DLB_EINVAL for a null handle or output, a bad mask, or a selection
+ * larger than DLB_NOALLOC_SCRATCH_BYTES (use dlb_get_fields); DLB_EHIP.
+ * All calls on one GPU share its buffer: calls that overlap on one GPU (from
+ * several host threads) race. */
+#define DLB_NOALLOC_SCRATCH_BYTES (32u << 20)
+int dlb_get_fields_noalloc(dlb_handle h, uint32_t mask, void* out, int out_f32);
+
 /* Reductions in FP64 on the device; synchronises.  out[0..18] (19 doubles):
  *   0 sum C, 1 sum H, 2 solid fraction sum((1+phi)/2)/(nx ny), 3 non-finite
  *   count, 4-5 hydrodynamic force (Sec. 3.4) -sum [1-q(phi)] f over all nodes,

@@ -715,6 +715,63 @@ int dlb_get_fields(dlb_handle h, uint32_t mask, void* out, int out_on_device, in
     return DLB_OK;
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Static staging buffer of dlb_get_fields_noalloc: a file-scope device array
+// (each GPU holds its own copy for the life of the process).  Host code never
+// passes the array's name to a kernel or a copy: the name is a host-side
+// stand-in, so its device address is looked up once per device and kept.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[DLB_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's copy of `scratch`; looked up with that
+// device current on the first call for it.
+int scratch_address(int dev, void** out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(DLB_EUNSUPPORTED, "device ordinal beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int cur = -1;
+        HIP_TRY(hipGetDevice(&cur));
+        if (cur != dev) HIP_TRY(hipSetDevice(dev));
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess) return fail(DLB_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return DLB_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int dlb_get_fields_noalloc(dlb_handle h, uint32_t mask, void* out, int out_f32) {
+    if (!h || !out) return fail(DLB_EINVAL, "null handle or output");
+    if (mask == 0 || mask >= (1u << 7)) return fail(DLB_EINVAL, "field mask must select bits 0..6");
+    const size_t N = (size_t)h->p.nx * h->p.ny;
+    const size_t bytes = (size_t)__builtin_popcount(mask) * N * (out_f32 ? 4 : 8);
+    if (bytes > (size_t)DLB_NOALLOC_SCRATCH_BYTES)
+        return fail(DLB_EINVAL, "selected fields exceed the static staging buffer (DLB_NOALLOC_SCRATCH_BYTES)");
+    hipPointerAttribute_t attr;
+    HIP_TRY(hipPointerGetAttributes(&attr, h->base));
+    void* scr = nullptr;
+    int rc = scratch_address(attr.device, &scr);
+    if (rc) return rc;
+    // k_fields writes every selected value, so nothing needs clearing first
+    h->ops.fields(h->kp, h->pop(h->pop_cur), h->flow(h->flow_cur), mask, scr, out_f32, h->stream, h->grid);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(out, scr, bytes, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return DLB_OK;
+}
+
 int dlb_reduce(dlb_handle h, double* out) {
     if (!h || !out) return fail(DLB_EINVAL, "null handle or output");
     h->ops.reduce(h->kp, h->pop(h->pop_cur), h->flow(h->flow_cur), h->red(), h->stream, h->grid);

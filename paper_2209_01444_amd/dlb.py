@@ -16,6 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "_lib", "libdlb.so")
 
 DLB_OK, DLB_EINVAL, DLB_ENOMEM, DLB_EHIP, DLB_ENAN, DLB_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+# size of the static staging buffer of dlb_get_fields_noalloc (DLB_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 32 << 20
 PRECISION = {"f64": 0, "f32": 1, "f16s": 2, "bf16s": 3, "f32m": 4}
 FIELDS = ("phi", "C", "U", "theta", "ux", "uy", "p")
 
@@ -39,7 +41,7 @@ KEEP_FLOW, KEEP_NONEQ = 1, 2  # continuation flags of dlb_set_fields_ex
 
 EXPORTS = (
     "dlb_state_bytes", "dlb_create", "dlb_destroy", "dlb_init_seed", "dlb_set_fields", "dlb_set_fields_ex", "dlb_step",
-    "dlb_step_timed", "dlb_step_count", "dlb_get_fields", "dlb_reduce", "dlb_checkpoint_bytes",
+    "dlb_step_timed", "dlb_step_count", "dlb_get_fields", "dlb_get_fields_noalloc", "dlb_reduce", "dlb_checkpoint_bytes",
     "dlb_save", "dlb_load", "dlb_copy_state", "dlb_sync", "dlb_equilibria", "dlb_copy_kernel", "dlb_strerror",
     "dlb_last_error", "dlb_batch_state_bytes", "dlb_batch_create", "dlb_batch_destroy",
     "dlb_batch_member", "dlb_batch_step", "dlb_batch_step_count", "dlb_batch_set_config",
@@ -71,6 +73,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "dlb_step_timed": (ctypes.c_int, [vp, i64, dp, dp, P(i64), P(i64)]),
         "dlb_step_count": (i64, [vp]),
         "dlb_get_fields": (ctypes.c_int, [vp, ctypes.c_uint32, vp, ctypes.c_int, ctypes.c_int]),
+        "dlb_get_fields_noalloc": (ctypes.c_int, [vp, ctypes.c_uint32, vp, ctypes.c_int]),
         "dlb_reduce": (ctypes.c_int, [vp, dp]),
         "dlb_checkpoint_bytes": (ctypes.c_size_t, [vp]),
         "dlb_save": (ctypes.c_int, [vp, vp, ctypes.c_size_t]),
@@ -255,6 +258,18 @@ class Solver:
         out = np.empty((len(sel), self.ny, self.nx), dtype=np.float64)
         _check(self.lib, self.lib.dlb_get_fields(self.handle, mask, out.ctypes.data_as(ctypes.c_void_p),
                                                  0, 0))
+        return {f: out[i] for i, f in enumerate(sel)}
+
+    def fields_noalloc(self, names=FIELDS, f32: bool = False) -> dict:
+        """As fields(), through dlb_get_fields_noalloc (a static device
+        staging buffer, no device allocation)."""
+        mask = 0
+        for nm in names:
+            mask |= 1 << FIELDS.index(nm)
+        sel = [f for f in FIELDS if mask & (1 << FIELDS.index(f))]
+        out = np.empty((len(sel), self.ny, self.nx), dtype=np.float32 if f32 else np.float64)
+        _check(self.lib, self.lib.dlb_get_fields_noalloc(self.handle, mask, out.ctypes.data_as(ctypes.c_void_p),
+                                                         int(f32)))
         return {f: out[i] for i, f in enumerate(sel)}
 
     def fields_device(self, names=FIELDS, f32: bool = True):
