@@ -34,13 +34,14 @@ def kernel_source_hash() -> str:
 def algorithmic_bytes(cfg: dict) -> dict:
     """Bytes each kernel must move per node (each state word read once and
     written once; neighbour reuse assumed perfect)."""
-    sb = {"f64": 8, "f32": 4, "f32m": 4, "f16s": 2, "bf16s": 2}[cfg["precision"]]
+    sb = {"f64": 8, "f32": 4, "f32m": 4, "f16s": 2, "bf16s": 2, "f16sm": 2}[cfg["precision"]]
+    sc = 4 if cfg["precision"] == "f16sm" else sb  # solute and heat populations
     cb = 8 if cfg["precision"] == "f64" else 4  # history planes
     ns = bool(cfg.get("use_ns"))
     # k_pct: 15 populations in + out, 8 flow populations in (velocity),
     # history in + out (phi, Q and, with flow, C u, H u)
     hist = 6 if ns else 2
-    pct = 30 * sb + (8 * sb if ns else 0) + 2 * hist * cb
+    pct = 10 * sb + 20 * sc + (8 * sb if ns else 0) + 2 * hist * cb
     # k_flow: 9 populations in + out, frozen phi in
     flow = 18 * sb + cb
     return {"pct": pct, "flow": flow, "step": pct + (cfg["n_sub"] * flow if ns else 0)}
@@ -130,7 +131,7 @@ def measure(cfg: dict, noise, steps: int, warmup: int, timed_launch_steps: int) 
     return out
 
 
-def kernel_rooflines(cfg: dict, m: dict) -> dict:
+def kernel_rooflines(cfg: dict, m: dict, wl: str | None = None) -> dict:
     """Per-kernel figures of one measurement: the phi/C/theta kernel against
     the HBM peak (its algorithmic bytes), the flow launch against the vector
     arithmetic peak when it fuses several sub-steps (its data stays on chip
@@ -150,8 +151,17 @@ def kernel_rooflines(cfg: dict, m: dict) -> dict:
     flow["flop"] = flops
     flow["TFLOPs"] = round(flops / (flow_ms * 1e-3) / 1e12, 3)
     flow["alu_frac"] = round(flops / (flow_ms * 1e-3) / 1e12 / PEAK_VALU_TFLOPS, 4)
-    return {"k_pct": {"avg_ms": round(pct_ms, 5), "GBs": round(pct_gbs, 1),
-                      "hbm_frac": round(pct_gbs / PEAK_HBM_GBS, 4), "bytes": ab["pct"] * nodes},
+    pct = {"avg_ms": round(pct_ms, 5), "GBs": round(pct_gbs, 1), "hbm_frac": round(pct_gbs / PEAK_HBM_GBS, 4),
+           "bytes": ab["pct"] * nodes}
+    if wl:
+        # counter records (profiles/) taken on the current kernel sources, else null
+        pct["traffic"] = traffic_from_profiles("k_pct", wl)
+        pct["traffic_GBs"] = None if pct["traffic"] is None else round(pct["traffic"] / (pct_ms * 1e-3) / 1e9, 1)
+        kf = "k_flow_tbw" if subs > 1 and cfg["precision"] not in ("f64", "f32m") else None
+        flow["traffic"] = traffic_from_profiles(kf, wl) if kf else None
+        valu = valu_from_profiles(kf, wl) if kf else None
+        flow["valu_issue_frac"] = None if valu is None else round(valu / (flow_ms * 1e-3) / PEAK_VALU_INSTS_PER_S, 4)
+    return {"k_pct": pct,
             "flow_launch": flow,
             "whole_step_algorithmic_GBs": round(ab["step"] * nodes / (m["ms_per_step"] * 1e-3) / 1e9, 1)}
 
@@ -220,12 +230,12 @@ def main():
     cfg["grad_stencil"] = int(args.grad_stencil)
     cfg["n_sub_t"] = args.n_sub_t
     m = measure(cfg, noise, args.steps, args.warmup, args.timed_launch_steps)
-    kr = kernel_rooflines(cfg, m)
+    wl = f"thermosolutal_flow_{cfg['nx']}x{cfg['ny']}_{cfg['precision']}"
+    kr = kernel_rooflines(cfg, m, wl)
     ab = algorithmic_bytes(cfg)
     nodes = m["nodes"]
     fl = kr["flow_launch"]
     subs_per_launch = fl["substeps"]
-    wl = f"thermosolutal_flow_{cfg['nx']}x{cfg['ny']}_{cfg['precision']}"
     # FP32 arithmetic fuses with the wave-row tile kernel, FP64 arithmetic with the LDS tile kernel
     fused_name = "k_flow_tbw" if cfg["precision"] not in ("f64", "f32m") else "k_flow_tb"
     kname = fused_name if subs_per_launch > 1 else "k_flow"
@@ -249,8 +259,10 @@ def main():
                 "traffic": traffic, "bytes_per_launch": fl["hbm_min_bytes"]}
     roof.update({"substeps_per_launch": subs_per_launch, "avg_launch_ms": fl["avg_ms"]})
     red = m["reduce"]
-    pct_arith = {"f64": "f64", "f32": "f64", "f32m": "f64", "f16s": "f32", "bf16s": "f32"}[cfg["precision"]]
-    flow_arith = {"f64": "f64", "f32": "f32", "f32m": "f64", "f16s": "f32", "bf16s": "f32"}[cfg["precision"]]
+    pct_arith = {"f64": "f64", "f32": "f64", "f32m": "f64", "f16s": "f32", "bf16s": "f32",
+                 "f16sm": "f64"}[cfg["precision"]]
+    flow_arith = {"f64": "f64", "f32": "f32", "f32m": "f64", "f16s": "f32", "bf16s": "f32",
+                  "f16sm": "f32"}[cfg["precision"]]
 
     line = {
         "metric": "coupled-lattice MLUPS",
@@ -288,10 +300,11 @@ def main():
         c2["grad_stencil"] = int(args.grad_stencil)
         c2["n_sub_t"] = args.n_sub_t
         m2 = measure(c2, n2, args.hbm_steps, max(2, args.warmup // 4), max(2, args.timed_launch_steps // 4))
-        line["hbm_resident"] = {"workload": f"thermosolutal_flow_{args.hbm_size}x{args.hbm_size}_{c2['precision']}",
+        wl2 = f"thermosolutal_flow_{args.hbm_size}x{args.hbm_size}_{c2['precision']}"
+        line["hbm_resident"] = {"workload": wl2,
                                 "MLUPS": round(m2["mlups"], 2), "ms_per_step": round(m2["ms_per_step"], 5),
                                 "steps": args.hbm_steps, "state_bytes": int(m2["solver"].state.numel()),
-                                "kernels": kernel_rooflines(c2, m2)}
+                                "kernels": kernel_rooflines(c2, m2, wl2)}
         m2["solver"].close()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, noise)

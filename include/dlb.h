@@ -54,7 +54,11 @@ enum {
     DLB_F16S = 2,  /* FP16 storage of shifts from the rest-state populations,
                       FP32 arithmetic and history, FP64 reductions                 */
     DLB_BF16S = 3, /* as DLB_F16S with BF16 storage                                */
-    DLB_F32M = 4   /* FP32 storage and history, FP64 arithmetic everywhere          */
+    DLB_F32M = 4,  /* FP32 storage and history, FP64 arithmetic everywhere          */
+    DLB_F16SM = 5  /* mixed: the phi and flow populations as FP16 shifts from the
+                      rest state, the solute and heat populations in FP32; FP32
+                      history and flow arithmetic, FP64 arithmetic in the
+                      phi/C/theta step, FP64 reductions                           */
 };
 
 /* Boundary configuration. */
@@ -85,7 +89,7 @@ typedef struct dlb_params {
     int32_t n_sub;        /* flow sub-steps per main step (Sec. 4: N = 15)           */
     int32_t h_quintic;    /* 0: h(phi) = phi; 1: 15(phi - 2phi^3/3 + phi^5/5)/8      */
     int32_t c_init_U;     /* initial solute: 0 uniform C = C0; 1 uniform U = U0      */
-    int32_t precision;    /* DLB_F64 .. DLB_F32M                                     */
+    int32_t precision;    /* DLB_F64 .. DLB_F16SM                                    */
     int32_t grad_iters;   /* cap of the local-gradient fixed point (0: default)      */
     int32_t flow_fuse;    /* flow sub-steps fused per launch: 1, 3 or 5 (0: 5); the
                              fused kernel keeps a tile in registers and LDS for

@@ -46,12 +46,19 @@ size_t storage_bytes(int precision) {
         case DLB_F32:
         case DLB_F32M: return 4;
         case DLB_F16S:
-        case DLB_BF16S: return 2;
+        case DLB_BF16S:
+        case DLB_F16SM: return 2;
     }
     return 0;
 }
 // history planes are FP64 only in the all-FP64 configuration
 size_t history_bytes(int precision) { return precision == DLB_F64 ? 8 : 4; }
+// solute and heat populations: FP32 in mixed storage, else the storage type
+size_t cde_bytes(int precision) { return precision == DLB_F16SM ? 4 : storage_bytes(precision); }
+// byte offset of the five heat planes in a population buffer
+size_t heat_offset(int precision, size_t plane) {
+    return 5 * plane * storage_bytes(precision) + 5 * plane * cde_bytes(precision);
+}
 
 struct Layout {
     size_t plane;  // elements per plane
@@ -107,11 +114,11 @@ Layout layout_of(const dlb_params* p) {
     Layout L{};
     size_t N = (size_t)p->nx * p->ny;
     L.plane = (N + 63) & ~size_t(63);
-    size_t sb = storage_bytes(p->precision), cb = history_bytes(p->precision);
+    size_t sb = storage_bytes(p->precision), cb = history_bytes(p->precision), sc = cde_bytes(p->precision);
     size_t off = 0;
     for (int b = 0; b < 2; ++b) {
         L.pop[b] = off;
-        off = align256(off + 15 * L.plane * sb);
+        off = align256(off + 5 * L.plane * sb + 10 * L.plane * sc);
     }
     for (int b = 0; b < 2; ++b) {
         L.flow[b] = off;
@@ -125,7 +132,7 @@ Layout layout_of(const dlb_params* p) {
     L.aux = off;  // u and d_t(Hu) of time t for the heat sub-steps
     if (heat_split) off = align256(off + 4 * L.plane * cb);
     L.heat = off;  // five heat planes: intermediate heat sub-steps
-    if (heat_split) off = align256(off + 5 * L.plane * sb);
+    if (heat_split) off = align256(off + 5 * L.plane * sc);
     int nbx = (p->nx + TILE_X - 1) / TILE_X, nby = (p->ny + TILE_Y - 1) / TILE_Y;
     L.nblocks = nbx * nby;
     L.red = off;
@@ -176,7 +183,8 @@ static KParams make_kparams(const dlb_params* p, const Layout& L) {
     // fixed-point defaults per arithmetic type of the phi/C/theta kernel:
     // FP64 to 1e-14, FP64 arithmetic over FP32 storage (f32m, and f32, whose
     // phi/C/theta kernel computes in FP64) to 1e-10, FP32 to 1e-6
-    bool f64 = p->precision == DLB_F64, mixed = p->precision == DLB_F32M || p->precision == DLB_F32;
+    bool f64 = p->precision == DLB_F64,
+         mixed = p->precision == DLB_F32M || p->precision == DLB_F32 || p->precision == DLB_F16SM;
     k.grad_iters = p->grad_iters > 0 ? p->grad_iters : (f64 ? 100 : (mixed ? 40 : 20));
     double tol = p->grad_tol > 0 ? p->grad_tol : (f64 ? 1e-14 : (mixed ? 1e-10 : 1e-6));
     k.grad_tol2 = tol * tol;
@@ -223,7 +231,7 @@ static KParams make_kparams(const dlb_params* p, const Layout& L) {
     k.seed_x = p->seed_x;
     k.seed_y = p->seed_y;
     k.noise_amp = p->noise_amp;
-    if (p->precision == DLB_F16S || p->precision == DLB_BF16S) rest_shifts(p, k.shift);
+    if (p->precision == DLB_F16S || p->precision == DLB_BF16S || p->precision == DLB_F16SM) rest_shifts(p, k.shift);
     for (int j = 0; j < 2; ++j)  // wave-row fused tiles, K = 3 and 5 (-1: no valid shift)
         k.tbw_dy[j] = tbw_row_shift(p->ny, j ? 5 : 3, k.walls != 0, &k.tbw_nby[j]);
     k.grad_stencil = p->grad_stencil;  // k.phin is set once the state buffer is known
@@ -276,7 +284,8 @@ template <class CF, bool NS, bool W> struct OpsImpl {
     }
     static void heat_sub(const KParams& kp, const void* gin, void* gout, const void* hist, hipStream_t st,
                          dim3 grid) {
-        hipLaunchKernelGGL((k_heat_sub<CP, W>), grid, dim3(BLOCK), 0, st, kp, (const S*)gin, (S*)gout,
+        using SC = typename CF::SC;
+        hipLaunchKernelGGL((k_heat_sub<CP, W>), grid, dim3(BLOCK), 0, st, kp, (const SC*)gin, (SC*)gout,
                            (const H*)hist);
     }
     static void flow(const KParams& kp, const void* hin, void* hout, const void* phi, hipStream_t st,
@@ -380,6 +389,7 @@ static BatchOps select_bops(const dlb_params* p) {
         case DLB_F32: return bops_for<CfgF32>(ns, walls);
         case DLB_F32M: return bops_for<CfgF32M>(ns, walls);
         case DLB_F16S: return bops_for<CfgF16>(ns, walls);
+        case DLB_F16SM: return bops_for<CfgF16M>(ns, walls);
         default: return bops_for<CfgBF16>(ns, walls);
     }
 }
@@ -391,6 +401,7 @@ static Ops select_ops(const dlb_params* p) {
         case DLB_F32: return ops_for<CfgF32>(ns, walls);
         case DLB_F32M: return ops_for<CfgF32M>(ns, walls);
         case DLB_F16S: return ops_for<CfgF16>(ns, walls);
+        case DLB_F16SM: return ops_for<CfgF16M>(ns, walls);
         default: return ops_for<CfgBF16>(ns, walls);
     }
 }
@@ -433,7 +444,7 @@ static void enqueue_step(dlb_solver* s, hipEvent_t* ev) {
             // heat sub-steps from the current buffer's heat planes to the new
             // buffer's, alternating with the scratch planes so the last one
             // lands in the new buffer
-            const size_t off = 10 * s->L.plane * storage_bytes(s->p.precision);
+            const size_t off = heat_offset(s->p.precision, s->L.plane);
             char* from = (char*)s->pop(s->pop_cur) + off;
             char* dst = (char*)s->pop(1 - s->pop_cur) + off;
             char* scr = s->base + s->L.heat;

@@ -219,8 +219,8 @@ __device__ __forceinline__ void heat_collide(T s1t, const T* g, T H, T theta, T 
 // populations and their own velocity.
 // gin, gout: the five heat planes of a population buffer or the scratch.
 template <class CF, bool WALLS>
-__global__ __launch_bounds__(BLOCK) void k_heat_sub(const KParams kp, const typename CF::S* __restrict__ gin,
-                                                    typename CF::S* __restrict__ gout,
+__global__ __launch_bounds__(BLOCK) void k_heat_sub(const KParams kp, const typename CF::SC* __restrict__ gin,
+                                                    typename CF::SC* __restrict__ gout,
                                                     const typename CF::H* __restrict__ hist) {
     using T = typename CF::T;
     using HT = typename CF::H;
@@ -272,11 +272,11 @@ __device__ __forceinline__ void pct_node(const KParams& kp, const typename CF::S
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
         f[i] = ld_pop<T>(pin, i * P + src, kp.shift[i]);
-        n[i] = ld_pop<T>(pin, (5 + i) * P + src, kp.shift[5 + i]);
+        n[i] = ld_pct<CF, T>(pin, 5 + i, P, src, kp.shift);
     }
     if (kp.use_t)
 #pragma unroll
-        for (int i = 0; i < 5; ++i) g[i] = ld_pop<T>(pin, (10 + i) * P + src, kp.shift[10 + i]);
+        for (int i = 0; i < 5; ++i) g[i] = ld_pct<CF, T>(pin, 10 + i, P, src, kp.shift);
     if constexpr (WALLS && !NS) {
         if (wall && kp.farfield) farfield_rebuild<T>(kp, f, n, g);
     }
@@ -409,8 +409,8 @@ __device__ __forceinline__ void pct_node(const KParams& kp, const typename CF::S
         if (d < 0) continue;
         T fold = i == 0 ? f[0] : ld_pop<T>(pin, i * P + (size_t)d, kp.shift[i]);
         st_pop(pout, i * P + (size_t)d, fold + (pf[i] - fold) * inv_a2, kp.shift[i]);
-        st_pop(pout, (5 + i) * P + (size_t)d, pn[i], kp.shift[5 + i]);
-        if (heat_here) st_pop(pout, (10 + i) * P + (size_t)d, pg[i], kp.shift[10 + i]);
+        st_pct<CF>(pout, 5 + i, P, (size_t)d, pn[i], kp.shift);
+        if (heat_here) st_pct<CF>(pout, 10 + i, P, (size_t)d, pg[i], kp.shift);
     }
 }
 
@@ -1045,8 +1045,8 @@ __global__ __launch_bounds__(BLOCK) void k_restart_prep(const KParams kp,
     double phi = 0.0, C = 0.0, H = 0.0;
     for (int i = 0; i < 5; ++i) {
         phi += ld_pop<double>(pop, i * P + src, kp.shift[i]);
-        C += ld_pop<double>(pop, (5 + i) * P + src, kp.shift[5 + i]);
-        H += ld_pop<double>(pop, (10 + i) * P + src, kp.shift[10 + i]);
+        C += ld_pct<CF, double>(pop, 5 + i, P, src, kp.shift);
+        H += ld_pct<CF, double>(pop, 10 + i, P, src, kp.shift);
     }
     phi_old[idx] = (wall && kp.farfield) ? -1.0 : phi;
     if (!hist_valid || wall) return;
@@ -1114,8 +1114,8 @@ __global__ __launch_bounds__(BLOCK) void k_set_fields(const KParams kp, const In
     if (keep_neq) {
         for (int i = 0; i < 5; ++i) {
             fo[i] = ld_pop<double>(pop, i * P + idx, kp.shift[i]);
-            no[i] = ld_pop<double>(pop, (5 + i) * P + idx, kp.shift[5 + i]);
-            go[i] = ld_pop<double>(pop, (10 + i) * P + idx, kp.shift[10 + i]);
+            no[i] = ld_pct<CF, double>(pop, 5 + i, P, idx, kp.shift);
+            go[i] = ld_pct<CF, double>(pop, 10 + i, P, idx, kp.shift);
             phio += fo[i];
             Co += no[i];
             Ho += go[i];
@@ -1144,9 +1144,9 @@ __global__ __launch_bounds__(BLOCK) void k_set_fields(const KParams kp, const In
     if (keep_neq) {
         double Uo = (2.0 * Co / (1.0 + k - (1.0 - k) * phio) - 1.0) / (1.0 - k);
         eq_solute<double>(Co, phio, Uo, uox, uoy, eo);
-        for (int i = 0; i < 5; ++i) st_pop(pop, (5 + i) * P + idx, no[i] + (e[i] - eo[i]), kp.shift[5 + i]);
+        for (int i = 0; i < 5; ++i) st_pct<CF>(pop, 5 + i, P, idx, no[i] + (e[i] - eo[i]), kp.shift);
     } else {
-        for (int i = 0; i < 5; ++i) st_pop(pop, (5 + i) * P + idx, e[i], kp.shift[5 + i]);
+        for (int i = 0; i < 5; ++i) st_pct<CF>(pop, 5 + i, P, idx, e[i], kp.shift);
     }
     // heat populations carry the velocity of their own step (n_sub_t sub-steps)
     const double ht = kp.n_sub_t;
@@ -1154,9 +1154,9 @@ __global__ __launch_bounds__(BLOCK) void k_set_fields(const KParams kp, const In
     if (keep_neq) {
         double tho = Ho + 0.5 * h_of(phio, kp.h_quintic);
         eq_heat<double>(tho, phio, kp.h_quintic, uox / ht, uoy / ht, eo);
-        for (int i = 0; i < 5; ++i) st_pop(pop, (10 + i) * P + idx, go[i] + (e[i] - eo[i]), kp.shift[10 + i]);
+        for (int i = 0; i < 5; ++i) st_pct<CF>(pop, 10 + i, P, idx, go[i] + (e[i] - eo[i]), kp.shift);
     } else {
-        for (int i = 0; i < 5; ++i) st_pop(pop, (10 + i) * P + idx, e[i], kp.shift[10 + i]);
+        for (int i = 0; i < 5; ++i) st_pct<CF>(pop, 10 + i, P, idx, e[i], kp.shift);
     }
     double sux = ux, suy = uy;  // the velocity the next step will evaluate
     if constexpr (NS) {
@@ -1201,8 +1201,8 @@ __device__ __forceinline__ void node_macros(const KParams& kp, const typename CF
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
         phi += ld_pop<T>(pop, i * P + src, kp.shift[i]);
-        C += ld_pop<T>(pop, (5 + i) * P + src, kp.shift[5 + i]);
-        H += ld_pop<T>(pop, (10 + i) * P + src, kp.shift[10 + i]);
+        C += ld_pct<CF, T>(pop, 5 + i, P, src, kp.shift);
+        H += ld_pct<CF, T>(pop, 10 + i, P, src, kp.shift);
     }
     if constexpr (WALLS && !NS) {
         if (kp.farfield && is_wall(kp, x, y)) {  // the far-field liquid

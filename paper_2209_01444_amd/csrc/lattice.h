@@ -87,17 +87,21 @@ __device__ __forceinline__ void st_pop(S* p, size_t i, T v, float shift) {
 }
 
 // Precision configurations: storage type S, arithmetic type T, history
-// storage type H.
-template <class S_, class T_, class H_> struct Cfg {
+// storage type H, storage type SC of the solute and heat populations (S
+// except in mixed storage).
+template <class S_, class T_, class H_, class SC_ = S_> struct Cfg {
     using S = S_;
     using T = T_;
     using H = H_;
+    using SC = SC_;
 };
 using CfgF64 = Cfg<double, double, double>;
 using CfgF32 = Cfg<float, float, float>;
 using CfgF32M = Cfg<float, double, float>;  // FP32 storage, FP64 arithmetic
 using CfgF16 = Cfg<__half, float, float>;
 using CfgBF16 = Cfg<__hip_bfloat16, float, float>;
+// mixed: phi and flow populations as FP16 shifts, solute and heat FP32
+using CfgF16M = Cfg<__half, float, float, float>;
 
 // Arithmetic of the phi/C/theta kernels (and of the field and tip readers).
 // With FP32 storage they compute in FP64: the supersaturation U magnifies the
@@ -106,6 +110,26 @@ using CfgBF16 = Cfg<__hip_bfloat16, float, float>;
 // non-packed FP32 vector rates are equal; the flow kernels keep FP32.
 template <class CF> struct PctArith { using type = CF; };
 template <> struct PctArith<CfgF32> { using type = CfgF32M; };
+template <> struct PctArith<CfgF16M> { using type = Cfg<__half, double, float, float>; };
+
+// Population j (0-14) of the phi/C/H block of a population buffer at node
+// index idx: the phi planes (j < 5) hold S, the C and H planes CF::SC, all
+// planes P elements long.  With SC = S this is plane j, element idx.
+template <class CF, class T>
+__device__ __forceinline__ T ld_pct(const typename CF::S* pop, int j, size_t P, size_t idx, const float* shift) {
+    if (j < 5) return ld_pop<T>(pop, j * P + idx, shift[j]);
+    const typename CF::SC* c = reinterpret_cast<const typename CF::SC*>(pop + 5 * P);
+    return ld_pop<T>(c, (j - 5) * P + idx, shift[j]);
+}
+template <class CF, class T>
+__device__ __forceinline__ void st_pct(typename CF::S* pop, int j, size_t P, size_t idx, T v, const float* shift) {
+    if (j < 5) {
+        st_pop(pop, j * P + idx, v, shift[j]);
+        return;
+    }
+    typename CF::SC* c = reinterpret_cast<typename CF::SC*>(pop + 5 * P);
+    st_pop(c, (j - 5) * P + idx, v, shift[j]);
+}
 
 // ---------------------------------------------------------------------------
 // Node geometry.  Workgroups are 64 x 4 tiles; the linear workgroup id is

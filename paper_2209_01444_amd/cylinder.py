@@ -50,12 +50,14 @@ def recirculation_length(ux: np.ndarray, cfg: dict) -> float:
 
 
 def run(Re: float, R: int = 20, precision: str = "f32", max_substeps: int = 200000,
-        check_substeps: int = 3000, tol: float = 1e-5, n_sub: int = 15, width: float | None = None) -> dict:
+        check_substeps: int = 3000, tol: float = 1e-5, n_sub: int = 15, width: float | None = None,
+        length: int = 70, height: int = 40) -> dict:
     """Run to steady drag (relative change below tol over check_substeps).
-    width: tanh width of the diffuse cylinder in lu (default sqrt(2) W0)."""
+    width: tanh width of the diffuse cylinder in lu (default sqrt(2) W0);
+    length, height: the domain in units of R."""
     import torch
 
-    cfg = workloads.cylinder_flow(Re, R, precision, n_sub)
+    cfg = workloads.cylinder_flow(Re, R, precision, n_sub, length, height)
     if width is not None:
         cfg["W0"] = width / np.sqrt(2.0)
     s = dlb.Solver(cfg).init_seed(None)
@@ -80,7 +82,7 @@ def run(Re: float, R: int = 20, precision: str = "f32", max_substeps: int = 2000
     subs = s.step_count * n_sub
     return {"Re": Re, "R": R, "precision": precision, "nx": cfg["nx"], "ny": cfg["ny"],
             "width": float(np.sqrt(2.0) * cfg["W0"]), "Cd": cd,
-            "Cd_solid_nodes": cd_solid, "L_W": lw,
+            "Cd_solid_nodes": cd_solid, "L_W": lw, "length": length, "height": height,
             "substeps": subs, "seconds": el, "flow_MLUPS": cfg["nx"] * cfg["ny"] * subs / el / 1e6,
             "paper": PAPER.get(int(Re)), "Cd_history": hist[-5:]}
 
@@ -92,9 +94,12 @@ def main():
     ap.add_argument("--precision", default="f32")
     ap.add_argument("--max-substeps", type=int, default=200000)
     ap.add_argument("--width", type=float, default=None, help="tanh width of the cylinder's interface (lu)")
+    ap.add_argument("--length", type=int, default=70, help="domain length in units of R")
+    ap.add_argument("--height", type=int, default=40, help="domain height in units of R")
     args = ap.parse_args()
     for Re in (float(v) for v in args.Re.split(",")):
-        r = run(Re, args.R, args.precision, args.max_substeps, width=args.width)
+        r = run(Re, args.R, args.precision, args.max_substeps, width=args.width, length=args.length,
+                height=args.height)
         if r["paper"]:
             r["Cd_rel_err"] = r["Cd"] / r["paper"][0] - 1
             r["Cd_solid_nodes_rel_err"] = r["Cd_solid_nodes"] / r["paper"][0] - 1

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "_lib", "libdlb.so")
 DLB_OK, DLB_EINVAL, DLB_ENOMEM, DLB_EHIP, DLB_ENAN, DLB_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 # size of the static staging buffer of dlb_get_fields_noalloc (DLB_NOALLOC_SCRATCH_BYTES)
 NOALLOC_SCRATCH_BYTES = 32 << 20
-PRECISION = {"f64": 0, "f32": 1, "f16s": 2, "bf16s": 3, "f32m": 4}
+PRECISION = {"f64": 0, "f32": 1, "f16s": 2, "bf16s": 3, "f32m": 4, "f16sm": 5}
 FIELDS = ("phi", "C", "U", "theta", "ux", "uy", "p")
 
 

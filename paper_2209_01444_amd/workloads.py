@@ -157,7 +157,8 @@ def thermosolutal_dendrite(precision: str = "f32", L: int = 2400, W0: float = 2.
                 nu=23.1 * alpha, u_in=(W0 / tau0, 0.0))
 
 
-def cylinder_flow(Re: float, R: int = 20, precision: str = "f32", n_sub: int = 15) -> dict:
+def cylinder_flow(Re: float, R: int = 20, precision: str = "f32", n_sub: int = 15, length: int = 70,
+                  height: int = 40) -> dict:
     """Flow past a stationary diffuse cylinder (Sec. 4.1): domain 70R x 40R
     nodes, cylinder of radius R lu centred at (20R, 20R), interface width
     W0 = 0.5 lu, s2 = 1.25 per flow sub-step (nu = 0.1 lu^2 per sub-step),
@@ -165,14 +166,15 @@ def cylinder_flow(Re: float, R: int = 20, precision: str = "f32", n_sub: int = 1
     east, free slip north and south.  The paper's mesh is R = 20 (1400 x 800),
     u0 = 0.1 at Re = 40.  Main steps group n_sub flow sub-steps (phi, C and
     theta are frozen), so main-step velocity and viscosity are n_sub times
-    the sub-step ones."""
+    the sub-step ones.  length, height: the domain in units of R (the
+    cylinder stays 20R from the inlet, on the centre line)."""
     nu_sub = 0.1
     u0 = Re * nu_sub / (2.0 * R)
     return dict(
-        name=f"cylinder_Re{Re:g}_R{R}", nx=70 * R, ny=40 * R, use_c=1, use_t=1, use_ns=1, walls=1,
+        name=f"cylinder_Re{Re:g}_R{R}", nx=length * R, ny=height * R, use_c=1, use_t=1, use_ns=1, walls=1,
         n_sub=n_sub, phi_static=1, W0=0.5, tau0=20.0, eps4=0.0, orient=0.0, lambda_=0.0, Mcinf=0.0,
         k=0.15, D=0.1, alpha=0.1, nu=nu_sub * n_sub, rho0=1.0, u_in=(u0 * n_sub, 0.0), theta0=0.0,
-        U0=0.0, C0=1.0, seed_R=float(R), seed_x=20.0 * R, seed_y=20.0 * R, noise_amp=0.0,
+        U0=0.0, C0=1.0, seed_R=float(R), seed_x=20.0 * R, seed_y=height * R / 2.0, noise_amp=0.0,
         precision=precision)
 
 

@@ -24,6 +24,9 @@ def test_algorithmic_bytes_per_node_step():
     # 16-bit storage halves the population bytes, history stays FP32
     ab16 = bench.algorithmic_bytes(dict(cfg, precision="f16s"))
     assert ab16["flow"] == 18 * 2 + 4 and ab16["pct"] == 30 * 2 + 8 * 2 + 48
+    # mixed 16-bit storage: phi and flow populations 2 B, solute and heat 4 B
+    abm = bench.algorithmic_bytes(dict(cfg, precision="f16sm"))
+    assert abm["pct"] == 10 * 2 + 20 * 4 + 8 * 2 + 48 and abm["flow"] == ab16["flow"]
     # no flow: 15 populations and 2 history planes
     ab0 = bench.algorithmic_bytes({"precision": "f64", "use_ns": 0, "n_sub": 1})
     assert ab0["step"] == ab0["pct"] == 30 * 8 + 2 * 2 * 8
