@@ -15,6 +15,7 @@ DEPS = SOURCES + [os.path.join(CSRC, f) for f in ("lattice.h", "kernels.h", "bat
     os.path.join(ROOT, "include", "dlb.h"), os.path.join(ROOT, "include", "dlb3.h")]
 SUR_LIB = os.path.join(LIBDIR, "libsur.so")
 SUR_SOURCES = [os.path.join(CSRC, "sur.hip")]
+SUR_DEPS = SUR_SOURCES + [os.path.join(ROOT, "include", "sur.h")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -45,11 +46,22 @@ def build(verbose: bool = False) -> str:
     return _compile(SOURCES, LIB, verbose)
 
 
-def stale() -> bool:
-    if not os.path.exists(LIB):
+def stale(lib: str = LIB, deps=None) -> bool:
+    """True if the library is missing or older than any of its sources."""
+    if not os.path.exists(lib):
         return True
-    t = os.path.getmtime(LIB)
-    return any(os.path.getmtime(d) > t for d in DEPS)
+    t = os.path.getmtime(lib)
+    return any(os.path.getmtime(d) > t for d in (DEPS if deps is None else deps))
+
+
+def warn_if_stale(lib: str, deps) -> None:
+    """Say so on stderr when a library is older than its sources: it still
+    loads (a copied tree may not keep modification times), but it may not be
+    the code the sources describe."""
+    if os.path.exists(lib) and stale(lib, deps):
+        newer = [os.path.basename(d) for d in deps if os.path.getmtime(d) > os.path.getmtime(lib)]
+        print(f"warning: {lib} is older than {', '.join(newer)}; rebuild with "
+              "`python paper_2209_01444_amd/build.py`", file=sys.stderr, flush=True)
 
 
 if __name__ == "__main__":

@@ -59,6 +59,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python paper_2209_01444_amd/build.py`"
                           " (there is no CPU fallback)")
+    if path == LIB_PATH:
+        from paper_2209_01444_amd import build
+        build.warn_if_stale(path, build.DEPS)
     lib = ctypes.CDLL(path)
     P, vp, d, i64 = ctypes.POINTER, ctypes.c_void_p, ctypes.c_double, ctypes.c_int64
     dp = P(d)

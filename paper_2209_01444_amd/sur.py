@@ -29,6 +29,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python paper_2209_01444_amd/build.py`")
+    if path == LIB_PATH:
+        from paper_2209_01444_amd import build
+        build.warn_if_stale(path, build.SUR_DEPS)
     lib = ctypes.CDLL(path)
     vp, fp, i, sz = ctypes.c_void_p, ctypes.POINTER(ctypes.c_float), ctypes.c_int, ctypes.c_size_t
     sig = {
@@ -231,3 +234,62 @@ def mfma_check(A: np.ndarray, B: np.ndarray) -> np.ndarray:
     d = np.empty((16, 16), dtype=np.float32)
     _check(lib, lib.sur_mfma_check(_fptr(a), _fptr(b), _fptr(d)))
     return d
+
+
+def layer_work(H: int, W: int, B: int = 1) -> list[dict]:
+    """Work of each 3x3 layer of a forward pass at H x W, batch B: flops
+    (2 x 9 x Cin_p x Cout per pixel, the padded input channels included, as
+    the matrix cores compute them) and the bytes a layer must move at least
+    (bf16 input and output activations once, bf16 weights once)."""
+    out = []
+    for name, ci, cip, co in layers():
+        level = int(name[3])
+        px = B * (H >> level) * (W >> level)
+        out.append({"layer": name, "level": level, "cin": ci, "cout": co, "pixels": px,
+                    "flop": 2.0 * 9 * cip * co * px,
+                    "bytes": 2.0 * px * (cip + co) + 2.0 * 9 * cip * co})
+    return out
+
+
+def forward_bench(size: int = 512, batch: int = 1, reps: int = 50, seed: int = 5) -> dict:
+    """Forward passes of a randomly initialised network (the arithmetic does
+    not depend on the weights), timed with HIP events on the network's
+    stream."""
+    import torch
+
+    rng = np.random.default_rng(seed)
+    P = {}
+    for name, ci, cip, co in layers():
+        P[name + ".W"] = rng.normal(size=(3, 3, co, ci)) * np.sqrt(2.0 / (9 * ci))
+        P[name + ".b"] = np.zeros(co)
+    P["head.W"] = rng.normal(size=(5, 32)) * 0.01
+    P["head.b"] = np.zeros(5)
+    net = Surrogate(batch, size, size)
+    net.set_params(flatten(P))
+    net.set_normalization(np.zeros(5), np.ones(5), np.ones(5))
+    x = torch.randn((batch, 5, size, size), dtype=torch.float32, device=net.device)
+    out = torch.empty((batch, 5, size, size), dtype=torch.float64, device=net.device)
+    for _ in range(3):
+        net.forward(x, out)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(net.stream)
+    for _ in range(reps):
+        net.forward(x, out)
+    ev[1].record(net.stream)
+    ev[1].synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / reps
+    flop = sum(w["flop"] for w in layer_work(size, size, batch))
+    return {"size": size, "batch": batch, "reps": reps, "forward_ms": ms, "conv_flop": flop,
+            "TFLOPs": flop / (ms * 1e-3) / 1e12}
+
+
+if __name__ == "__main__":
+    import argparse
+    import json
+
+    ap = argparse.ArgumentParser(description="forward-pass timing of the surrogate U-Net")
+    ap.add_argument("--size", type=int, default=512)
+    ap.add_argument("--batch", type=int, default=1)
+    ap.add_argument("--reps", type=int, default=50)
+    a = ap.parse_args()
+    print(json.dumps(forward_bench(a.size, a.batch, a.reps)), flush=True)

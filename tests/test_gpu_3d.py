@@ -208,8 +208,13 @@ def test_3d_parity_16bit_storage(dlb3, walls, precision):
         _say(f"  t={t} " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
         assert max(errs.values()) <= tol, errs
     rg, ro = s.reduce(), o.reduce()
+    # the sums move by the rounding of the stored differences: at most half a
+    # 16-bit spacing of the largest (order one) per node
+    half_ulp = {"f16s": 2.0 ** -11, "bf16s": 2.0 ** -8}[precision]
+    nodes = cfg["nx"] * cfg["ny"] * cfg["nz"]
     for key in ("sum_C", "sum_H"):
-        assert rg[key] == pytest.approx(ro[key], rel=tol / 10, abs=tol), key
+        _say(f"  {key} drift against the oracle {rg[key] - ro[key]:+.3e} (bound {nodes * half_ulp:.2f})")
+        assert abs(rg[key] - ro[key]) <= nodes * half_ulp, key
     assert rg["solid_fraction"] == pytest.approx(ro["solid_fraction"], rel=tol)
     assert rg["nonfinite"] == 0
 
@@ -233,6 +238,30 @@ def test_3d_melt_flow_16bit_storage(dlb3, walls, precision):
         # velocity and pressure relative to their largest magnitude
         errs.update({k: _rel(gf[k], of[k]) for k in O.FLOW_FIELDS})
         _say(f"  t={t} " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
-        bad = {k: v for k, v in errs.items() if v > (10 * tol if k == "p" else tol)}
+        bad = {k: v for k, v in errs.items() if v > tol}
         assert not bad, bad
 
+
+
+def test_3d_fp16_storage_keeps_growth(dlb3):
+    """Growth with FP16 storage of every 3-D lattice against the FP64 GPU
+    run (itself matched to the oracle above): the thermosolutal seed of the
+    3-D benchmark on a 64^3 grid with walls, 600 steps.  The six tip
+    velocities (last 100 steps) stay within 1% (measured 0.1%) and the
+    solid fraction within 1% (0.21%).  BF16 storage misses both by 7-12%
+    over the same run and is not held to them."""
+    from paper_2209_01444_amd import bench3d
+    _say("case: 3-D growth, 64^3, 600 steps, FP16 storage vs FP64")
+    out = {}
+    for precision in ("f64", "f16s"):
+        s = dlb3.Solver3(bench3d.workload(64, precision)).init_seed()
+        s.step(500)
+        a = s.reduce()["tip_s"]
+        s.step(100)
+        r = s.reduce()
+        out[precision] = ((r["tip_s"] - a) / 100, r["solid_fraction"], r["nonfinite"])
+    (v0, fs0, _), (v1, fs1, bad) = out["f64"], out["f16s"]
+    ev, efs = np.abs(v1 / v0 - 1), abs(fs1 / fs0 - 1)
+    _say(f"  v f64 {np.round(v0, 6)}; FP16 errors {np.round(ev, 5)}, solid fraction {efs:.2e}")
+    assert bad == 0 and np.all(v0 > 1e-3)
+    assert ev.max() <= 1e-2 and efs <= 1e-2

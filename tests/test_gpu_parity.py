@@ -395,20 +395,29 @@ def test_static_cylinder_matches_oracle(dlb, precision, tol):
 
 
 @pytest.mark.parametrize("Re", [20, 40])
-def test_cylinder_drag_matches_the_paper(dlb, Re):
+def test_cylinder_drag_and_wake_converge_to_the_paper(dlb, Re):
     """Pin of the flow lattice and the diffuse fluid-solid force against the
-    paper's table of Sec. 4.1 (stationary cylinder, R = 20 lu on the paper's
-    1400 x 800 mesh): C_d = 2.153 / 1.598 and L_W = 1.853 / 4.491 at Re =
-    20 / 40.  The solver gives C_d 2.6% / 3.2% and L_W 10% / 9% above them;
-    the bars are 5% and 15%.  (The literal alternative reading of the force,
-    f summed over the solid nodes only, gives C_d 27% low.)"""
+    paper's table of Sec. 4.1 (stationary cylinder; C_d = 2.153 / 1.598 and
+    L_W = 1.853 / 4.491 at Re = 20 / 40), on the paper's mesh (R = 20 lu,
+    1400 x 800) and at twice its resolution (R = 40 lu, the interface width
+    W0 = 0.5 lu kept).  C_d: within 5% at both (measured +1.8% / -1.6% at
+    Re 20, +2.7% / -0.2% at Re 40).  L_W is 9.9% / 8.6% long at R = 20 and
+    5.4% / 4.3% at R = 40: the excess halves with the grid spacing, and the
+    first-order extrapolation 2 L_W(40) - L_W(20) lands within 1% of the
+    paper's value (bar 2%); the wake's length does not change with a twice
+    longer domain and grows by 1-2% with twice the height (see the design
+    notes), so neither explains it."""
     from paper_2209_01444_amd import cylinder
-    _say(f"case: cylinder Re={Re}, 1400x800, FP32, to steady drag")
-    r = cylinder.run(Re, 20, "f32")
+    _say(f"case: cylinder Re={Re}, R = 20 and 40 lu, FP32, to steady drag")
     cd_ref, lw_ref = cylinder.PAPER[Re]
-    _say(f"  C_d {r['Cd']:.4f} (paper {cd_ref}), L_W {r['L_W']:.3f} (paper {lw_ref}), {r['substeps']} sub-steps")
-    assert abs(r["Cd"] / cd_ref - 1) < 0.05
-    assert abs(r["L_W"] / lw_ref - 1) < 0.15
+    r20 = cylinder.run(Re, 20, "f32")
+    r40 = cylinder.run(Re, 40, "f32", max_substeps=400000)
+    lw_inf = 2.0 * r40["L_W"] - r20["L_W"]
+    _say(f"  C_d {r20['Cd']:.4f} / {r40['Cd']:.4f} (paper {cd_ref}); L_W {r20['L_W']:.4f} / {r40['L_W']:.4f}, "
+         f"extrapolated {lw_inf:.4f} (paper {lw_ref}); sub-steps {r20['substeps']} / {r40['substeps']}")
+    assert abs(r20["Cd"] / cd_ref - 1) < 0.05 and abs(r40["Cd"] / cd_ref - 1) < 0.05
+    assert abs(r40["L_W"] - lw_ref) < 0.7 * abs(r20["L_W"] - lw_ref)
+    assert abs(lw_inf / lw_ref - 1) < 0.02
 
 
 def test_thermal_dendrite_tip_velocity_matches_the_paper(dlb):
