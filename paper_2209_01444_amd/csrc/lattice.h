@@ -336,6 +336,16 @@ template <class T> __device__ __forceinline__ T fmadd(T a, T b, T c) {
     else return __builtin_fma(a, b, c);
 }
 
+// x/3 with 1/3 = 21/64 + 1/192: the product by 21/64 is exact inside the
+// fused multiply-add and the rounding of 1/192 weighs 1/64 of the result,
+// so x/3 is within one rounding of its correctly rounded value.  A rounded
+// 1/3 (FP32: 3e-8 high) is the same for every node and sub-step; scaling the
+// momentum into the third-order moments by it left the FP32 velocity 15x and
+// the pressure 7x further from FP64 after 30000 flow sub-steps.
+template <class T> __device__ __forceinline__ T third(T x) {
+    return fmadd(x, T(21.0 / 64.0), x * T(1.0 / 192.0));
+}
+
 // One MRT collision (Sec. 3.4, Appendix B transform); returns post-collision
 // populations (shifted h_0).  Moments share their partial sums; the inverse
 // transform is written with the halved and quartered moment combinations:
@@ -348,7 +358,8 @@ template <class T> __device__ __forceinline__ T fmadd(T a, T b, T c) {
 // 2p + |u|^2 - sum_{i>0} h_i, the same number by the definition of p, so that
 // sum_{i>0} h_i (the pressure) changes in a collision only by
 // (s2 - 1)(2p + |u|^2 - m3 - m4), in which the rounding of p's 3/5 enters
-// once more scaled by s2 - 1 (see p below).  Fused multiply-adds are spelled
+// once more scaled by s2 - 1 (see p below); the third-order moments take
+// m1/3 and m2/3 through third().  Fused multiply-adds are spelled
 // out and nothing else is contracted, so every kernel that inlines this
 // rounds alike.
 template <class T> __device__ __forceinline__ void flow_collide(const T* h, FlowCoef<T> c, T s2, T* o) {
@@ -372,7 +383,7 @@ template <class T> __device__ __forceinline__ void flow_collide(const T* h, Flow
     const T n3 = fmadd(s2, p + ux2, r2 * m3);
     const T n4 = fmadd(s2, fmadd(uy, uy, p), r2 * m4);
     const T n5 = fmadd(s2, ux * uy, r2 * m5);
-    const T n6 = m2 * T(1.0 / 3.0), n7 = m1 * T(1.0 / 3.0);
+    const T n6 = third(m2), n7 = third(m1);
     const T n8 = fmadd(T(2), p, uu) - rest;
     o[0] = (n8 - n3) - n4;
     const T hn8 = T(-0.5) * n8;
@@ -409,15 +420,16 @@ __device__ __forceinline__ void flow_collide_force(const T* h, T phi, const KPar
     const T n4 = (r2 * m4 + s2 * (p + uy * uy)) + g2 * (T(2) * vp * Fy * uy);
     const T n5 = (r2 * m5 + s2 * (ux * uy)) + g2 * (vp * (Fx * uy + Fy * ux));
     const T m1 = ux + T(0.5) * (Fx + m.Fx), m2 = uy + T(0.5) * (Fy + m.Fy);
-    const T n6 = m2 * T(1.0 / 3.0), n7 = m1 * T(1.0 / 3.0);
-    const T n8 = ((p + uu) + vp * uF) * T(1.0 / 3.0);
+    const T n6 = third(m2), n7 = third(m1);
+    const T n8 = third((p + uu) + vp * uF);
     o[0] = (n8 - n3) - n4;
     const T hn8 = T(-0.5) * n8;
     const T a1 = T(0.5) * n3 + hn8, a2 = T(0.5) * n4 + hn8;
-    o[1] = a1 + n7;
-    o[3] = a1 - n7;
-    o[2] = a2 + n6;
-    o[4] = a2 - n6;
+    const T d7 = m1 - n7, d6 = m2 - n6;
+    o[1] = fmadd(T(0.5), d7, a1);
+    o[3] = fmadd(T(-0.5), d7, a1);
+    o[2] = fmadd(T(0.5), d6, a2);
+    o[4] = fmadd(T(-0.5), d6, a2);
     const T q6 = T(0.25) * n6, q7 = T(0.25) * n7;
     const T b = T(0.25) * n8 + q6, bc = T(0.25) * n8 - q6;
     const T t1 = T(0.25) * n5 + q7, t2 = T(0.25) * n5 - q7;
