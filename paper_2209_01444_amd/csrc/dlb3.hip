@@ -427,15 +427,28 @@ __global__ __launch_bounds__(BX* BY) void k3_flow(const K3 kp, const S* __restri
     }
     const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     const T p = T(0.5) * (rest - T(0.5) * uu);  // cs^2/(1 - w0) (rest - w0 |u|^2/(2 cs^2))
+    // The parts of the equilibrium and the forcing that carry mass, momentum
+    // and pressure are built from one twelfth of p, u and F_b (3 w = 1/6 on
+    // the axes is twice 1/12, on the diagonals 1/12), so that they sum back to
+    // 2p, u and F_b/2 up to unbiased rounding; weights 1/18 and 1/36 rounded
+    // to FP32 would scale them by 1 + 7.5e-9 every sub-step.  1/12 is
+    // 21/256 + 1/768: the first exact, the rounding of the second 5e-10 of
+    // the result.  h_0^eq closes the mass: minus the sum of the others.
+    auto twelfth = [](T v) { return v * T(21.0 / 256.0) + v * T(1.0 / 768.0); };
+    const T tp = twelfth(p);
+    const T tu[3] = {twelfth(u[0]), twelfth(u[1]), twelfth(u[2])};
+    const T tf[3] = {twelfth(Fb[0]), twelfth(Fb[1]), twelfth(Fb[2])};
     T heq[19], Pi[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+    T moving = T(0);
 #pragma unroll
-    for (int i = 0; i < 19; ++i) {
+    for (int i = 1; i < 19; ++i) {
         const int ax = EX19[i], ay = EY19[i], az = EZ19[i];
         const int nn = ax * ax + ay * ay + az * az;
-        const T w = nn == 0 ? T(1.0 / 3.0) : (nn == 1 ? T(1.0 / 18.0) : T(1.0 / 36.0));
+        const T w = nn == 1 ? T(1.0 / 18.0) : T(1.0 / 36.0);
         const T cu = T(ax) * u[0] + T(ay) * u[1] + T(az) * u[2];
-        const T sig = i == 0 ? T(-2) * p : w * T(3) * p;
-        heq[i] = sig + w * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * uu);
+        const T lin = (T(ax) * tu[0] + T(ay) * tu[1] + T(az) * tu[2]) + tp;  // 3 w (p + c.u) / (nn == 1 ? 2 : 1)
+        heq[i] = (nn == 1 ? T(2) * lin : lin) + w * (T(4.5) * cu * cu - T(1.5) * uu);
+        moving += heq[i];
         const T dn = h[i] - heq[i];
         Pi[0] += T(ax * ax) * dn;
         Pi[1] += T(ay * ay) * dn;
@@ -444,6 +457,7 @@ __global__ __launch_bounds__(BX* BY) void k3_flow(const K3 kp, const S* __restri
         Pi[4] += T(ax * az) * dn;
         Pi[5] += T(ay * az) * dn;
     }
+    heq[0] = -moving;
     const T r = T(1) - T(kp.s2u);
     const int xp = x + 1 == kp.nx ? 0 : x + 1, xm = x == 0 ? kp.nx - 1 : x - 1;
     const int yp = y + 1 == kp.ny ? 0 : y + 1, ym = y == 0 ? kp.ny - 1 : y - 1;
@@ -452,8 +466,9 @@ __global__ __launch_bounds__(BX* BY) void k3_flow(const K3 kp, const S* __restri
     for (int i = 0; i < 19; ++i) {
         const int ax = EX19[i], ay = EY19[i], az = EZ19[i];
         const int nn = ax * ax + ay * ay + az * az;
-        const T w = nn == 0 ? T(1.0 / 3.0) : (nn == 1 ? T(1.0 / 18.0) : T(1.0 / 36.0));
-        T post = heq[i] + T(0.5) * (w * T(3) * (T(ax) * Fb[0] + T(ay) * Fb[1] + T(az) * Fb[2]));
+        // forcing (1 - 1/2) 3 w c.F_b: c.F_b/12 on the axes, half that on the diagonals
+        const T cf = T(ax) * tf[0] + T(ay) * tf[1] + T(az) * tf[2];
+        T post = heq[i] + (nn == 1 ? cf : T(0.5) * cf);
         if (nn == 0) post += r * -((Pi[0] + Pi[1]) + Pi[2]);
         else if (nn == 1) post += r * T(0.5) * (ax ? Pi[0] : (ay ? Pi[1] : Pi[2]));
         else post += r * T(0.25) * (az == 0 ? T(ax * ay) * Pi[3] : (ay == 0 ? T(ax * az) * Pi[4] : T(ay * az) * Pi[5]));
