@@ -192,6 +192,23 @@ def calibrate_copy(nbytes: int = 1 << 30, reps: int = 5):
                       "copy_GBs": 2 * nbytes * reps / el / 1e9}), flush=True)
 
 
+def surrogate_leg() -> dict:
+    """Third part of the metric: time to main step 10000 of the hybrid loop
+    (K = 100 network jumps, L = 100 lattice Boltzmann steps after each, the
+    2% tip-velocity check with fallback) with the stored 512^2 network,
+    against plain lattice Boltzmann, on the seed held out of its training."""
+    from paper_2209_01444_amd import surrogate
+
+    if not os.path.exists(surrogate.BUNDLE):
+        return {"skipped": f"no trained network at {os.path.relpath(surrogate.BUNDLE, ROOT)}"}
+    r = surrogate.speedup_check()
+    return {"metric": "surrogate time-to-solution speedup", "value": round(r["speedup"], 3),
+            "tip_velocity_rel_err": round(r["tip_v_rel_err"], 5), "bound": r["tol"],
+            "accepted": r["accepted"], "jumps": r["jumps"], "plain_s": round(r["plain_seconds"], 4),
+            "hybrid_s": round(r["hybrid_seconds"], 4), "size": r["size"], "K": r["K"], "L": r["L"], "T": r["T"],
+            "network": os.path.relpath(surrogate.BUNDLE, ROOT)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -211,6 +228,8 @@ def main():
                     help="also measure the workload at this grid size, whose state does not fit the "
                          "last-level cache (0: skip)")
     ap.add_argument("--hbm-steps", type=int, default=100)
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="skip the surrogate leg (hybrid loop with the stored network against plain LB)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -306,6 +325,8 @@ def main():
                                 "steps": args.hbm_steps, "state_bytes": int(m2["solver"].state.numel()),
                                 "kernels": kernel_rooflines(c2, m2, wl2)}
         m2["solver"].close()
+    if not args.no_surrogate:
+        line["surrogate"] = surrogate_leg()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, noise)
     print(json.dumps(line), flush=True)

@@ -268,15 +268,39 @@ __device__ __forceinline__ void pct_node(const KParams& kp, const typename CF::S
     const bool wall = WALLS && is_wall(kp, x, y);
     const size_t src = wall ? inward_idx(kp, x, y) : idx;
 
-    T f[5], n[5], g[5] = {T(0), T(0), T(0), T(0), T(0)};
+    // Every load of the node is issued before its arithmetic: the kernel is
+    // bound by HBM, and groups of loads each waited for in turn keep fewer
+    // bytes in flight.  All fifteen population planes and the history planes
+    // exist whatever the flags, so the loads are unconditional; what a flag
+    // leaves unused is discarded.
+    T f[5], n[5], g[5];
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
         f[i] = ld_pop<T>(pin, i * P + src, kp.shift[i]);
         n[i] = ld_pct<CF, T>(pin, 5 + i, P, src, kp.shift);
+        g[i] = ld_pct<CF, T>(pin, 10 + i, P, src, kp.shift);
     }
-    if (kp.use_t)
+    T hr[9];
+    if constexpr (NS) {
 #pragma unroll
-        for (int i = 0; i < 5; ++i) g[i] = ld_pct<CF, T>(pin, 10 + i, P, src, kp.shift);
+        for (int i = 0; i < 9; ++i) hr[i] = ld_pop<T>(hin, i * P + src, kp.shift[15 + i]);
+    }
+    constexpr int NH = NS ? 6 : 2;
+    T hv[NH];
+#pragma unroll
+    for (int j = 0; j < NH; ++j) hv[j] = T(hist[j * P + idx]);
+    long long dst[5];
+    T fold[5];
+    fold[0] = f[0];
+    dst[0] = push_dest<WALLS>(kp, x, y, C5X[0], C5Y[0]);
+#pragma unroll
+    for (int i = 1; i < 5; ++i) {
+        dst[i] = push_dest<WALLS>(kp, x, y, C5X[i], C5Y[i]);
+        fold[i] = ld_pop<T>(pin, i * P + (dst[i] < 0 ? idx : (size_t)dst[i]), kp.shift[i]);
+    }
+    if (!kp.use_t)
+#pragma unroll
+        for (int i = 0; i < 5; ++i) g[i] = T(0);
     if constexpr (WALLS && !NS) {
         if (wall && kp.farfield) farfield_rebuild<T>(kp, f, n, g);
     }
@@ -300,7 +324,12 @@ __device__ __forceinline__ void pct_node(const KParams& kp, const typename CF::S
         uy = fm.uy * T(kp.nsub_d);
     } else if constexpr (NS) {
         T h[9];
-        flow_node<T, S, WALLS>(kp, hin, x, y, idx, phi, h);
+        if (wall) {
+            wall_rebuild<T, false>(kp, x, y, hr, phi, h);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) h[i] = hr[i];
+        }
         T d57 = h[5] - h[7], d68 = h[6] - h[8];
         T mx = (h[1] - h[3]) + (d57 - d68);
         T my = (h[2] - h[4]) + (d57 + d68);
@@ -326,13 +355,13 @@ __device__ __forceinline__ void pct_node(const KParams& kp, const typename CF::S
     T dQ = T(0), dphi = T(0), dCx = T(0), dCy = T(0), dHx = T(0), dHy = T(0);
     const T Cux = C * ux, Cuy = C * uy, Hux = H * ux, Huy = H * uy;
     if (hist_valid) {
-        dphi = phi - T(hist[idx]);
-        dQ = Q - T(hist[P + idx]);
+        dphi = phi - hv[0];
+        dQ = Q - hv[1];
         if constexpr (NS) {
-            dCx = Cux - T(hist[2 * P + idx]);
-            dCy = Cuy - T(hist[3 * P + idx]);
-            dHx = Hux - T(hist[4 * P + idx]);
-            dHy = Huy - T(hist[5 * P + idx]);
+            dCx = Cux - hv[2];
+            dCy = Cuy - hv[3];
+            dHx = Hux - hv[4];
+            dHy = Huy - hv[5];
         }
     }
     hist[idx] = HT(phi);
@@ -405,10 +434,9 @@ __device__ __forceinline__ void pct_node(const KParams& kp, const typename CF::S
     // ---- streaming (push).  phi: f(y,t+1) = f(y,t) + (post - f(y,t)) / a_s^2 ----
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
-        long long d = push_dest<WALLS>(kp, x, y, C5X[i], C5Y[i]);
+        const long long d = dst[i];
         if (d < 0) continue;
-        T fold = i == 0 ? f[0] : ld_pop<T>(pin, i * P + (size_t)d, kp.shift[i]);
-        st_pop(pout, i * P + (size_t)d, fold + (pf[i] - fold) * inv_a2, kp.shift[i]);
+        st_pop(pout, i * P + (size_t)d, fold[i] + (pf[i] - fold[i]) * inv_a2, kp.shift[i]);
         st_pct<CF>(pout, 5 + i, P, (size_t)d, pn[i], kp.shift);
         if (heat_here) st_pct<CF>(pout, 10 + i, P, (size_t)d, pg[i], kp.shift);
     }

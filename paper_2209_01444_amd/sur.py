@@ -179,6 +179,7 @@ class Surrogate:
         w = np.ascontiguousarray(w5, dtype=np.float32)
         assert w.shape == (5,)
         _check(self.lib, self.lib.sur_set_loss_weights(self.handle, _fptr(w)))
+        self.loss_weights = w.copy()
 
     def _dev(self, t, dtype):
         assert t.is_cuda and t.dtype == dtype and t.is_contiguous()

@@ -25,6 +25,7 @@ from __future__ import annotations
 import argparse
 import json
 import math
+import os
 import time
 
 import numpy as np
@@ -33,6 +34,10 @@ from paper_2209_01444_amd import dlb, workloads
 from paper_2209_01444_amd import sur as sur_mod
 
 FIELDS5 = ("phi", "C", "theta", "ux", "uy")
+
+# A network trained by this module's command line at 512^2 (K = 100, 32
+# training seeds, 32000 Adam steps; see save_bundle for the format)
+BUNDLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "unet32_512_k100.npz")
 
 
 def sweep_cases(count: int, size: int, seed: int):
@@ -236,6 +241,73 @@ def compare(h, p):
                 "accepted": h["accepted"], "fallbacks": h["fallbacks"]}
 
 
+def conv_weight_mask() -> np.ndarray:
+    """True at the entries of the flat parameter vector that hold 3x3
+    convolution weights (which the forward pass uses in bfloat16)."""
+    from paper_2209_01444_amd import sur as sm
+
+    parts = []
+    for _, _, cip, co in sm.layers():
+        parts += [np.ones(9 * co * cip, dtype=bool), np.zeros(co, dtype=bool)]
+    parts.append(np.zeros(165, dtype=bool))  # 1x1 head, FP32
+    return np.concatenate(parts)
+
+
+def to_bf16_bits(x: np.ndarray) -> np.ndarray:
+    """FP32 -> bfloat16 bit patterns, rounded to nearest even (finite input)."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    return ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+
+
+def from_bf16_bits(b: np.ndarray) -> np.ndarray:
+    return (np.asarray(b, dtype=np.uint16).astype(np.uint32) << 16).view(np.float32)
+
+
+def save_bundle(path: str, net, meta: dict) -> None:
+    """Trained network as one .npz: the 3x3 weights as bfloat16 bit patterns
+    (what the forward pass computes with, so nothing is lost for inference),
+    biases and the 1x1 head in FP32, the input and residual normalisation,
+    the loss weights and the training options (JSON text)."""
+    flat = net.get_params()
+    mask = conv_weight_mask()
+    np.savez(path, w_bf16=to_bf16_bits(flat[mask]), rest=flat[~mask].astype(np.float32),
+             mean=net.mean, std=net.std, rstd=net.rstd, loss_weights=np.asarray(net.loss_weights, np.float64),
+             meta=np.array(json.dumps(meta)))
+
+
+def load_bundle(path: str = BUNDLE, batch: int = 1):
+    """The network of a save_bundle file on the GPU: (Surrogate, options)."""
+    z = np.load(path)  # plain arrays only (no pickle)
+    meta = json.loads(str(z["meta"]))
+    mask = conv_weight_mask()
+    flat = np.empty(mask.size, dtype=np.float32)
+    flat[mask] = from_bf16_bits(z["w_bf16"])
+    flat[~mask] = z["rest"]
+    n = int(meta["size"])
+    net = sur_mod.Surrogate(batch, n, n)
+    net.set_params(flat)
+    net.set_normalization(z["mean"], z["std"], z["rstd"])
+    net.set_loss_weights(z["loss_weights"])
+    return net, meta
+
+
+def speedup_check(path: str = BUNDLE, T: int = 10000, L: int = 100, tol: float = 0.02) -> dict:
+    """Time to main step T of the hybrid loop with a stored network against
+    plain lattice Boltzmann, on the seed held out of its training, with the
+    final tip-velocity error of every arm."""
+    net, meta = load_bundle(path)
+    cfg, noise = sweep_cases(int(meta["train_seeds"]) + 1, int(meta["size"]), int(meta["seed"]))[-1]
+    run_plain(cfg, noise, 200)  # kernels loaded and launch paths warm before either timed run
+    plain = run_plain(cfg, noise, T)
+    hyb = run_hybrid(cfg, noise, T, int(meta["t0"]), int(meta["K"]), L, net, tol, restart=meta["restart"])
+    r = compare(hyb, plain)
+    r.update({"plain_seconds": plain["seconds"], "hybrid_seconds": hyb["seconds"],
+              "jumps": hyb["accepted"] + hyb["fallbacks"], "size": int(meta["size"]), "K": int(meta["K"]),
+              "L": L, "T": T, "tol": tol})
+    net.close()
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--size", type=int, default=512)
@@ -250,9 +322,9 @@ def main():
     ap.add_argument("--T", type=int, default=10000)
     ap.add_argument("--tol", type=float, default=0.02)
     ap.add_argument("--seed", type=int, default=5)
-    ap.add_argument("--save", default="", help="write the trained FP32 parameters (.npy) here")
-    ap.add_argument("--load", default="", help="skip training: FP32 parameters (.npy) from --save "
-                    "of a run with the same data options")
+    ap.add_argument("--save", default="", help="write the trained network (.npz, see save_bundle) here")
+    ap.add_argument("--load", default="", help="skip training: a network written by --save (its size, K, "
+                    "seeds and restart replace the options given here)")
     ap.add_argument("--restart", default="continue", choices=("continue", "equilibrium"))
     ap.add_argument("--loss-weights", default="1,1,1,0,0",
                     help="per-channel loss weights (phi, C, theta, ux, uy); the continuation restart "
@@ -260,26 +332,31 @@ def main():
     args = ap.parse_args()
     import torch
 
+    if args.load:
+        net, meta = load_bundle(args.load, batch=args.batch)
+        args.size, args.K, args.seed, args.train_seeds = meta["size"], meta["K"], meta["seed"], meta["train_seeds"]
+        args.t0, args.restart, args.iters = meta["t0"], meta["restart"], meta["iters"]
+        lw = np.asarray(net.loss_weights)
     n = args.size
     cases = sweep_cases(args.train_seeds + 1, n, args.seed)
     train_cases, test_case = cases[:-1], cases[-1]
-    t_gen = time.perf_counter()
-    X, Y = make_dataset(train_cases, args.t0, args.K, args.pairs)
-    t_gen = time.perf_counter() - t_gen
-    mean, std, rstd = normalization(X, Y)
-    print(json.dumps({"pairs": int(X.shape[0]), "gen_seconds": t_gen, "mean": mean.tolist(),
-                      "std": std.tolist(), "rstd": rstd.tolist()}), flush=True)
-
-    net = sur_mod.Surrogate(args.batch, n, n)
-    net.set_params(sur_mod.flatten(init_params(args.seed)))
-    net.set_normalization(mean, std, rstd)
-    lw = np.array([float(v) for v in args.loss_weights.split(",")])
-    net.set_loss_weights(lw)
     if args.load:
-        net.set_params(np.load(args.load))
+        X = make_dataset([test_case], args.t0, args.K, 1)[0]
         losses, t_train = [math.nan], 0.0
     else:
+        t_gen = time.perf_counter()
+        X, Y = make_dataset(train_cases, args.t0, args.K, args.pairs)
+        t_gen = time.perf_counter() - t_gen
+        mean, std, rstd = normalization(X, Y)
+        print(json.dumps({"pairs": int(X.shape[0]), "gen_seconds": t_gen, "mean": mean.tolist(),
+                          "std": std.tolist(), "rstd": rstd.tolist()}), flush=True)
+        net = sur_mod.Surrogate(args.batch, n, n)
+        net.set_params(sur_mod.flatten(init_params(args.seed)))
+        net.set_normalization(mean, std, rstd)
+        lw = np.array([float(v) for v in args.loss_weights.split(",")])
+        net.set_loss_weights(lw)
         losses, t_train = train(net, X, Y, args.iters, args.batch, args.lr, seed=args.seed)
+        del Y
     # forward timing at batch 1
     x1 = X[:1].contiguous()
     o1 = torch.empty((1, 5, n, n), dtype=torch.float64, device="cuda")
@@ -291,7 +368,9 @@ def main():
     torch.cuda.synchronize()
     fwd_ms = (time.perf_counter() - tf) / 20 * 1e3
     if args.save:
-        np.save(args.save, net.get_params())
+        save_bundle(args.save, net, {"size": n, "K": args.K, "t0": args.t0, "seed": args.seed,
+                                     "train_seeds": args.train_seeds, "pairs": args.pairs, "iters": args.iters,
+                                     "batch": args.batch, "lr": args.lr, "restart": args.restart})
 
     cfg, noise = test_case
     Xv, Yv = make_dataset([test_case], args.t0, args.K, (args.T - args.t0) // args.K - 1)

@@ -19,8 +19,8 @@ against the oracle on a 192^2 channel after 1500 steps, tip velocity 1%
 fraction 1e-3 / 5e-3 (1.6e-4 / 1.9e-3), theta 2e-3 / 0.3 relative L-inf
 (7.8e-4 / 0.11); on the 1024^2 benchmark workload after 20000 steps against
 the FP64 GPU run (validated against the oracle by the parity tests), f16sm
-tip velocity within the 2% the storage mode is meant to hold (1.6%), tip
-radius 2% (0.9%) and solid fraction 1% (0.19%)."""
+tip velocity within the 2% the storage mode is meant to hold (1.3%), tip
+radius 2% (0.9%) and solid fraction 1% (0.18%)."""
 import numpy as np
 import pytest
 
