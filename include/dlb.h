@@ -288,10 +288,20 @@ int64_t dlb_batch_step_count(dlb_batch_handle b);
  * (1..64) and the fused flow kernel (1..16). */
 int dlb_batch_set_config(dlb_batch_handle b, int fuse, int bpc_node, int bpc_tb);
 int dlb_batch_get_config(dlb_batch_handle b, int* out3);
+/* Node tile of the batched phi/C/theta and one-sub-step flow launches:
+ * tile_width x (256 / tile_width) nodes, tile_width 32, 64 (default), 128 or
+ * 256; every member's results are the same for each.  The fused flow
+ * launch's tile is set by the fuse depth: its 64 x 32 extended tile stores a
+ * (64 - 2K) x (32 - 2K) centre.  DLB_EINVAL for another width.  get returns
+ * the width, or a negative error code. */
+int dlb_batch_set_node_tile(dlb_batch_handle b, int tile_width);
+int dlb_batch_get_node_tile(dlb_batch_handle b);
 /* Autotuner: times trial_steps batch steps (HIP events) for each candidate
- * launch configuration, keeps the fastest, returns its ms per step.  The
- * trial steps consume the state: call it before initialising the members
- * (member step counters restart at 0).  Synchronises. */
+ * launch configuration (fuse depth and fused workgroups per CU, then node
+ * workgroups per CU, then node tile shape), keeps the fastest, returns its
+ * ms per step.  The trial steps consume the state: call it before
+ * initialising the members (member step counters restart at 0).
+ * Synchronises. */
 int dlb_batch_autotune(dlb_batch_handle b, int trial_steps, double* ms_best);
 
 const char* dlb_strerror(int code);

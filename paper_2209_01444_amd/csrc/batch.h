@@ -19,7 +19,8 @@ struct SeedDesc {
     void* flow[2];
     void* hist;
     int hist_valid;
-    int tile0;      // first 64x4 tile of this seed in the node-kernel work list
+    int tile0;      // first node tile of this seed in the node-kernel work list
+    int node_nbx;   // node tiles per row (tile width x 256/width nodes, set per batch)
     int tb0[2];     // first extended tile in the fused-flow work list, K = 3 / K = 5
     int tb_nbx[2];  // extended tiles per row, K = 3 / K = 5
 };
@@ -36,9 +37,16 @@ __device__ __forceinline__ int seed_of(const SeedDesc* __restrict__ d, int count
     return lo;
 }
 
+// node (x, y) of this thread in node tile t of a seed: tiles of 2^tw_log2
+// columns by BLOCK >> tw_log2 rows, one node per thread
+__device__ __forceinline__ void batch_node(const SeedDesc& sd, int t, int tw_log2, int& x, int& y) {
+    x = ((t % sd.node_nbx) << tw_log2) + (threadIdx.x & ((1 << tw_log2) - 1));
+    y = (t / sd.node_nbx) * (BLOCK >> tw_log2) + (threadIdx.x >> tw_log2);
+}
+
 template <class CF, bool NS, bool WALLS>
 __global__ __launch_bounds__(BLOCK) void k_pct_batch(const SeedDesc* __restrict__ d, int count,
-                                                     int total, int cur, int fcur) {
+                                                     int total, int cur, int fcur, int tw_log2) {
     using S = typename CF::S;
     using H = typename CF::H;
     const int chunk = (total + gridDim.x - 1) / gridDim.x;
@@ -47,9 +55,8 @@ __global__ __launch_bounds__(BLOCK) void k_pct_batch(const SeedDesc* __restrict_
     for (int item = beg; item < end; ++item) {
         while (s + 1 < count && d[s + 1].tile0 <= item) ++s;
         const SeedDesc& sd = d[s];
-        const int t = item - sd.tile0;
-        const int x = (t % sd.kp.nbx) * TILE_X + (threadIdx.x & (TILE_X - 1));
-        const int y = (t / sd.kp.nbx) * TILE_Y + (threadIdx.x >> 6);
+        int x, y;
+        batch_node(sd, item - sd.tile0, tw_log2, x, y);
         if (x < sd.kp.nx && y < sd.kp.ny)
             pct_node<CF, NS, WALLS>(sd.kp, (const S*)sd.pop[cur], (S*)sd.pop[1 - cur],
                                     (const S*)sd.flow[fcur], (H*)sd.hist, sd.hist_valid, x, y);
@@ -58,7 +65,7 @@ __global__ __launch_bounds__(BLOCK) void k_pct_batch(const SeedDesc* __restrict_
 
 template <class CF, bool WALLS>
 __global__ __launch_bounds__(BLOCK) void k_flow_batch(const SeedDesc* __restrict__ d, int count,
-                                                      int total, int fcur) {
+                                                      int total, int fcur, int tw_log2) {
     using S = typename CF::S;
     using H = typename CF::H;
     const int chunk = (total + gridDim.x - 1) / gridDim.x;
@@ -67,9 +74,8 @@ __global__ __launch_bounds__(BLOCK) void k_flow_batch(const SeedDesc* __restrict
     for (int item = beg; item < end; ++item) {
         while (s + 1 < count && d[s + 1].tile0 <= item) ++s;
         const SeedDesc& sd = d[s];
-        const int t = item - sd.tile0;
-        const int x = (t % sd.kp.nbx) * TILE_X + (threadIdx.x & (TILE_X - 1));
-        const int y = (t / sd.kp.nbx) * TILE_Y + (threadIdx.x >> 6);
+        int x, y;
+        batch_node(sd, item - sd.tile0, tw_log2, x, y);
         if (x < sd.kp.nx && y < sd.kp.ny)
             flow_step_node<CF, WALLS>(sd.kp, (const S*)sd.flow[fcur], (S*)sd.flow[1 - fcur],
                                       (const H*)sd.hist, x, y);

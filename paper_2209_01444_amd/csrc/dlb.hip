@@ -257,8 +257,8 @@ struct Ops {
 };
 
 struct BatchOps {
-    void (*pct)(const SeedDesc*, int, int, int, int, int, hipStream_t);
-    void (*flow)(const SeedDesc*, int, int, int, int, hipStream_t);
+    void (*pct)(const SeedDesc*, int, int, int, int, int, int, hipStream_t);
+    void (*flow)(const SeedDesc*, int, int, int, int, int, hipStream_t);
     void (*flow_tb)(int, const SeedDesc*, int, int, int, int, hipStream_t);
 };
 
@@ -351,13 +351,15 @@ template <class CF, bool NS, bool W> struct OpsImpl {
     }
 
     // batched persistent launches
-    static void b_pct(const SeedDesc* d, int count, int total, int cur, int fcur, int blocks,
+    static void b_pct(const SeedDesc* d, int count, int total, int cur, int fcur, int tw_log2, int blocks,
                       hipStream_t st) {
         hipLaunchKernelGGL((k_pct_batch<CP, NS, W>), dim3(blocks), dim3(BLOCK), 0, st, d, count, total,
-                           cur, fcur);
+                           cur, fcur, tw_log2);
     }
-    static void b_flow(const SeedDesc* d, int count, int total, int fcur, int blocks, hipStream_t st) {
-        hipLaunchKernelGGL((k_flow_batch<CF, W>), dim3(blocks), dim3(BLOCK), 0, st, d, count, total, fcur);
+    static void b_flow(const SeedDesc* d, int count, int total, int fcur, int tw_log2, int blocks,
+                       hipStream_t st) {
+        hipLaunchKernelGGL((k_flow_batch<CF, W>), dim3(blocks), dim3(BLOCK), 0, st, d, count, total, fcur,
+                           tw_log2);
     }
     static void b_flow_tb(int K, const SeedDesc* d, int count, int total, int fcur, int blocks,
                           hipStream_t st) {
@@ -904,6 +906,7 @@ struct dlb_batch {
     int pop_cur = 0, flow_cur = 0;
     int64_t step = 0;
     int fuse = 5, bpc_node = 8, bpc_tb = 2, num_cu = 256;
+    int node_tw_log2 = 6;  // node tiles of 64 x 4 nodes
     BatchOps ops;
     hipGraphExec_t graph = nullptr;
     int graph_pop = -1, graph_flow = -1;
@@ -949,9 +952,24 @@ static int upload_desc(dlb_batch* b) {
     return DLB_OK;
 }
 
+// Node-kernel work list for tiles of 2^tw_log2 x (BLOCK >> tw_log2) nodes:
+// each member's first tile and tiles per row; the caller uploads it.
+static void batch_node_tiles(dlb_batch* b, int tw_log2) {
+    const int tw = 1 << tw_log2, th = BLOCK >> tw_log2;
+    b->total_tiles = 0;
+    for (int i = 0; i < b->count; ++i) {
+        const dlb_params& p = b->members[i]->p;
+        const int nbx = (p.nx + tw - 1) / tw, nby = (p.ny + th - 1) / th;
+        b->desc[i].tile0 = b->total_tiles;
+        b->desc[i].node_nbx = nbx;
+        b->total_tiles += nbx * nby;
+    }
+    b->node_tw_log2 = tw_log2;
+}
+
 static void batch_enqueue_step(dlb_batch* b, int fuse, int bpc_node, int bpc_tb) {
     const int bn = std::min(b->total_tiles, b->num_cu * bpc_node);
-    b->ops.pct(b->d_desc, b->count, b->total_tiles, b->pop_cur, b->flow_cur, bn, b->stream);
+    b->ops.pct(b->d_desc, b->count, b->total_tiles, b->pop_cur, b->flow_cur, b->node_tw_log2, bn, b->stream);
     b->pop_cur ^= 1;
     if (b->p0.use_ns) {
         int left = b->p0.n_sub;
@@ -963,7 +981,7 @@ static void batch_enqueue_step(dlb_batch* b, int fuse, int bpc_node, int bpc_tb)
             left -= fuse;
         }
         for (; left > 0; --left) {
-            b->ops.flow(b->d_desc, b->count, b->total_tiles, b->flow_cur, bn, b->stream);
+            b->ops.flow(b->d_desc, b->count, b->total_tiles, b->flow_cur, b->node_tw_log2, bn, b->stream);
             b->flow_cur ^= 1;
         }
     }
@@ -1027,8 +1045,6 @@ int dlb_batch_create(const dlb_params* ps, int count, void* dev_state, size_t by
         d.flow[0] = m->flow(0);
         d.flow[1] = m->flow(1);
         d.hist = m->hist();
-        d.tile0 = b->total_tiles;
-        b->total_tiles += m->L.nblocks;
         const int Ks[2] = {3, 5};
         for (int L = 0; L < 2; ++L) {
             int OX = EX - 2 * Ks[L], OY = EY - 2 * Ks[L];
@@ -1039,6 +1055,7 @@ int dlb_batch_create(const dlb_params* ps, int count, void* dev_state, size_t by
         }
         b->desc.push_back(d);
     }
+    batch_node_tiles(b, 6);
     b->d_desc = (SeedDesc*)((char*)dev_state + total - align256((size_t)count * sizeof(SeedDesc)));
     rc = upload_desc(b);
     if (rc) {
@@ -1077,6 +1094,25 @@ int dlb_batch_set_config(dlb_batch_handle b, int fuse, int bpc_node, int bpc_tb)
         b->graph = nullptr;
     }
     return DLB_OK;
+}
+
+int dlb_batch_set_node_tile(dlb_batch_handle b, int tile_width) {
+    if (!b) return fail(DLB_EINVAL, "null batch");
+    int lg = -1;
+    for (int k = 5; k <= 8; ++k)
+        if (tile_width == (1 << k)) lg = k;
+    if (lg < 0) return fail(DLB_EINVAL, "node tile width must be 32, 64, 128 or 256");
+    batch_node_tiles(b, lg);
+    if (b->graph) {
+        (void)hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    return upload_desc(b);
+}
+
+int dlb_batch_get_node_tile(dlb_batch_handle b) {
+    if (!b) return fail(DLB_EINVAL, "null batch");
+    return 1 << b->node_tw_log2;
 }
 
 int dlb_batch_get_config(dlb_batch_handle b, int* out3) {
@@ -1187,6 +1223,20 @@ int dlb_batch_autotune(dlb_batch_handle b, int trial_steps, double* ms_best) {
         if (rc) return rc;
         if (ms < best) best = ms, bn = n;
     }
+    // node tile shape: 64 x 4 (timed above), 128 x 2, 256 x 1, 32 x 8
+    int blg = b->node_tw_log2;
+    for (int lg : {7, 8, 5}) {
+        if (lg == blg) continue;
+        batch_node_tiles(b, lg);
+        rc = upload_desc(b);
+        if (rc) return rc;
+        float ms = 0.f;
+        rc = batch_time(b, bf, bn, bt, trial_steps, &ms);
+        if (rc) return rc;
+        if (ms < best) best = ms, blg = lg;
+    }
+    rc = dlb_batch_set_node_tile(b, 1 << blg);
+    if (rc) return rc;
     rc = dlb_batch_set_config(b, bf, bn, bt);
     if (rc) return rc;
     // the trial steps consumed the state: members must be (re-)initialised

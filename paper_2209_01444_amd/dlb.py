@@ -45,7 +45,7 @@ EXPORTS = (
     "dlb_save", "dlb_load", "dlb_copy_state", "dlb_sync", "dlb_equilibria", "dlb_copy_kernel", "dlb_strerror",
     "dlb_last_error", "dlb_batch_state_bytes", "dlb_batch_create", "dlb_batch_destroy",
     "dlb_batch_member", "dlb_batch_step", "dlb_batch_step_count", "dlb_batch_set_config",
-    "dlb_batch_get_config", "dlb_batch_autotune",
+    "dlb_batch_get_config", "dlb_batch_set_node_tile", "dlb_batch_get_node_tile", "dlb_batch_autotune",
 )
 
 _lib = None
@@ -95,6 +95,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "dlb_batch_step_count": (i64, [vp]),
         "dlb_batch_set_config": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
         "dlb_batch_get_config": (ctypes.c_int, [vp, P(ctypes.c_int)]),
+        "dlb_batch_set_node_tile": (ctypes.c_int, [vp, ctypes.c_int]),
+        "dlb_batch_get_node_tile": (ctypes.c_int, [vp]),
         "dlb_batch_autotune": (ctypes.c_int, [vp, ctypes.c_int, dp]),
     }
     for name, (res, args) in sig.items():
@@ -371,6 +373,17 @@ class Batch:
         out = (ctypes.c_int * 3)()
         _check(self.lib, self.lib.dlb_batch_get_config(self.handle, out))
         return tuple(out)
+
+    def set_node_tile(self, width: int):
+        """Node tile of the batched node kernels: width x 256/width nodes."""
+        _check(self.lib, self.lib.dlb_batch_set_node_tile(self.handle, int(width)))
+
+    @property
+    def node_tile(self) -> int:
+        w = int(self.lib.dlb_batch_get_node_tile(self.handle))
+        if w < 0:
+            _check(self.lib, w)
+        return w
 
     def autotune(self, trial_steps: int = 20) -> float:
         """Pick the fastest launch configuration (consumes the state)."""

@@ -37,13 +37,14 @@ def tuned(batch: dlb.Batch, cases, trial_steps: int = 5) -> dict:
     if os.path.exists(TUNE_CACHE):
         with open(TUNE_CACHE) as fh:
             cache = json.load(fh)
-    if key in cache:
+    if key in cache and "node_tile" in cache[key]:
         batch.set_config(*cache[key]["config"])
+        batch.set_node_tile(cache[key]["node_tile"])
         return cache[key]
     for m, (_, noise) in zip(batch.members, cases):
         m.init_seed(noise)
     ms = batch.autotune(trial_steps)
-    rec = {"config": list(batch.config()), "ms_per_step": ms}
+    rec = {"config": list(batch.config()), "node_tile": batch.node_tile, "ms_per_step": ms}
     cache[key] = rec
     os.makedirs(os.path.dirname(TUNE_CACHE), exist_ok=True)
     with open(TUNE_CACHE, "w") as fh:
@@ -96,6 +97,7 @@ def main():
     el = time.perf_counter() - t0
     out = {"members": len(cases), "nodes": nodes, "steps": args.steps - 1, "seconds": el,
            "aggregate_MLUPS": nodes * (args.steps - 1) / el / 1e6, "config": b.config(),
+           "node_tile": b.node_tile,
            "precision": args.precision}
     if args.snapshots:
         out["note"] = "timing includes snapshot transfers"
@@ -106,6 +108,7 @@ def main():
         idx = np.random.default_rng(0).choice(len(cases), size=min(args.check, len(cases)), replace=False)
         b2 = dlb.Batch([c for c, _ in cases])
         b2.set_config(*tune["config"])
+        b2.set_node_tile(tune["node_tile"])
         for m, (_, noise) in zip(b2.members, cases):
             m.init_seed(noise)
         b2.step(args.check_steps)

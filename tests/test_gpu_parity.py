@@ -740,6 +740,33 @@ def test_batch_members_match_single_runs(dlb, precision, fuse):
         assert m.step_count == 23
 
 
+@pytest.mark.parametrize("width", [32, 128, 256])
+def test_batch_node_tile_shapes_give_the_same_members(dlb, width):
+    """The node tile of the batched node kernels (width x 256/width nodes)
+    changes only which threads handle which nodes: with fuse 1 every flow
+    sub-step also runs on node tiles, and each member is bit for bit the
+    single solver's at every width.  Widths other than 32/64/128/256 are
+    refused."""
+    _say(f"case: batch node tile {width} x {256 // width}, f32 fuse=1 vs single runs")
+    cases = _sweep_cfgs("f32", 1)
+    b = dlb.Batch([c for c, _ in cases])
+    for m, (_, noise) in zip(b.members, cases):
+        m.init_seed(noise)
+    b.set_config(1, 8, 2)
+    b.set_node_tile(width)
+    assert b.node_tile == width
+    b.step(11)
+    for i, (m, (cfg, noise)) in enumerate(zip(b.members, cases)):
+        s = dlb.Solver(cfg).init_seed(noise).step(11)
+        fb, fs = m.fields(), s.fields()
+        for k in FIELDS:
+            assert np.array_equal(fb[k], fs[k]), f"member {i} field {k} differs at node tile {width}"
+    for bad in (0, 16, 48, 512):
+        with pytest.raises(dlb.DlbError):
+            b.set_node_tile(bad)
+    assert b.node_tile == width
+
+
 @pytest.mark.parametrize("precision,fuse,tol", [("f64", 3, 1e-10), ("f32", 5, 1e-4)])
 def test_batch_members_match_the_oracle(dlb, precision, fuse, tol):
     """Batch members against the CPU oracle directly: three members of
@@ -770,8 +797,9 @@ def test_batch_autotune_and_member_rules(dlb):
         m.init_seed(noise)
     ms = b.autotune(3)
     fuse, bn, bt = b.config()
-    _say(f"  tuned: fuse={fuse} node blocks/CU={bn} fused blocks/CU={bt}, {ms:.4f} ms/step")
-    assert ms > 0 and fuse in (1, 3, 5)
+    _say(f"  tuned: fuse={fuse} node blocks/CU={bn} fused blocks/CU={bt} node tile {b.node_tile}, "
+         f"{ms:.4f} ms/step")
+    assert ms > 0 and fuse in (1, 3, 5) and b.node_tile in (32, 64, 128, 256)
     with pytest.raises(dlb.DlbError):
         b.members[0].step(1)
     for m, (_, noise) in zip(b.members, cases):
