@@ -723,6 +723,7 @@ __device__ __forceinline__ void flow_tbw_tile(const KParams& kp, const typename 
     T h[R][9];
     T phi_yw = T(0);  // frozen phi inward of this wave's wall row y = 0 or ny - 1
     FlowCoef<T> fc[R];
+    bool liq[R];
     int gy[R];
     bool ex[R];
 #pragma unroll
@@ -749,6 +750,7 @@ __device__ __forceinline__ void flow_tbw_tile(const KParams& kp, const typename 
             for (int i = 0; i < 9; ++i) h[r][i] = T(0);
         }
         fc[r] = flow_coef(phi);
+        liq[r] = __ballot(phi == T(-1)) == __ballot(1);  // wave-uniform: every lane of the row in the melt
     }
     // rebuild lanes of the wall-column pass: lane j < 8 takes side j / R,
     // row j % R of this wave; the frozen phi of that node's inward neighbour
@@ -765,7 +767,10 @@ __device__ __forceinline__ void flow_tbw_tile(const KParams& kp, const typename 
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             T o[9];
-            flow_collide<T>(h[r], fc[r], s2, o);
+            if (liq[r])
+                flow_collide<T, true>(h[r], fc[r], s2, o);
+            else
+                flow_collide<T>(h[r], fc[r], s2, o);
             // x streaming: c_x = +1 from the left lane, c_x = -1 from the right lane
             h[r][0] = o[0];
             h[r][2] = o[2];

@@ -362,7 +362,8 @@ template <class T> __device__ __forceinline__ T third(T x) {
 // m1/3 and m2/3 through third().  Fused multiply-adds are spelled
 // out and nothing else is contracted, so every kernel that inlines this
 // rounds alike.
-template <class T> __device__ __forceinline__ void flow_collide(const T* h, FlowCoef<T> c, T s2, T* o) {
+template <class T, bool LIQUID = false>
+__device__ __forceinline__ void flow_collide(const T* h, FlowCoef<T> c, T s2, T* o) {
 #pragma clang fp contract(off)
     const T d57 = h[5] - h[7], d68 = h[6] - h[8];
     const T s57 = h[5] + h[7], s68 = h[6] + h[8], e = s57 + s68;
@@ -371,8 +372,9 @@ template <class T> __device__ __forceinline__ void flow_collide(const T* h, Flow
     const T my = (h[2] - h[4]) + (d57 + d68);
     const T m3 = (h[1] + h[3]) + e, m4 = s24 + e, m5 = s57 - s68;
     const T rest = m3 + s24;  // sum of h_1 .. h_8
-    const T ux = mx * c.cu, uy = my * c.cu;
-    const T m1 = mx * c.c1, m2 = my * c.c1;  // s1 = 1: u + F/2
+    // in the melt (phi = -1) both factors are exactly 1
+    const T ux = LIQUID ? mx : mx * c.cu, uy = LIQUID ? my : my * c.cu;
+    const T m1 = LIQUID ? mx : mx * c.c1, m2 = LIQUID ? my : my * c.c1;  // s1 = 1: u + F/2
     const T ux2 = ux * ux, uu = fmadd(uy, uy, ux2);
     // p = 0.6 rest - 0.4 |u|^2 with 0.6 = 0.625 - 0.025: 0.625 is exact and
     // the rounding of 0.025 is 6e-10 of p, against 4e-8 for a rounded 0.6,
