@@ -91,7 +91,8 @@ typedef struct dlb_params {
     int32_t c_init_U;     /* initial solute: 0 uniform C = C0; 1 uniform U = U0      */
     int32_t precision;    /* DLB_F64 .. DLB_F16SM                                    */
     int32_t grad_iters;   /* cap of the local-gradient fixed point (0: default)      */
-    int32_t flow_fuse;    /* flow sub-steps fused per launch: 1, 3 or 5 (0: 5); the
+    int32_t flow_fuse;    /* flow sub-steps fused per launch: 1, 3 or 5 (0: 5 with
+                             FP32 flow arithmetic, 3 with FP64: f64, f32m); the
                              fused kernel keeps a tile in registers and LDS for
                              that many sub-steps; results equal the unfused ones */
     int32_t phi_static;   /* 1: phi, C and theta stay as set (no phi/C/theta
