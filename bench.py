@@ -198,17 +198,23 @@ def surrogate_leg() -> dict:
     """Third part of the metric: time to main step 10000 of the hybrid loop
     (K = 100 network jumps, L = 100 lattice Boltzmann steps after each, the
     2% tip-velocity check with fallback) with the stored 512^2 network,
-    against plain lattice Boltzmann, on the seed held out of its training."""
+    against plain lattice Boltzmann, on the seed held out of its training;
+    and the same with L = 50."""
     from paper_2209_01444_amd import surrogate
 
     if not os.path.exists(surrogate.BUNDLE):
         return {"skipped": f"no trained network at {os.path.relpath(surrogate.BUNDLE, ROOT)}"}
-    r = surrogate.speedup_check()
-    return {"metric": "surrogate time-to-solution speedup", "value": round(r["speedup"], 3),
-            "tip_velocity_rel_err": round(r["tip_v_rel_err"], 5), "bound": r["tol"],
-            "accepted": r["accepted"], "jumps": r["jumps"], "plain_s": round(r["plain_seconds"], 4),
-            "hybrid_s": round(r["hybrid_seconds"], 4), "size": r["size"], "K": r["K"], "L": r["L"], "T": r["T"],
-            "network": os.path.relpath(surrogate.BUNDLE, ROOT)}
+    def one(L):
+        r = surrogate.speedup_check(L=L)
+        return {"value": round(r["speedup"], 3), "tip_velocity_rel_err": round(r["tip_v_rel_err"], 5),
+                "accepted": r["accepted"], "jumps": r["jumps"], "plain_s": round(r["plain_seconds"], 4),
+                "hybrid_s": round(r["hybrid_seconds"], 4), "L": L}
+
+    main = one(100)
+    return {"metric": "surrogate time-to-solution speedup", **main, "bound": 0.02, "size": 512, "K": 100,
+            "T": 10000, "network": os.path.relpath(surrogate.BUNDLE, ROOT),
+            # a shorter lattice Boltzmann window after each jump: faster, closer to the bound
+            "L50": one(50)}
 
 
 def main():
