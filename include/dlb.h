@@ -112,6 +112,14 @@ typedef struct dlb_params {
                              time-t value, diffusivity alpha/n_sub_t per
                              sub-step.  0 or 1: one step inside the phi/C/theta
                              update.  Not available in batches                   */
+    int32_t tile_rows;    /* rows of the fused flow tile (FP32 flow arithmetic,
+                             flow_fuse 3 or 5): 32 (8 waves) or 48 (12 waves:
+                             less halo, fewer tiles resident); 0 chooses 48
+                             where the grid has at least four rounds of tall
+                             tiles for the device's compute units, else 32.
+                             Results do not depend on it.  48 with FP64 flow
+                             arithmetic or unfused sub-steps: DLB_EUNSUPPORTED.
+                             Batches use 32                                      */
     double W0, tau0;      /* interface width and kinetic time (Sec. 2)              */
     double eps4, orient;  /* anisotropy strength and crystal orientation (rad)      */
     double lambda, Mcinf, k;   /* coupling, M c_inf, partition coefficient          */

@@ -78,6 +78,8 @@ int check_params(const dlb_params* p) {
     if (p->isothermal != 0 && p->isothermal != 1) return fail(DLB_EINVAL, "isothermal must be 0 or 1");
     if (p->grad_stencil != 0 && p->grad_stencil != 1) return fail(DLB_EINVAL, "grad_stencil must be 0 or 1");
     if (p->n_sub_t < 0 || p->n_sub_t > 256) return fail(DLB_EINVAL, "n_sub_t must be in [0, 256]");
+    if (p->tile_rows != 0 && p->tile_rows != 32 && p->tile_rows != 48)
+        return fail(DLB_EINVAL, "tile_rows must be 0 (automatic), 32 or 48");
     const bool forced = p->force_x != 0.0 || p->force_y != 0.0 || p->varphi != 0.0;
     if (!(std::isfinite(p->force_x) && std::isfinite(p->force_y) && std::isfinite(p->varphi)))
         return fail(DLB_EINVAL, "force and varphi must be finite");
@@ -232,8 +234,11 @@ static KParams make_kparams(const dlb_params* p, const Layout& L) {
     k.seed_y = p->seed_y;
     k.noise_amp = p->noise_amp;
     if (p->precision == DLB_F16S || p->precision == DLB_BF16S || p->precision == DLB_F16SM) rest_shifts(p, k.shift);
-    for (int j = 0; j < 2; ++j)  // wave-row fused tiles, K = 3 and 5 (-1: no valid shift)
-        k.tbw_dy[j] = tbw_row_shift(p->ny, j ? 5 : 3, k.walls != 0, &k.tbw_nby[j]);
+    for (int t = 0; t < 2; ++t)  // wave-row fused tiles of 8 and 12 waves, K = 3 and 5 (-1: no valid shift)
+        for (int j = 0; j < 2; ++j)
+            k.tbw_dy[t][j] = tbw_row_shift(p->ny, j ? 5 : 3, k.walls != 0, &k.tbw_nby[t][j],
+                                           t ? TbWaveT<TBW_TALL_NW>::EY : TbWave::EY);
+    k.tbw_tall = 0;  // chosen in dlb_create
     k.grad_stencil = p->grad_stencil;  // k.phin is set once the state buffer is known
     return k;
 }
@@ -307,11 +312,19 @@ template <class CF, bool NS, bool W> struct OpsImpl {
         using G = TbGeom<T>;
         constexpr int OX = G::EX - 2 * K, OY = G::EY - 2 * K;
         const int nbx = (kp.nx + OX - 1) / OX;
-        const int nby = sizeof(T) == 4 ? kp.tbw_nby[K == 5] : (kp.ny + OY - 1) / OY;
-        if constexpr (sizeof(T) == 4)
+        const int nby = sizeof(T) == 4 ? kp.tbw_nby[0][K == 5] : (kp.ny + OY - 1) / OY;
+        if constexpr (sizeof(T) == 4) {
+            if (kp.tbw_tall) {
+                constexpr int NWT = TBW_TALL_NW, OYT = TbWaveT<NWT>::EY - 2 * K;
+                static_assert(OYT > 0, "tall tile");
+                const int nbt = kp.tbw_nby[1][K == 5];
+                hipLaunchKernelGGL((k_flow_tbw<CF, W, K, NWT>), dim3(nbx * nbt), dim3(64 * NWT), 0, st, kp,
+                                   (const S*)hin, (S*)hout, (const H*)phi, nbx, nbx * nbt);
+                return;
+            }
             hipLaunchKernelGGL((k_flow_tbw<CF, W, K>), dim3(nbx * nby), dim3(G::THREADS), 0, st, kp,
                                (const S*)hin, (S*)hout, (const H*)phi, nbx, nbx * nby);
-        else
+        } else
             hipLaunchKernelGGL((k_flow_tb<CF, W, G::EX, G::EY, K>), dim3(nbx * nby), dim3(G::THREADS), 0, st,
                                kp, (const S*)hin, (S*)hout, (const H*)phi, nbx, nbx * nby);
     }
@@ -543,7 +556,7 @@ int dlb_create(const dlb_params* p, void* dev_state, size_t bytes, void* hip_str
     s->p = *p;
     s->L = L;
     s->kp = make_kparams(p, L);
-    if (s->kp.tbw_dy[0] < 0 || s->kp.tbw_dy[1] < 0) {  // not reached for ny >= 3
+    if (s->kp.tbw_dy[0][0] < 0 || s->kp.tbw_dy[0][1] < 0) {  // not reached for ny >= 3
         delete s;
         return fail(DLB_EUNSUPPORTED, "no row shift of the fused flow tiles fits this grid height");
     }
@@ -563,6 +576,27 @@ int dlb_create(const dlb_params* p, void* dev_state, size_t bytes, void* hip_str
     if (s->fuse != 1 && s->fuse != 3 && s->fuse != 5) {
         delete s;
         return fail(DLB_EINVAL, "flow_fuse must be 0 (default), 1, 3 or 5");
+    }
+    // fused tile height (FP32 flow arithmetic): 48 rows on grids whose tall
+    // tiles fill at least four rounds of the resident slots (two tiles per
+    // compute unit), where the smaller halo pays; 32 rows otherwise, where the
+    // launch's last round would run few tiles
+    const bool tall_ok = !fp64_flow && s->fuse > 1 && s->kp.tbw_dy[1][s->fuse == 5] >= 0;
+    if (p->tile_rows == 48 && !tall_ok) {
+        delete s;
+        return fail(DLB_EUNSUPPORTED, "tile_rows 48 needs FP32 flow arithmetic, fused sub-steps and a row shift "
+                                      "that fits the grid");
+    }
+    if (p->tile_rows == 0 && tall_ok) {
+        int dev = 0, ncu = 256;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
+            ncu = 256;
+        const int OX = TbWave::EX - 2 * s->fuse;
+        const long tiles = (long)((p->nx + OX - 1) / OX) * s->kp.tbw_nby[1][s->fuse == 5];
+        s->kp.tbw_tall = tiles >= 4L * 2 * ncu;
+    } else {
+        s->kp.tbw_tall = p->tile_rows == 48;
     }
     *out = s;
     return DLB_OK;
@@ -1053,7 +1087,7 @@ int dlb_batch_create(const dlb_params* ps, int count, void* dev_state, size_t by
         const int Ks[2] = {3, 5};
         for (int L = 0; L < 2; ++L) {
             int OX = EX - 2 * Ks[L], OY = EY - 2 * Ks[L];
-            int nbx = (ps[i].nx + OX - 1) / OX, nby = f64 ? (ps[i].ny + OY - 1) / OY : m->kp.tbw_nby[L];
+            int nbx = (ps[i].nx + OX - 1) / OX, nby = f64 ? (ps[i].ny + OY - 1) / OY : m->kp.tbw_nby[0][L];
             d.tb0[L] = b->total_tb[L];
             d.tb_nbx[L] = nbx;
             b->total_tb[L] += nbx * nby;

@@ -623,16 +623,21 @@ __device__ __forceinline__ void flow_tb_tile(const KParams& kp, const typename C
 // extended region holds no wall node run the variant without walls
 // (flow_tbw_tile_any).
 // ---------------------------------------------------------------------------
-struct TbWave {
-    static constexpr int NW = 8, R = 4, EX = 64, EY = NW * R;
+template <int NW_> struct TbWaveT {
+    static constexpr int NW = NW_, R = 4, EX = 64, EY = NW_ * R;
 };
+// the tile of 8 waves (64 x 32 nodes), and the tall one of 12 (64 x 48): less
+// halo per stored node, fewer tiles resident per compute unit; the host takes
+// the tall one where a grid has enough tiles to fill several rounds
+using TbWave = TbWaveT<8>;
+constexpr int TBW_TALL_NW = 12;
 
 // Row shift of the wave-row tiling for K fused sub-steps (tile origin
 // y = by OY - K - dy): the smallest tile count among shifts dy in [0, 2R)
 // for which every wall row falling into a tile has its inward row in the
 // same wave.  Returns dy (0 without walls) and sets *nby; -1 if none.
-inline int tbw_row_shift(int ny, int K, bool walls, int* nby) {
-    constexpr int R = TbWave::R, EY = TbWave::EY;
+inline int tbw_row_shift(int ny, int K, bool walls, int* nby, int EY = TbWave::EY) {
+    constexpr int R = TbWave::R;
     const int OY = EY - 2 * K;
     if (!walls) {
         *nby = (ny + OY - 1) / OY;
@@ -679,32 +684,33 @@ __device__ __forceinline__ void wave_lds_sync() {
 // of the wave's last row, k 3-5 the down-movers 4, 7, 8 of its first row)
 // and the wall-column pass [wave][side (west, east)][row][population],
 // rows padded to 12 floats
-struct TbwLds {
-    float xch[2][TbWave::NW][6][64];
-    float xw_in[TbWave::NW][2][TbWave::R][12];
-    float xw_out[TbWave::NW][2][TbWave::R][12];
+template <int NW> struct TbwLds {
+    float xch[2][NW][6][64];
+    float xw_in[NW][2][TbWave::R][12];
+    float xw_out[NW][2][TbWave::R][12];
 };
-__device__ __forceinline__ TbwLds& tbw_lds() {
-    __shared__ TbwLds l;
+template <int NW> __device__ __forceinline__ TbwLds<NW>& tbw_lds() {
+    __shared__ TbwLds<NW> l;
     return l;
 }
 
-template <class CF, bool WALLS, int K>
+template <class CF, bool WALLS, int K, int NW_ = TbWave::NW>
 __device__ __forceinline__ void flow_tbw_tile(const KParams& kp, const typename CF::S* __restrict__ hin,
                                               typename CF::S* __restrict__ hout,
                                               const typename CF::H* __restrict__ phi_t, int bx, int by) {
     using T = typename CF::T;
     using S = typename CF::S;
+    using TW = TbWaveT<NW_>;
     static_assert(sizeof(T) == 4, "wave-row tile is for FP32 arithmetic");
-    constexpr int NW = TbWave::NW, R = TbWave::R, EX = TbWave::EX, EY = TbWave::EY;
+    constexpr int NW = TW::NW, R = TW::R, EX = TW::EX, EY = TW::EY;
     constexpr int OX = EX - 2 * K, OY = EY - 2 * K;
-    TbwLds& lds = tbw_lds();
+    TbwLds<NW>& lds = tbw_lds<NW>();
     auto& xch = lds.xch;
     auto& xw_in = lds.xw_in;
     auto& xw_out = lds.xw_out;
     const size_t P = (size_t)kp.plane;
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int X0 = bx * OX - K, Y0 = by * OY - K - kp.tbw_dy[K == 5];  // tbw_dy = 0 without walls
+    const int X0 = bx * OX - K, Y0 = by * OY - K - kp.tbw_dy[NW != TbWave::NW][K == 5];  // 0 without walls
     int gx = X0 + lane;
     bool xin = true;
     if constexpr (WALLS) {
@@ -887,19 +893,20 @@ __device__ __forceinline__ void flow_tbw_tile(const KParams& kp, const typename 
 // A wave-row tile of a channel grid whose extended region holds no wall
 // node runs the tile code without walls (no bounds or wall tests, fewer
 // registers live): same arithmetic, same results.
-template <class CF, bool WALLS, int K>
+template <class CF, bool WALLS, int K, int NW = TbWave::NW>
 __device__ __forceinline__ void flow_tbw_tile_any(const KParams& kp, const typename CF::S* __restrict__ hin,
                                                   typename CF::S* __restrict__ hout,
                                                   const typename CF::H* __restrict__ phi_t, int bx, int by) {
     if constexpr (WALLS) {
-        constexpr int EX = TbWave::EX, EY = TbWave::EY, OX = EX - 2 * K, OY = EY - 2 * K;
-        const int X0 = bx * OX - K, Y0 = by * OY - K - kp.tbw_dy[K == 5];
+        using TW = TbWaveT<NW>;
+        constexpr int EX = TW::EX, EY = TW::EY, OX = EX - 2 * K, OY = EY - 2 * K;
+        const int X0 = bx * OX - K, Y0 = by * OY - K - kp.tbw_dy[NW != TbWave::NW][K == 5];
         if (X0 >= 1 && X0 + EX - 1 <= kp.nx - 2 && Y0 >= 1 && Y0 + EY - 1 <= kp.ny - 2) {
-            flow_tbw_tile<CF, false, K>(kp, hin, hout, phi_t, bx, by);
+            flow_tbw_tile<CF, false, K, NW>(kp, hin, hout, phi_t, bx, by);
             return;
         }
     }
-    flow_tbw_tile<CF, WALLS, K>(kp, hin, hout, phi_t, bx, by);
+    flow_tbw_tile<CF, WALLS, K, NW>(kp, hin, hout, phi_t, bx, by);
 }
 
 // Tile geometry of the fused flow launch per arithmetic type: the wave-row
@@ -955,15 +962,14 @@ __device__ __forceinline__ void tbw_tile_of(int b, int nbx, int nby, int& bx, in
     }
 }
 
-template <class CF, bool WALLS, int K>
-__global__ __launch_bounds__(64 * TbWave::NW) void k_flow_tbw(const KParams kp,
-                                                               const typename CF::S* __restrict__ hin,
-                                                               typename CF::S* __restrict__ hout,
-                                                               const typename CF::H* __restrict__ phi_t,
-                                                               int nbx, int nblocks) {
+template <class CF, bool WALLS, int K, int NW = TbWave::NW>
+__global__ __launch_bounds__(64 * NW) void k_flow_tbw(const KParams kp, const typename CF::S* __restrict__ hin,
+                                                      typename CF::S* __restrict__ hout,
+                                                      const typename CF::H* __restrict__ phi_t, int nbx,
+                                                      int nblocks) {
     int bx, by;
     tbw_tile_of<WALLS>(blockIdx.x, nbx, nblocks / nbx, bx, by);
-    flow_tbw_tile_any<CF, WALLS, K>(kp, hin, hout, phi_t, bx, by);
+    flow_tbw_tile_any<CF, WALLS, K, NW>(kp, hin, hout, phi_t, bx, by);
 }
 
 template <class CF, bool WALLS, int EX, int EY, int K>

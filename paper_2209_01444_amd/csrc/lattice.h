@@ -34,7 +34,9 @@ struct KParams {
     double nsub_d, uin_x_sub, uin_y_sub, grad_tol2;
     double seed_R, seed_x, seed_y, noise_amp, orient;
     float shift[24];        // storage shifts (rest-state populations) for 16-bit storage
-    int tbw_dy[2], tbw_nby[2];  // row shift and tile rows of the wave-row fused tiles, K = 3 / 5
+    // row shift and tile rows of the wave-row fused tiles [8 / 12 waves][K = 3 / 5];
+    // tbw_tall: the single-solver launch takes the 12-wave tile
+    int tbw_dy[2][2], tbw_nby[2][2], tbw_tall;
     int grad_stencil;           // 1: grad phi from the nine-point stencil of the plane phin
     const void* phin;           // phi at time t per node (history type), grad_stencil only
     int n_sub_t;                // heat sub-steps per main step (1: within k_pct)

@@ -31,7 +31,8 @@ class DlbError(RuntimeError):
 class DlbParams(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
         "nx", "ny", "use_ns", "bc", "n_sub", "h_quintic", "c_init_U", "precision", "grad_iters",
-        "flow_fuse", "phi_static", "isothermal", "grad_stencil", "n_sub_t")] + [(n, ctypes.c_double) for n in (
+        "flow_fuse", "phi_static", "isothermal", "grad_stencil", "n_sub_t", "tile_rows")] + [
+        (n, ctypes.c_double) for n in (
             "W0", "tau0", "eps4", "orient", "lambda_", "Mcinf", "k", "D", "alpha", "nu", "rho0",
             "u_in_x", "u_in_y", "theta0", "U0", "C0", "seed_R", "seed_x", "seed_y", "noise_amp",
             "grad_tol", "force_x", "force_y", "varphi")]
@@ -114,7 +115,7 @@ def _check(lib, rc: int):
 
 DEFAULTS = dict(
     nx=64, ny=64, use_ns=0, walls=0, n_sub=1, h_quintic=0, c_init_U=0, precision="f64",
-    grad_iters=0, flow_fuse=0, phi_static=0, grad_stencil=0, n_sub_t=1, W0=1.0, tau0=20.0, eps4=0.05, orient=0.0, lambda_=0.0, Mcinf=0.0, k=0.15, D=0.1,
+    grad_iters=0, flow_fuse=0, phi_static=0, grad_stencil=0, n_sub_t=1, tile_rows=0, W0=1.0, tau0=20.0, eps4=0.05, orient=0.0, lambda_=0.0, Mcinf=0.0, k=0.15, D=0.1,
     alpha=0.1, nu=0.1, rho0=1.0, u_in=(0.0, 0.0), theta0=0.0, U0=0.0, C0=1.0, seed_R=8.0,
     seed_x=None, seed_y=None, noise_amp=0.0, grad_tol=0.0, use_c=1, use_t=1,
     force_x=0.0, force_y=0.0, varphi=0.0,
@@ -147,6 +148,7 @@ def make_params(cfg: dict) -> DlbParams:
     p.isothermal = 0 if c["use_t"] else 1
     p.grad_stencil = int(c["grad_stencil"])
     p.n_sub_t = int(c["n_sub_t"])
+    p.tile_rows = int(c["tile_rows"])
     for name in ("W0", "tau0", "eps4", "orient", "lambda_", "Mcinf", "k", "D", "alpha", "nu", "rho0",
                  "theta0", "U0", "C0", "seed_R", "noise_amp", "grad_tol", "force_x", "force_y", "varphi"):
         setattr(p, name, float(c[name]))

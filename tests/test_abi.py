@@ -147,3 +147,32 @@ def test_3d_16bit_storage_sizes():
     assert size["f32"] - size["f16s"] >= 2 * 21 * 28 * lp * 2
     q = dlb3.make_params(dict(nx=32, ny=30, nz=28, precision=4))
     assert lib.dlb3_state_bytes(ctypes.byref(q)) == 0
+
+
+def test_params_struct_layout_matches_the_header(tmp_path):
+    """dlb_params as the C compiler lays it out from include/dlb.h (size and
+    every field's offset) against the ctypes mirror in the binding."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    fields = [f[0] for f in dlb.DlbParams._fields_]
+    cname = {"lambda_": "lambda"}
+    body = "\n".join(f'    printf("%s %zu\\n", "{f}", offsetof(dlb_params, {cname.get(f, f)}));' for f in fields)
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include <stdint.h>\n#include \"dlb.h\"\n"
+                   "int main(void) {\n" + body + '\n    printf("sizeof %zu\\n", sizeof(dlb_params));\n'
+                   "    return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    out = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                       text=True).stdout.splitlines())
+    assert int(out.pop("sizeof")) == ctypes.sizeof(dlb.DlbParams)
+    for f in fields:
+        assert int(out[f]) == getattr(dlb.DlbParams, f).offset, f
+
+
+def test_tile_rows_is_validated():
+    cfg, _ = W.thermosolutal_flow(64, 64, seed=2, precision="f32")
+    p = dlb.make_params(dict(cfg, tile_rows=40))
+    assert dlb.load_library().dlb_state_bytes(ctypes.byref(p)) == 0  # invalid parameters

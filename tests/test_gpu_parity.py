@@ -740,6 +740,25 @@ def test_batch_members_match_single_runs(dlb, precision, fuse):
         assert m.step_count == 23
 
 
+@pytest.mark.parametrize("walls,precision,fuse,shape", [(1, "f32", 5, (333, 271)), (0, "f32", 5, (200, 150)),
+                                                      (1, "f16sm", 5, (150, 203)), (1, "f32", 3, (97, 300))])
+def test_tall_fused_tiles_store_the_same_values(dlb, walls, precision, fuse, shape):
+    """The fused flow launch with 48-row tiles (12 waves) against 32-row
+    tiles (8 waves) on ragged channel and periodic grids: the stored fields
+    are bit for bit the same (each stored node's arithmetic does not depend
+    on the tiling).  A 48-row request with FP64 flow arithmetic is refused."""
+    nx, ny = shape
+    _say(f"case: tall fused tiles {nx}x{ny} walls={walls} {precision} fuse={fuse}")
+    cfg, noise = W.thermosolutal_flow(nx, ny, seed=2, precision=precision)
+    cfg.update(walls=walls, flow_fuse=fuse)
+    a = dlb.Solver(dict(cfg, tile_rows=32)).init_seed(noise).step(30).fields()
+    b = dlb.Solver(dict(cfg, tile_rows=48)).init_seed(noise).step(30).fields()
+    for k in FIELDS:
+        assert np.array_equal(a[k], b[k]), k
+    with pytest.raises(dlb.DlbError):
+        dlb.Solver(dict(cfg, precision="f64", tile_rows=48))
+
+
 @pytest.mark.parametrize("width", [32, 128, 256])
 def test_batch_node_tile_shapes_give_the_same_members(dlb, width):
     """The node tile of the batched node kernels (width x 256/width nodes)
