@@ -154,9 +154,10 @@ def run_hybrid(cfg, noise, T: int, t_start: int, K: int, L: int, net=None, tol: 
     s.step(L)
     t = t_start
     accepted, fallbacks, errs, vj, vexp = 0, 0, [], [], []
+    s_now = None  # tips of the current state when already measured
     while t + K + L + 100 <= T:
         backup.copy_from(s)
-        s0 = tips(s)
+        s0 = tips(s) if s_now is None else s_now
         if jump == "lb":
             s.step(K)
         x = s.fields_device(FIELDS5)
@@ -178,9 +179,11 @@ def run_hybrid(cfg, noise, T: int, t_start: int, K: int, L: int, net=None, tol: 
             s.step(K)
             prev = (t + K, tips(s))
             s.step(L)
+            s_now = None
             fallbacks += 1
         else:
             prev = (t + K, s1)
+            s_now = s2  # the state after the L steps is the next cycle's start
             accepted += 1
         t += K + L
     s.step(T - 100 - t)
