@@ -35,8 +35,8 @@ from paper_2209_01444_amd import sur as sur_mod
 
 FIELDS5 = ("phi", "C", "theta", "ux", "uy")
 
-# A network trained by this module's command line at 512^2 (K = 100, 32
-# training seeds, 64000 Adam steps; see save_bundle for the format)
+# A network trained by this module's command line at 512^2 (K = 100, 48
+# training seeds, 100000 Adam steps; see save_bundle for the format)
 BUNDLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "unet32_512_k100.npz")
 
 

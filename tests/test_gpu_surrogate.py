@@ -277,13 +277,13 @@ def test_trained_network_gains_over_the_method_without_it(sur):
 
 def test_stored_network_speeds_up_the_hybrid_loop(sur):
     """The time-to-solution gain at 512^2 with the network stored in the
-    package (trained by the surrogate command line: 32 seeds, 64000 Adam
+    package (trained by the surrogate command line: 48 seeds, 100000 Adam
     steps), on the seed held out of its training: the hybrid loop (K = 100,
     L = 100, the 2% tip-velocity check with fallback) against plain lattice
     Boltzmann to main step 10000.  Bars from the measured values with
-    margin (1.57-1.59x, 45 of 47 jumps, 0.68%): at least 1.3x faster, at
-    least 40 of the 47 jumps accepted, the final tip velocity of every arm
-    within 2% of plain lattice Boltzmann."""
+    margin (1.65x, 46 of 47 jumps, 1.30%): at least 1.3x faster, at least
+    40 of the 47 jumps accepted, the final tip velocity of every arm within
+    2% of plain lattice Boltzmann."""
     import os
 
     from paper_2209_01444_amd import surrogate as S
