@@ -9,6 +9,14 @@ excess partition then falls like the square of the interface Peclet number
 Pe = V W0 / D; without the current, or with a wrong sign or scale, it is of
 first order (solute is trapped or over-rejected).
 
+The factor 1 + (1 - k) U of the current is c / c_l^0 at the interface
+(U's definition, Sec. 2): written for the concentration c, the solute
+equation with the current is linear and homogeneous in c for a given phase
+field history, so a melt without solute keeps none however the front
+moves.  A current whose size does not vanish with c (the factor dropped, or
+1 + U in its place) drives solute out of nothing, to negative
+concentrations.
+
 Torque and force (Sec. 3.4, Eq. HDforce): the force and torque on the solid
 are minus the momentum and the angular momentum (about the centroid of the
 solid) that the diffuse fluid-solid force gives the fluid in one collision
@@ -86,6 +94,47 @@ def test_planar_alloy_front_does_not_trap_solute(dim):
     slope = np.polyfit(np.log(pe), np.log(np.abs(excess)), 1)[0]
     print("exponent", slope)
     assert 1.7 <= slope <= 2.5
+
+
+def _solute_free_front(dim, W0, theta0=-0.1, travel_W0=15.0):
+    """Largest |C| left in a melt that holds no solute (C = 0) after a planar
+    front, driven by a uniform undercooling theta0 alone (Mc_inf = 0, so the
+    phase field does not see C), has swept travel_W0 interface widths of it;
+    lattice units scale with W0 (tau0 = W0^2 / 0.05, D = 0.05 W0)."""
+    tau0 = W0 * W0 / 0.05
+    nx, ny = int(64 * W0), 4
+    x0 = 8 * W0
+    prof = np.tanh((x0 - np.arange(nx)) / (np.sqrt(2.0) * W0))
+    cfg = dict(nx=nx, ny=ny, use_t=0, walls=1, W0=W0, tau0=tau0, eps4=0.0, lambda_=3.191,
+               Mcinf=0.0, k=0.15, D=0.05 * W0, theta0=theta0)
+    if dim == 2:
+        o = O.Oracle(dict(cfg, use_c=1, use_ns=0)).set_fields(np.repeat(prof[None, :], ny, 0),
+                                                             np.zeros((ny, nx)))
+        line = lambda a: a[ny // 2]  # noqa: E731
+    else:
+        o = O3.Oracle3(dict(cfg, nz=ny)).set_fields(
+            np.ascontiguousarray(np.broadcast_to(prof, (ny, ny, nx))), np.zeros((ny, ny, nx)))
+        line = lambda a: a[ny // 2, ny // 2]  # noqa: E731
+    s = x0
+    while s < x0 + travel_W0 * W0:
+        o.step(int(tau0))
+        p = line(o.fields()["phi"])
+        j = np.where((p[:-1] > 0) & (p[1:] <= 0))[0][-1]
+        s = j + p[j] / (p[j] - p[j + 1])
+        assert s + 8 * W0 < nx, "front ran to the end of the strip"
+    return np.abs(o.fields()["C"]).max()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_solute_free_melt_stays_free_under_a_moving_front(dim):
+    """C = 0 is a solution of the solute equation with the anti-trapping
+    current for any front motion; the lattice keeps it up to a
+    discretisation error that falls faster than dx/W0 (C in units of c_l^0,
+    the equilibrium liquid concentration)."""
+    coarse, fine = (_solute_free_front(dim, W0) for W0 in (2.0, 4.0))
+    print(f"max |C|: {coarse:.3e} at W0 = 2 lu, {fine:.3e} at W0 = 4 lu")
+    assert coarse < 1e-2 and fine < 2.5e-3
+    assert coarse / fine > 3.0
 
 
 def _body_and_flow(nx=44, ny=38):

@@ -101,6 +101,10 @@ MUTATIONS = [
      TC + "test_planar_alloy_front_does_not_trap_solute[2]"),
     ("anti-trapping with W0^2", JAT, JAT.replace("p->W0 *", "p->W0 * p->W0 *"),
      TC + "test_planar_alloy_front_does_not_trap_solute[2]"),
+    ("anti-trapping without its 1 + (1-k)U factor", JAT, JAT.replace("(1.0 + (1.0 - p->k) * U) * ", ""),
+     TC + "test_solute_free_melt_stays_free_under_a_moving_front[2]"),
+    ("anti-trapping factor 1 + U", JAT, JAT.replace("(1.0 + (1.0 - p->k) * U)", "(1.0 + U)"),
+     TC + "test_solute_free_melt_stays_free_under_a_moving_front[2]"),
     ("sign of the torque", "T -= rx * Fb[1] - ry * Fb[0];", "T += rx * Fb[1] - ry * Fb[0];",
      TC + "test_force_and_torque_balance_the_fluid_momentum"),
     ("torque about the origin", "double rx = (x % s->nx) - cx, ry = (x / s->nx) - cy;",
@@ -137,6 +141,10 @@ MUTATIONS_3D = [
      TC + "test_planar_alloy_front_does_not_trap_solute[3]"),
     ("3-D: anti-trapping with W0^2", JAT3, JAT3.replace("p->W0 *", "p->W0 * p->W0 *"),
      TC + "test_planar_alloy_front_does_not_trap_solute[3]"),
+    ("3-D: anti-trapping without its 1 + (1-k)U factor", JAT3, JAT3.replace("(1.0 + (1.0 - p->k) * U) * ", ""),
+     TC + "test_solute_free_melt_stays_free_under_a_moving_front[3]"),
+    ("3-D: anti-trapping factor 1 + U", JAT3, JAT3.replace("(1.0 + (1.0 - p->k) * U)", "(1.0 + U)"),
+     TC + "test_solute_free_melt_stays_free_under_a_moving_front[3]"),
 ]
 
 
