@@ -1262,10 +1262,12 @@ int dlb_batch_autotune(dlb_batch_handle b, int trial_steps, double* ms_best) {
         if (rc) return rc;
         if (ms < best) best = ms, bn = n;
     }
-    // node tile shape: 64 x 4 (timed above), 128 x 2, 256 x 1, 32 x 8
-    int blg = b->node_tw_log2;
-    for (int lg : {7, 8, 5}) {
-        if (lg == blg) continue;
+    // node tile shape among 64 x 4, 128 x 2, 256 x 1 and 32 x 8; the one the
+    // batch holds now was timed above
+    const int cur = b->node_tw_log2;
+    int blg = cur;
+    for (int lg : {6, 7, 8, 5}) {
+        if (lg == cur) continue;
         batch_node_tiles(b, lg);
         rc = upload_desc(b);
         if (rc) return rc;
