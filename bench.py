@@ -159,7 +159,9 @@ def kernel_rooflines(cfg: dict, m: dict, wl: str | None = None) -> dict:
         # counter records (profiles/) taken on the current kernel sources, else null
         pct["traffic"] = traffic_from_profiles("k_pct", wl)
         pct["traffic_GBs"] = None if pct["traffic"] is None else round(pct["traffic"] / (pct_ms * 1e-3) / 1e9, 1)
-        kf = "k_flow_tbw" if subs > 1 and cfg["precision"] not in ("f64", "f32m") else None
+        # counter records exist for the wave-row fused kernel and the one-sub-step kernel
+        kf = ("k_flow" if subs == 1 else
+              "k_flow_tbw" if cfg["precision"] not in ("f64", "f32m") else None)
         flow["traffic"] = traffic_from_profiles(kf, wl) if kf else None
         valu = valu_from_profiles(kf, wl) if kf else None
         flow["valu_issue_frac"] = None if valu is None else round(valu / (flow_ms * 1e-3) / PEAK_VALU_INSTS_PER_S, 4)
