@@ -2,9 +2,10 @@
 //
 // A batch holds independent seeds (grids of any size, their own physical
 // parameters) that step in lockstep.  Each kernel class runs as one
-// persistent launch: workgroup b walks the contiguous slice
-// [b*chunk, (b+1)*chunk) of a global list of (seed, tile) work items, so a
-// workgroup sweeps neighbouring tiles of one seed in turn.  Per node the
+// persistent launch over a global list of (seed, tile) work items, seed by
+// seed and row by row: the list is cut into one band per XCD and the
+// workgroups of an XCD take the items of their band in turn (batch_span), so
+// neighbouring tiles of a seed run together under one L2.  Per node the
 // arithmetic is the single-solver kernels' (same device functions), so every
 // member evolves bit for bit as it would alone.
 #pragma once
@@ -44,15 +45,31 @@ __device__ __forceinline__ void batch_node(const SeedDesc& sd, int t, int tw_log
     y = (t / sd.node_nbx) * (BLOCK >> tw_log2) + (threadIdx.x >> tw_log2);
 }
 
+// Items of a persistent batch launch taken by this block: the work list is
+// cut into 8 contiguous bands, one per XCD (block b runs on XCD b mod 8),
+// and the blocks of one XCD interleave over their band, so that tiles
+// sharing halo rows or streaming targets (the next tile row of the same
+// seed) run at the same time under one L2.  A grid that is not a multiple
+// of 8 blocks interleaves over the whole list.  Items rise within a block.
+struct BatchSpan {
+    int beg, end, stride;
+};
+__device__ __forceinline__ BatchSpan batch_span(int total) {
+    if (gridDim.x % 8 == 0) {
+        const int band = (total + 7) / 8, x = (int)(blockIdx.x % 8);
+        return {x * band + (int)(blockIdx.x / 8), min((x + 1) * band, total), (int)(gridDim.x / 8)};
+    }
+    return {(int)blockIdx.x, total, (int)gridDim.x};
+}
+
 template <class CF, bool NS, bool WALLS>
 __global__ __launch_bounds__(BLOCK) void k_pct_batch(const SeedDesc* __restrict__ d, int count,
                                                      int total, int cur, int fcur, int tw_log2) {
     using S = typename CF::S;
     using H = typename CF::H;
-    const int chunk = (total + gridDim.x - 1) / gridDim.x;
-    const int beg = blockIdx.x * chunk, end = min(beg + chunk, total);
-    int s = beg < end ? seed_of(d, count, beg, -1) : 0;
-    for (int item = beg; item < end; ++item) {
+    const BatchSpan w = batch_span(total);
+    int s = w.beg < w.end ? seed_of(d, count, w.beg, -1) : 0;
+    for (int item = w.beg; item < w.end; item += w.stride) {
         while (s + 1 < count && d[s + 1].tile0 <= item) ++s;
         const SeedDesc& sd = d[s];
         int x, y;
@@ -68,10 +85,9 @@ __global__ __launch_bounds__(BLOCK) void k_flow_batch(const SeedDesc* __restrict
                                                       int total, int fcur, int tw_log2) {
     using S = typename CF::S;
     using H = typename CF::H;
-    const int chunk = (total + gridDim.x - 1) / gridDim.x;
-    const int beg = blockIdx.x * chunk, end = min(beg + chunk, total);
-    int s = beg < end ? seed_of(d, count, beg, -1) : 0;
-    for (int item = beg; item < end; ++item) {
+    const BatchSpan w = batch_span(total);
+    int s = w.beg < w.end ? seed_of(d, count, w.beg, -1) : 0;
+    for (int item = w.beg; item < w.end; item += w.stride) {
         while (s + 1 < count && d[s + 1].tile0 <= item) ++s;
         const SeedDesc& sd = d[s];
         int x, y;
@@ -87,11 +103,10 @@ __global__ __launch_bounds__(TbGeom<typename CF::T>::THREADS) void k_flow_tb_bat
                                                                                   int count, int total, int fcur) {
     using S = typename CF::S;
     using H = typename CF::H;
-    const int chunk = (total + gridDim.x - 1) / gridDim.x;
-    const int beg = blockIdx.x * chunk, end = min(beg + chunk, total);
     constexpr int L = K == 5 ? 1 : 0;
-    int s = beg < end ? seed_of(d, count, beg, L) : 0;
-    for (int item = beg; item < end; ++item) {
+    const BatchSpan w = batch_span(total);
+    int s = w.beg < w.end ? seed_of(d, count, w.beg, L) : 0;
+    for (int item = w.beg; item < w.end; item += w.stride) {
         while (s + 1 < count && d[s + 1].tb0[L] <= item) ++s;
         const SeedDesc& sd = d[s];
         const int t = item - sd.tb0[L];
