@@ -1242,7 +1242,7 @@ int dlb_batch_autotune(dlb_batch_handle b, int trial_steps, double* ms_best) {
     if (!b || trial_steps < 1) return fail(DLB_EINVAL, "null batch or trial_steps < 1");
     int rc = upload_desc(b);
     if (rc) return rc;
-    const int fuses[3] = {5, 3, 1}, bns[4] = {4, 8, 16, 32}, bts[4] = {1, 2, 3, 4};
+    const int fuses[3] = {5, 3, 1}, bns[5] = {4, 8, 16, 32, 64}, bts[4] = {1, 2, 3, 4};
     float best = 1e30f;
     int bf = b->fuse, bn = b->bpc_node, bt = b->bpc_tb;
     // coordinate search: fused-launch shape first, then the node-kernel grid
