@@ -293,8 +293,9 @@ dlb_handle dlb_batch_member(dlb_batch_handle b, int i);
 int dlb_batch_step(dlb_batch_handle b, int64_t n);
 int64_t dlb_batch_step_count(dlb_batch_handle b);
 /* Launch configuration: flow sub-steps fused per launch (1, 3, 5) and the
- * persistent grid as workgroups per compute unit for the node kernels
- * (1..64) and the fused flow kernel (1..16). */
+ * grid as workgroups per compute unit for the node kernels (1..4096; a grid
+ * with at least one workgroup per node tile runs one tile per workgroup) and
+ * the fused flow kernel (1..16).  DLB_EINVAL outside these ranges. */
 int dlb_batch_set_config(dlb_batch_handle b, int fuse, int bpc_node, int bpc_tb);
 int dlb_batch_get_config(dlb_batch_handle b, int* out3);
 /* Node tile of the batched phi/C/theta and one-sub-step flow launches:

@@ -14,11 +14,16 @@
 
 namespace dlb {
 
+// A member's arrays are byte offsets into the batch's state buffer, whose
+// base the kernels take as an argument: pointers derived from a kernel
+// argument are known to address global memory, so the compiler emits global
+// loads and stores, where pointers read from memory would give generic
+// (flat) ones.
 struct SeedDesc {
     KParams kp;
-    void* pop[2];
-    void* flow[2];
-    void* hist;
+    size_t pop[2];
+    size_t flow[2];
+    size_t hist;
     int hist_valid;
     int tile0;      // first node tile of this seed in the node-kernel work list
     int node_nbx;   // node tiles per row (tile width x 256/width nodes, set per batch)
@@ -63,8 +68,8 @@ __device__ __forceinline__ BatchSpan batch_span(int total) {
 }
 
 template <class CF, bool NS, bool WALLS>
-__global__ __launch_bounds__(BLOCK) void k_pct_batch(const SeedDesc* __restrict__ d, int count,
-                                                     int total, int cur, int fcur, int tw_log2) {
+__global__ __launch_bounds__(BLOCK) void k_pct_batch(char* __restrict__ base, const SeedDesc* __restrict__ d,
+                                                     int count, int total, int cur, int fcur, int tw_log2) {
     using S = typename CF::S;
     using H = typename CF::H;
     const BatchSpan w = batch_span(total);
@@ -75,14 +80,14 @@ __global__ __launch_bounds__(BLOCK) void k_pct_batch(const SeedDesc* __restrict_
         int x, y;
         batch_node(sd, item - sd.tile0, tw_log2, x, y);
         if (x < sd.kp.nx && y < sd.kp.ny)
-            pct_node<CF, NS, WALLS>(sd.kp, (const S*)sd.pop[cur], (S*)sd.pop[1 - cur],
-                                    (const S*)sd.flow[fcur], (H*)sd.hist, sd.hist_valid, x, y);
+            pct_node<CF, NS, WALLS>(sd.kp, (const S*)(base + sd.pop[cur]), (S*)(base + sd.pop[1 - cur]),
+                                    (const S*)(base + sd.flow[fcur]), (H*)(base + sd.hist), sd.hist_valid, x, y);
     }
 }
 
 template <class CF, bool WALLS>
-__global__ __launch_bounds__(BLOCK) void k_flow_batch(const SeedDesc* __restrict__ d, int count,
-                                                      int total, int fcur, int tw_log2) {
+__global__ __launch_bounds__(BLOCK) void k_flow_batch(char* __restrict__ base, const SeedDesc* __restrict__ d,
+                                                      int count, int total, int fcur, int tw_log2) {
     using S = typename CF::S;
     using H = typename CF::H;
     const BatchSpan w = batch_span(total);
@@ -93,13 +98,14 @@ __global__ __launch_bounds__(BLOCK) void k_flow_batch(const SeedDesc* __restrict
         int x, y;
         batch_node(sd, item - sd.tile0, tw_log2, x, y);
         if (x < sd.kp.nx && y < sd.kp.ny)
-            flow_step_node<CF, WALLS>(sd.kp, (const S*)sd.flow[fcur], (S*)sd.flow[1 - fcur],
-                                      (const H*)sd.hist, x, y);
+            flow_step_node<CF, WALLS>(sd.kp, (const S*)(base + sd.flow[fcur]), (S*)(base + sd.flow[1 - fcur]),
+                                      (const H*)(base + sd.hist), x, y);
     }
 }
 
 template <class CF, bool WALLS, int K>
-__global__ __launch_bounds__(TbGeom<typename CF::T>::THREADS) void k_flow_tb_batch(const SeedDesc* __restrict__ d,
+__global__ __launch_bounds__(TbGeom<typename CF::T>::THREADS) void k_flow_tb_batch(char* __restrict__ base,
+                                                                                  const SeedDesc* __restrict__ d,
                                                                                   int count, int total, int fcur) {
     using S = typename CF::S;
     using H = typename CF::H;
@@ -110,8 +116,8 @@ __global__ __launch_bounds__(TbGeom<typename CF::T>::THREADS) void k_flow_tb_bat
         while (s + 1 < count && d[s + 1].tb0[L] <= item) ++s;
         const SeedDesc& sd = d[s];
         const int t = item - sd.tb0[L];
-        flow_fused_tile<CF, WALLS, K>(sd.kp, (const S*)sd.flow[fcur], (S*)sd.flow[1 - fcur],
-                                      (const H*)sd.hist, t % sd.tb_nbx[L], t / sd.tb_nbx[L]);
+        flow_fused_tile<CF, WALLS, K>(sd.kp, (const S*)(base + sd.flow[fcur]), (S*)(base + sd.flow[1 - fcur]),
+                                      (const H*)(base + sd.hist), t % sd.tb_nbx[L], t / sd.tb_nbx[L]);
         __syncthreads();  // LDS of this tile is reused by the next
     }
 }

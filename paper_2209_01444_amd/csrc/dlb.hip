@@ -262,9 +262,9 @@ struct Ops {
 };
 
 struct BatchOps {
-    void (*pct)(const SeedDesc*, int, int, int, int, int, int, hipStream_t);
-    void (*flow)(const SeedDesc*, int, int, int, int, int, hipStream_t);
-    void (*flow_tb)(int, const SeedDesc*, int, int, int, int, hipStream_t);
+    void (*pct)(char*, const SeedDesc*, int, int, int, int, int, int, hipStream_t);
+    void (*flow)(char*, const SeedDesc*, int, int, int, int, int, hipStream_t);
+    void (*flow_tb)(int, char*, const SeedDesc*, int, int, int, int, hipStream_t);
 };
 
 template <class CF, bool NS, bool W> struct OpsImpl {
@@ -364,25 +364,25 @@ template <class CF, bool NS, bool W> struct OpsImpl {
     }
 
     // batched persistent launches
-    static void b_pct(const SeedDesc* d, int count, int total, int cur, int fcur, int tw_log2, int blocks,
-                      hipStream_t st) {
-        hipLaunchKernelGGL((k_pct_batch<CP, NS, W>), dim3(blocks), dim3(BLOCK), 0, st, d, count, total,
+    static void b_pct(char* base, const SeedDesc* d, int count, int total, int cur, int fcur, int tw_log2,
+                      int blocks, hipStream_t st) {
+        hipLaunchKernelGGL((k_pct_batch<CP, NS, W>), dim3(blocks), dim3(BLOCK), 0, st, base, d, count, total,
                            cur, fcur, tw_log2);
     }
-    static void b_flow(const SeedDesc* d, int count, int total, int fcur, int tw_log2, int blocks,
+    static void b_flow(char* base, const SeedDesc* d, int count, int total, int fcur, int tw_log2, int blocks,
                        hipStream_t st) {
-        hipLaunchKernelGGL((k_flow_batch<CF, W>), dim3(blocks), dim3(BLOCK), 0, st, d, count, total, fcur,
-                           tw_log2);
+        hipLaunchKernelGGL((k_flow_batch<CF, W>), dim3(blocks), dim3(BLOCK), 0, st, base, d, count, total,
+                           fcur, tw_log2);
     }
-    static void b_flow_tb(int K, const SeedDesc* d, int count, int total, int fcur, int blocks,
+    static void b_flow_tb(int K, char* base, const SeedDesc* d, int count, int total, int fcur, int blocks,
                           hipStream_t st) {
         constexpr int TH = TbGeom<typename CF::T>::THREADS;
         if (K == 3)
-            hipLaunchKernelGGL((k_flow_tb_batch<CF, W, 3>), dim3(blocks), dim3(TH), 0, st, d, count, total,
-                               fcur);
+            hipLaunchKernelGGL((k_flow_tb_batch<CF, W, 3>), dim3(blocks), dim3(TH), 0, st, base, d, count,
+                               total, fcur);
         else
-            hipLaunchKernelGGL((k_flow_tb_batch<CF, W, 5>), dim3(blocks), dim3(TH), 0, st, d, count, total,
-                               fcur);
+            hipLaunchKernelGGL((k_flow_tb_batch<CF, W, 5>), dim3(blocks), dim3(TH), 0, st, base, d, count,
+                               total, fcur);
     }
     static BatchOps bops() { return BatchOps{b_pct, b_flow, b_flow_tb}; }
 };
@@ -940,6 +940,7 @@ struct dlb_batch {
     std::vector<dlb_solver*> members;
     std::vector<SeedDesc> desc;
     SeedDesc* d_desc = nullptr;
+    char* base = nullptr;  // the caller's state buffer: member arrays are offsets into it
     int total_tiles = 0, total_tb[2] = {0, 0};
     hipStream_t stream = nullptr;
     int pop_cur = 0, flow_cur = 0;
@@ -1008,19 +1009,21 @@ static void batch_node_tiles(dlb_batch* b, int tw_log2) {
 
 static void batch_enqueue_step(dlb_batch* b, int fuse, int bpc_node, int bpc_tb) {
     const int bn = std::min(b->total_tiles, b->num_cu * bpc_node);
-    b->ops.pct(b->d_desc, b->count, b->total_tiles, b->pop_cur, b->flow_cur, b->node_tw_log2, bn, b->stream);
+    b->ops.pct(b->base, b->d_desc, b->count, b->total_tiles, b->pop_cur, b->flow_cur, b->node_tw_log2, bn,
+               b->stream);
     b->pop_cur ^= 1;
     if (b->p0.use_ns) {
         int left = b->p0.n_sub;
         while (fuse > 1 && left >= fuse) {
             int L = fuse == 5 ? 1 : 0;
             int bt = std::min(b->total_tb[L], b->num_cu * bpc_tb);
-            b->ops.flow_tb(fuse, b->d_desc, b->count, b->total_tb[L], b->flow_cur, bt, b->stream);
+            b->ops.flow_tb(fuse, b->base, b->d_desc, b->count, b->total_tb[L], b->flow_cur, bt, b->stream);
             b->flow_cur ^= 1;
             left -= fuse;
         }
         for (; left > 0; --left) {
-            b->ops.flow(b->d_desc, b->count, b->total_tiles, b->flow_cur, b->node_tw_log2, bn, b->stream);
+            b->ops.flow(b->base, b->d_desc, b->count, b->total_tiles, b->flow_cur, b->node_tw_log2, bn,
+                        b->stream);
             b->flow_cur ^= 1;
         }
     }
@@ -1059,6 +1062,7 @@ int dlb_batch_create(const dlb_params* ps, int count, void* dev_state, size_t by
     b->count = count;
     b->p0 = ps[0];
     b->stream = (hipStream_t)hip_stream;
+    b->base = (char*)dev_state;
     b->ops = select_bops(&ps[0]);
     int dev = 0, ncu = 256;
     if (hipGetDevice(&dev) == hipSuccess &&
@@ -1079,11 +1083,11 @@ int dlb_batch_create(const dlb_params* ps, int count, void* dev_state, size_t by
         b->members.push_back(m);
         SeedDesc d{};
         d.kp = m->kp;
-        d.pop[0] = m->pop(0);
-        d.pop[1] = m->pop(1);
-        d.flow[0] = m->flow(0);
-        d.flow[1] = m->flow(1);
-        d.hist = m->hist();
+        d.pop[0] = (size_t)((char*)m->pop(0) - b->base);
+        d.pop[1] = (size_t)((char*)m->pop(1) - b->base);
+        d.flow[0] = (size_t)((char*)m->flow(0) - b->base);
+        d.flow[1] = (size_t)((char*)m->flow(1) - b->base);
+        d.hist = (size_t)((char*)m->hist() - b->base);
         const int Ks[2] = {3, 5};
         for (int L = 0; L < 2; ++L) {
             int OX = EX - 2 * Ks[L], OY = EY - 2 * Ks[L];
@@ -1123,7 +1127,7 @@ dlb_handle dlb_batch_member(dlb_batch_handle b, int i) {
 
 int dlb_batch_set_config(dlb_batch_handle b, int fuse, int bpc_node, int bpc_tb) {
     if (!b) return fail(DLB_EINVAL, "null batch");
-    if ((fuse != 1 && fuse != 3 && fuse != 5) || bpc_node < 1 || bpc_node > 64 || bpc_tb < 1 || bpc_tb > 16)
+    if ((fuse != 1 && fuse != 3 && fuse != 5) || bpc_node < 1 || bpc_node > 4096 || bpc_tb < 1 || bpc_tb > 16)
         return fail(DLB_EINVAL, "fuse in {1,3,5}, blocks per CU in [1,64] (node) and [1,16] (fused)");
     b->fuse = fuse;
     b->bpc_node = bpc_node;
@@ -1242,7 +1246,7 @@ int dlb_batch_autotune(dlb_batch_handle b, int trial_steps, double* ms_best) {
     if (!b || trial_steps < 1) return fail(DLB_EINVAL, "null batch or trial_steps < 1");
     int rc = upload_desc(b);
     if (rc) return rc;
-    const int fuses[3] = {5, 3, 1}, bns[5] = {4, 8, 16, 32, 64}, bts[4] = {1, 2, 3, 4};
+    const int fuses[3] = {5, 3, 1}, bns[6] = {4, 16, 64, 256, 1024, 4096}, bts[4] = {1, 2, 3, 4};
     float best = 1e30f;
     int bf = b->fuse, bn = b->bpc_node, bt = b->bpc_tb;
     // coordinate search: fused-launch shape first, then the node-kernel grid
