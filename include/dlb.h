@@ -272,7 +272,7 @@ int dlb_copy_kernel(void* dst, const void* src, size_t bytes, void* hip_stream);
 /* ---------------------------------------------------------------------------
  * Batches: many independent solvers (any grid sizes, their own physical
  * parameters; shared precision, use_ns, bc and n_sub) stepped in lockstep,
- * each kernel class as one persistent launch over a (seed, tile) work list.
+ * each kernel class as one launch over a (seed, tile) work list.
  * Every member evolves bit for bit as it would alone with the same
  * flow_fuse.  The caller owns one device buffer for the whole batch.
  * ------------------------------------------------------------------------- */
@@ -293,9 +293,10 @@ dlb_handle dlb_batch_member(dlb_batch_handle b, int i);
 int dlb_batch_step(dlb_batch_handle b, int64_t n);
 int64_t dlb_batch_step_count(dlb_batch_handle b);
 /* Launch configuration: flow sub-steps fused per launch (1, 3, 5) and the
- * grid as workgroups per compute unit for the node kernels (1..4096; a grid
- * with at least one workgroup per node tile runs one tile per workgroup) and
- * the fused flow kernel (1..16).  DLB_EINVAL outside these ranges. */
+ * grids as workgroups per compute unit for the node kernels and for the
+ * fused flow kernel (1..4096 each; a grid with at least one workgroup per
+ * tile runs one tile per workgroup, a smaller one loops its workgroups over
+ * the tiles).  DLB_EINVAL outside these ranges. */
 int dlb_batch_set_config(dlb_batch_handle b, int fuse, int bpc_node, int bpc_tb);
 int dlb_batch_get_config(dlb_batch_handle b, int* out3);
 /* Node tile of the batched phi/C/theta and one-sub-step flow launches:

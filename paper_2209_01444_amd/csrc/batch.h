@@ -1,11 +1,13 @@
 // batch.h -- one launch per kernel class for many independent solvers.
 //
 // A batch holds independent seeds (grids of any size, their own physical
-// parameters) that step in lockstep.  Each kernel class runs as one
-// persistent launch over a global list of (seed, tile) work items, seed by
-// seed and row by row: the list is cut into one band per XCD and the
-// workgroups of an XCD take the items of their band in turn (batch_span), so
-// neighbouring tiles of a seed run together under one L2.  Per node the
+// parameters) that step in lockstep.  Each kernel class runs as one launch
+// over a global list of (seed, tile) work items, seed by seed and row by row:
+// the list is cut into one band per XCD and the workgroups of an XCD take the
+// items of their band in turn (batch_span), so neighbouring tiles of a seed
+// run together under one L2.  The grid is a launch parameter: fewer
+// workgroups than items make it persistent (each loops over its items), as
+// many give one item per workgroup.  Per node the
 // arithmetic is the single-solver kernels' (same device functions), so every
 // member evolves bit for bit as it would alone.
 #pragma once
@@ -50,7 +52,7 @@ __device__ __forceinline__ void batch_node(const SeedDesc& sd, int t, int tw_log
     y = (t / sd.node_nbx) * (BLOCK >> tw_log2) + (threadIdx.x >> tw_log2);
 }
 
-// Items of a persistent batch launch taken by this block: the work list is
+// Items of a batch launch taken by this block: the work list is
 // cut into 8 contiguous bands, one per XCD (block b runs on XCD b mod 8),
 // and the blocks of one XCD interleave over their band, so that tiles
 // sharing halo rows or streaming targets (the next tile row of the same

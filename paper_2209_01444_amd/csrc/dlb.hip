@@ -1127,7 +1127,7 @@ dlb_handle dlb_batch_member(dlb_batch_handle b, int i) {
 
 int dlb_batch_set_config(dlb_batch_handle b, int fuse, int bpc_node, int bpc_tb) {
     if (!b) return fail(DLB_EINVAL, "null batch");
-    if ((fuse != 1 && fuse != 3 && fuse != 5) || bpc_node < 1 || bpc_node > 4096 || bpc_tb < 1 || bpc_tb > 16)
+    if ((fuse != 1 && fuse != 3 && fuse != 5) || bpc_node < 1 || bpc_node > 4096 || bpc_tb < 1 || bpc_tb > 4096)
         return fail(DLB_EINVAL, "fuse in {1,3,5}, blocks per CU in [1,64] (node) and [1,16] (fused)");
     b->fuse = fuse;
     b->bpc_node = bpc_node;
@@ -1246,7 +1246,7 @@ int dlb_batch_autotune(dlb_batch_handle b, int trial_steps, double* ms_best) {
     if (!b || trial_steps < 1) return fail(DLB_EINVAL, "null batch or trial_steps < 1");
     int rc = upload_desc(b);
     if (rc) return rc;
-    const int fuses[3] = {5, 3, 1}, bns[6] = {4, 16, 64, 256, 1024, 4096}, bts[4] = {1, 2, 3, 4};
+    const int fuses[3] = {5, 3, 1}, bns[6] = {4, 16, 64, 256, 1024, 4096}, bts[6] = {1, 2, 3, 4, 32, 4096};
     float best = 1e30f;
     int bf = b->fuse, bn = b->bpc_node, bt = b->bpc_tb;
     // coordinate search: fused-launch shape first, then the node-kernel grid

@@ -326,8 +326,8 @@ class Solver:
 
 
 class Batch:
-    """Independent solvers stepped in lockstep by one persistent launch per
-    kernel class (see dlb_batch_* in include/dlb.h)."""
+    """Independent solvers stepped in lockstep by one launch per kernel
+    class over a (seed, tile) work list (see dlb_batch_* in include/dlb.h)."""
 
     def __init__(self, cfgs: list[dict], device: str = "cuda:0"):
         import torch

@@ -1,5 +1,5 @@
-"""Batched sweep: many seeds of uneven grid sizes in one persistent,
-graph-replayed launch per kernel class, with the project's autotuner.
+"""Batched sweep: many seeds of uneven grid sizes in one graph-replayed
+launch per kernel class, with the project's autotuner.
 
     python -m paper_2209_01444_amd.sweep --count 256 --steps 1000
     python -m paper_2209_01444_amd.sweep --count 256 --steps 10000 --snapshots out/ --every 100

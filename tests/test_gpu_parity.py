@@ -819,8 +819,8 @@ def test_batch_autotune_and_member_rules(dlb):
     _say(f"  tuned: fuse={fuse} node blocks/CU={bn} fused blocks/CU={bt} node tile {b.node_tile}, "
          f"{ms:.4f} ms/step")
     assert ms > 0 and fuse in (1, 3, 5) and b.node_tile in (32, 64, 128, 256)
-    assert bn in (4, 16, 64, 256, 1024, 4096) and bt in (1, 2, 3, 4)
-    for bad in ((5, 4097, 2), (5, 0, 2), (4, 64, 2), (5, 64, 17)):
+    assert bn in (4, 16, 64, 256, 1024, 4096) and bt in (1, 2, 3, 4, 32, 4096)
+    for bad in ((5, 4097, 2), (5, 0, 2), (4, 64, 2), (5, 64, 4097), (5, 64, 0)):
         with pytest.raises(dlb.DlbError):
             b.set_config(*bad)
     # tuning again from another node tile searches the same candidates
