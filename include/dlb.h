@@ -296,7 +296,8 @@ int64_t dlb_batch_step_count(dlb_batch_handle b);
  * grids as workgroups per compute unit for the node kernels and for the
  * fused flow kernel (1..4096 each; a grid with at least one workgroup per
  * tile runs one tile per workgroup, a smaller one loops its workgroups over
- * the tiles).  DLB_EINVAL outside these ranges. */
+ * the tiles; the default is 5, 4096, 4096).  DLB_EINVAL outside these
+ * ranges. */
 int dlb_batch_set_config(dlb_batch_handle b, int fuse, int bpc_node, int bpc_tb);
 int dlb_batch_get_config(dlb_batch_handle b, int* out3);
 /* Node tile of the batched phi/C/theta and one-sub-step flow launches:

@@ -945,7 +945,7 @@ struct dlb_batch {
     hipStream_t stream = nullptr;
     int pop_cur = 0, flow_cur = 0;
     int64_t step = 0;
-    int fuse = 5, bpc_node = 8, bpc_tb = 2, num_cu = 256;
+    int fuse = 5, bpc_node = 4096, bpc_tb = 4096, num_cu = 256;  // grids: one tile per workgroup
     int node_tw_log2 = 6;  // node tiles of 64 x 4 nodes
     BatchOps ops;
     hipGraphExec_t graph = nullptr;

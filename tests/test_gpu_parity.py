@@ -700,7 +700,7 @@ def test_create_rejects_small_buffer(dlb):
 
 
 # ---------------------------------------------------------------------------
-# Batched persistent launches
+# Batched launches
 # ---------------------------------------------------------------------------
 
 def _sweep_cfgs(precision="f32", fuse=5):
@@ -722,8 +722,8 @@ def _sweep_cfgs(precision="f32", fuse=5):
 @pytest.mark.parametrize("precision,fuse", [("f32", 5), ("f64", 3), ("f32", 1)])
 def test_batch_members_match_single_runs(dlb, precision, fuse):
     """A batch of seeds of different sizes and parameters, stepped by one
-    persistent launch per kernel class, evolves every member bit for bit
-    like a single solver with the same settings."""
+    launch per kernel class, evolves every member bit for bit like a single
+    solver with the same settings."""
     _say(f"case: batch of 6 seeds {precision} fuse={fuse} vs single runs")
     cases = _sweep_cfgs(precision, fuse)
     b = dlb.Batch([c for c, _ in cases])
@@ -738,6 +738,30 @@ def test_batch_members_match_single_runs(dlb, precision, fuse):
         for k in FIELDS:
             assert np.array_equal(fb[k], fs[k]), f"member {i} field {k} differs"
         assert m.step_count == 23
+
+
+@pytest.mark.parametrize("fuse", [5, 1])
+def test_batch_workgroups_looping_over_tiles_give_the_same_members(dlb, fuse):
+    """The smallest grids (one workgroup per compute unit) on a batch with
+    more tiles than workgroups: each workgroup takes several tiles of its
+    XCD's band in turn, and every member still evolves bit for bit like a
+    single solver."""
+    _say(f"case: batch of 3 seeds, 1 workgroup per CU, f32 fuse={fuse} vs single runs")
+    cases = []
+    for i, (nx, ny) in enumerate([(1024, 512), (200, 200), (64, 64)]):
+        cfg, noise = W.thermosolutal_flow(nx, ny, seed=300 + i, precision="f32")
+        cfg.update(seed_R=8.0, flow_fuse=fuse)
+        cases.append((cfg, noise))
+    b = dlb.Batch([c for c, _ in cases])
+    for m, (_, noise) in zip(b.members, cases):
+        m.init_seed(noise)
+    b.set_config(fuse, 1, 1)
+    b.step(12)
+    for i, (m, (cfg, noise)) in enumerate(zip(b.members, cases)):
+        s = dlb.Solver(cfg).init_seed(noise).step(12)
+        fb, fs = m.fields(), s.fields()
+        for k in FIELDS:
+            assert np.array_equal(fb[k], fs[k]), f"member {i} field {k} differs"
 
 
 @pytest.mark.parametrize("walls,precision,fuse,shape", [(1, "f32", 5, (333, 271)), (0, "f32", 5, (200, 150)),
