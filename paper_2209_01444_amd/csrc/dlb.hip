@@ -1007,8 +1007,14 @@ static void batch_node_tiles(dlb_batch* b, int tw_log2) {
     b->node_tw_log2 = tw_log2;
 }
 
+// Batch grids are a multiple of the 8 XCDs, so that batch_span gives every
+// XCD one contiguous band of the work list (a grid trimmed to the item count
+// would otherwise interleave the items over the XCDs); surplus workgroups
+// find their range empty.
+static int batch_grid(int items, int num_cu, int per_cu) { return (std::min(items, num_cu * per_cu) + 7) & ~7; }
+
 static void batch_enqueue_step(dlb_batch* b, int fuse, int bpc_node, int bpc_tb) {
-    const int bn = std::min(b->total_tiles, b->num_cu * bpc_node);
+    const int bn = batch_grid(b->total_tiles, b->num_cu, bpc_node);
     b->ops.pct(b->base, b->d_desc, b->count, b->total_tiles, b->pop_cur, b->flow_cur, b->node_tw_log2, bn,
                b->stream);
     b->pop_cur ^= 1;
@@ -1016,7 +1022,7 @@ static void batch_enqueue_step(dlb_batch* b, int fuse, int bpc_node, int bpc_tb)
         int left = b->p0.n_sub;
         while (fuse > 1 && left >= fuse) {
             int L = fuse == 5 ? 1 : 0;
-            int bt = std::min(b->total_tb[L], b->num_cu * bpc_tb);
+            const int bt = batch_grid(b->total_tb[L], b->num_cu, bpc_tb);
             b->ops.flow_tb(fuse, b->base, b->d_desc, b->count, b->total_tb[L], b->flow_cur, bt, b->stream);
             b->flow_cur ^= 1;
             left -= fuse;
