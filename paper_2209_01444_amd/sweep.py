@@ -63,9 +63,11 @@ def main():
     ap.add_argument("--snapshots", default="")
     ap.add_argument("--every", type=int, default=100)
     ap.add_argument("--max-size", type=int, default=1024)
+    ap.add_argument("--sizes", default="128,256,512,1024", help="grid sizes the seeds draw from")
     args = ap.parse_args()
 
-    cases = [c for c in workloads.batched_sweep(args.count, args.seed)
+    sizes = tuple(int(v) for v in args.sizes.split(","))
+    cases = [c for c in workloads.batched_sweep(args.count, args.seed, sizes)
              if c[0]["nx"] <= args.max_size]
     for c, _ in cases:
         c["precision"] = args.precision

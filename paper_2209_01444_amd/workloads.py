@@ -56,14 +56,16 @@ def thermosolutal_flow(nx: int = 1024, ny: int = 1024, seed: int = 2, precision:
     return cfg, noise
 
 
-def batched_sweep(count: int = 256, seed: int = 4) -> list[tuple[dict, np.ndarray]]:
-    """Independent seeds for a batched sweep: size from {128..1024}^2,
-    undercooling ~ U[0.3, 0.65], eps4 ~ U[0.02, 0.05], orientation ~ U[0, pi/4),
-    u0 ~ U[0, 0.02]; otherwise the thermosolutal set."""
+def batched_sweep(count: int = 256, seed: int = 4,
+                  sizes: tuple[int, ...] = (128, 256, 512, 1024)) -> list[tuple[dict, np.ndarray]]:
+    """Independent seeds for a batched sweep: size drawn from `sizes` (square
+    grids, {128..1024}^2 by default), undercooling ~ U[0.3, 0.65], eps4 ~
+    U[0.02, 0.05], orientation ~ U[0, pi/4), u0 ~ U[0, 0.02]; otherwise the
+    thermosolutal set."""
     rng = np.random.default_rng(seed)
     out = []
     for i in range(count):
-        n = int(rng.choice([128, 256, 512, 1024]))
+        n = int(rng.choice(list(sizes)))
         delta = float(rng.uniform(0.3, 0.65))
         eps4 = float(rng.uniform(0.02, 0.05))
         orient = float(rng.uniform(0.0, math.pi / 4))
