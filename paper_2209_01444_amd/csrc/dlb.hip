@@ -1134,7 +1134,7 @@ dlb_handle dlb_batch_member(dlb_batch_handle b, int i) {
 int dlb_batch_set_config(dlb_batch_handle b, int fuse, int bpc_node, int bpc_tb) {
     if (!b) return fail(DLB_EINVAL, "null batch");
     if ((fuse != 1 && fuse != 3 && fuse != 5) || bpc_node < 1 || bpc_node > 4096 || bpc_tb < 1 || bpc_tb > 4096)
-        return fail(DLB_EINVAL, "fuse in {1,3,5}, blocks per CU in [1,64] (node) and [1,16] (fused)");
+        return fail(DLB_EINVAL, "fuse in {1,3,5}, workgroups per CU in [1,4096] (node and fused)");
     b->fuse = fuse;
     b->bpc_node = bpc_node;
     b->bpc_tb = bpc_tb;
