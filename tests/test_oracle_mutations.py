@@ -66,6 +66,14 @@ MUTATIONS = [
      T + "test_uniform_U_and_theta_are_steady_across_a_still_front"),
     ("half the interface force", "Fb[0] = (1.0 - qt) * fx;", "Fb[0] = 0.5 * (1.0 - qt) * fx;",
      TT + "test_fully_solid_node_stops_the_flow"),
+    ("phase-field rate without a_s^2", "return 1.0 / (as * as * W2t * 3.0 + 0.5);", "return 1.0 / (W2t * 3.0 + 0.5);",
+     T + "test_phase_field_mode_decay_with_fixed_anisotropy"),
+    ("solute rate without 1 - k", "double s1c = 1.0 / (3.0 * p->D * (1.0 - p->k) + 0.5);",
+     "double s1c = 1.0 / (3.0 * p->D + 0.5);", T + "test_solute_and_heat_modes_decay_at_the_diffusivity"),
+    ("heat rate with 2 alpha", "double s1t = 1.0 / (3.0 * p->alpha / heat_sub(p) + 0.5);",
+     "double s1t = 1.0 / (6.0 * p->alpha / heat_sub(p) + 0.5);", T + "test_solute_and_heat_modes_decay_at_the_diffusivity"),
+    ("flow second moments relaxed at 1", "double s[9] = {1.0, 1.0, 1.0, s2, s2, s2, 1.0, 1.0, 1.0};",
+     "double s[9] = {1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0};", T + "test_taylor_green_decay_with_two_time_scaling"),
     ("viscosity not rescaled by N", "double nu_sub = p->nu / (double)p->n_sub;",
      "double nu_sub = p->nu;", T + "test_taylor_green_decay_with_two_time_scaling"),
     ("h(phi)/2 dropped from g_0^eq", "out[0] = W5[0] * theta - 0.5 * hp;",
