@@ -74,6 +74,12 @@ MUTATIONS = [
      "double s1t = 1.0 / (6.0 * p->alpha / heat_sub(p) + 0.5);", T + "test_solute_and_heat_modes_decay_at_the_diffusivity"),
     ("flow second moments relaxed at 1", "double s[9] = {1.0, 1.0, 1.0, s2, s2, s2, 1.0, 1.0, 1.0};",
      "double s[9] = {1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0};", T + "test_taylor_green_decay_with_two_time_scaling"),
+    ("coupling source with 1 - phi^2 once", "double Q = ph * om - p->lambda * (theta + p->Mcinf * U) * om * om;",
+     "double Q = ph * om - p->lambda * (theta + p->Mcinf * U) * om;", T + "test_undercooled_planar_front_speed"),
+    ("inflow velocity in main-step units", "ub[0] = s->p.u_in_x / s->p.n_sub;", "ub[0] = s->p.u_in_x;",
+     T + "test_uniform_channel_flow_is_steady"),
+    ("solid weight (1 - phi)/2 in the reductions", "double w = 0.5 * (1.0 + s->phi[x]);",
+     "double w = 0.5 * (1.0 - s->phi[x]);", TC + "test_force_and_torque_balance_the_fluid_momentum"),
     ("viscosity not rescaled by N", "double nu_sub = p->nu / (double)p->n_sub;",
      "double nu_sub = p->nu;", T + "test_taylor_green_decay_with_two_time_scaling"),
     ("h(phi)/2 dropped from g_0^eq", "out[0] = W5[0] * theta - 0.5 * hp;",
