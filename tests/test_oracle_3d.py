@@ -5,8 +5,9 @@ What fixes it other than itself: the cubic anisotropy's closed values along
 <100>, <110> and <111>; N against finite differences of a_s and orthogonal to
 the gradient; with g_z = 0 the 2-D oracle's (independently written)
 anisotropy; diffusion modes decaying at D k^2 and alpha k^2 at second order;
-the linearised phase-field mode about phi = -1 with a_s fixed; conservation
-of C and H; the cubic symmetry of a centred seed."""
+the linearised phase-field mode about phi = -1 with a_s fixed; the
+solvability speed of an undercooled planar front; conservation of C and H;
+the cubic symmetry of a centred seed."""
 import math
 
 import numpy as np
@@ -98,6 +99,41 @@ def test_phase_field_mode_decay_with_fixed_anisotropy(a):
     rate = -math.log(a2 / a1) / n
     exact = (W0**2 * a * a * k * k + 2) / (tau0 * a * a)
     assert rate / exact - 1 == pytest.approx(0.0, abs=5e-3)
+
+
+@pytest.mark.parametrize("theta0", [-0.02, -0.01])
+def test_undercooled_planar_front_speed(theta0):
+    """Phase-field equation in a uniform undercooling (Mc_inf = 0, so the
+    solute does not act on it; heat lattice off): solvability of the tanh
+    front gives, to first order in theta0, v = -(4/5) lambda theta0 w /
+    (tau0 a_s^2) with w = sqrt(2) W0 a_s, and a_s = 1 + eps along a lattice
+    axis in 3-D as in 2-D.  Pins the coupling source of Sec. 2 in 3-D."""
+    W0, eps = 4.0, 0.05
+    a = 1 + eps
+    w = math.sqrt(2) * W0 * a
+    L, tau0 = int(48 * W0), 20.0 * W0 * W0 / 4
+    x = np.arange(L).astype(float)
+    prof = -np.tanh((x - L / 4) / w) * np.tanh((x - 3 * L / 4) / w)
+    cfg = dict(nx=L, ny=4, nz=4, use_t=0, W0=W0, tau0=tau0, lambda_=1.0, theta0=theta0, Mcinf=0.0,
+               eps4=eps)
+    o = O.Oracle3(cfg).set_fields(np.ascontiguousarray(np.broadcast_to(prof, (4, 4, L))))
+
+    def front(phi):
+        r = phi[0, 0]
+        for j in range(L // 2, L - 1):
+            if r[j] > 0 >= r[j + 1]:
+                return j + r[j] / (r[j] - r[j + 1])
+        raise AssertionError("front lost")
+
+    o.step(int(5 * tau0))
+    x1 = front(o.fields()["phi"])
+    m = int(10 * tau0)
+    o.step(m)
+    x2 = front(o.fields()["phi"])
+    v = (x2 - x1) / m
+    exact = -(4 / 5) * theta0 * w / (tau0 * a * a)
+    print(f"v = {v:.6e}, solvability {exact:.6e}")
+    assert v / exact - 1 == pytest.approx(0.0, abs=1e-2)
 
 
 @pytest.fixture(scope="module")

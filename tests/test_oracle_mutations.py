@@ -147,6 +147,8 @@ MUTATIONS_3D = [
      "(CX[i] * H * u[0] + CY[i] * H * u[1] + CZ[i] * H * u[2]) * 3.0;", T3 + "test_advected_heat_mode_keeps_alpha_and_u"),
     ("3-D: anisotropy strength", "out[1 + a] = g2 * as * (4.0 * eps * dsum);", "out[1 + a] = g2 * as * (3.0 * eps * dsum);",
      T3 + "test_torque_vector_is_the_gradient_of_a_s"),
+    ("3-D: coupling source with 1 - phi^2 once", "double Q = ph * om - p->lambda * (th + p->Mcinf * U) * om * om;",
+     "double Q = ph * om - p->lambda * (th + p->Mcinf * U) * om;", T3 + "test_undercooled_planar_front_speed"),
     ("3-D: anti-trapping current dropped", JAT3, "double c = 0.0;",
      TC + "test_planar_alloy_front_does_not_trap_solute[3]"),
     ("3-D: anti-trapping without 1/(2 sqrt 2)", JAT3, JAT3.replace("-1.0 / (2.0 * sqrt(2.0))", "-1.0"),
