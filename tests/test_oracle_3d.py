@@ -6,7 +6,8 @@ What fixes it other than itself: the cubic anisotropy's closed values along
 the gradient; with g_z = 0 the 2-D oracle's (independently written)
 anisotropy; diffusion modes decaying at D k^2 and alpha k^2 at second order;
 the linearised phase-field mode about phi = -1 with a_s fixed; the
-solvability speed of an undercooled planar front; conservation of C and H;
+solvability speed of an undercooled planar front; uniform U and theta
+staying uniform across a still front; conservation of C and H;
 the cubic symmetry of a centred seed."""
 import math
 
@@ -134,6 +135,37 @@ def test_undercooled_planar_front_speed(theta0):
     exact = -(4 / 5) * theta0 * w / (tau0 * a * a)
     print(f"v = {v:.6e}, solvability {exact:.6e}")
     assert v / exact - 1 == pytest.approx(0.0, abs=1e-2)
+
+
+def _still_front_drift(W0):
+    eps = 0.05
+    L = int(32 * W0)
+    w = math.sqrt(2) * W0 * (1 + eps)
+    x = np.arange(L).astype(float)
+    prof = -np.tanh((x - L / 4) / w) * np.tanh((x - 3 * L / 4) / w)
+    phi = np.ascontiguousarray(np.broadcast_to(prof, (4, 4, L)))
+    k, U0, th0 = 0.15, -0.3, -0.4
+    C = 0.5 * (1 + k - (1 - k) * phi) * (1 + (1 - k) * U0)
+    cfg = dict(nx=L, ny=4, nz=4, use_t=1, W0=W0, tau0=20 * W0 * W0, lambda_=0.0, theta0=th0, eps4=eps, k=k,
+               D=0.1, alpha=0.1)
+    o = O.Oracle3(cfg).set_fields(phi, C, np.full_like(phi, th0))
+    o.step(2000)
+    f = o.fields()
+    assert np.ptp(f["C"]) > 0.3  # C itself is far from uniform
+    return np.abs(f["U"] - U0).max(), np.abs(f["theta"] - th0).max()
+
+
+def test_uniform_U_and_theta_are_steady_across_a_still_front():
+    """Across a stationary front (lambda = 0: d_t phi = 0, no anti-trapping
+    current) the solute equation reads d_t C = D(1-k) div(q grad U), so a
+    uniform U is steady although C jumps by the partition ratio, and the heat
+    equation keeps a uniform theta although H = theta - h(phi)/2 jumps.
+    Pins the U grad(q) auxiliary term and the h(phi)/2 split in 3-D; the
+    residual drift of U is a discretisation error that falls with dx/W0."""
+    devs = [_still_front_drift(W0) for W0 in (2.0, 4.0)]
+    print("U and theta drift at W0 = 2, 4:", devs)
+    assert devs[0][0] < 2e-2 and devs[1][0] < 3e-3 and devs[0][0] / devs[1][0] > 3
+    assert devs[0][1] < 1e-4 and devs[1][1] < 1e-4
 
 
 @pytest.fixture(scope="module")

@@ -147,6 +147,14 @@ MUTATIONS_3D = [
      "(CX[i] * H * u[0] + CY[i] * H * u[1] + CZ[i] * H * u[2]) * 3.0;", T3 + "test_advected_heat_mode_keeps_alpha_and_u"),
     ("3-D: anisotropy strength", "out[1 + a] = g2 * as * (4.0 * eps * dsum);", "out[1 + a] = g2 * as * (3.0 * eps * dsum);",
      T3 + "test_torque_vector_is_the_gradient_of_a_s"),
+    ("3-D: sign of U grad q", "U * (-0.5 * gx)", "U * (0.5 * gx)",
+     T3 + "test_uniform_U_and_theta_are_steady_across_a_still_front"),
+    ("3-D: solute rate without 1 - k",
+     "static double s1_solute(const o3_params* p) { return 1.0 / (p->D * (1.0 - p->k) / CS2 + 0.5); }",
+     "static double s1_solute(const o3_params* p) { return 1.0 / (p->D / CS2 + 0.5); }",
+     T3 + "test_diffusion_mode_decays_at_the_diffusivity"),
+    ("3-D: h(phi)/2 dropped from g_0^eq", "o[0] = W7[0] * theta - 0.5 * h_of(phi, quintic);",
+     "o[0] = W7[0] * theta;", T3 + "test_uniform_U_and_theta_are_steady_across_a_still_front"),
     ("3-D: coupling source with 1 - phi^2 once", "double Q = ph * om - p->lambda * (th + p->Mcinf * U) * om * om;",
      "double Q = ph * om - p->lambda * (th + p->Mcinf * U) * om;", T3 + "test_undercooled_planar_front_speed"),
     ("3-D: anti-trapping current dropped", JAT3, "double c = 0.0;",
