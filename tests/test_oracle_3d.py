@@ -6,7 +6,8 @@ What fixes it other than itself: the cubic anisotropy's closed values along
 the gradient; with g_z = 0 the 2-D oracle's (independently written)
 anisotropy; diffusion modes decaying at D k^2 and alpha k^2 at second order;
 the linearised phase-field mode about phi = -1 with a_s fixed; the
-solvability speed of an undercooled planar front; uniform U and theta
+solvability speed of an undercooled planar front; the anisotropic
+relaxation rate of an undulated front (the N forcing); uniform U and theta
 staying uniform across a still front; conservation of C and H;
 the cubic symmetry of a centred seed."""
 import math
@@ -135,6 +136,44 @@ def test_undercooled_planar_front_speed(theta0):
     exact = -(4 / 5) * theta0 * w / (tau0 * a * a)
     print(f"v = {v:.6e}, solvability {exact:.6e}")
     assert v / exact - 1 == pytest.approx(0.0, abs=1e-2)
+
+
+def test_front_undulation_relaxes_with_anisotropic_stiffness():
+    """lambda = 0: a planar front (normal along x) carrying a small cosine
+    undulation along y, uniform in z, relaxes by anisotropic curvature flow
+    at (W0^2/tau0)(a_s + a_s'') q^2 / a_s^2.  In the x-y plane the cubic
+    anisotropy is the planar one, a_s = 1 + eps cos 4psi, so a_s + a_s'' =
+    1 - 15 eps along x.  The a_s'' part comes only from the vector N of Sec. 2
+    through the forcing G of the phase-field lattice, whose sign and size
+    this pins in 3-D (N vanishes on fronts along a lattice axis)."""
+    eps, W0 = 0.05, 2.0
+    tau0, ny, nz = 20 * W0 * W0, 128, 3
+    nx = int(32 * W0)
+    q = 2 * math.pi / ny
+    a = 1 + eps
+    w = math.sqrt(2) * W0 * a
+    Y, X = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    phi2 = -np.tanh((X - nx / 4 - 0.5 * np.cos(q * Y)) / w) * np.tanh((X - 3 * nx / 4) / w)
+    cfg = dict(nx=nx, ny=ny, nz=nz, use_t=0, W0=W0, tau0=tau0, lambda_=0.0, theta0=0.0, eps4=eps)
+    o = O.Oracle3(cfg).set_fields(np.ascontiguousarray(np.broadcast_to(phi2, (nz, ny, nx))))
+
+    def undulation(f):
+        pos = []
+        for j in range(ny):
+            r = f[nz // 2, j]
+            i = [i for i in range(nx // 2) if r[i] <= 0 < r[i + 1]][0]
+            pos.append(i + (-r[i]) / (r[i + 1] - r[i]))
+        return 2 * np.mean(np.array(pos) * np.cos(q * np.arange(ny)))
+
+    o.step(int(2 * tau0))
+    a1 = undulation(o.fields()["phi"])
+    m = int(10 * tau0)
+    o.step(m)
+    a2 = undulation(o.fields()["phi"])
+    rate = -math.log(a2 / a1) / m
+    pred = (W0 * W0 / tau0) * (1 - 15 * eps) * q * q / a**2
+    print(f"rate {rate:.4e}, predicted {pred:.4e}")
+    assert rate / pred - 1 == pytest.approx(0.0, abs=0.1)
 
 
 def _still_front_drift(W0):

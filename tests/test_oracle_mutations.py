@@ -147,6 +147,9 @@ MUTATIONS_3D = [
      "(CX[i] * H * u[0] + CY[i] * H * u[1] + CZ[i] * H * u[2]) * 3.0;", T3 + "test_advected_heat_mode_keeps_alpha_and_u"),
     ("3-D: anisotropy strength", "out[1 + a] = g2 * as * (4.0 * eps * dsum);", "out[1 + a] = g2 * as * (3.0 * eps * dsum);",
      T3 + "test_torque_vector_is_the_gradient_of_a_s"),
+    ("3-D: sign of G^phi", "G[i] = -W7[i] * (CX[i] * lg[4] + CY[i] * lg[5] + CZ[i] * lg[6]) / a2;",
+     "G[i] = W7[i] * (CX[i] * lg[4] + CY[i] * lg[5] + CZ[i] * lg[6]) / a2;",
+     T3 + "test_front_undulation_relaxes_with_anisotropic_stiffness"),
     ("3-D: sign of U grad q", "U * (-0.5 * gx)", "U * (0.5 * gx)",
      T3 + "test_uniform_U_and_theta_are_steady_across_a_still_front"),
     ("3-D: solute rate without 1 - k",
