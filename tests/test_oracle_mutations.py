@@ -76,6 +76,12 @@ MUTATIONS = [
      "double s[9] = {1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0};", T + "test_taylor_green_decay_with_two_time_scaling"),
     ("coupling source with 1 - phi^2 once", "double Q = ph * om - p->lambda * (theta + p->Mcinf * U) * om * om;",
      "double Q = ph * om - p->lambda * (theta + p->Mcinf * U) * om;", T + "test_undercooled_planar_front_speed"),
+    ("free slip keeps the transverse velocity", "                ub[0] = uf[0];\n                ub[1] = 0.0;",
+     "                ub[0] = uf[0];\n                ub[1] = uf[1];",
+     T + "test_channel_conserves_mass_past_an_off_centre_solid"),
+    ("outflow pressure from the neighbour", "ub[1] = (y == 0 || y == s->ny - 1) ? 0.0 : uf[1];\n                pb = 0.0;",
+     "ub[1] = (y == 0 || y == s->ny - 1) ? 0.0 : uf[1];\n                pb = pf;",
+     T + "test_channel_conserves_mass_past_an_off_centre_solid"),
     ("inflow velocity in main-step units", "ub[0] = s->p.u_in_x / s->p.n_sub;", "ub[0] = s->p.u_in_x;",
      T + "test_uniform_channel_flow_is_steady"),
     ("solid weight (1 - phi)/2 in the reductions", "double w = 0.5 * (1.0 + s->phi[x]);",
