@@ -354,6 +354,31 @@ def test_uniform_channel_flow_is_steady():
     np.testing.assert_allclose(f["theta"], -0.4, rtol=1e-13)
 
 
+def test_seed_profile_is_the_stationary_interface():
+    """The initial seed's profile (Sec. 4) is the model's stationary planar
+    interface across its normal (tanh of distance over sqrt(2) W0 with a_s = 1),
+    so with lambda = 0 and no anisotropy its width keeps its value while the
+    disc shrinks by curvature flow, dR/dt = -(W0^2/tau0)/R."""
+    W0, n, R = 2.0, 128, 40.0
+    tau0 = W0 * W0 / 0.05
+    cfg = dict(nx=n, ny=n, use_c=0, use_t=0, use_ns=0, W0=W0, tau0=tau0, lambda_=0.0, eps4=0.0,
+               seed_R=R, seed_x=64.0, seed_y=64.0, theta0=0.0)
+    o = O.Oracle(cfg).init_seed()
+
+    def crossing(phi):
+        r = phi[64, 64:]
+        j = [i for i in range(len(r) - 1) if r[i] > 0 >= r[i + 1]][0]
+        return r[j + 1] - r[j], j + r[j] / (r[j] - r[j + 1])
+
+    d0, r0 = crossing(o.fields()["phi"])
+    o.step(400)
+    d1, r1 = crossing(o.fields()["phi"])
+    shrink = -(W0 * W0 / tau0) * 400 / R
+    print(f"step across the crossing {d0:.4f} -> {d1:.4f}; radius {r0:.4f} -> {r1:.4f} (curvature flow {shrink:.4f})")
+    assert d1 / d0 == pytest.approx(1.0, abs=0.02)
+    assert (r1 - r0) / shrink == pytest.approx(1.0, abs=0.05)
+
+
 def test_channel_conserves_mass_past_an_off_centre_solid():
     """Channel walls (Sec. 4 and 4.1: inflow at the west, du/dx = 0 and p = 0
     at the east, free slip north and south) around a static diffuse disc off

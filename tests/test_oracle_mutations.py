@@ -76,6 +76,16 @@ MUTATIONS = [
      "double s[9] = {1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0};", T + "test_taylor_green_decay_with_two_time_scaling"),
     ("coupling source with 1 - phi^2 once", "double Q = ph * om - p->lambda * (theta + p->Mcinf * U) * om * om;",
      "double Q = ph * om - p->lambda * (theta + p->Mcinf * U) * om;", T + "test_undercooled_planar_front_speed"),
+    ("seed width without sqrt 2", "double ph = tanh((p->seed_R - d) / (sqrt(2.0) * p->W0));",
+     "double ph = tanh((p->seed_R - d) / p->W0);", T + "test_seed_profile_is_the_stationary_interface"),
+    ("force fraction of the liquid", "double qt = 0.5 * (1.0 - phi);", "double qt = 0.5 * (1.0 + phi);",
+     T + "test_diffuse_solid_brakes_the_flow"),
+    ("forcing without (1 - S/2)", "acc += ((i == j ? 1.0 : 0.0) - 0.5 * L9[i * 9 + j]) * F[j];",
+     "acc += (i == j ? 1.0 : 0.0) * F[j];", T + "test_diffuse_solid_brakes_the_flow"),
+    ("pressure with the rest population", "if (i) rest += h[i];", "rest += h[i];",
+     T + "test_uniform_channel_flow_is_steady"),
+    ("corner walls from the x neighbour only", "int yf = y < 1 ? 1 : (y > s->ny - 2 ? s->ny - 2 : y);",
+     "int yf = y;", T + "test_channel_conserves_mass_past_an_off_centre_solid"),
     ("free slip keeps the transverse velocity", "                ub[0] = uf[0];\n                ub[1] = 0.0;",
      "                ub[0] = uf[0];\n                ub[1] = uf[1];",
      T + "test_channel_conserves_mass_past_an_off_centre_solid"),
