@@ -8,7 +8,8 @@ anisotropy; diffusion modes decaying at D k^2 and alpha k^2 at second order;
 the linearised phase-field mode about phi = -1 with a_s fixed; the
 solvability speed of an undercooled planar front; the anisotropic
 relaxation rate of an undulated front (the N forcing); uniform U and theta
-staying uniform across a still front; conservation of C and H;
+staying uniform across a still front; the seed profile as the stationary
+interface; mass conservation along a channel; conservation of C and H;
 the cubic symmetry of a centred seed."""
 import math
 
@@ -176,6 +177,31 @@ def test_front_undulation_relaxes_with_anisotropic_stiffness():
     assert rate / pred - 1 == pytest.approx(0.0, abs=0.1)
 
 
+def test_seed_profile_is_the_stationary_interface():
+    """The spherical seed's profile (tanh of distance over sqrt(2) W0, Sec. 4)
+    is the model's stationary interface across its normal: with lambda = 0 and
+    no anisotropy its width keeps its value while the sphere shrinks by
+    mean-curvature flow, R^2 = R0^2 - 4 (W0^2/tau0) t."""
+    W0, n, R = 2.0, 48, 14.0
+    tau0 = W0 * W0 / 0.05
+    cfg = dict(nx=n, ny=n, nz=n, use_t=0, W0=W0, tau0=tau0, lambda_=0.0, eps4=0.0, seed_R=R, seed_x=24.0,
+               seed_y=24.0, seed_z=24.0, theta0=0.0)
+    o = O.Oracle3(cfg).init_seed()
+
+    def crossing(phi):
+        r = phi[24, 24, 24:]
+        j = [i for i in range(len(r) - 1) if r[i] > 0 >= r[i + 1]][0]
+        return r[j + 1] - r[j], j + r[j] / (r[j] - r[j + 1])
+
+    d0, r0 = crossing(o.fields()["phi"])
+    o.step(200)
+    d1, r1 = crossing(o.fields()["phi"])
+    shrink = math.sqrt(r0 * r0 - 4 * (W0 * W0 / tau0) * 200) - r0
+    print(f"step across the crossing {d0:.4f} -> {d1:.4f}; radius {r0:.3f} -> {r1:.3f} (curvature flow {shrink:.3f})")
+    assert d1 / d0 == pytest.approx(1.0, abs=0.04)
+    assert (r1 - r0) / shrink == pytest.approx(1.0, abs=0.05)
+
+
 def _still_front_drift(W0):
     eps = 0.05
     L = int(32 * W0)
@@ -245,6 +271,31 @@ def _c19():
          (1, -1, 0), (-1, 1, 0), (1, 0, 1), (-1, 0, -1), (1, 0, -1), (-1, 0, 1), (0, 1, 1), (0, -1, -1),
          (0, 1, -1), (0, -1, 1)]
     return np.array(e, float)
+
+
+def test_channel_conserves_mass_past_an_off_centre_solid():
+    """Channel walls in 3-D (inflow at x = 0, du/dx = 0 and p = 0 at the
+    outlet, free slip on the y and z walls) around a quasi-static diffuse
+    sphere (lambda = 0, slow phase field) off the centre line: no mass
+    crosses the free-slip walls, so the flux sum_yz u_x is the same in every
+    column up to the decaying start-up transient; the wall nodes come out of
+    the rebuilt populations with u_y = 0 or u_z = 0 up to the pull of the
+    sphere's diffuse tail, and p = 0 at the outlet."""
+    nx, ny, nz, u0 = 40, 16, 12, 0.03
+    cfg = dict(nx=nx, ny=ny, nz=nz, use_t=1, walls=1, W0=1.0, tau0=2000.0, eps4=0.0, lambda_=0.0, Mcinf=0.0,
+               k=0.15, D=0.1, alpha=0.1, theta0=0.0, C0=1.0, use_ns=1, n_sub=3, nu=0.45, u0x=u0)
+    z, y, x = np.mgrid[0:nz, 0:ny, 0:nx].astype(float)
+    phi = np.tanh((3.0 - np.sqrt((x - 12) ** 2 + (y - 9.5) ** 2 + (z - 5.5) ** 2)) / math.sqrt(2.0))
+    o = O.Oracle3(cfg).set_fields(np.ascontiguousarray(phi))
+    o.step(250)
+    f = o.fields()
+    flux = f["ux"].sum(axis=(0, 1))[1:-1]
+    spread = np.ptp(flux) / (u0 * ny * nz)
+    print(f"flux spread {spread:.3e}, |u_y| max {np.abs(f['uy']).max():.3e}")
+    assert np.abs(f["uy"]).max() > 0.3 * u0  # the sphere does turn the stream
+    assert spread < 0.15
+    assert np.abs(f["uy"][:, [0, -1], :]).max() < 1e-3 and np.abs(f["uz"][[0, -1], :, :]).max() < 1e-3
+    assert np.abs(f["p"][:, :, -1]).max() < 1e-12
 
 
 def test_d3q19_equilibrium_moments():

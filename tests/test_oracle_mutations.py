@@ -163,6 +163,14 @@ MUTATIONS_3D = [
      "(CX[i] * H * u[0] + CY[i] * H * u[1] + CZ[i] * H * u[2]) * 3.0;", T3 + "test_advected_heat_mode_keeps_alpha_and_u"),
     ("3-D: anisotropy strength", "out[1 + a] = g2 * as * (4.0 * eps * dsum);", "out[1 + a] = g2 * as * (3.0 * eps * dsum);",
      T3 + "test_torque_vector_is_the_gradient_of_a_s"),
+    ("3-D: seed width without sqrt 2", "tanh((p->seed_R - d) / (sqrt(2.0) * p->W0));",
+     "tanh((p->seed_R - d) / p->W0);", T3 + "test_seed_profile_is_the_stationary_interface"),
+    ("3-D: free slip keeps the transverse velocity",
+     "                } else {\n                    ub[0] = uf[0];\n                    ub[1] = ywall ? 0.0 : uf[1];",
+     "                } else {\n                    ub[0] = uf[0];\n                    ub[1] = uf[1];",
+     T3 + "test_channel_conserves_mass_past_an_off_centre_solid"),
+    ("3-D: outflow pressure from the neighbour", "                    pb = 0.0;", "                    pb = pf;",
+     T3 + "test_channel_conserves_mass_past_an_off_centre_solid"),
     ("3-D: sign of G^phi", "G[i] = -W7[i] * (CX[i] * lg[4] + CY[i] * lg[5] + CZ[i] * lg[6]) / a2;",
      "G[i] = W7[i] * (CX[i] * lg[4] + CY[i] * lg[5] + CZ[i] * lg[6]) / a2;",
      T3 + "test_front_undulation_relaxes_with_anisotropic_stiffness"),
