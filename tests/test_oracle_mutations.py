@@ -2,8 +2,10 @@
 
 Each case plants one mistake (a dropped term, a wrong sign or factor) in a
 private copy of the oracle source, builds it, and runs the pin that should
-catch it against the mutant in a child pytest; the child must fail.  This
-runs on the CPU only."""
+catch it against the mutant in a child pytest; the child must fail.  The
+mutants are built and run side by side (a module fixture); this runs on the
+CPU only."""
+import concurrent.futures
 import os
 import subprocess
 import sys
@@ -199,32 +201,50 @@ MUTATIONS_3D = [
 ]
 
 
-@pytest.mark.parametrize("label,old,new,pin", MUTATIONS_3D, ids=[m[0] for m in MUTATIONS_3D])
-def test_pin_catches_planted_mistake_3d(tmp_path, label, old, new, pin):
-    src = open(SRC3).read()
-    assert src.count(old) == 1, f"mutation anchor not unique/found: {old!r}"
-    mut_c = tmp_path / "mutant3.c"
-    mut_c.write_text(src.replace(old, new))
-    lib = tmp_path / "libmutant3.so"
-    subprocess.run(["gcc", "-O2", "-std=gnu11", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
-                    "-o", str(lib), str(mut_c), "-lm"], check=True)
-    env = dict(os.environ, DLB3_ORACLE_LIB=str(lib))
+def _run_mutant(workdir, dim, label, old, new, pin):
+    """Build the oracle with one planted mistake and run its pin against it in
+    a child pytest; returns (child's return code, the tail of its output)."""
+    src_path, env_var = (SRC, "DLB_ORACLE_LIB") if dim == 2 else (SRC3, "DLB3_ORACLE_LIB")
+    src = open(src_path).read()
+    if src.count(old) != 1:
+        return None, f"mutation anchor not unique/found: {old!r}"
+    os.makedirs(workdir, exist_ok=True)
+    mut_c = os.path.join(workdir, "mutant.c")
+    lib = os.path.join(workdir, "libmutant.so")
+    with open(mut_c, "w") as fh:
+        fh.write(src.replace(old, new))
+    inc = ["-I", os.path.dirname(SRC)] if dim == 2 else []
+    subprocess.run(["gcc", "-O2", "-std=gnu11", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared", *inc,
+                    "-o", lib, mut_c, "-lm"], check=True)
+    # the children run side by side, one OpenMP thread each
+    env = dict(os.environ, **{env_var: lib, "OMP_NUM_THREADS": "1"})
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", pin],
-                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
-    assert r.returncode != 0, f"pin {pin} did not catch: {label}\n{r.stdout[-2000:]}"
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=900)
+    return r.returncode, r.stdout[-2000:]
+
+
+@pytest.fixture(scope="module")
+def mutant_runs(tmp_path_factory):
+    """Every planted mistake, built and run against its pin in parallel child
+    processes; keyed by (dimension, label)."""
+    cases = [(2, *m) for m in MUTATIONS] + [(3, *m) for m in MUTATIONS_3D]
+    base = tmp_path_factory.mktemp("mutants")
+    workers = max(1, min(8, os.cpu_count() or 1))
+    with concurrent.futures.ThreadPoolExecutor(max_workers=workers) as ex:
+        futs = {(dim, label): ex.submit(_run_mutant, os.path.join(base, f"m{i:03d}"), dim, label, old, new, pin)
+                for i, (dim, label, old, new, pin) in enumerate(cases)}
+        return {key: fut.result() for key, fut in futs.items()}
+
+
+@pytest.mark.parametrize("label,old,new,pin", MUTATIONS_3D, ids=[m[0] for m in MUTATIONS_3D])
+def test_pin_catches_planted_mistake_3d(mutant_runs, label, old, new, pin):
+    rc, out = mutant_runs[(3, label)]
+    assert rc is not None, out
+    assert rc != 0, f"pin {pin} did not catch: {label}\n{out}"
 
 
 @pytest.mark.parametrize("label,old,new,pin", MUTATIONS, ids=[m[0] for m in MUTATIONS])
-def test_pin_catches_planted_mistake(tmp_path, label, old, new, pin):
-    src = open(SRC).read()
-    assert src.count(old) == 1, f"mutation anchor not unique/found: {old!r}"
-    mut_c = tmp_path / "mutant.c"
-    mut_c.write_text(src.replace(old, new))
-    lib = tmp_path / "libmutant.so"
-    subprocess.run(["gcc", "-O2", "-std=gnu11", "-fopenmp", "-ffp-contract=off", "-fPIC",
-                    "-shared", "-I", os.path.dirname(SRC), "-o", str(lib), str(mut_c), "-lm"],
-                   check=True)
-    env = dict(os.environ, DLB_ORACLE_LIB=str(lib))
-    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", pin],
-                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
-    assert r.returncode != 0, f"pin {pin} did not catch: {label}\n{r.stdout[-2000:]}"
+def test_pin_catches_planted_mistake(mutant_runs, label, old, new, pin):
+    rc, out = mutant_runs[(2, label)]
+    assert rc is not None, out
+    assert rc != 0, f"pin {pin} did not catch: {label}\n{out}"
