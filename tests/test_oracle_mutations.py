@@ -78,6 +78,12 @@ MUTATIONS = [
      "double s[9] = {1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0};", T + "test_taylor_green_decay_with_two_time_scaling"),
     ("coupling source with 1 - phi^2 once", "double Q = ph * om - p->lambda * (theta + p->Mcinf * U) * om * om;",
      "double Q = ph * om - p->lambda * (theta + p->Mcinf * U) * om;", T + "test_undercooled_planar_front_speed"),
+    ("heat advection with theta instead of H", "double Hux = H * ux, Huy = H * uy;",
+     "double Hux = theta * ux, Huy = theta * uy;", TT + "test_cde_equilibrium_moment_conditions"),
+    ("heat advection without 1/cs^2", "out[i] = W5[i] * theta + W5[i] * (3.0 * cu);",
+     "out[i] = W5[i] * theta + W5[i] * cu;", T + "test_advected_mode_keeps_the_diffusivity"),
+    ("solute rest population with w0", "out[0] = C + (W5[0] - 1.0) * qU;", "out[0] = C + W5[0] * qU;",
+     TC + "test_solute_free_melt_stays_free_under_a_moving_front"),
     ("seed width without sqrt 2", "double ph = tanh((p->seed_R - d) / (sqrt(2.0) * p->W0));",
      "double ph = tanh((p->seed_R - d) / p->W0);", T + "test_seed_profile_is_the_stationary_interface"),
     ("force fraction of the liquid", "double qt = 0.5 * (1.0 - phi);", "double qt = 0.5 * (1.0 + phi);",
